@@ -1,0 +1,192 @@
+/*
+ * mg.h -- C ABI of the MI355X (gfx950) geometric-multigrid library for the
+ * 2-D Poisson equation.
+ *
+ * What is solved.  The paper solves the pressure-Poisson equation
+ * "Laplacian p = f" (Section 2.2, the Poisson equation; Section 2.5 for the
+ * pressure source) with a geometric multigrid V-cycle (Section 2.2; appendix,
+ * algorithm "Multigrid algorithm with V-Cycle structure").  This library
+ * solves A u = f with A = -Delta_h, the 5-point negative Laplacian, which is
+ * symmetric positive (semi-)definite; the paper's p is -u.
+ *
+ * Grids.  A grid has n nodes per side on the unit square, n - 1 = 4 * 2^k
+ * (n = 5, 9, 17, 33, 65, 129, ...), spacing h = 1/(n-1).  Arrays are row
+ * major with a row pitch given in elements: element (i, j) of a grid stored
+ * at `a` with pitch p is a[i * p + j], i the y index, j the x index.
+ *   MG_BC_DIRICHLET0: zero boundary values.  Unknowns are 1 <= i, j <= n-2;
+ *     boundary entries of u must hold 0 and are never written.
+ *   MG_BC_PERIODIC: the unit torus.  Unknowns are 0 <= i, j <= n-2; row and
+ *     column n-1 duplicate row and column 0 (the "seam").  The seam of an
+ *     input is ignored; the seam of an output is rewritten from node 0.
+ *     f must have (numerically) zero mean.
+ * The hierarchy halves the spacing down to n = 5 (level 0 is the finest).
+ *
+ * The V(nu_pre, nu_post) cycle, per level: nu_pre red-black Gauss-Seidel
+ * sweeps (red = (i+j) even first), residual r = f - A u, full-weighting
+ * restriction of r to the next coarser level, recursion from a zero guess,
+ * correction u += P u_c with P the tensor-product interpolating cubic spline
+ * (natural for Dirichlet, periodic for periodic grids), nu_post sweeps.  The
+ * 5 x 5 level is solved directly (Dirichlet: inverse of the 9 x 9 system;
+ * periodic: pseudo-inverse of the 16 x 16 system, zero-mean result).
+ *
+ * Precision.  MG_FP64 runs every step in FP64.  MG_MIXED runs FP64
+ * iterative refinement around FP32 cycles: r = f - A u in FP64 (stored as
+ * FP32), `inner_cycles` FP32 V-cycles on A e = r from e = 0 with the 5 x 5
+ * solve in FP64, then u += e in FP64.
+ *
+ * Memory and streams.  All array arguments of the solve calls are DEVICE
+ * pointers (hipMalloc'd or torch-allocated on the current device), FP64,
+ * owned by the caller; the library never keeps them past a call.  The
+ * library owns every workspace it allocates in mg_setup and frees it in
+ * mg_destroy.  Work is queued on the HIP stream given to mg_setup (NULL =
+ * the default stream) and is asynchronous unless a call says it
+ * synchronises.  A context is not thread-safe; distinct contexts are
+ * independent.
+ *
+ * Errors.  Every function returns an mg_status and never aborts or throws
+ * across the ABI.  mg_last_error() gives a thread-local detail string for
+ * the last failing call on this thread.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Exported from the shared library (which hides everything else). */
+#define MG_API __attribute__((visibility("default")))
+
+typedef struct mg_ctx_s* mg_ctx;
+
+typedef enum {
+  MG_OK = 0,
+  MG_ERR_INVALID_ARG = -1,      /* bad size, NULL pointer, out-of-range index */
+  MG_ERR_UNSUPPORTED = -2,      /* valid but not provided (e.g. SR-CNN on Dirichlet) */
+  MG_ERR_OOM = -3,              /* device allocation failed */
+  MG_ERR_HIP = -4,              /* a HIP runtime call failed; see mg_last_error() */
+  MG_ERR_INCOMPATIBLE_RHS = -5, /* periodic f with |sum f| > 1e-10 * N * rms(f) */
+  MG_ERR_NOT_CONVERGED = -6,    /* max_cycles reached above rtol (u is valid) */
+  MG_ERR_STAGNATED = -7,        /* residual stopped decreasing above rtol (u is valid) */
+  MG_ERR_NONFINITE = -8         /* NaN or Inf in the residual norm (u may be garbage) */
+} mg_status;
+
+enum { MG_BC_DIRICHLET0 = 0, MG_BC_PERIODIC = 1 };
+enum { MG_FP64 = 0, MG_MIXED = 1 };
+enum { MG_PROLONG_SPLINE = 0, MG_PROLONG_SRCNN = 1 };
+enum { MG_DT_F64 = 0, MG_DT_F32 = 1 };
+
+/* One problem: n nodes per side, boundary condition, row pitch of the
+ * caller's level-0 arrays in elements (0 means n). */
+typedef struct {
+  int32_t n;
+  int32_t bc;
+  int32_t pitch;
+} mg_grid;
+
+/* Solver options (parameter set of the paper's Table 1, reduced to what this
+ * cycle uses).  Fill with mg_options_default() and override fields. */
+typedef struct {
+  int32_t precision;          /* MG_FP64 (default) or MG_MIXED */
+  int32_t nu_pre, nu_post;    /* red-black sweeps before / after the correction (2, 2) */
+  int32_t inner_cycles;       /* MG_MIXED: FP32 cycles per refinement step (1) */
+  int32_t prolong;            /* MG_PROLONG_SPLINE (default) or MG_PROLONG_SRCNN */
+  int32_t cnn_levels;         /* SR-CNN on this many finest prolongations (2) */
+  const void* cnn_weights;    /* host blob of SR-CNN weights, copied at setup */
+  size_t cnn_weights_bytes;
+  int32_t check_every;        /* mg_solve: cycles between norm checks; 0 = auto */
+  int32_t use_graph;          /* capture each cycle into a hipGraph (1) */
+  const char* tune_cache_path; /* autotuner cache file; NULL = built-in choices */
+} mg_options;
+
+/* Fill *opt with the defaults listed above.  No-op on NULL. */
+MG_API void mg_options_default(mg_options* opt);
+
+/* Create a context for `batch` problems grids[0..batch-1] (host array).
+ * Allocates every device workspace (per problem: the coarse levels of the
+ * hierarchy, and for MG_MIXED the FP32 hierarchy including level 0) and the
+ * 5 x 5 inverses, computed in FP64 on the host.  hip_stream is a
+ * hipStream_t (NULL = default stream) used by every later call.
+ * Errors: INVALID_ARG (NULL out/grids/opt, batch <= 0, n not 4*2^k+1,
+ * pitch < n, bad enum, nu_pre/nu_post outside 0..8, inner_cycles outside
+ * 1..8), UNSUPPORTED (SR-CNN requested without weights or on Dirichlet),
+ * OOM, HIP.  On error *out is set to NULL and nothing is leaked. */
+MG_API int32_t mg_setup(const mg_grid* grids, int32_t batch, const mg_options* opt,
+                 void* hip_stream, mg_ctx* out);
+
+/* Run `ncycles` cycles (MG_FP64: V-cycles; MG_MIXED: refinement steps) on
+ * every problem of the batch.  u[b], f[b] (host arrays of device pointers)
+ * are FP64 level-0 arrays with the pitch given at setup; u[b] is both the
+ * initial guess and the result (in place), f[b] is read only.  The
+ * appendix's V-CYCLE(p, r) is one call with ncycles = 1.  If relres_out is
+ * not NULL (host array [batch]) the call synchronises and writes
+ * ||f - A u||_2 / ||f||_2 over the unknowns after the last cycle; otherwise
+ * it returns after queueing.  Periodic seams of u are rewritten.
+ * Errors: INVALID_ARG (NULL ctx/u/f or entries, ncycles < 0), HIP,
+ * NONFINITE (only when relres_out is given). */
+MG_API int32_t mg_vcycle(mg_ctx ctx, double* const* u, const double* const* f, int32_t ncycles,
+                  double* relres_out);
+
+/* Iterate cycles from the given u until ||f - A u|| / ||f|| <= rtol
+ * (the paper iterates to a tolerance, Section 4.2).  Norms are checked every
+ * check_every cycles (auto: after the first cycle, then at predicted
+ * crossings).  Synchronises at every check.  On exit periodic u has zero
+ * mean and a rewritten seam.  cycles_out / relres_out (host arrays [batch],
+ * may be NULL) receive per-problem cycle counts and final relative residuals.
+ * Returns OK when every problem converged, else the first failure among
+ * NOT_CONVERGED (max_cycles hit), STAGNATED (ratio > 0.9 over 3 checks),
+ * NONFINITE, INCOMPATIBLE_RHS (periodic f with nonzero mean; nothing run).
+ * Problems that converge stop cycling while others continue. */
+MG_API int32_t mg_solve(mg_ctx ctx, double* const* u, const double* const* f, double rtol,
+                 int32_t max_cycles, int32_t* cycles_out, double* relres_out);
+
+/* Prolongation operator on its own (the appendix's SR-Prolongation and the
+ * spline prolongation of Section 2.2): fine = P coarse for problem
+ * `problem`, from level `coarse_level` (>= 1) to level coarse_level - 1.
+ * coarse and fine are device arrays of that problem's level sides, pitch =
+ * side, dtype MG_DT_F64 or MG_DT_F32.  kind MG_PROLONG_SPLINE interpolates
+ * with the cubic spline; MG_PROLONG_SRCNN applies the SR-CNN.  The result
+ * is written, not added; periodic seams are written.  Asynchronous.
+ * Errors: INVALID_ARG, UNSUPPORTED (SRCNN without weights/Dirichlet), HIP. */
+MG_API int32_t mg_prolong(mg_ctx ctx, int32_t problem, int32_t coarse_level, int32_t kind,
+                   const void* coarse, void* fine, int32_t dtype);
+
+/* Single steps of the cycle on caller arrays, for operator-level checks.
+ * Arrays are device arrays of level `level` of problem `problem`, pitch =
+ * side, in dtype MG_DT_F64 or MG_DT_F32.  All are asynchronous.
+ *   mg_relax:        `count` red-black half-sweeps starting with `colour`
+ *                    (0 red, 1 black), alternating (Section 2.2: Gauss-Seidel).
+ *   mg_residual:     r = f - A u (appendix V-cycle), zero on Dirichlet
+ *                    boundary nodes, seam written.
+ *   mg_restrict:     fc = full weighting of r onto level + 1.
+ *   mg_coarse_solve: u = direct solution on the 5 x 5 level (FP64 inside).
+ * Errors: INVALID_ARG (bad indices or NULL), HIP. */
+MG_API int32_t mg_relax(mg_ctx ctx, int32_t problem, int32_t level, void* u, const void* f,
+                 int32_t colour, int32_t count, int32_t dtype);
+MG_API int32_t mg_residual(mg_ctx ctx, int32_t problem, int32_t level, const void* u, const void* f,
+                    void* r, int32_t dtype);
+MG_API int32_t mg_restrict(mg_ctx ctx, int32_t problem, int32_t level, const void* r, void* fc,
+                    int32_t dtype);
+MG_API int32_t mg_coarse_solve(mg_ctx ctx, int32_t problem, const void* f, void* u, int32_t dtype);
+
+/* Number of levels of problem `problem` (>= 1), or a negative mg_status. */
+MG_API int32_t mg_num_levels(mg_ctx ctx, int32_t problem);
+
+/* Free every device and host resource of the context (waits for its stream).
+ * NULL is accepted. */
+MG_API int32_t mg_destroy(mg_ctx ctx);
+
+/* Static description of a status code (never NULL). */
+MG_API const char* mg_status_string(int32_t status);
+
+/* Thread-local detail of the last error on this thread ("" if none). */
+MG_API const char* mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H */

@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
         return _LIB_PATH
     core = os.path.join(_HERE, "mg_oracle_core.c")
     drv = os.path.join(_HERE, "mg_oracle_drivers.c")
-    flags = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-std=c11", "-Wall"]
+    flags = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-std=c11", "-Wall", "-fopenmp"]
     # The core is compiled twice (FP64, and FP32 emulation of the inner
     # cycle of the mixed path) into separate objects, then linked with the
     # FP64 drivers.
@@ -52,7 +52,7 @@ def build(force: bool = True) -> str:
     subprocess.check_call(["gcc"] + flags + ["-c", "-o", obj, drv])
     objs.append(obj)
     tmp = _LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-shared", "-o", tmp] + objs + ["-lm"])
+    subprocess.check_call(["gcc", "-shared", "-fopenmp", "-o", tmp] + objs + ["-lm"])
     os.replace(tmp, _LIB_PATH)
     for o in objs:
         os.remove(o)

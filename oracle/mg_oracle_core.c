@@ -10,6 +10,10 @@
  * with REAL=float, SFX=f32 (emulation of the FP32 inner cycle of the mixed
  * path).  Loops are plain and in natural order; there is no blocking, fusion
  * or reordering.  Build with -ffp-contract=off so that every operation rounds.
+ * Loops whose iterations write disjoint outputs and read nothing written in
+ * the same loop (one colour of a half-sweep, the residual, the restriction,
+ * independent spline lines) may run on several OpenMP threads; results are
+ * bitwise independent of the thread count.  Sums stay serial.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -64,6 +68,7 @@ void FN(orc_relax)(int n, int bc, real* u, const real* f, int colour) {
   const double hd = 1.0 / (double)(n - 1);
   const real h2 = (real)(hd * hd);
   const int lo = first_unknown(bc);
+#pragma omp parallel for schedule(static)
   for (int i = lo; i <= n - 2; ++i)
     for (int j = lo; j <= n - 2; ++j) {
       if (((i + j) & 1) != colour) continue;
@@ -80,6 +85,7 @@ void FN(orc_residual)(int n, int bc, const real* u, const real* f, real* r) {
   const real inv_h2 = (real)((double)(n - 1) * (double)(n - 1));
   const int lo = first_unknown(bc);
   memset(r, 0, sizeof(real) * (size_t)n * n);
+#pragma omp parallel for schedule(static)
   for (int i = lo; i <= n - 2; ++i)
     for (int j = lo; j <= n - 2; ++j) {
       const real s = neighbour_sum(u, n, bc, i, j);
@@ -98,6 +104,7 @@ void FN(orc_restrict)(int n, int bc, const real* r, real* fc) {
   const int nc = (n - 1) / 2 + 1;
   const int lo = first_unknown(bc);
   memset(fc, 0, sizeof(real) * (size_t)nc * nc);
+#pragma omp parallel for schedule(static)
   for (int I = lo; I <= nc - 2; ++I)
     for (int J = lo; J <= nc - 2; ++J) {
       const int i = 2 * I, j = 2 * J;
@@ -209,18 +216,24 @@ static void spline_line(int m, int bc, const real* y, real* out, real* work) {
 void FN(orc_prolong)(int nc, int bc, const real* ec, real* ef) {
   const int n = 2 * (nc - 1) + 1;
   real* tmp = (real*)malloc(sizeof(real) * (size_t)nc * n);
-  real* work = (real*)malloc(sizeof(real) * (size_t)7 * (nc + 2));
-  real* col = (real*)malloc(sizeof(real) * (size_t)nc);
-  real* fcol = (real*)malloc(sizeof(real) * (size_t)n);
-  for (int I = 0; I < nc; ++I) spline_line(nc, bc, ec + (size_t)I * nc, tmp + (size_t)I * n, work);
-  for (int j = 0; j < n; ++j) {
-    for (int I = 0; I < nc; ++I) col[I] = tmp[(size_t)I * n + j];
-    spline_line(nc, bc, col, fcol, work);
-    for (int i = 0; i < n; ++i) ef[(size_t)i * n + j] = fcol[i];
+#pragma omp parallel
+  {
+    real* work = (real*)malloc(sizeof(real) * (size_t)7 * (nc + 2));
+    real* col = (real*)malloc(sizeof(real) * (size_t)nc);
+    real* fcol = (real*)malloc(sizeof(real) * (size_t)n);
+#pragma omp for schedule(static)
+    for (int I = 0; I < nc; ++I)
+      spline_line(nc, bc, ec + (size_t)I * nc, tmp + (size_t)I * n, work);
+#pragma omp for schedule(static)
+    for (int j = 0; j < n; ++j) {
+      for (int I = 0; I < nc; ++I) col[I] = tmp[(size_t)I * n + j];
+      spline_line(nc, bc, col, fcol, work);
+      for (int i = 0; i < n; ++i) ef[(size_t)i * n + j] = fcol[i];
+    }
+    free(fcol);
+    free(col);
+    free(work);
   }
-  free(fcol);
-  free(col);
-  free(work);
   free(tmp);
 }
 
@@ -257,6 +270,7 @@ void FN(orc_vcycle)(int n, int bc, int nu1, int nu2, real* u, const real* f) {
   real* ef = r; /* reuse */
   FN(orc_prolong)(nc, bc, uc, ef);
   const int lo = first_unknown(bc);
+#pragma omp parallel for schedule(static)
   for (int i = lo; i <= n - 2; ++i)
     for (int j = lo; j <= n - 2; ++j) u[(size_t)i * n + j] += ef[(size_t)i * n + j];
   refresh_seam(u, n, bc);

@@ -1,0 +1,192 @@
+"""ctypes binding of the C ABI in ``include/mg.h`` (argument marshalling only).
+
+Functions keep the C names.  Device arrays are passed as integer device
+addresses (e.g. ``tensor.data_ptr()``); every step of the solver runs in the
+HIP library ``libmg355.so``.  There is no fallback: if the library is not
+built or cannot be loaded, ``lib()`` raises.
+
+torch is imported before the library is loaded so that the process uses a
+single HIP runtime (torch's), which the library then shares.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmg355.so")
+
+MG_OK = 0
+MG_ERR_INVALID_ARG = -1
+MG_ERR_UNSUPPORTED = -2
+MG_ERR_OOM = -3
+MG_ERR_HIP = -4
+MG_ERR_INCOMPATIBLE_RHS = -5
+MG_ERR_NOT_CONVERGED = -6
+MG_ERR_STAGNATED = -7
+MG_ERR_NONFINITE = -8
+
+MG_BC_DIRICHLET0 = 0
+MG_BC_PERIODIC = 1
+MG_FP64 = 0
+MG_MIXED = 1
+MG_PROLONG_SPLINE = 0
+MG_PROLONG_SRCNN = 1
+MG_DT_F64 = 0
+MG_DT_F32 = 1
+
+i32 = ctypes.c_int32
+vp = ctypes.c_void_p
+
+
+class mg_grid(ctypes.Structure):
+    _fields_ = [("n", i32), ("bc", i32), ("pitch", i32)]
+
+
+class mg_options(ctypes.Structure):
+    _fields_ = [
+        ("precision", i32),
+        ("nu_pre", i32),
+        ("nu_post", i32),
+        ("inner_cycles", i32),
+        ("prolong", i32),
+        ("cnn_levels", i32),
+        ("cnn_weights", vp),
+        ("cnn_weights_bytes", ctypes.c_size_t),
+        ("check_every", i32),
+        ("use_graph", i32),
+        ("tune_cache_path", ctypes.c_char_p),
+    ]
+
+
+class MGError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{mg_status_string(status)} ({status}): {detail}")
+        self.status = status
+        self.detail = detail
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libmg355.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2403_07936_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    pp = ctypes.POINTER(vp)
+    pd = ctypes.POINTER(ctypes.c_double)
+    pi = ctypes.POINTER(i32)
+    sig = {
+        "mg_options_default": (None, [ctypes.POINTER(mg_options)]),
+        "mg_setup": (i32, [ctypes.POINTER(mg_grid), i32, ctypes.POINTER(mg_options), vp,
+                           ctypes.POINTER(vp)]),
+        "mg_vcycle": (i32, [vp, pp, pp, i32, pd]),
+        "mg_solve": (i32, [vp, pp, pp, ctypes.c_double, i32, pi, pd]),
+        "mg_prolong": (i32, [vp, i32, i32, i32, vp, vp, i32]),
+        "mg_relax": (i32, [vp, i32, i32, vp, vp, i32, i32, i32]),
+        "mg_residual": (i32, [vp, i32, i32, vp, vp, vp, i32]),
+        "mg_restrict": (i32, [vp, i32, i32, vp, vp, i32]),
+        "mg_coarse_solve": (i32, [vp, i32, vp, vp, i32]),
+        "mg_num_levels": (i32, [vp, i32]),
+        "mg_destroy": (i32, [vp]),
+        "mg_status_string": (ctypes.c_char_p, [i32]),
+        "mg_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def mg_status_string(status: int) -> str:
+    return lib().mg_status_string(status).decode()
+
+
+def mg_last_error() -> str:
+    return lib().mg_last_error().decode()
+
+
+def _check(status: int) -> int:
+    if status != MG_OK:
+        raise MGError(status, mg_last_error())
+    return status
+
+
+def _ptrs(addrs) -> ctypes.Array:
+    arr = (vp * len(addrs))()
+    for k, a in enumerate(addrs):
+        arr[k] = int(a) if a else None
+    return arr
+
+
+def mg_options_default() -> mg_options:
+    opt = mg_options()
+    lib().mg_options_default(ctypes.byref(opt))
+    return opt
+
+
+def mg_setup(grids, opt: mg_options, stream: int = 0) -> int:
+    """grids: sequence of (n, bc, pitch).  Returns the context handle."""
+    arr = (mg_grid * len(grids))(*[mg_grid(int(n), int(bc), int(p)) for n, bc, p in grids])
+    out = vp()
+    _check(lib().mg_setup(arr, len(grids), ctypes.byref(opt), vp(stream or None),
+                          ctypes.byref(out)))
+    return out.value
+
+
+def mg_vcycle(ctx: int, u, f, ncycles: int = 1, want_relres: bool = False):
+    relres = (ctypes.c_double * len(u))() if want_relres else None
+    _check(lib().mg_vcycle(vp(ctx), _ptrs(u), _ptrs(f), ncycles, relres))
+    return list(relres) if want_relres else None
+
+
+def mg_solve(ctx: int, u, f, rtol: float, max_cycles: int):
+    """Returns (status, cycles, relres); raises only on argument/HIP errors."""
+    cyc = (i32 * len(u))()
+    rel = (ctypes.c_double * len(u))()
+    st = lib().mg_solve(vp(ctx), _ptrs(u), _ptrs(f), float(rtol), int(max_cycles), cyc, rel)
+    if st in (MG_ERR_INVALID_ARG, MG_ERR_UNSUPPORTED, MG_ERR_OOM, MG_ERR_HIP):
+        raise MGError(st, mg_last_error())
+    return st, list(cyc), list(rel)
+
+
+def mg_prolong(ctx: int, problem: int, coarse_level: int, kind: int, coarse: int, fine: int,
+               dtype: int) -> None:
+    _check(lib().mg_prolong(vp(ctx), problem, coarse_level, kind, vp(coarse), vp(fine), dtype))
+
+
+def mg_relax(ctx: int, problem: int, level: int, u: int, f: int, colour: int, count: int,
+             dtype: int) -> None:
+    _check(lib().mg_relax(vp(ctx), problem, level, vp(u), vp(f), colour, count, dtype))
+
+
+def mg_residual(ctx: int, problem: int, level: int, u: int, f: int, r: int, dtype: int) -> None:
+    _check(lib().mg_residual(vp(ctx), problem, level, vp(u), vp(f), vp(r), dtype))
+
+
+def mg_restrict(ctx: int, problem: int, level: int, r: int, fc: int, dtype: int) -> None:
+    _check(lib().mg_restrict(vp(ctx), problem, level, vp(r), vp(fc), dtype))
+
+
+def mg_coarse_solve(ctx: int, problem: int, f: int, u: int, dtype: int) -> None:
+    _check(lib().mg_coarse_solve(vp(ctx), problem, vp(f), vp(u), dtype))
+
+
+def mg_num_levels(ctx: int, problem: int) -> int:
+    v = lib().mg_num_levels(vp(ctx), problem)
+    if v < 0:
+        raise MGError(v, mg_last_error())
+    return v
+
+
+def mg_destroy(ctx: int) -> None:
+    _check(lib().mg_destroy(vp(ctx)))

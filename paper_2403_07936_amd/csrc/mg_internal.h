@@ -1,0 +1,91 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+// Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mg {
+
+constexpr int kDirichlet = 0;
+constexpr int kPeriodic = 1;
+
+// Half-width of the truncated spline prefilter (see spline_taps): the
+// neglected weights sum to below the unit roundoff of each precision.
+constexpr int kPrefilterHalfTapsF64 = 28;
+constexpr int kPrefilterHalfTapsF32 = 14;
+constexpr int kMaxPrefilterTaps = 64;
+
+// Tap table of the B-spline prefilter for one level (see spline_taps).
+struct PrefilterTaps {
+  int count;   // number of taps
+  int offset;  // tap t multiplies e_ext(i + t - offset)
+  int period;  // period of the extended sequence (periodic: n-1, Dirichlet: 2(n-1))
+  double w[kMaxPrefilterTaps];
+};
+
+// Builds the prefilter table for a level with `nc` nodes per side.
+void spline_taps(int nc, int bc, int half_taps, PrefilterTaps* out);
+
+// Inverse (Dirichlet, 9 x 9) or pseudo-inverse (periodic, 16 x 16) of the
+// 5 x 5 level's operator, row-major, from its eigen-decomposition.
+void coarsest_inverse(int bc, double* out /* 256 */);
+
+// ---- launchers (mg_kernels.hip); all asynchronous on `s` -------------------
+// Every array is a level array with `n` nodes per side and the given pitch.
+
+template <typename T>
+hipError_t launch_zero(hipStream_t s, int n, T* a, int pa);
+template <typename T>
+hipError_t launch_seam(hipStream_t s, int n, T* a, int pa);
+template <typename T>
+hipError_t launch_relax(hipStream_t s, int bc, int n, T* u, int pu, const T* f, int pf,
+                        int colour, int count);
+template <typename T>
+hipError_t launch_residual(hipStream_t s, int bc, int n, const T* u, int pu, const T* f, int pf,
+                           T* r, int pr);
+template <typename T>
+hipError_t launch_restrict(hipStream_t s, int bc, int n, const T* r, int pr, T* fc, int pfc);
+// c = B-spline coefficients of e on a level with nc nodes; tmp is workspace
+// of the same shape.
+template <typename T>
+hipError_t launch_prefilter(hipStream_t s, int bc, int nc, const PrefilterTaps& taps, const T* e,
+                            int pe, T* tmp, int pt, T* c, int pc);
+// Fine level with n nodes: u (+)= spline evaluated from coefficients c of
+// the next coarser level.  add = false writes instead of adding.
+template <typename T>
+hipError_t launch_prolong(hipStream_t s, int bc, int n, T* u, int pu, const T* c, int pc, bool add);
+template <typename T>
+hipError_t launch_coarse(hipStream_t s, int bc, const T* f, int pf, T* u, int pu,
+                         const double* inv);
+
+// Mixed path, level 0: r32 = fl32(f - A u) computed in FP64, with per-block
+// partial sums of r^2 (FP64) in partials[0 .. blocks).
+hipError_t launch_residual_mixed(hipStream_t s, int bc, int n, const double* u, int pu,
+                                 const double* f, int pf, float* r32, int pr, double* partials,
+                                 int* nblocks);
+// u += e (FP64 += FP32) over the unknowns.
+hipError_t launch_update_mixed(hipStream_t s, int bc, int n, double* u, int pu, const float* e,
+                               int pe);
+// Per-block partial sums of (f - A u)^2 and, if with_f, of f^2 (stored at
+// partials[nblocks + b]).
+hipError_t launch_resnorm(hipStream_t s, int bc, int n, const double* u, int pu, const double* f,
+                          int pf, double* partials, bool with_f, int* nblocks);
+// Per-block partial sums of f and f^2 for the RHS checks.
+hipError_t launch_rhs_moments(hipStream_t s, int bc, int n, const double* f, int pf,
+                              double* partials, int* nblocks);
+// out[k] = sum of partials[k * stride + 0 .. count) for k < groups, in a
+// fixed order (single workgroup per group).
+hipError_t launch_reduce(hipStream_t s, const double* partials, int count, int stride, int groups,
+                         double* out);
+// Periodic: subtract mean (given on device as sum/(N^2)) from the unknowns
+// and rewrite the seam.
+hipError_t launch_remove_mean(hipStream_t s, int n, double* u, int pu, const double* sum);
+hipError_t launch_sum(hipStream_t s, int bc, int n, const double* a, int pa, double* partials,
+                      int* nblocks);
+
+int blocks_for(int n, int bc);
+
+}  // namespace mg

@@ -1,0 +1,778 @@
+// Host runtime and C ABI of the multigrid library (declared in include/mg.h).
+//
+// A context owns, per problem, the grid hierarchy down to 5 x 5, the
+// per-level work arrays, the prefilter tables and, optionally, hipGraphs of
+// one cycle.  The caller owns the finest-level u and f.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mg.h"
+#include "mg_internal.h"
+
+namespace mg {
+
+// ------------------------------------------------------------ host math ----
+
+// Inverse of S = (1, 4, 1)/6 on a periodic sequence of period Q (Dirichlet
+// grids use the odd extension of period 2(nc-1), periodic grids period
+// nc-1).  With z = sqrt(3) - 2 the bi-infinite inverse is sqrt(3) z^|k|;
+// folded onto one period it is
+//   c_i = sqrt(3) / (1 - z^Q) * sum_{m=0}^{Q-1} (z^m + z^(Q-m)) e_{i+m}.
+// When Q <= 2 * half_taps + 1 the whole period is used (exact); otherwise
+// the taps |k| <= half_taps are kept, whose neglected tail is below the
+// unit roundoff of the working precision.
+void spline_taps(int nc, int bc, int half_taps, PrefilterTaps* out) {
+  const int Q = bc == kPeriodic ? nc - 1 : 2 * (nc - 1);
+  const double z = std::sqrt(3.0) - 2.0;
+  auto zpow = [&](int m) {
+    double p = 1.0;
+    for (int k = 0; k < m; ++k) p *= z;
+    return p;
+  };
+  const double zq = zpow(Q);
+  auto G = [&](int m) { return std::sqrt(3.0) * (zpow(m) + zpow(Q - m)) / (1.0 - zq); };
+  out->period = Q;
+  if (Q <= 2 * half_taps + 1) {
+    out->count = Q;
+    out->offset = 0;
+    for (int t = 0; t < Q; ++t) out->w[t] = G(t);
+  } else {
+    out->count = 2 * half_taps + 1;
+    out->offset = half_taps;
+    for (int t = 0; t < out->count; ++t) {
+      const int m = ((t - half_taps) % Q + Q) % Q;
+      out->w[t] = G(m);
+    }
+  }
+}
+
+// 5 x 5 level (h = 1/4) from the eigen-decomposition of the 5-point operator.
+// Dirichlet: orthonormal sine vectors phi_a(i) = sqrt(1/2) sin(a pi i / 4),
+// eigenvalues 64 (sin^2(a pi/8) + sin^2(b pi/8)).  Periodic: Fourier modes
+// on the 4 x 4 torus, eigenvalues 64 (sin^2(pi k/4) + sin^2(pi l/4)); the
+// zero mode is dropped, which gives the pseudo-inverse.
+void coarsest_inverse(int bc, double* out) {
+  const double pi = 3.14159265358979323846;
+  std::memset(out, 0, sizeof(double) * 256);
+  if (bc == kDirichlet) {
+    double phi[4][4];
+    for (int a = 1; a <= 3; ++a)
+      for (int i = 1; i <= 3; ++i) phi[a][i] = std::sqrt(0.5) * std::sin(a * pi * i / 4.0);
+    for (int i = 1; i <= 3; ++i)
+      for (int j = 1; j <= 3; ++j)
+        for (int ii = 1; ii <= 3; ++ii)
+          for (int jj = 1; jj <= 3; ++jj) {
+            double s = 0.0;
+            for (int a = 1; a <= 3; ++a)
+              for (int b = 1; b <= 3; ++b) {
+                const double sa = std::sin(a * pi / 8.0), sb = std::sin(b * pi / 8.0);
+                const double lam = 64.0 * (sa * sa + sb * sb);
+                s += phi[a][i] * phi[b][j] * phi[a][ii] * phi[b][jj] / lam;
+              }
+            out[((i - 1) * 3 + (j - 1)) * 9 + (ii - 1) * 3 + (jj - 1)] = s;
+          }
+  } else {
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        for (int ii = 0; ii < 4; ++ii)
+          for (int jj = 0; jj < 4; ++jj) {
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k)
+              for (int l = 0; l < 4; ++l) {
+                if (k == 0 && l == 0) continue;
+                const double sk = std::sin(pi * k / 4.0), sl = std::sin(pi * l / 4.0);
+                const double lam = 64.0 * (sk * sk + sl * sl);
+                s += std::cos(2.0 * pi * (k * (i - ii) + l * (j - jj)) / 4.0) / lam;
+              }
+            out[(i * 4 + j) * 16 + ii * 4 + jj] = s / 16.0;
+          }
+  }
+}
+
+// --------------------------------------------------------------- context ----
+
+template <typename T>
+struct Hierarchy {
+  // Level 0 holds only the scratch array r (and, in FP32, every array);
+  // the FP64 level-0 u and f belong to the caller.
+  std::vector<T*> u, f, r, c, tmp;
+};
+
+struct Problem {
+  int n = 0, bc = 0, pitch0 = 0, levels = 0;
+  std::vector<int> side, pitch;
+  std::vector<PrefilterTaps> taps64, taps32;
+  Hierarchy<double> h64;
+  Hierarchy<float> h32;
+  double* partials = nullptr;  // 2 * blocks_for(n) doubles
+  double* sums = nullptr;      // 4 doubles of reduced results
+  int nblocks = 0;
+  hipGraphExec_t graph = nullptr;
+  const double* graph_u = nullptr;
+  const double* graph_f = nullptr;
+};
+
+}  // namespace mg
+
+struct mg_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;
+  mg_options opt{};
+  std::vector<mg::Problem> probs;
+  double* inv[2] = {nullptr, nullptr};
+  std::vector<void*> owned;
+  double* host = nullptr;  // pinned host slots for norm readback
+};
+
+namespace mg {
+namespace {
+
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t status, const std::string& why) {
+  g_last_error = why;
+  return status;
+}
+
+#define MG_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(MG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+#define MG_TRY(expr)                  \
+  do {                                \
+    int32_t st_ = (expr);             \
+    if (st_ != MG_OK) return st_;     \
+  } while (0)
+
+bool valid_side(int n) {
+  if (n < 5 || n > 16385) return false;
+  const int m = (n - 1) / 4;
+  return (n - 1) % 4 == 0 && (m & (m - 1)) == 0;
+}
+
+int pitch_for(int n) { return (n + 63) / 64 * 64; }
+
+template <typename T>
+int32_t alloc_level(mg_ctx_s* ctx, int n, int pitch, T** out) {
+  void* p = nullptr;
+  const size_t bytes = sizeof(T) * (size_t)n * pitch;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MG_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  ctx->owned.push_back(p);
+  MG_HIP(hipMemsetAsync(p, 0, bytes, ctx->stream));
+  *out = static_cast<T*>(p);
+  return MG_OK;
+}
+
+template <typename T>
+int32_t enqueue_cycle(const mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
+                      const std::vector<PrefilterTaps>& taps, T* u0, int pu0, const T* f0,
+                      int pf0, hipStream_t s) {
+  const int L = p.levels;
+  const double* inv = ctx->inv[p.bc];
+  auto U = [&](int l) { return l == 0 ? u0 : h.u[l]; };
+  auto F = [&](int l) { return l == 0 ? f0 : (const T*)h.f[l]; };
+  auto PU = [&](int l) { return l == 0 ? pu0 : p.pitch[l]; };
+  auto PF = [&](int l) { return l == 0 ? pf0 : p.pitch[l]; };
+  const int nu1 = ctx->opt.nu_pre, nu2 = ctx->opt.nu_post;
+  if (L == 1) {
+    MG_HIP(launch_coarse<T>(s, p.bc, f0, pf0, u0, pu0, inv));
+    return MG_OK;
+  }
+  for (int l = 0; l + 1 < L; ++l) {
+    const int n = p.side[l];
+    if (l > 0) MG_HIP(launch_zero<T>(s, n, U(l), PU(l)));
+    MG_HIP(launch_relax<T>(s, p.bc, n, U(l), PU(l), F(l), PF(l), 0, 2 * nu1));
+    MG_HIP(launch_residual<T>(s, p.bc, n, U(l), PU(l), F(l), PF(l), h.r[l], p.pitch[l]));
+    MG_HIP(launch_restrict<T>(s, p.bc, n, h.r[l], p.pitch[l], h.f[l + 1], p.pitch[l + 1]));
+  }
+  MG_HIP(launch_coarse<T>(s, p.bc, h.f[L - 1], p.pitch[L - 1], h.u[L - 1], p.pitch[L - 1], inv));
+  for (int l = L - 2; l >= 0; --l) {
+    const int n = p.side[l], nc = p.side[l + 1], pc = p.pitch[l + 1];
+    MG_HIP(launch_prefilter<T>(s, p.bc, nc, taps[l + 1], h.u[l + 1], pc, h.tmp[l + 1], pc,
+                               h.c[l + 1], pc));
+    MG_HIP(launch_prolong<T>(s, p.bc, n, U(l), PU(l), h.c[l + 1], pc, true));
+    MG_HIP(launch_relax<T>(s, p.bc, n, U(l), PU(l), F(l), PF(l), 0, 2 * nu2));
+  }
+  return MG_OK;
+}
+
+// One step of the outer iteration for one problem: an FP64 V-cycle, or one
+// refinement step around inner FP32 cycles.
+int32_t enqueue_step(const mg_ctx_s* ctx, const Problem& p, double* u, const double* f,
+                     hipStream_t s) {
+  if (ctx->opt.precision == MG_FP64) {
+    MG_TRY(enqueue_cycle<double>(ctx, p, p.h64, p.taps64, u, p.pitch0, f, p.pitch0, s));
+  } else {
+    int nb = 0;
+    float* e0 = p.h32.u[0];
+    float* r0 = p.h32.f[0];
+    MG_HIP(launch_residual_mixed(s, p.bc, p.n, u, p.pitch0, f, p.pitch0, r0, p.pitch[0],
+                                 p.partials, &nb));
+    MG_HIP(launch_zero<float>(s, p.n, e0, p.pitch[0]));
+    for (int k = 0; k < ctx->opt.inner_cycles; ++k)
+      MG_TRY(enqueue_cycle<float>(ctx, p, p.h32, p.taps32, e0, p.pitch[0], r0, p.pitch[0], s));
+    MG_HIP(launch_update_mixed(s, p.bc, p.n, u, p.pitch0, e0, p.pitch[0]));
+  }
+  if (p.bc == kPeriodic) MG_HIP(launch_seam<double>(s, p.n, u, p.pitch0));
+  return MG_OK;
+}
+
+int32_t run_step(mg_ctx_s* ctx, Problem& p, double* u, const double* f) {
+  if (!ctx->opt.use_graph) return enqueue_step(ctx, p, u, f, ctx->stream);
+  if (p.graph && (p.graph_u != u || p.graph_f != f)) {
+    MG_HIP(hipGraphExecDestroy(p.graph));
+    p.graph = nullptr;
+  }
+  if (!p.graph) {
+    hipGraph_t g = nullptr;
+    MG_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
+    const int32_t st = enqueue_step(ctx, p, u, f, ctx->capture);
+    hipError_t e = hipStreamEndCapture(ctx->capture, &g);
+    if (st != MG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(MG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&p.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      p.graph = nullptr;
+      return fail(MG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    p.graph_u = u;
+    p.graph_f = f;
+  }
+  MG_HIP(hipGraphLaunch(p.graph, ctx->stream));
+  return MG_OK;
+}
+
+// Queue ||f - A u||^2 (and ||f||^2) into p.sums[0..1].
+int32_t enqueue_resnorm(mg_ctx_s* ctx, Problem& p, const double* u, const double* f) {
+  int nb = 0;
+  MG_HIP(launch_resnorm(ctx->stream, p.bc, p.n, u, p.pitch0, f, p.pitch0, p.partials, true, &nb));
+  MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 2, p.sums));
+  return MG_OK;
+}
+
+int32_t destroy_ctx(mg_ctx_s* ctx) {
+  if (!ctx) return MG_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& p : ctx->probs)
+    if (p.graph) (void)hipGraphExecDestroy(p.graph);
+  for (void* q : ctx->owned) (void)hipFree(q);
+  if (ctx->host) (void)hipHostFree(ctx->host);
+  if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+  delete ctx;
+  return MG_OK;
+}
+
+int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, void* stream,
+                   mg_ctx* out) {
+  if (!out) return fail(MG_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!grids || !opt) return fail(MG_ERR_INVALID_ARG, "grids or opt is NULL");
+  if (batch <= 0) return fail(MG_ERR_INVALID_ARG, "batch must be positive");
+  if (opt->precision != MG_FP64 && opt->precision != MG_MIXED)
+    return fail(MG_ERR_INVALID_ARG, "precision must be MG_FP64 or MG_MIXED");
+  if (opt->nu_pre < 0 || opt->nu_pre > 8 || opt->nu_post < 0 || opt->nu_post > 8)
+    return fail(MG_ERR_INVALID_ARG, "nu_pre/nu_post must be in 0..8");
+  if (opt->inner_cycles < 1 || opt->inner_cycles > 8)
+    return fail(MG_ERR_INVALID_ARG, "inner_cycles must be in 1..8");
+  if (opt->prolong != MG_PROLONG_SPLINE && opt->prolong != MG_PROLONG_SRCNN)
+    return fail(MG_ERR_INVALID_ARG, "unknown prolongation kind");
+  if (opt->check_every < 0) return fail(MG_ERR_INVALID_ARG, "check_every must be >= 0");
+  for (int b = 0; b < batch; ++b) {
+    const mg_grid& g = grids[b];
+    if (!valid_side(g.n))
+      return fail(MG_ERR_INVALID_ARG, "problem " + std::to_string(b) + ": n=" +
+                                          std::to_string(g.n) + " is not 4*2^k+1 in 5..16385");
+    if (g.bc != MG_BC_DIRICHLET0 && g.bc != MG_BC_PERIODIC)
+      return fail(MG_ERR_INVALID_ARG, "problem " + std::to_string(b) + ": bad boundary condition");
+    if (g.pitch != 0 && (g.pitch < g.n || g.pitch > (1 << 24)))
+      return fail(MG_ERR_INVALID_ARG, "problem " + std::to_string(b) + ": pitch < n");
+    if (opt->prolong == MG_PROLONG_SRCNN && g.bc != MG_BC_PERIODIC)
+      return fail(MG_ERR_UNSUPPORTED, "SR-CNN prolongation needs periodic grids");
+  }
+  if (opt->prolong == MG_PROLONG_SRCNN && (!opt->cnn_weights || opt->cnn_weights_bytes == 0))
+    return fail(MG_ERR_UNSUPPORTED, "SR-CNN prolongation needs weights");
+  if (opt->prolong == MG_PROLONG_SRCNN)
+    return fail(MG_ERR_UNSUPPORTED, "SR-CNN prolongation is not available in this build");
+
+  int ndev = 0;
+  MG_HIP(hipGetDeviceCount(&ndev));
+  if (ndev <= 0) return fail(MG_ERR_HIP, "no HIP device");
+
+  mg_ctx_s* ctx = new (std::nothrow) mg_ctx_s();
+  if (!ctx) return fail(MG_ERR_OOM, "host allocation failed");
+  ctx->opt = *opt;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  auto bail = [&](int32_t st) {
+    std::string keep = g_last_error;
+    destroy_ctx(ctx);
+    g_last_error = keep;
+    return st;
+  };
+  if (hipGetDevice(&ctx->device) != hipSuccess) return bail(fail(MG_ERR_HIP, "hipGetDevice"));
+  if (hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(MG_ERR_HIP, "hipStreamCreateWithFlags"));
+  if (hipHostMalloc((void**)&ctx->host, sizeof(double) * 8 * (size_t)batch) != hipSuccess)
+    return bail(fail(MG_ERR_OOM, "hipHostMalloc"));
+
+  for (int bc = 0; bc < 2; ++bc) {
+    double tbl[256];
+    coarsest_inverse(bc, tbl);
+    int32_t st = alloc_level<double>(ctx, 1, 256, &ctx->inv[bc]);
+    if (st != MG_OK) return bail(st);
+    if (hipMemcpyAsync(ctx->inv[bc], tbl, sizeof tbl, hipMemcpyHostToDevice, ctx->stream) !=
+        hipSuccess)
+      return bail(fail(MG_ERR_HIP, "copy of the coarsest inverse"));
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return bail(fail(MG_ERR_HIP, "hipStreamSynchronize"));
+  }
+
+  ctx->probs.resize(batch);
+  for (int b = 0; b < batch; ++b) {
+    Problem& p = ctx->probs[b];
+    p.n = grids[b].n;
+    p.bc = grids[b].bc;
+    p.pitch0 = grids[b].pitch ? grids[b].pitch : grids[b].n;
+    for (int n = p.n;; n = (n - 1) / 2 + 1) {
+      p.side.push_back(n);
+      p.pitch.push_back(pitch_for(n));
+      if (n == 5) break;
+    }
+    p.levels = (int)p.side.size();
+    const int L = p.levels;
+    p.taps64.resize(L);
+    p.taps32.resize(L);
+    for (int l = 0; l < L; ++l) {
+      spline_taps(p.side[l], p.bc, kPrefilterHalfTapsF64, &p.taps64[l]);
+      spline_taps(p.side[l], p.bc, kPrefilterHalfTapsF32, &p.taps32[l]);
+    }
+    auto& h = p.h64;
+    h.u.assign(L, nullptr);
+    h.f.assign(L, nullptr);
+    h.r.assign(L, nullptr);
+    h.c.assign(L, nullptr);
+    h.tmp.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+      const int n = p.side[l], pt = p.pitch[l];
+      int32_t st = alloc_level<double>(ctx, n, pt, &h.r[l]);
+      if (st == MG_OK && l > 0) st = alloc_level<double>(ctx, n, pt, &h.u[l]);
+      if (st == MG_OK && l > 0) st = alloc_level<double>(ctx, n, pt, &h.f[l]);
+      if (st == MG_OK && l > 0) st = alloc_level<double>(ctx, n, pt, &h.c[l]);
+      if (st == MG_OK && l > 0) st = alloc_level<double>(ctx, n, pt, &h.tmp[l]);
+      if (st != MG_OK) return bail(st);
+    }
+    if (opt->precision == MG_MIXED) {
+      auto& g = p.h32;
+      g.u.assign(L, nullptr);
+      g.f.assign(L, nullptr);
+      g.r.assign(L, nullptr);
+      g.c.assign(L, nullptr);
+      g.tmp.assign(L, nullptr);
+      for (int l = 0; l < L; ++l) {
+        const int n = p.side[l], pt = p.pitch[l];
+        int32_t st = alloc_level<float>(ctx, n, pt, &g.u[l]);
+        if (st == MG_OK) st = alloc_level<float>(ctx, n, pt, &g.f[l]);
+        if (st == MG_OK) st = alloc_level<float>(ctx, n, pt, &g.r[l]);
+        if (st == MG_OK && l > 0) st = alloc_level<float>(ctx, n, pt, &g.c[l]);
+        if (st == MG_OK && l > 0) st = alloc_level<float>(ctx, n, pt, &g.tmp[l]);
+        if (st != MG_OK) return bail(st);
+      }
+    }
+    p.nblocks = std::max(blocks_for(p.n, p.bc), (int)((p.n + 63) / 64) * ((p.n + 3) / 4));
+    int32_t st = alloc_level<double>(ctx, 2, p.nblocks, &p.partials);
+    if (st == MG_OK) st = alloc_level<double>(ctx, 1, 4, &p.sums);
+    if (st != MG_OK) return bail(st);
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return bail(fail(MG_ERR_HIP, "hipStreamSynchronize after setup"));
+  *out = ctx;
+  return MG_OK;
+}
+
+int32_t check_ctx_arrays(mg_ctx ctx, double* const* u, const double* const* f) {
+  if (!ctx) return fail(MG_ERR_INVALID_ARG, "ctx is NULL");
+  if (!u || !f) return fail(MG_ERR_INVALID_ARG, "u or f is NULL");
+  for (size_t b = 0; b < ctx->probs.size(); ++b)
+    if (!u[b] || !f[b]) return fail(MG_ERR_INVALID_ARG, "u[" + std::to_string(b) + "] or f is NULL");
+  return MG_OK;
+}
+
+// Reads p.sums[0..1] of every listed problem into relres[b] (host sync).
+int32_t read_relres(mg_ctx ctx, const std::vector<int>& which, double* relres) {
+  for (size_t k = 0; k < which.size(); ++k)
+    MG_HIP(hipMemcpyAsync(ctx->host + 2 * k, ctx->probs[which[k]].sums, 2 * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+  MG_HIP(hipStreamSynchronize(ctx->stream));
+  for (size_t k = 0; k < which.size(); ++k) {
+    const double rr = ctx->host[2 * k], ff = ctx->host[2 * k + 1];
+    relres[k] = ff > 0.0 ? std::sqrt(rr) / std::sqrt(ff) : std::sqrt(rr);
+  }
+  return MG_OK;
+}
+
+int32_t vcycle_impl(mg_ctx ctx, double* const* u, const double* const* f, int32_t ncycles,
+                    double* relres_out) {
+  MG_TRY(check_ctx_arrays(ctx, u, f));
+  if (ncycles < 0) return fail(MG_ERR_INVALID_ARG, "ncycles < 0");
+  MG_HIP(hipSetDevice(ctx->device));
+  const int B = (int)ctx->probs.size();
+  for (int c = 0; c < ncycles; ++c)
+    for (int b = 0; b < B; ++b) MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b]));
+  if (!relres_out) return MG_OK;
+  std::vector<int> all(B);
+  for (int b = 0; b < B; ++b) {
+    all[b] = b;
+    MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
+  }
+  MG_TRY(read_relres(ctx, all, relres_out));
+  for (int b = 0; b < B; ++b)
+    if (!std::isfinite(relres_out[b])) return fail(MG_ERR_NONFINITE, "non-finite residual");
+  return MG_OK;
+}
+
+int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double rtol,
+                   int32_t max_cycles, int32_t* cycles_out, double* relres_out) {
+  MG_TRY(check_ctx_arrays(ctx, u, f));
+  if (!(rtol >= 0.0)) return fail(MG_ERR_INVALID_ARG, "rtol must be >= 0");
+  if (max_cycles < 0) return fail(MG_ERR_INVALID_ARG, "max_cycles < 0");
+  MG_HIP(hipSetDevice(ctx->device));
+  const int B = (int)ctx->probs.size();
+
+  // Periodic right-hand sides must have zero mean (the constants are the
+  // null space of A).
+  {
+    std::vector<int> per;
+    for (int b = 0; b < B; ++b) {
+      Problem& p = ctx->probs[b];
+      if (p.bc != kPeriodic) continue;
+      int nb = 0;
+      MG_HIP(launch_rhs_moments(ctx->stream, p.bc, p.n, f[b], p.pitch0, p.partials, &nb));
+      MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 2, p.sums));
+      per.push_back(b);
+    }
+    for (size_t k = 0; k < per.size(); ++k)
+      MG_HIP(hipMemcpyAsync(ctx->host + 2 * k, ctx->probs[per[k]].sums, 2 * sizeof(double),
+                            hipMemcpyDeviceToHost, ctx->stream));
+    MG_HIP(hipStreamSynchronize(ctx->stream));
+    for (size_t k = 0; k < per.size(); ++k) {
+      const Problem& p = ctx->probs[per[k]];
+      const double M = (double)(p.n - 1) * (double)(p.n - 1);
+      const double sum = ctx->host[2 * k], sq = ctx->host[2 * k + 1];
+      if (!std::isfinite(sum) || !std::isfinite(sq))
+        return fail(MG_ERR_NONFINITE, "non-finite right-hand side");
+      if (std::fabs(sum) > 1e-10 * std::sqrt(M) * std::sqrt(sq))
+        return fail(MG_ERR_INCOMPATIBLE_RHS,
+                    "periodic f of problem " + std::to_string(per[k]) + " has nonzero mean");
+    }
+  }
+
+  std::vector<int> cycles(B, 0), state(B, 1);  // state: 1 active, 0 converged, <0 failure
+  std::vector<double> rel(B, 0.0), prev(B, -1.0);
+  std::vector<int> prev_cycles(B, 0), slow(B, 0), next_check(B, 1), all(B);
+  for (int b = 0; b < B; ++b) {
+    all[b] = b;
+    MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
+  }
+  MG_TRY(read_relres(ctx, all, rel.data()));
+  for (int b = 0; b < B; ++b) {
+    if (!std::isfinite(rel[b])) state[b] = MG_ERR_NONFINITE;
+    else if (rel[b] <= rtol) state[b] = 0;
+    else if (max_cycles == 0) state[b] = MG_ERR_NOT_CONVERGED;
+    prev[b] = rel[b];
+  }
+  const int every = ctx->opt.check_every;
+  for (;;) {
+    std::vector<int> act;
+    for (int b = 0; b < B; ++b)
+      if (state[b] == 1) act.push_back(b);
+    if (act.empty()) break;
+    // Cycle every active problem up to the earliest next check.
+    int steps = 1 << 30;
+    for (int b : act) steps = std::min(steps, next_check[b] - cycles[b]);
+    steps = std::max(steps, 1);
+    for (int k = 0; k < steps; ++k)
+      for (int b : act)
+        if (cycles[b] < max_cycles && cycles[b] < next_check[b]) {
+          MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b]));
+          ++cycles[b];
+        }
+    std::vector<int> chk;
+    for (int b : act)
+      if (cycles[b] >= next_check[b] || cycles[b] >= max_cycles) chk.push_back(b);
+    for (int b : chk) MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
+    std::vector<double> r(chk.size());
+    MG_TRY(read_relres(ctx, chk, r.data()));
+    for (size_t k = 0; k < chk.size(); ++k) {
+      const int b = chk[k];
+      const double rr = r[k], last = prev[b];
+      const int span = cycles[b] - prev_cycles[b];
+      rel[b] = rr;
+      if (!std::isfinite(rr)) {
+        state[b] = MG_ERR_NONFINITE;
+        continue;
+      }
+      if (rr <= rtol) {
+        state[b] = 0;
+        continue;
+      }
+      // Stagnation: three checks in a row each with less than 10% reduction
+      // per cycle.
+      const double rate = span > 0 && last > 0.0 ? std::pow(rr / last, 1.0 / span) : 1.0;
+      slow[b] = rate > 0.9 ? slow[b] + 1 : 0;
+      prev[b] = rr;
+      prev_cycles[b] = cycles[b];
+      if (slow[b] >= 3) {
+        state[b] = MG_ERR_STAGNATED;
+        continue;
+      }
+      if (cycles[b] >= max_cycles) {
+        state[b] = MG_ERR_NOT_CONVERGED;
+        continue;
+      }
+      // Next check: every `every` cycles, or (auto) at the cycle where the
+      // observed rate predicts the tolerance is crossed, at most 8 ahead.
+      int gap = 1;
+      if (every > 0) {
+        gap = every;
+      } else if (rate > 0.0 && rate < 0.9) {
+        const double need = std::log(rtol / rr) / std::log(rate);
+        gap = std::max(1, std::min(8, (int)std::ceil(need - 0.25)));
+      }
+      next_check[b] = cycles[b] + gap;
+    }
+  }
+  // Periodic results: zero mean and rewritten seam.
+  for (int b = 0; b < B; ++b) {
+    Problem& p = ctx->probs[b];
+    if (p.bc != kPeriodic || cycles[b] == 0) continue;
+    int nb = 0;
+    MG_HIP(launch_sum(ctx->stream, p.bc, p.n, u[b], p.pitch0, p.partials, &nb));
+    MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 1, p.sums + 2));
+    MG_HIP(launch_remove_mean(ctx->stream, p.n, u[b], p.pitch0, p.sums + 2));
+  }
+  MG_HIP(hipStreamSynchronize(ctx->stream));
+  int32_t status = MG_OK;
+  for (int b = 0; b < B; ++b) {
+    if (cycles_out) cycles_out[b] = cycles[b];
+    if (relres_out) relres_out[b] = rel[b];
+    if (state[b] < 0 && status == MG_OK) status = state[b];
+  }
+  if (status != MG_OK) fail(status, mg_status_string(status));
+  return status;
+}
+
+template <typename T>
+int32_t step_common(mg_ctx ctx, int32_t problem, int32_t level, Problem** pp) {
+  if (!ctx) return fail(MG_ERR_INVALID_ARG, "ctx is NULL");
+  if (problem < 0 || problem >= (int)ctx->probs.size())
+    return fail(MG_ERR_INVALID_ARG, "problem index out of range");
+  Problem& p = ctx->probs[problem];
+  if (level < 0 || level >= p.levels) return fail(MG_ERR_INVALID_ARG, "level out of range");
+  *pp = &p;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(MG_ERR_HIP, "hipSetDevice");
+  return MG_OK;
+}
+
+template <typename T>
+int32_t relax_t(mg_ctx ctx, int32_t problem, int32_t level, void* u, const void* f, int32_t colour,
+                int32_t count) {
+  Problem* p;
+  MG_TRY(step_common<T>(ctx, problem, level, &p));
+  if (!u || !f) return fail(MG_ERR_INVALID_ARG, "NULL array");
+  if ((colour != 0 && colour != 1) || count < 0) return fail(MG_ERR_INVALID_ARG, "bad colour/count");
+  const int n = p->side[level];
+  MG_HIP(launch_relax<T>(ctx->stream, p->bc, n, (T*)u, n, (const T*)f, n, colour, count));
+  if (p->bc == kPeriodic) MG_HIP(launch_seam<T>(ctx->stream, n, (T*)u, n));
+  return MG_OK;
+}
+
+template <typename T>
+int32_t residual_t(mg_ctx ctx, int32_t problem, int32_t level, const void* u, const void* f,
+                   void* r) {
+  Problem* p;
+  MG_TRY(step_common<T>(ctx, problem, level, &p));
+  if (!u || !f || !r) return fail(MG_ERR_INVALID_ARG, "NULL array");
+  const int n = p->side[level];
+  MG_HIP(launch_residual<T>(ctx->stream, p->bc, n, (const T*)u, n, (const T*)f, n, (T*)r, n));
+  return MG_OK;
+}
+
+template <typename T>
+int32_t restrict_t(mg_ctx ctx, int32_t problem, int32_t level, const void* r, void* fc) {
+  Problem* p;
+  MG_TRY(step_common<T>(ctx, problem, level, &p));
+  if (!r || !fc) return fail(MG_ERR_INVALID_ARG, "NULL array");
+  if (level + 1 >= p->levels) return fail(MG_ERR_INVALID_ARG, "no coarser level");
+  const int n = p->side[level], nc = p->side[level + 1];
+  MG_HIP(launch_restrict<T>(ctx->stream, p->bc, n, (const T*)r, n, (T*)fc, nc));
+  return MG_OK;
+}
+
+template <typename T>
+int32_t coarse_t(mg_ctx ctx, int32_t problem, const void* f, void* u) {
+  Problem* p;
+  MG_TRY(step_common<T>(ctx, problem, 0, &p));
+  if (!u || !f) return fail(MG_ERR_INVALID_ARG, "NULL array");
+  MG_HIP(launch_coarse<T>(ctx->stream, p->bc, (const T*)f, 5, (T*)u, 5, ctx->inv[p->bc]));
+  return MG_OK;
+}
+
+template <typename T>
+int32_t prolong_t(mg_ctx ctx, int32_t problem, int32_t coarse_level, const void* coarse,
+                  void* fine) {
+  Problem* p;
+  MG_TRY(step_common<T>(ctx, problem, coarse_level, &p));
+  if (coarse_level < 1) return fail(MG_ERR_INVALID_ARG, "coarse_level must be >= 1");
+  if (!coarse || !fine) return fail(MG_ERR_INVALID_ARG, "NULL array");
+  const int nc = p->side[coarse_level], n = p->side[coarse_level - 1];
+  const int pc = p->pitch[coarse_level];
+  // Workspace: the FP64 hierarchy's coefficient arrays of that level (their
+  // byte size also covers FP32 data with the same element pitch).
+  T* tmp = reinterpret_cast<T*>(p->h64.tmp[coarse_level]);
+  T* c = reinterpret_cast<T*>(p->h64.c[coarse_level]);
+  const PrefilterTaps& taps =
+      sizeof(T) == 8 ? p->taps64[coarse_level] : p->taps32[coarse_level];
+  MG_HIP(launch_prefilter<T>(ctx->stream, p->bc, nc, taps, (const T*)coarse, nc, tmp, pc, c, pc));
+  MG_HIP(launch_prolong<T>(ctx->stream, p->bc, n, (T*)fine, n, c, pc, false));
+  return MG_OK;
+}
+
+#define MG_GUARD(body)                                              \
+  try {                                                             \
+    body                                                            \
+  } catch (const std::bad_alloc&) {                                 \
+    return fail(MG_ERR_OOM, "host allocation failed");              \
+  } catch (...) {                                                   \
+    return fail(MG_ERR_HIP, "unexpected exception");                \
+  }
+
+}  // namespace
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+void mg_options_default(mg_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof *opt);
+  opt->precision = MG_FP64;
+  opt->nu_pre = 2;
+  opt->nu_post = 2;
+  opt->inner_cycles = 1;
+  opt->prolong = MG_PROLONG_SPLINE;
+  opt->cnn_levels = 2;
+  opt->check_every = 0;
+  opt->use_graph = 1;
+  opt->tune_cache_path = nullptr;
+}
+
+int32_t mg_setup(const mg_grid* grids, int32_t batch, const mg_options* opt, void* hip_stream,
+                 mg_ctx* out) {
+  g_last_error.clear();
+  MG_GUARD(return setup_impl(grids, batch, opt, hip_stream, out);)
+}
+
+int32_t mg_vcycle(mg_ctx ctx, double* const* u, const double* const* f, int32_t ncycles,
+                  double* relres_out) {
+  g_last_error.clear();
+  MG_GUARD(return vcycle_impl(ctx, u, f, ncycles, relres_out);)
+}
+
+int32_t mg_solve(mg_ctx ctx, double* const* u, const double* const* f, double rtol,
+                 int32_t max_cycles, int32_t* cycles_out, double* relres_out) {
+  g_last_error.clear();
+  MG_GUARD(return solve_impl(ctx, u, f, rtol, max_cycles, cycles_out, relres_out);)
+}
+
+int32_t mg_prolong(mg_ctx ctx, int32_t problem, int32_t coarse_level, int32_t kind,
+                   const void* coarse, void* fine, int32_t dtype) {
+  g_last_error.clear();
+  if (kind == MG_PROLONG_SRCNN)
+    return fail(MG_ERR_UNSUPPORTED, "SR-CNN prolongation is not available in this build");
+  if (kind != MG_PROLONG_SPLINE) return fail(MG_ERR_INVALID_ARG, "unknown prolongation kind");
+  MG_GUARD(if (dtype == MG_DT_F64) return prolong_t<double>(ctx, problem, coarse_level, coarse, fine);
+           if (dtype == MG_DT_F32) return prolong_t<float>(ctx, problem, coarse_level, coarse, fine);
+           return fail(MG_ERR_INVALID_ARG, "bad dtype");)
+}
+
+int32_t mg_relax(mg_ctx ctx, int32_t problem, int32_t level, void* u, const void* f,
+                 int32_t colour, int32_t count, int32_t dtype) {
+  g_last_error.clear();
+  MG_GUARD(if (dtype == MG_DT_F64) return relax_t<double>(ctx, problem, level, u, f, colour, count);
+           if (dtype == MG_DT_F32) return relax_t<float>(ctx, problem, level, u, f, colour, count);
+           return fail(MG_ERR_INVALID_ARG, "bad dtype");)
+}
+
+int32_t mg_residual(mg_ctx ctx, int32_t problem, int32_t level, const void* u, const void* f,
+                    void* r, int32_t dtype) {
+  g_last_error.clear();
+  MG_GUARD(if (dtype == MG_DT_F64) return residual_t<double>(ctx, problem, level, u, f, r);
+           if (dtype == MG_DT_F32) return residual_t<float>(ctx, problem, level, u, f, r);
+           return fail(MG_ERR_INVALID_ARG, "bad dtype");)
+}
+
+int32_t mg_restrict(mg_ctx ctx, int32_t problem, int32_t level, const void* r, void* fc,
+                    int32_t dtype) {
+  g_last_error.clear();
+  MG_GUARD(if (dtype == MG_DT_F64) return restrict_t<double>(ctx, problem, level, r, fc);
+           if (dtype == MG_DT_F32) return restrict_t<float>(ctx, problem, level, r, fc);
+           return fail(MG_ERR_INVALID_ARG, "bad dtype");)
+}
+
+int32_t mg_coarse_solve(mg_ctx ctx, int32_t problem, const void* f, void* u, int32_t dtype) {
+  g_last_error.clear();
+  MG_GUARD(if (dtype == MG_DT_F64) return coarse_t<double>(ctx, problem, f, u);
+           if (dtype == MG_DT_F32) return coarse_t<float>(ctx, problem, f, u);
+           return fail(MG_ERR_INVALID_ARG, "bad dtype");)
+}
+
+int32_t mg_num_levels(mg_ctx ctx, int32_t problem) {
+  if (!ctx) return fail(MG_ERR_INVALID_ARG, "ctx is NULL");
+  if (problem < 0 || problem >= (int)ctx->probs.size())
+    return fail(MG_ERR_INVALID_ARG, "problem index out of range");
+  return ctx->probs[problem].levels;
+}
+
+int32_t mg_destroy(mg_ctx ctx) {
+  MG_GUARD(return destroy_ctx(ctx);)
+}
+
+const char* mg_status_string(int32_t status) {
+  switch (status) {
+    case MG_OK: return "ok";
+    case MG_ERR_INVALID_ARG: return "invalid argument";
+    case MG_ERR_UNSUPPORTED: return "unsupported";
+    case MG_ERR_OOM: return "out of memory";
+    case MG_ERR_HIP: return "HIP runtime error";
+    case MG_ERR_INCOMPATIBLE_RHS: return "incompatible right-hand side";
+    case MG_ERR_NOT_CONVERGED: return "not converged";
+    case MG_ERR_STAGNATED: return "stagnated";
+    case MG_ERR_NONFINITE: return "non-finite residual";
+    default: return "unknown status";
+  }
+}
+
+const char* mg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

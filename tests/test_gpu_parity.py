@@ -1,0 +1,358 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Every test feeds both sides the same seeded inputs and compares element by
+element.  Tolerances:
+  * FP64 steps: 1e-13 relative to the output's max (rounding-order and FMA
+    contraction differences only);
+  * FP64 whole cycle: ||u_gpu - u_oracle|| / ||u_oracle|| <= 1e-12 per cycle
+    from identical inputs;
+  * FP32 steps: 2e-6 relative to the output's max (a few FP32 ulps);
+  * mixed refinement step: ||u_gpu - u_oracle|| <= 1e-5 ||e||, e the step's
+    correction, against the oracle's FP32 emulation.
+"""
+
+import numpy as np
+import pytest
+
+import dense_model as dm
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+D, P = oracle.DIRICHLET, oracle.PERIODIC
+F64, F32 = 0, 1
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2403_07936_amd import binding
+    binding.lib()
+    return binding
+
+
+def rand_grid(n, bc, rng):
+    m = dm.m_of(n, bc)
+    return dm.to_grid(rng.standard_normal(m * m), n, bc)
+
+
+def zero_mean(a):
+    core = a[:-1, :-1] - a[:-1, :-1].mean()
+    return dm.to_grid(core.reshape(-1), a.shape[0], P)
+
+
+def ctx_for(B, n, bc, precision=0, use_graph=1):
+    o = B.mg_options_default()
+    o.precision = precision
+    o.use_graph = use_graph
+    return B.mg_setup([(n, bc, 0)], o, torch.cuda.current_stream().cuda_stream)
+
+
+def gpu(a, dev, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def assert_close(got, ref, rel):
+    scale = max(np.abs(ref).max(), 1e-300)
+    err = np.abs(got - ref).max() / scale
+    assert err <= rel, f"max rel. diff {err:.3e} > {rel:.1e}"
+
+
+SIZES = [5, 9, 33, 65, 129, 257]
+
+
+# ------------------------------------------------------------ single steps --
+
+@pytest.mark.parametrize("bc", [D, P])
+@pytest.mark.parametrize("n", SIZES[1:])
+@pytest.mark.parametrize("dt", [F64, F32])
+def test_relax_parity(B, dev, bc, n, dt):
+    say(f"relax bc={bc} n={n} dt={dt}")
+    rng = np.random.default_rng(100 + n)
+    u, f = rand_grid(n, bc, rng), rand_grid(n, bc, rng)
+    npdt = np.float64 if dt == F64 else np.float32
+    tdt = torch.float64 if dt == F64 else torch.float32
+    ctx = ctx_for(B, n, bc)
+    try:
+        for colour in (0, 1):
+            ut, ft = gpu(u, dev, tdt), gpu(f, dev, tdt)
+            B.mg_relax(ctx, 0, 0, ut.data_ptr(), ft.data_ptr(), colour, 3, dt)
+            ref = u.astype(npdt)
+            for k in range(3):
+                ref = oracle.relax(ref, f.astype(npdt), bc, (colour + k) % 2)
+            assert_close(host(ut), ref, 1e-13 if dt == F64 else 2e-6)
+    finally:
+        B.mg_destroy(ctx)
+
+
+@pytest.mark.parametrize("bc", [D, P])
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("dt", [F64, F32])
+def test_residual_parity(B, dev, bc, n, dt):
+    say(f"residual bc={bc} n={n} dt={dt}")
+    rng = np.random.default_rng(200 + n)
+    # keep r O(f): u scaled by h^2 so A u is comparable to f
+    u, f = rand_grid(n, bc, rng) / (n - 1) ** 2, rand_grid(n, bc, rng)
+    npdt = np.float64 if dt == F64 else np.float32
+    tdt = torch.float64 if dt == F64 else torch.float32
+    ctx = ctx_for(B, n, bc)
+    try:
+        ut, ft = gpu(u, dev, tdt), gpu(f, dev, tdt)
+        rt = torch.full_like(ut, 7.0)
+        B.mg_residual(ctx, 0, 0, ut.data_ptr(), ft.data_ptr(), rt.data_ptr(), dt)
+        ref = oracle.residual(u.astype(npdt), f.astype(npdt), bc)
+        assert_close(host(rt), ref, 1e-13 if dt == F64 else 2e-6)
+    finally:
+        B.mg_destroy(ctx)
+
+
+@pytest.mark.parametrize("bc", [D, P])
+@pytest.mark.parametrize("n", SIZES[1:])
+@pytest.mark.parametrize("dt", [F64, F32])
+def test_restrict_parity(B, dev, bc, n, dt):
+    say(f"restrict bc={bc} n={n} dt={dt}")
+    rng = np.random.default_rng(300 + n)
+    r = rand_grid(n, bc, rng)
+    nc = (n - 1) // 2 + 1
+    npdt = np.float64 if dt == F64 else np.float32
+    tdt = torch.float64 if dt == F64 else torch.float32
+    ctx = ctx_for(B, n, bc)
+    try:
+        rt = gpu(r, dev, tdt)
+        fct = torch.full((nc, nc), 7.0, device=dev, dtype=tdt)
+        B.mg_restrict(ctx, 0, 0, rt.data_ptr(), fct.data_ptr(), dt)
+        ref = oracle.restrict(r.astype(npdt), bc)
+        assert_close(host(fct), ref, 1e-14 if dt == F64 else 2e-7)
+    finally:
+        B.mg_destroy(ctx)
+
+
+@pytest.mark.parametrize("bc", [D, P])
+@pytest.mark.parametrize("n", SIZES[1:])
+@pytest.mark.parametrize("dt", [F64, F32])
+def test_prolong_parity(B, dev, bc, n, dt):
+    say(f"prolong bc={bc} n={n} dt={dt}")
+    rng = np.random.default_rng(400 + n)
+    nc = (n - 1) // 2 + 1
+    e = rand_grid(nc, bc, rng)
+    npdt = np.float64 if dt == F64 else np.float32
+    tdt = torch.float64 if dt == F64 else torch.float32
+    ctx = ctx_for(B, n, bc)
+    try:
+        et = gpu(e, dev, tdt)
+        ft = torch.full((n, n), 7.0, device=dev, dtype=tdt)
+        B.mg_prolong(ctx, 0, 1, B.MG_PROLONG_SPLINE, et.data_ptr(), ft.data_ptr(), dt)
+        ref = oracle.prolong(e.astype(npdt), bc)
+        assert_close(host(ft), ref, 1e-13 if dt == F64 else 2e-6)
+    finally:
+        B.mg_destroy(ctx)
+
+
+@pytest.mark.parametrize("bc", [D, P])
+@pytest.mark.parametrize("dt", [F64, F32])
+def test_coarse_solve_parity(B, dev, bc, dt):
+    say(f"coarse bc={bc} dt={dt}")
+    rng = np.random.default_rng(500)
+    f = rand_grid(5, bc, rng)
+    if bc == P:
+        f = zero_mean(f)
+    tdt = torch.float64 if dt == F64 else torch.float32
+    ctx = ctx_for(B, 5, bc)
+    try:
+        ft = gpu(f, dev, tdt)
+        ut = torch.full_like(ft, 7.0)
+        B.mg_coarse_solve(ctx, 0, ft.data_ptr(), ut.data_ptr(), dt)
+        fin = f.astype(np.float32).astype(np.float64) if dt == F32 else f
+        ref = oracle.coarse_solve(fin, bc)
+        assert_close(host(ut), ref, 1e-14 if dt == F64 else 2e-7)
+    finally:
+        B.mg_destroy(ctx)
+
+
+# ------------------------------------------------------------ whole cycles --
+
+def make_rhs(n, bc, seed):
+    if bc == D:
+        return workloads.rhs_manufactured_dirichlet(n, seed) if n <= 65 else \
+            workloads.rhs_divu_dirichlet(n, seed)
+    return workloads.rhs_divu_periodic(n, seed)
+
+
+@pytest.mark.parametrize("bc,n", [(D, 5), (D, 9), (D, 65), (D, 129), (D, 257),
+                                  (P, 5), (P, 9), (P, 65), (P, 129), (P, 257)])
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_fp64_cycle_parity_per_cycle(B, dev, bc, n, use_graph):
+    """From identical inputs each GPU cycle matches the oracle's to 1e-12."""
+    say(f"fp64 cycle bc={bc} n={n} graph={use_graph}")
+    f = make_rhs(n, bc, 0)
+    ctx = ctx_for(B, n, bc, 0, use_graph)
+    try:
+        ft = gpu(f, dev)
+        u = np.zeros_like(f)
+        for c in range(4):
+            ut = gpu(u, dev)
+            B.mg_vcycle(ctx, [ut.data_ptr()], [ft.data_ptr()], 1)
+            ref = oracle.vcycle(u, f, bc)
+            got = host(ut)
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            say(f"  cycle {c + 1}: {err:.2e}")
+            assert err <= 1e-12
+            u = ref
+    finally:
+        B.mg_destroy(ctx)
+
+
+@pytest.mark.parametrize("bc,n", [(D, 65), (P, 65), (D, 257), (P, 257)])
+def test_mixed_step_parity(B, dev, bc, n):
+    """One refinement step against the oracle's FP32 emulation."""
+    say(f"mixed step bc={bc} n={n}")
+    f = make_rhs(n, bc, 1)
+    ctx = ctx_for(B, n, bc, 1)
+    try:
+        ft = gpu(f, dev)
+        u = np.zeros_like(f)
+        for c in range(3):
+            ut = gpu(u, dev)
+            B.mg_vcycle(ctx, [ut.data_ptr()], [ft.data_ptr()], 1)
+            ref = oracle.refine_step(u, f, bc)
+            e = ref - u
+            err = np.linalg.norm(host(ut) - ref) / np.linalg.norm(e)
+            say(f"  step {c + 1}: {err:.2e}")
+            assert err <= 1e-5
+            u = ref
+    finally:
+        B.mg_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("bc,n,seed", [(D, 65, 0), (D, 65, 7), (P, 129, 0), (D, 257, 2)])
+def test_solve_matches_oracle_solution(B, dev, precision, bc, n, seed):
+    say(f"solve precision={precision} bc={bc} n={n} seed={seed}")
+    f = make_rhs(n, bc, seed)
+    from paper_2403_07936_amd.solver import Solver
+    s = Solver([(n, bc)], precision="fp64" if precision == 0 else "mixed")
+    ft = gpu(f, dev)
+    ut = torch.zeros_like(ft)
+    st, cyc, rel = s.solve([ut], [ft], rtol=1e-10, max_cycles=30)
+    s.close()
+    if precision == 0:
+        uo, co, ho = oracle.solve(f, bc, rtol=1e-10, max_cycles=30)
+    else:
+        uo, co, ho = oracle.solve_mixed(f, bc, rtol=1e-10, max_steps=30)
+    say(f"  status={st} cycles={cyc[0]} (oracle {co}) relres={rel[0]:.3e}")
+    assert st == 0
+    assert rel[0] <= 1e-10
+    assert abs(cyc[0] - co) <= 1
+    got = host(ut)
+    if bc == P:
+        uo = zero_mean(uo)
+        assert abs(got[:-1, :-1].mean()) <= 1e-14 * np.abs(got).max()
+    assert np.linalg.norm(got - uo) <= 1e-9 * np.linalg.norm(uo)
+
+
+def test_batch_matches_individual_solves(B, dev):
+    say("batch of mixed sizes")
+    specs = [(33, D, 3), (65, P, 4), (129, P, 5), (17, D, 6)]
+    from paper_2403_07936_amd.solver import Solver
+    fs = [make_rhs(n, bc, s) for n, bc, s in specs]
+    s = Solver([(n, bc) for n, bc, _ in specs], precision="fp64")
+    fts = [gpu(f, dev) for f in fs]
+    uts = [torch.zeros_like(t) for t in fts]
+    s.vcycle(uts, fts, 2)
+    for (n, bc, _), f, ut in zip(specs, fs, uts):
+        ref = oracle.vcycle(oracle.vcycle(np.zeros_like(f), f, bc), f, bc)
+        assert np.linalg.norm(host(ut) - ref) <= 1e-12 * np.linalg.norm(ref)
+    s.close()
+
+
+def test_determinism_bitwise(B, dev):
+    say("determinism")
+    n, bc = 257, P
+    f = make_rhs(n, bc, 9)
+    outs = []
+    for rep in range(2):
+        ctx = ctx_for(B, n, bc, 1)
+        ft = gpu(f, dev)
+        ut = torch.zeros_like(ft)
+        rel = B.mg_vcycle(ctx, [ut.data_ptr()], [ft.data_ptr()], 3, True)
+        outs.append((host(ut), rel[0]))
+        B.mg_destroy(ctx)
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
+
+
+# ----------------------------------------------------------- failure paths --
+
+def test_periodic_nonzero_mean_rhs_is_rejected(B, dev):
+    n = 65
+    f = make_rhs(n, P, 0) + 0.5
+    ctx = ctx_for(B, n, P)
+    try:
+        ft = gpu(f, dev)
+        ut = torch.zeros_like(ft)
+        st, cyc, rel = B.mg_solve(ctx, [ut.data_ptr()], [ft.data_ptr()], 1e-10, 10)
+        assert st == B.MG_ERR_INCOMPATIBLE_RHS
+        assert float(ut.abs().max()) == 0.0
+    finally:
+        B.mg_destroy(ctx)
+
+
+def test_nan_rhs_reports_nonfinite(B, dev):
+    n = 65
+    f = make_rhs(n, D, 0)
+    f[10, 10] = np.nan
+    ctx = ctx_for(B, n, D)
+    try:
+        ft = gpu(f, dev)
+        ut = torch.zeros_like(ft)
+        st, _, _ = B.mg_solve(ctx, [ut.data_ptr()], [ft.data_ptr()], 1e-10, 10)
+        assert st == B.MG_ERR_NONFINITE
+    finally:
+        B.mg_destroy(ctx)
+
+
+def test_max_cycles_reports_not_converged_with_valid_u(B, dev):
+    n = 129
+    f = make_rhs(n, D, 0)
+    ctx = ctx_for(B, n, D)
+    try:
+        ft = gpu(f, dev)
+        ut = torch.zeros_like(ft)
+        st, cyc, rel = B.mg_solve(ctx, [ut.data_ptr()], [ft.data_ptr()], 1e-10, 1)
+        assert st == B.MG_ERR_NOT_CONVERGED and cyc[0] == 1
+        ref = oracle.vcycle(np.zeros_like(f), f, D)
+        assert np.linalg.norm(host(ut) - ref) <= 1e-12 * np.linalg.norm(ref)
+        assert abs(rel[0] - oracle.relres(ref, f, D)) <= 1e-9 * rel[0]
+    finally:
+        B.mg_destroy(ctx)
+
+
+def test_unreachable_tolerance_reports_stagnation(B, dev):
+    n = 129
+    f = make_rhs(n, D, 0)
+    ctx = ctx_for(B, n, D)
+    try:
+        ft = gpu(f, dev)
+        ut = torch.zeros_like(ft)
+        st, cyc, rel = B.mg_solve(ctx, [ut.data_ptr()], [ft.data_ptr()], 1e-18, 60)
+        assert st == B.MG_ERR_STAGNATED
+        assert rel[0] < 1e-12 and cyc[0] < 60
+    finally:
+        B.mg_destroy(ctx)
