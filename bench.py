@@ -1,0 +1,210 @@
+"""Benchmark: grid-points/s per V-cycle and time to 1e-10 relative residual.
+
+Default workload: 2-D Poisson on a 4097 x 4097 zero-Dirichlet grid (11
+levels), sine-basis divergence-of-velocity source with a k^(-5/3) spectrum,
+V(2,2) cycles with red-black Gauss-Seidel, full weighting, cubic-spline
+prolongation and a direct 5 x 5 solve.  Both the plain FP64 path and the
+mixed path (FP64 refinement around FP32 cycles) are timed; the faster one is
+the headline.  A step is one cycle of the headline path (one V-cycle, or one
+refinement step with its FP32 V-cycle) on the resident grid.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dirichlet4097",
+                    choices=["dirichlet4097", "periodic1025", "dirichlet65"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def main() -> int:
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (this build has no multi-GPU path); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2403_07936_amd import binding as B
+    from paper_2403_07936_amd.solver import Solver
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    B.lib()
+
+    log(f"generating {args.workload} seed {args.seed}")
+    n, bc, f = workloads.workload(args.workload, args.seed)
+    unknowns = workloads.grid_unknowns(n, bc)
+    ft = torch.from_numpy(f).to(dev)
+    ut = torch.zeros_like(ft)
+
+    def timed_steps(s: Solver, K: int, W: int) -> float:
+        ut.zero_()
+        s.vcycle([ut], [ft], W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            s.vcycle([ut], [ft], 1)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / K
+
+    def time_to_tol(s: Solver, reps: int = 3):
+        best = None
+        for _ in range(reps):
+            ut.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, cyc, rel = s.solve([ut], [ft], rtol=1e-10, max_cycles=50)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, st, cyc[0], rel[0])
+        return best
+
+    results = {}
+    for prec in ("fp64", "mixed"):
+        s = Solver([(n, bc)], precision=prec, use_graph=True)
+        sec = timed_steps(s, args.steps, args.warmup)
+        tt = time_to_tol(s)
+        u_final = ut.clone()
+        results[prec] = {"solver": s, "sec_per_step": sec, "ttt": tt, "u": u_final}
+        log(f"{prec}: {sec * 1e3:.3f} ms/cycle, {unknowns / sec:.3e} pts/s; "
+            f"to 1e-10: {tt[0] * 1e3:.2f} ms, {tt[2]} cycles, relres {tt[3]:.2e}, status {tt[1]}")
+
+    head = min(results, key=lambda p: results[p]["sec_per_step"])
+    hs = results[head]["solver"]
+
+    # Per-kernel timing: the same number of steps again with every launch
+    # bracketed by HIP events on the solver's stream (no graph capture).
+    B.mg_timing_enable(hs.ctx, True)
+    ut.zero_()
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        hs.vcycle([ut], [ft], 1)
+    torch.cuda.synchronize()
+    kern = []
+    for kind in range(B.MG_K_COUNT):
+        cnt, ms, by = B.mg_timing_read(hs.ctx, kind, 0)
+        if cnt:
+            kern.append((ms, kind, cnt, by))
+    B.mg_timing_enable(hs.ctx, False)
+    kern.sort(reverse=True)
+    ms, kind, cnt, by = kern[0]
+    avg_ms = ms / cnt
+    achieved = (by / cnt) / (avg_ms * 1e-3) / 1e9
+    per_kernel = {B.mg_kernel_name(k): {"launches": c, "avg_us": 1e3 * m / c,
+                                        "GBps": (b / c) / (m / c * 1e-3) / 1e9}
+                  for m, k, c, b in kern}
+    log(f"level-0 kernels (events): {json.dumps(per_kernel)}")
+    roofline = {"bound": "hbm", "kernel": B.mg_kernel_name(kind), "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2),
+                "bytes_per_launch": by / cnt}
+
+    extra = {}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        log(f"oracle FP64 solve for the error check ({threads} threads)")
+        t0 = time.perf_counter()
+        uo, co, ho = oracle.solve(f, bc, rtol=1e-10, max_cycles=50)
+        t_orc = time.perf_counter() - t0
+        for prec in results:
+            got = results[prec]["u"].cpu().numpy()
+            a, b = got, uo
+            if bc == workloads.rhs.PERIODIC:
+                a = a[:-1, :-1] - a[:-1, :-1].mean()
+                b = b[:-1, :-1] - b[:-1, :-1].mean()
+            extra[f"err_vs_oracle_fp64_{prec}"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        extra["oracle_fp64_cycles_to_tol"] = int(co)
+        extra["oracle_fp64_time_to_tol_s"] = round(t_orc, 3)
+
+        log(f"CPU baseline: oracle {head} cycles for ~{args.cpu_seconds:.0f} s")
+        u = np.zeros_like(f)
+        step = (lambda u: oracle.vcycle(u, f, bc)) if head == "fp64" else \
+            (lambda u: oracle.refine_step(u, f, bc))
+        count, t0 = 0, time.perf_counter()
+        while True:
+            u = step(u)
+            count += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds and count >= 2:
+                break
+        cpu = {"value": round(unknowns * count / el, 1), "unit": "grid-points/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{count} {head} cycles of {args.workload} ({el:.1f} s, plain C oracle, "
+                         f"OpenMP over independent grid lines)"}
+
+    hr = results[head]
+    sec = hr["sec_per_step"]
+    out = {
+        "metric": "grid-points/s per V-cycle + time to 1e-10 rel. residual, 4097² Poisson",
+        "value": round(unknowns / sec, 1),
+        "unit": "grid-points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n,
+                   "bc": "dirichlet" if bc == 0 else "periodic", "unknowns": unknowns,
+                   "levels": hs.num_levels(), "cycle": "V(2,2) red-black GS, full weighting, "
+                   "cubic-spline prolongation, direct 5x5 solve", "precision": head,
+                   "seed": args.seed},
+        "time_to_tol_s": round(hr["ttt"][0], 6),
+        "cycles_to_tol": hr["ttt"][2],
+        "final_relres": hr["ttt"][3],
+        "paths": {p: {"ms_per_cycle": round(r["sec_per_step"] * 1e3, 4),
+                      "grid_points_per_s": round(unknowns / r["sec_per_step"], 1),
+                      "time_to_tol_s": round(r["ttt"][0], 6), "cycles_to_tol": r["ttt"][2],
+                      "final_relres": r["ttt"][3], "status": r["ttt"][1]}
+                  for p, r in results.items()},
+        "roofline": roofline,
+        "kernels_level0": per_kernel,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    for r in results.values():
+        r["solver"].close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -172,6 +172,38 @@ MG_API int32_t mg_restrict(mg_ctx ctx, int32_t problem, int32_t level, const voi
                     int32_t dtype);
 MG_API int32_t mg_coarse_solve(mg_ctx ctx, int32_t problem, const void* f, void* u, int32_t dtype);
 
+/* Kernel classes for the timing diagnostics below. */
+enum {
+  MG_K_RELAX = 0,          /* one red-black half-sweep */
+  MG_K_RESIDUAL = 1,       /* r = f - A u */
+  MG_K_RESTRICT = 2,       /* full weighting */
+  MG_K_PREFILTER = 3,      /* spline coefficients (both axes) */
+  MG_K_PROLONG = 4,        /* spline evaluation and correction */
+  MG_K_COARSE = 5,         /* 5 x 5 direct solve */
+  MG_K_RESIDUAL_MIXED = 6, /* FP64 residual stored as FP32 */
+  MG_K_UPDATE_MIXED = 7,   /* u += e */
+  MG_K_RESNORM = 8,        /* residual norm partial sums */
+  MG_K_ZERO = 9,           /* zero fill */
+  MG_K_COUNT = 16
+};
+
+/* Diagnostics: while enabled, cycles run without graph capture and every
+ * kernel launch is bracketed by HIP events on the context's stream.
+ * Enabling clears earlier records.  Errors: INVALID_ARG, HIP. */
+MG_API int32_t mg_timing_enable(mg_ctx ctx, int32_t enable);
+
+/* Totals over the launches recorded since timing was enabled, for kernel
+ * class `kind` on level `level` (-1 = all levels): number of launches,
+ * summed event time in milliseconds and summed algorithmic bytes (the bytes
+ * the operation must read and write at its arithmetic precision, counted
+ * once per array element).  Synchronises the context's stream.
+ * Errors: INVALID_ARG, HIP. */
+MG_API int32_t mg_timing_read(mg_ctx ctx, int32_t kind, int32_t level, int64_t* launches,
+                              double* total_ms, double* bytes);
+
+/* Static name of a kernel class ("?" if unknown). */
+MG_API const char* mg_kernel_name(int32_t kind);
+
 /* Number of levels of problem `problem` (>= 1), or a negative mg_status. */
 MG_API int32_t mg_num_levels(mg_ctx ctx, int32_t problem);
 

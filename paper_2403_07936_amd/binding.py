@@ -95,6 +95,10 @@ def lib() -> ctypes.CDLL:
         "mg_restrict": (i32, [vp, i32, i32, vp, vp, i32]),
         "mg_coarse_solve": (i32, [vp, i32, vp, vp, i32]),
         "mg_num_levels": (i32, [vp, i32]),
+        "mg_timing_enable": (i32, [vp, i32]),
+        "mg_timing_read": (i32, [vp, i32, i32, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "mg_kernel_name": (ctypes.c_char_p, [i32]),
         "mg_destroy": (i32, [vp]),
         "mg_status_string": (ctypes.c_char_p, [i32]),
         "mg_last_error": (ctypes.c_char_p, []),
@@ -186,6 +190,27 @@ def mg_num_levels(ctx: int, problem: int) -> int:
     if v < 0:
         raise MGError(v, mg_last_error())
     return v
+
+
+MG_K_COUNT = 16
+
+
+def mg_timing_enable(ctx: int, enable: bool) -> None:
+    _check(lib().mg_timing_enable(vp(ctx), int(bool(enable))))
+
+
+def mg_timing_read(ctx: int, kind: int, level: int = -1):
+    """Returns (launches, total_ms, algorithmic_bytes) for a kernel class."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    _check(lib().mg_timing_read(vp(ctx), kind, level, ctypes.byref(n), ctypes.byref(ms),
+                                ctypes.byref(by)))
+    return n.value, ms.value, by.value
+
+
+def mg_kernel_name(kind: int) -> str:
+    return lib().mg_kernel_name(kind).decode()
 
 
 def mg_destroy(ctx: int) -> None:

@@ -122,7 +122,19 @@ struct Problem {
 
 }  // namespace mg
 
+namespace mg {
+struct TimingRec {
+  int kind, level;
+  double bytes;
+  hipEvent_t a, b;
+};
+}  // namespace mg
+
 struct mg_ctx_s {
+  bool timing = false;
+  std::vector<mg::TimingRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
   int device = 0;
   hipStream_t stream = nullptr;
   hipStream_t capture = nullptr;
@@ -156,6 +168,34 @@ int32_t fail(int32_t status, const std::string& why) {
     if (st_ != MG_OK) return st_;     \
   } while (0)
 
+hipEvent_t take_event(mg_ctx_s* ctx) {
+  if (ctx->pool_used < ctx->pool.size()) return ctx->pool[ctx->pool_used++];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  ctx->pool.push_back(e);
+  ctx->pool_used++;
+  return e;
+}
+
+// Runs `launch` (returning hipError_t); while timing is enabled and the work
+// goes to the context's own stream, brackets it with a pair of events.
+template <class Launch>
+int32_t timed(mg_ctx_s* ctx, hipStream_t s, int kind, int level, double bytes, Launch&& launch) {
+  if (!ctx->timing || s != ctx->stream) {
+    MG_HIP(launch());
+    return MG_OK;
+  }
+  hipEvent_t a = take_event(ctx), b = take_event(ctx);
+  if (!a || !b) return fail(MG_ERR_HIP, "hipEventCreate failed");
+  MG_HIP(hipEventRecord(a, s));
+  MG_HIP(launch());
+  MG_HIP(hipEventRecord(b, s));
+  ctx->recs.push_back({kind, level, bytes, a, b});
+  return MG_OK;
+}
+
+double unknowns_side(int n, int bc) { return bc == kDirichlet ? n - 2 : n - 1; }
+
 bool valid_side(int n) {
   if (n < 5 || n > 16385) return false;
   const int m = (n - 1) / 4;
@@ -180,7 +220,7 @@ int32_t alloc_level(mg_ctx_s* ctx, int n, int pitch, T** out) {
 }
 
 template <typename T>
-int32_t enqueue_cycle(const mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
+int32_t enqueue_cycle(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
                       const std::vector<PrefilterTaps>& taps, T* u0, int pu0, const T* f0,
                       int pf0, hipStream_t s) {
   const int L = p.levels;
@@ -190,51 +230,81 @@ int32_t enqueue_cycle(const mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
   auto PU = [&](int l) { return l == 0 ? pu0 : p.pitch[l]; };
   auto PF = [&](int l) { return l == 0 ? pf0 : p.pitch[l]; };
   const int nu1 = ctx->opt.nu_pre, nu2 = ctx->opt.nu_post;
+  const double sz = sizeof(T);
+  const int bc = p.bc;
   if (L == 1) {
-    MG_HIP(launch_coarse<T>(s, p.bc, f0, pf0, u0, pu0, inv));
-    return MG_OK;
+    return timed(ctx, s, MG_K_COARSE, 0, 50 * sz,
+                 [&] { return launch_coarse<T>(s, bc, f0, pf0, u0, pu0, inv); });
   }
-  for (int l = 0; l + 1 < L; ++l) {
+  auto sweeps = [&](int l, int count) -> int32_t {
     const int n = p.side[l];
-    if (l > 0) MG_HIP(launch_zero<T>(s, n, U(l), PU(l)));
-    MG_HIP(launch_relax<T>(s, p.bc, n, U(l), PU(l), F(l), PF(l), 0, 2 * nu1));
-    MG_HIP(launch_residual<T>(s, p.bc, n, U(l), PU(l), F(l), PF(l), h.r[l], p.pitch[l]));
-    MG_HIP(launch_restrict<T>(s, p.bc, n, h.r[l], p.pitch[l], h.f[l + 1], p.pitch[l + 1]));
+    const double m = unknowns_side(n, bc);
+    for (int k = 0; k < count; ++k)
+      MG_TRY(timed(ctx, s, MG_K_RELAX, l, 1.5 * m * m * sz, [&] {
+        return launch_relax<T>(s, bc, n, U(l), PU(l), F(l), PF(l), k & 1, 1);
+      }));
+    return MG_OK;
+  };
+  for (int l = 0; l + 1 < L; ++l) {
+    const int n = p.side[l], nc = p.side[l + 1];
+    const double nn = (double)n * n;
+    if (l > 0)
+      MG_TRY(timed(ctx, s, MG_K_ZERO, l, nn * sz, [&] { return launch_zero<T>(s, n, U(l), PU(l)); }));
+    MG_TRY(sweeps(l, 2 * nu1));
+    MG_TRY(timed(ctx, s, MG_K_RESIDUAL, l, 3 * nn * sz, [&] {
+      return launch_residual<T>(s, bc, n, U(l), PU(l), F(l), PF(l), h.r[l], p.pitch[l]);
+    }));
+    MG_TRY(timed(ctx, s, MG_K_RESTRICT, l, (nn + (double)nc * nc) * sz, [&] {
+      return launch_restrict<T>(s, bc, n, h.r[l], p.pitch[l], h.f[l + 1], p.pitch[l + 1]);
+    }));
   }
-  MG_HIP(launch_coarse<T>(s, p.bc, h.f[L - 1], p.pitch[L - 1], h.u[L - 1], p.pitch[L - 1], inv));
+  MG_TRY(timed(ctx, s, MG_K_COARSE, L - 1, 50 * sz, [&] {
+    return launch_coarse<T>(s, bc, h.f[L - 1], p.pitch[L - 1], h.u[L - 1], p.pitch[L - 1], inv);
+  }));
   for (int l = L - 2; l >= 0; --l) {
     const int n = p.side[l], nc = p.side[l + 1], pc = p.pitch[l + 1];
-    MG_HIP(launch_prefilter<T>(s, p.bc, nc, taps[l + 1], h.u[l + 1], pc, h.tmp[l + 1], pc,
-                               h.c[l + 1], pc));
-    MG_HIP(launch_prolong<T>(s, p.bc, n, U(l), PU(l), h.c[l + 1], pc, true));
-    MG_HIP(launch_relax<T>(s, p.bc, n, U(l), PU(l), F(l), PF(l), 0, 2 * nu2));
+    const double m = unknowns_side(n, bc), ncc = (double)nc * nc;
+    MG_TRY(timed(ctx, s, MG_K_PREFILTER, l + 1, 4 * ncc * sz, [&] {
+      return launch_prefilter<T>(s, bc, nc, taps[l + 1], h.u[l + 1], pc, h.tmp[l + 1], pc,
+                                 h.c[l + 1], pc);
+    }));
+    MG_TRY(timed(ctx, s, MG_K_PROLONG, l, (2 * m * m + ncc) * sz, [&] {
+      return launch_prolong<T>(s, bc, n, U(l), PU(l), h.c[l + 1], pc, true);
+    }));
+    MG_TRY(sweeps(l, 2 * nu2));
   }
   return MG_OK;
 }
 
 // One step of the outer iteration for one problem: an FP64 V-cycle, or one
 // refinement step around inner FP32 cycles.
-int32_t enqueue_step(const mg_ctx_s* ctx, const Problem& p, double* u, const double* f,
+int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f,
                      hipStream_t s) {
+  const double m = unknowns_side(p.n, p.bc), nn = (double)p.n * p.n;
   if (ctx->opt.precision == MG_FP64) {
     MG_TRY(enqueue_cycle<double>(ctx, p, p.h64, p.taps64, u, p.pitch0, f, p.pitch0, s));
   } else {
     int nb = 0;
     float* e0 = p.h32.u[0];
     float* r0 = p.h32.f[0];
-    MG_HIP(launch_residual_mixed(s, p.bc, p.n, u, p.pitch0, f, p.pitch0, r0, p.pitch[0],
-                                 p.partials, &nb));
-    MG_HIP(launch_zero<float>(s, p.n, e0, p.pitch[0]));
+    MG_TRY(timed(ctx, s, MG_K_RESIDUAL_MIXED, 0, 20 * nn, [&] {
+      return launch_residual_mixed(s, p.bc, p.n, u, p.pitch0, f, p.pitch0, r0, p.pitch[0],
+                                   p.partials, &nb);
+    }));
+    MG_TRY(timed(ctx, s, MG_K_ZERO, 0, 4 * nn,
+                 [&] { return launch_zero<float>(s, p.n, e0, p.pitch[0]); }));
     for (int k = 0; k < ctx->opt.inner_cycles; ++k)
       MG_TRY(enqueue_cycle<float>(ctx, p, p.h32, p.taps32, e0, p.pitch[0], r0, p.pitch[0], s));
-    MG_HIP(launch_update_mixed(s, p.bc, p.n, u, p.pitch0, e0, p.pitch[0]));
+    MG_TRY(timed(ctx, s, MG_K_UPDATE_MIXED, 0, 20 * m * m, [&] {
+      return launch_update_mixed(s, p.bc, p.n, u, p.pitch0, e0, p.pitch[0]);
+    }));
   }
   if (p.bc == kPeriodic) MG_HIP(launch_seam<double>(s, p.n, u, p.pitch0));
   return MG_OK;
 }
 
 int32_t run_step(mg_ctx_s* ctx, Problem& p, double* u, const double* f) {
-  if (!ctx->opt.use_graph) return enqueue_step(ctx, p, u, f, ctx->stream);
+  if (!ctx->opt.use_graph || ctx->timing) return enqueue_step(ctx, p, u, f, ctx->stream);
   if (p.graph && (p.graph_u != u || p.graph_f != f)) {
     MG_HIP(hipGraphExecDestroy(p.graph));
     p.graph = nullptr;
@@ -265,7 +335,10 @@ int32_t run_step(mg_ctx_s* ctx, Problem& p, double* u, const double* f) {
 // Queue ||f - A u||^2 (and ||f||^2) into p.sums[0..1].
 int32_t enqueue_resnorm(mg_ctx_s* ctx, Problem& p, const double* u, const double* f) {
   int nb = 0;
-  MG_HIP(launch_resnorm(ctx->stream, p.bc, p.n, u, p.pitch0, f, p.pitch0, p.partials, true, &nb));
+  const double m = unknowns_side(p.n, p.bc);
+  MG_TRY(timed(ctx, ctx->stream, MG_K_RESNORM, 0, 16 * m * m, [&] {
+    return launch_resnorm(ctx->stream, p.bc, p.n, u, p.pitch0, f, p.pitch0, p.partials, true, &nb);
+  }));
   MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 2, p.sums));
   return MG_OK;
 }
@@ -277,6 +350,7 @@ int32_t destroy_ctx(mg_ctx_s* ctx) {
   for (auto& p : ctx->probs)
     if (p.graph) (void)hipGraphExecDestroy(p.graph);
   for (void* q : ctx->owned) (void)hipFree(q);
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->host) (void)hipHostFree(ctx->host);
   if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   delete ctx;
@@ -745,6 +819,54 @@ int32_t mg_coarse_solve(mg_ctx ctx, int32_t problem, const void* f, void* u, int
   MG_GUARD(if (dtype == MG_DT_F64) return coarse_t<double>(ctx, problem, f, u);
            if (dtype == MG_DT_F32) return coarse_t<float>(ctx, problem, f, u);
            return fail(MG_ERR_INVALID_ARG, "bad dtype");)
+}
+
+int32_t mg_timing_enable(mg_ctx ctx, int32_t enable) {
+  g_last_error.clear();
+  if (!ctx) return fail(MG_ERR_INVALID_ARG, "ctx is NULL");
+  MG_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->recs.clear();
+  ctx->pool_used = 0;
+  ctx->timing = enable != 0;
+  return MG_OK;
+}
+
+int32_t mg_timing_read(mg_ctx ctx, int32_t kind, int32_t level, int64_t* launches,
+                       double* total_ms, double* bytes) {
+  g_last_error.clear();
+  if (!ctx) return fail(MG_ERR_INVALID_ARG, "ctx is NULL");
+  if (kind < 0 || kind >= MG_K_COUNT) return fail(MG_ERR_INVALID_ARG, "bad kernel class");
+  MG_HIP(hipStreamSynchronize(ctx->stream));
+  int64_t cnt = 0;
+  double ms = 0.0, by = 0.0;
+  for (const auto& r : ctx->recs) {
+    if (r.kind != kind || (level >= 0 && r.level != level)) continue;
+    float t = 0.f;
+    MG_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ++cnt;
+    ms += t;
+    by += r.bytes;
+  }
+  if (launches) *launches = cnt;
+  if (total_ms) *total_ms = ms;
+  if (bytes) *bytes = by;
+  return MG_OK;
+}
+
+const char* mg_kernel_name(int32_t kind) {
+  switch (kind) {
+    case MG_K_RELAX: return "relax";
+    case MG_K_RESIDUAL: return "residual";
+    case MG_K_RESTRICT: return "restrict";
+    case MG_K_PREFILTER: return "prefilter";
+    case MG_K_PROLONG: return "prolong";
+    case MG_K_COARSE: return "coarse";
+    case MG_K_RESIDUAL_MIXED: return "residual_mixed";
+    case MG_K_UPDATE_MIXED: return "update_mixed";
+    case MG_K_RESNORM: return "resnorm";
+    case MG_K_ZERO: return "zero";
+    default: return "?";
+  }
 }
 
 int32_t mg_num_levels(mg_ctx ctx, int32_t problem) {
