@@ -100,6 +100,8 @@ typedef struct {
   int32_t check_every;        /* mg_solve: cycles between norm checks; 0 = auto */
   int32_t use_graph;          /* capture each cycle into a hipGraph (1) */
   const char* tune_cache_path; /* autotuner cache file; NULL = built-in choices */
+  int32_t kernel_path;        /* 0: fused LDS-tiled kernels (default); 1: one launch
+                                 per operation (reference schedule, same arithmetic) */
 } mg_options;
 
 /* Fill *opt with the defaults listed above.  No-op on NULL. */
@@ -184,6 +186,9 @@ enum {
   MG_K_UPDATE_MIXED = 7,   /* u += e */
   MG_K_RESNORM = 8,        /* residual norm partial sums */
   MG_K_ZERO = 9,           /* zero fill */
+  MG_K_DOWN = 10,          /* fused: 2 sweeps + residual + restriction */
+  MG_K_UP = 11,            /* fused: spline correction + 2 sweeps */
+  MG_K_TAIL = 12,          /* fused: all levels <= 65 x 65 in one workgroup */
   MG_K_COUNT = 16
 };
 

@@ -59,6 +59,7 @@ class mg_options(ctypes.Structure):
         ("check_every", i32),
         ("use_graph", i32),
         ("tune_cache_path", ctypes.c_char_p),
+        ("kernel_path", i32),
     ]
 
 

@@ -18,6 +18,10 @@ constexpr int kPrefilterHalfTapsF64 = 28;
 constexpr int kPrefilterHalfTapsF32 = 14;
 constexpr int kMaxPrefilterTaps = 64;
 
+// Levels with at most this many nodes per side run inside the single-
+// workgroup tail kernel.
+constexpr int kTailMaxSide = 65;
+
 // Tap table of the B-spline prefilter for one level (see spline_taps).
 struct PrefilterTaps {
   int count;   // number of taps
@@ -87,5 +91,31 @@ hipError_t launch_sum(hipStream_t s, int bc, int n, const double* a, int pa, dou
                       int* nblocks);
 
 int blocks_for(int n, int bc);
+
+// ---- fused launchers (mg_fused.hip) -----------------------------------------
+// Sets the LDS limits of the tail kernels; call once per process/device.
+hipError_t fused_init();
+// Down pass of one level (n > kTailMaxSide): 2 red-black sweeps from uin
+// (nullptr = zero guess) written to uout (must differ from uin), then
+// fc = full weighting of f - A u on the next level.
+template <typename T>
+hipError_t launch_down(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
+                       const T* f, int pf, T* fc, int pfc);
+// Up pass: uout = uin + P c (c = prefiltered coarse correction), then 2
+// red-black sweeps.  uout must differ from uin.
+template <typename T>
+hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
+                     const T* f, int pf, const T* c, int pc);
+// c = spline coefficients of e (level with nc nodes), via tmp.
+template <typename T>
+hipError_t launch_prefilter_iir(hipStream_t s, int bc, int nc, const T* e, int pe, T* tmp, int pt,
+                                T* c, int pc);
+// Whole cycle from side nt (<= kTailMaxSide) down to 5 in one workgroup.
+// uin: initial guess (nullptr = zero); uout (nullable): result; cout
+// (nullable): prefiltered result; taps: device table for levels nt, .., 5.
+template <typename T>
+hipError_t launch_tail(hipStream_t s, int bc, int nt, const T* uin, int pui, T* uout, int puo,
+                       const T* f, int pf, T* cout, int pco, const double* inv,
+                       const PrefilterTaps* taps);
 
 }  // namespace mg

@@ -110,6 +110,9 @@ struct Problem {
   int n = 0, bc = 0, pitch0 = 0, levels = 0;
   std::vector<int> side, pitch;
   std::vector<PrefilterTaps> taps64, taps32;
+  PrefilterTaps* taps64_dev = nullptr;  // device copies (read by the tail kernel)
+  PrefilterTaps* taps32_dev = nullptr;
+  int tail = 0;                         // first level handled by the tail kernel
   Hierarchy<double> h64;
   Hierarchy<float> h32;
   double* partials = nullptr;  // 2 * blocks_for(n) doubles
@@ -276,13 +279,70 @@ int32_t enqueue_cycle(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
   return MG_OK;
 }
 
+// The fused schedule: down passes to the first level of at most 65 x 65,
+// the tail kernel, then prefilter + up passes back to level 0.  Level l's
+// pre-smoothed u goes to h.r[l] (ping-pong against h.u[l] / u0).
+template <typename T>
+int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
+                            const PrefilterTaps* taps_dev, T* u0, int pu0, const T* f0, int pf0,
+                            bool zero_guess, hipStream_t s) {
+  const int t = p.tail, bc = p.bc;
+  const double sz = sizeof(T);
+  auto F = [&](int l) { return l == 0 ? f0 : (const T*)h.f[l]; };
+  auto PF = [&](int l) { return l == 0 ? pf0 : p.pitch[l]; };
+  for (int l = 0; l < t; ++l) {
+    const int n = p.side[l];
+    const double m = unknowns_side(n, bc), mc = unknowns_side(p.side[l + 1], bc);
+    const T* uin = (l == 0 && !zero_guess) ? u0 : nullptr;
+    const double bytes = ((uin ? 3 : 2) * m * m + mc * mc) * sz;
+    MG_TRY(timed(ctx, s, MG_K_DOWN, l, bytes, [&] {
+      return launch_down<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l), h.f[l + 1],
+                            p.pitch[l + 1]);
+    }));
+  }
+  {
+    const int nt = p.side[t];
+    const T* uin = (t == 0 && !zero_guess) ? u0 : nullptr;
+    T* uout = t == 0 ? u0 : nullptr;
+    T* cout = t == 0 ? nullptr : h.c[t];
+    const double nn = (double)nt * nt;
+    MG_TRY(timed(ctx, s, MG_K_TAIL, t, (uin ? 3 : 2) * nn * sz, [&] {
+      return launch_tail<T>(s, bc, nt, uin, pu0, uout, pu0, F(t), PF(t), cout, p.pitch[t],
+                            ctx->inv[bc], taps_dev + t);
+    }));
+  }
+  for (int l = t - 1; l >= 0; --l) {
+    const int n = p.side[l], nc = p.side[l + 1], pc = p.pitch[l + 1];
+    const double m = unknowns_side(n, bc), ncc = (double)nc * nc;
+    if (l + 1 < t)
+      MG_TRY(timed(ctx, s, MG_K_PREFILTER, l + 1, 4 * ncc * sz, [&] {
+        return launch_prefilter_iir<T>(s, bc, nc, h.u[l + 1], pc, h.tmp[l + 1], pc, h.c[l + 1], pc);
+      }));
+    T* uout = l == 0 ? u0 : h.u[l];
+    const int puo = l == 0 ? pu0 : p.pitch[l];
+    MG_TRY(timed(ctx, s, MG_K_UP, l, (3 * m * m + ncc) * sz, [&] {
+      return launch_up<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l), h.c[l + 1], pc);
+    }));
+  }
+  return MG_OK;
+}
+
+bool use_fused(const mg_ctx_s* ctx) {
+  return ctx->opt.kernel_path == 0 && ctx->opt.nu_pre == 2 && ctx->opt.nu_post == 2;
+}
+
 // One step of the outer iteration for one problem: an FP64 V-cycle, or one
 // refinement step around inner FP32 cycles.
 int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f,
                      hipStream_t s) {
   const double m = unknowns_side(p.n, p.bc), nn = (double)p.n * p.n;
+  const bool fused = use_fused(ctx);
   if (ctx->opt.precision == MG_FP64) {
-    MG_TRY(enqueue_cycle<double>(ctx, p, p.h64, p.taps64, u, p.pitch0, f, p.pitch0, s));
+    if (fused)
+      MG_TRY(enqueue_cycle_fused<double>(ctx, p, p.h64, p.taps64_dev, u, p.pitch0, f, p.pitch0,
+                                         false, s));
+    else
+      MG_TRY(enqueue_cycle<double>(ctx, p, p.h64, p.taps64, u, p.pitch0, f, p.pitch0, s));
   } else {
     int nb = 0;
     float* e0 = p.h32.u[0];
@@ -291,10 +351,16 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
       return launch_residual_mixed(s, p.bc, p.n, u, p.pitch0, f, p.pitch0, r0, p.pitch[0],
                                    p.partials, &nb);
     }));
-    MG_TRY(timed(ctx, s, MG_K_ZERO, 0, 4 * nn,
-                 [&] { return launch_zero<float>(s, p.n, e0, p.pitch[0]); }));
-    for (int k = 0; k < ctx->opt.inner_cycles; ++k)
-      MG_TRY(enqueue_cycle<float>(ctx, p, p.h32, p.taps32, e0, p.pitch[0], r0, p.pitch[0], s));
+    if (fused) {
+      for (int k = 0; k < ctx->opt.inner_cycles; ++k)
+        MG_TRY(enqueue_cycle_fused<float>(ctx, p, p.h32, p.taps32_dev, e0, p.pitch[0], r0,
+                                          p.pitch[0], k == 0, s));
+    } else {
+      MG_TRY(timed(ctx, s, MG_K_ZERO, 0, 4 * nn,
+                   [&] { return launch_zero<float>(s, p.n, e0, p.pitch[0]); }));
+      for (int k = 0; k < ctx->opt.inner_cycles; ++k)
+        MG_TRY(enqueue_cycle<float>(ctx, p, p.h32, p.taps32, e0, p.pitch[0], r0, p.pitch[0], s));
+    }
     MG_TRY(timed(ctx, s, MG_K_UPDATE_MIXED, 0, 20 * m * m, [&] {
       return launch_update_mixed(s, p.bc, p.n, u, p.pitch0, e0, p.pitch[0]);
     }));
@@ -372,6 +438,8 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
   if (opt->prolong != MG_PROLONG_SPLINE && opt->prolong != MG_PROLONG_SRCNN)
     return fail(MG_ERR_INVALID_ARG, "unknown prolongation kind");
   if (opt->check_every < 0) return fail(MG_ERR_INVALID_ARG, "check_every must be >= 0");
+  if (opt->kernel_path != 0 && opt->kernel_path != 1)
+    return fail(MG_ERR_INVALID_ARG, "kernel_path must be 0 or 1");
   for (int b = 0; b < batch; ++b) {
     const mg_grid& g = grids[b];
     if (!valid_side(g.n))
@@ -408,6 +476,10 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
     return bail(fail(MG_ERR_HIP, "hipStreamCreateWithFlags"));
   if (hipHostMalloc((void**)&ctx->host, sizeof(double) * 8 * (size_t)batch) != hipSuccess)
     return bail(fail(MG_ERR_OOM, "hipHostMalloc"));
+  {
+    hipError_t e = fused_init();
+    if (e != hipSuccess) return bail(fail(MG_ERR_HIP, std::string("fused_init: ") + hipGetErrorString(e)));
+  }
 
   for (int bc = 0; bc < 2; ++bc) {
     double tbl[256];
@@ -439,6 +511,21 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
     for (int l = 0; l < L; ++l) {
       spline_taps(p.side[l], p.bc, kPrefilterHalfTapsF64, &p.taps64[l]);
       spline_taps(p.side[l], p.bc, kPrefilterHalfTapsF32, &p.taps32[l]);
+    }
+    p.tail = 0;
+    while (p.side[p.tail] > kTailMaxSide) ++p.tail;
+    {
+      const size_t tb = sizeof(PrefilterTaps) * (size_t)L;
+      unsigned char* d = nullptr;
+      int32_t st = alloc_level<unsigned char>(ctx, 2, (int)tb, &d);
+      if (st != MG_OK) return bail(st);
+      p.taps64_dev = reinterpret_cast<PrefilterTaps*>(d);
+      p.taps32_dev = reinterpret_cast<PrefilterTaps*>(d + tb);
+      if (hipMemcpyAsync(p.taps64_dev, p.taps64.data(), tb, hipMemcpyHostToDevice, ctx->stream) !=
+              hipSuccess ||
+          hipMemcpyAsync(p.taps32_dev, p.taps32.data(), tb, hipMemcpyHostToDevice, ctx->stream) !=
+              hipSuccess)
+        return bail(fail(MG_ERR_HIP, "copy of the prefilter tables"));
     }
     auto& h = p.h64;
     h.u.assign(L, nullptr);
@@ -759,6 +846,7 @@ void mg_options_default(mg_options* opt) {
   opt->check_every = 0;
   opt->use_graph = 1;
   opt->tune_cache_path = nullptr;
+  opt->kernel_path = 0;
 }
 
 int32_t mg_setup(const mg_grid* grids, int32_t batch, const mg_options* opt, void* hip_stream,
@@ -865,6 +953,9 @@ const char* mg_kernel_name(int32_t kind) {
     case MG_K_UPDATE_MIXED: return "update_mixed";
     case MG_K_RESNORM: return "resnorm";
     case MG_K_ZERO: return "zero";
+    case MG_K_DOWN: return "down";
+    case MG_K_UP: return "up";
+    case MG_K_TAIL: return "tail";
     default: return "?";
   }
 }

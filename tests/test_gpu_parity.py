@@ -49,10 +49,11 @@ def zero_mean(a):
     return dm.to_grid(core.reshape(-1), a.shape[0], P)
 
 
-def ctx_for(B, n, bc, precision=0, use_graph=1):
+def ctx_for(B, n, bc, precision=0, use_graph=1, kernel_path=0):
     o = B.mg_options_default()
     o.precision = precision
     o.use_graph = use_graph
+    o.kernel_path = kernel_path
     return B.mg_setup([(n, bc, 0)], o, torch.cuda.current_stream().cuda_stream)
 
 
@@ -195,18 +196,21 @@ def make_rhs(n, bc, seed):
     return workloads.rhs_divu_periodic(n, seed)
 
 
-@pytest.mark.parametrize("bc,n", [(D, 5), (D, 9), (D, 65), (D, 129), (D, 257),
-                                  (P, 5), (P, 9), (P, 65), (P, 129), (P, 257)])
-@pytest.mark.parametrize("use_graph", [0, 1])
-def test_fp64_cycle_parity_per_cycle(B, dev, bc, n, use_graph):
+CYCLE_CASES = [(D, 5), (D, 9), (D, 33), (D, 65), (D, 129), (D, 257), (D, 513),
+               (P, 5), (P, 9), (P, 33), (P, 65), (P, 129), (P, 257), (P, 513)]
+
+
+@pytest.mark.parametrize("bc,n", CYCLE_CASES)
+@pytest.mark.parametrize("kernel_path,use_graph", [(0, 1), (0, 0), (1, 1)])
+def test_fp64_cycle_parity_per_cycle(B, dev, bc, n, kernel_path, use_graph):
     """From identical inputs each GPU cycle matches the oracle's to 1e-12."""
-    say(f"fp64 cycle bc={bc} n={n} graph={use_graph}")
+    say(f"fp64 cycle bc={bc} n={n} path={kernel_path} graph={use_graph}")
     f = make_rhs(n, bc, 0)
-    ctx = ctx_for(B, n, bc, 0, use_graph)
+    ctx = ctx_for(B, n, bc, 0, use_graph, kernel_path)
     try:
         ft = gpu(f, dev)
         u = np.zeros_like(f)
-        for c in range(4):
+        for c in range(3):
             ut = gpu(u, dev)
             B.mg_vcycle(ctx, [ut.data_ptr()], [ft.data_ptr()], 1)
             ref = oracle.vcycle(u, f, bc)
@@ -219,12 +223,13 @@ def test_fp64_cycle_parity_per_cycle(B, dev, bc, n, use_graph):
         B.mg_destroy(ctx)
 
 
-@pytest.mark.parametrize("bc,n", [(D, 65), (P, 65), (D, 257), (P, 257)])
-def test_mixed_step_parity(B, dev, bc, n):
+@pytest.mark.parametrize("bc,n", [(D, 65), (P, 65), (D, 257), (P, 257), (P, 513)])
+@pytest.mark.parametrize("kernel_path", [0, 1])
+def test_mixed_step_parity(B, dev, bc, n, kernel_path):
     """One refinement step against the oracle's FP32 emulation."""
-    say(f"mixed step bc={bc} n={n}")
+    say(f"mixed step bc={bc} n={n} path={kernel_path}")
     f = make_rhs(n, bc, 1)
-    ctx = ctx_for(B, n, bc, 1)
+    ctx = ctx_for(B, n, bc, 1, 1, kernel_path)
     try:
         ft = gpu(f, dev)
         u = np.zeros_like(f)
@@ -239,6 +244,35 @@ def test_mixed_step_parity(B, dev, bc, n):
             u = ref
     finally:
         B.mg_destroy(ctx)
+
+
+@pytest.mark.parametrize("name", ["dirichlet4097", "periodic1025"])
+def test_full_size_cycle_parity(B, dev, name):
+    """The benchmark configurations at full size, in the launch configuration
+    the benchmark times (fused kernels, graph): one FP64 cycle and one mixed
+    step from the same state, against the oracle, on every grid point."""
+    say(f"full size {name}")
+    n, bc, f = workloads.workload(name, 0)
+    ft = gpu(f, dev)
+    u1 = oracle.vcycle(np.zeros_like(f), f, bc)   # a nonzero starting state
+    for precision in (0, 1):
+        ctx = ctx_for(B, n, bc, precision)
+        try:
+            ut = gpu(u1, dev)
+            B.mg_vcycle(ctx, [ut.data_ptr()], [ft.data_ptr()], 1)
+            got = host(ut)
+        finally:
+            B.mg_destroy(ctx)
+        if precision == 0:
+            ref = oracle.vcycle(u1, f, bc)
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            say(f"  fp64 cycle: {err:.2e}")
+            assert err <= 1e-12
+        else:
+            ref = oracle.refine_step(u1, f, bc)
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref - u1)
+            say(f"  mixed step: {err:.2e}")
+            assert err <= 1e-5
 
 
 @pytest.mark.parametrize("precision", [0, 1])
