@@ -100,8 +100,9 @@ typedef struct {
   int32_t check_every;        /* mg_solve: cycles between norm checks; 0 = auto */
   int32_t use_graph;          /* capture each cycle into a hipGraph (1) */
   const char* tune_cache_path; /* autotuner cache file; NULL = built-in choices */
-  int32_t kernel_path;        /* 0: fused LDS-tiled kernels (default); 1: one launch
-                                 per operation (reference schedule, same arithmetic) */
+  int32_t kernel_path;        /* 0: fused register-streaming passes (default);
+                                 1: one launch per operation (reference schedule);
+                                 2: fused LDS-tiled passes.  Same arithmetic. */
 } mg_options;
 
 /* Fill *opt with the defaults listed above.  No-op on NULL. */

@@ -106,6 +106,14 @@ hipError_t launch_down(hipStream_t s, int bc, int n, const T* uin, int pui, T* u
 template <typename T>
 hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
                      const T* f, int pf, const T* c, int pc);
+// Register-streaming versions of the two passes (mg_stream.hip); same
+// contracts.  hs = rows per wavefront segment (even, <= 64).
+template <typename T>
+hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
+                              int puo, const T* f, int pf, T* fc, int pfc, int hs);
+template <typename T>
+hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
+                            const T* f, int pf, const T* c, int pc, int hs);
 // c = spline coefficients of e (level with nc nodes), via tmp.
 template <typename T>
 hipError_t launch_prefilter_iir(hipStream_t s, int bc, int nc, const T* e, int pe, T* tmp, int pt,

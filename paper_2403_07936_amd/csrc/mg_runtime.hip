@@ -134,6 +134,7 @@ struct TimingRec {
 }  // namespace mg
 
 struct mg_ctx_s {
+  int seg_rows = 64;  // rows per wavefront segment of the streaming passes
   bool timing = false;
   std::vector<mg::TimingRec> recs;
   std::vector<hipEvent_t> pool;
@@ -296,8 +297,11 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
     const T* uin = (l == 0 && !zero_guess) ? u0 : nullptr;
     const double bytes = ((uin ? 3 : 2) * m * m + mc * mc) * sz;
     MG_TRY(timed(ctx, s, MG_K_DOWN, l, bytes, [&] {
-      return launch_down<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l), h.f[l + 1],
-                            p.pitch[l + 1]);
+      if (ctx->opt.kernel_path == 2)
+        return launch_down<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l), h.f[l + 1],
+                              p.pitch[l + 1]);
+      return launch_down_stream<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l),
+                                   h.f[l + 1], p.pitch[l + 1], ctx->seg_rows);
     }));
   }
   {
@@ -321,14 +325,17 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
     T* uout = l == 0 ? u0 : h.u[l];
     const int puo = l == 0 ? pu0 : p.pitch[l];
     MG_TRY(timed(ctx, s, MG_K_UP, l, (3 * m * m + ncc) * sz, [&] {
-      return launch_up<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l), h.c[l + 1], pc);
+      if (ctx->opt.kernel_path == 2)
+        return launch_up<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l), h.c[l + 1], pc);
+      return launch_up_stream<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l),
+                                 h.c[l + 1], pc, ctx->seg_rows);
     }));
   }
   return MG_OK;
 }
 
 bool use_fused(const mg_ctx_s* ctx) {
-  return ctx->opt.kernel_path == 0 && ctx->opt.nu_pre == 2 && ctx->opt.nu_post == 2;
+  return ctx->opt.kernel_path != 1 && ctx->opt.nu_pre == 2 && ctx->opt.nu_post == 2;
 }
 
 // One step of the outer iteration for one problem: an FP64 V-cycle, or one
@@ -438,8 +445,8 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
   if (opt->prolong != MG_PROLONG_SPLINE && opt->prolong != MG_PROLONG_SRCNN)
     return fail(MG_ERR_INVALID_ARG, "unknown prolongation kind");
   if (opt->check_every < 0) return fail(MG_ERR_INVALID_ARG, "check_every must be >= 0");
-  if (opt->kernel_path != 0 && opt->kernel_path != 1)
-    return fail(MG_ERR_INVALID_ARG, "kernel_path must be 0 or 1");
+  if (opt->kernel_path < 0 || opt->kernel_path > 2)
+    return fail(MG_ERR_INVALID_ARG, "kernel_path must be 0, 1 or 2");
   for (int b = 0; b < batch; ++b) {
     const mg_grid& g = grids[b];
     if (!valid_side(g.n))

@@ -201,7 +201,7 @@ CYCLE_CASES = [(D, 5), (D, 9), (D, 33), (D, 65), (D, 129), (D, 257), (D, 513),
 
 
 @pytest.mark.parametrize("bc,n", CYCLE_CASES)
-@pytest.mark.parametrize("kernel_path,use_graph", [(0, 1), (0, 0), (1, 1)])
+@pytest.mark.parametrize("kernel_path,use_graph", [(0, 1), (0, 0), (1, 1), (2, 1)])
 def test_fp64_cycle_parity_per_cycle(B, dev, bc, n, kernel_path, use_graph):
     """From identical inputs each GPU cycle matches the oracle's to 1e-12."""
     say(f"fp64 cycle bc={bc} n={n} path={kernel_path} graph={use_graph}")
@@ -224,7 +224,7 @@ def test_fp64_cycle_parity_per_cycle(B, dev, bc, n, kernel_path, use_graph):
 
 
 @pytest.mark.parametrize("bc,n", [(D, 65), (P, 65), (D, 257), (P, 257), (P, 513)])
-@pytest.mark.parametrize("kernel_path", [0, 1])
+@pytest.mark.parametrize("kernel_path", [0, 1, 2])
 def test_mixed_step_parity(B, dev, bc, n, kernel_path):
     """One refinement step against the oracle's FP32 emulation."""
     say(f"mixed step bc={bc} n={n} path={kernel_path}")
