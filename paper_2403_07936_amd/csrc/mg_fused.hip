@@ -195,98 +195,279 @@ __global__ void __launch_bounds__(kThreads)
 // B-spline prefilter along one axis: c = S^-1 e with S = (1, 4, 1)/6 on the
 // extended sequence.  S^-1 = g / ((1 - z q^-1)(1 - z q)), z = sqrt(3) - 2,
 // g = 12 - 6 sqrt(3): a causal recursion p_k = e_k + z p_{k-1} followed by an
-// anti-causal one m_k = p_k + z m_{k+1}, c_k = g m_k.  Each 64-node segment
-// starts both recursions K nodes outside itself from a zero state; the
-// neglected state is below |z|^K of the data.
-constexpr int kSeg = 64;
+// anti-causal one m_k = p_k + z m_{k+1}, c_k = g m_k.  A thread filters one
+// segment of S nodes of one line held in registers; both recursions start K
+// nodes outside the segment from a zero state, and the neglected state is
+// below |z|^K of the data.
+constexpr double kZ = -0.26794919243112270647;  // sqrt(3) - 2
+constexpr double kG = 1.60769515458673623882;   // 12 - 6 sqrt(3)
 
-template <typename T>
-__device__ __forceinline__ void iir_segment(T* v, int stride, int K) {
-  const T z = T(-0.26794919243112270647);  // sqrt(3) - 2
-  const T g = T(1.60769515458673623882);   // 12 - 6 sqrt(3)
-  const int L = kSeg + 2 * K;
+template <typename T, int L, int K>
+__device__ __forceinline__ void iir_regs(T (&v)[L]) {
+  const T z = T(kZ), g = T(kG);
   T p = T(0);
+#pragma unroll
   for (int k = 0; k < L; ++k) {
-    p = v[k * stride] + z * p;
-    v[k * stride] = p;
+    p = v[k] + z * p;
+    v[k] = p;
   }
   T m = T(0);
+#pragma unroll
   for (int k = L - 1; k >= K; --k) {
-    m = v[k * stride] + z * m;
-    if (k < K + kSeg) v[k * stride] = g * m;
+    m = v[k] + z * m;
+    v[k] = g * m;
   }
 }
 
-// Along x: a workgroup of 64 threads filters 64 rows over one 64-column
-// segment, one row per thread, in an LDS tile with padded rows.
-template <typename T, int BC, int K>
-__global__ void __launch_bounds__(64)
-    k_pre_x(int nc, const T* __restrict__ e, int pe, T* __restrict__ out, int po) {
-  constexpr int L = kSeg + 2 * K;
-  constexpr int P = (L + 31) / 32 * 32 + 1;
-  __shared__ T buf[64 * P];
-  const int r0 = blockIdx.y * 64, s0 = blockIdx.x * kSeg;
-  for (int k = threadIdx.x; k < 64 * L; k += 64) {
-    const int row = k / L, col = k - row * L;
-    const int gr = r0 + row;
-    T v = T(0);
-    if (gr < nc) {
-      bool neg;
-      const int j = ext_node_any<BC>(s0 - K + col, nc, &neg);
-      v = e[(size_t)gr * pe + j];
-      v = neg ? -v : v;
-    }
-    buf[row * P + col] = v;
+template <typename T>
+struct PreCfg {
+  static constexpr int K = sizeof(T) == 8 ? kPrefilterHalfTapsF64 : kPrefilterHalfTapsF32;
+  static constexpr int S = sizeof(T) == 8 ? 16 : 32;  // segment length
+  static constexpr int L = S + 2 * K;
+  // LDS row pitch for the x pass: lanes read rows with this stride, chosen
+  // so that 32 consecutive rows fall on distinct banks.
+  static constexpr int P = sizeof(T) == 8 ? (L + 15) / 16 * 16 + 1 : L + 1 - (L % 2);
+};
+
+// Along y: one thread per (column, segment); lanes are consecutive columns,
+// so every load and store is coalesced.
+template <typename T, int BC>
+__global__ void __launch_bounds__(256)
+    k_pre_y(int nc, const T* __restrict__ in, int pi, T* __restrict__ out, int po, int nseg) {
+  using C = PreCfg<T>;
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int seg = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (seg >= nseg) return;
+  const int r0 = seg * C::S;
+  const bool cok = col < nc;
+  const int cc = cok ? col : 0;
+  T v[C::L];
+#pragma unroll
+  for (int k = 0; k < C::L; ++k) {
+    bool neg;
+    const int r = ext_node_any<BC>(r0 - C::K + k, nc, &neg);
+    const T x = cok ? in[(size_t)r * pi + cc] : T(0);
+    v[k] = neg ? -x : x;
   }
-  __syncthreads();
-  iir_segment<T>(buf + threadIdx.x * P, 1, K);
-  __syncthreads();
-  for (int k = threadIdx.x; k < 64 * kSeg; k += 64) {
-    const int row = k / kSeg, j = k - row * kSeg;
-    const int gr = r0 + row, gc = s0 + j;
-    if (gr >= nc || gc >= nc) continue;
-    T v = buf[row * P + K + j];
-    if (BC == kDirichlet && (gc == 0 || gc == nc - 1)) v = T(0);
-    out[(size_t)gr * po + gc] = v;
+  iir_regs<T, C::L, C::K>(v);
+  if (!cok) return;
+#pragma unroll
+  for (int j = 0; j < C::S; ++j) {
+    const int r = r0 + j;
+    if (r >= nc) break;
+    T y = v[C::K + j];
+    if (BC == kDirichlet && (r == 0 || r == nc - 1)) y = T(0);
+    out[(size_t)r * po + col] = y;
   }
 }
 
-// Along y: a workgroup of 64 threads filters 64 columns over one 64-row
-// segment, one column per thread.
-template <typename T, int BC, int K>
+// Along x: a wavefront filters one segment of 64 rows.  The 64 x L tile is
+// loaded and stored row by row (coalesced) through LDS, and each lane runs
+// the recursion of one row in registers.
+template <typename T, int BC>
 __global__ void __launch_bounds__(64)
-    k_pre_y(int nc, const T* __restrict__ in, int pi, T* __restrict__ out, int po) {
-  constexpr int L = kSeg + 2 * K;
-  __shared__ T buf[L * 64];
-  const int c0 = blockIdx.x * 64, s0 = blockIdx.y * kSeg;
-  for (int k = threadIdx.x; k < 64 * L; k += 64) {
-    const int row = k / 64, col = k - row * 64;
-    const int gc = c0 + col;
-    T v = T(0);
-    if (gc < nc) {
+    k_pre_x(int nc, const T* __restrict__ in, int pi, T* __restrict__ out, int po) {
+  using C = PreCfg<T>;
+  __shared__ T buf[64 * C::P];
+  const int lane = threadIdx.x;
+  const int r0 = blockIdx.y * 64, s0 = blockIdx.x * C::S;
+#pragma unroll
+  for (int cp = 0; cp < (C::L + 63) / 64; ++cp) {
+    const int c = lane + 64 * cp;
+    if (c < C::L) {
       bool neg;
-      const int i = ext_node_any<BC>(s0 - K + row, nc, &neg);
-      v = in[(size_t)i * pi + gc];
-      v = neg ? -v : v;
+      const int j = ext_node_any<BC>(s0 - C::K + c, nc, &neg);
+#pragma unroll 8
+      for (int r = 0; r < 64; ++r) {
+        const int gr = r0 + r;
+        const T x = gr < nc ? in[(size_t)gr * pi + j] : T(0);
+        buf[r * C::P + c] = neg ? -x : x;
+      }
     }
-    buf[k] = v;
   }
   __syncthreads();
-  iir_segment<T>(buf + threadIdx.x, 64, K);
+  T v[C::L];
+#pragma unroll
+  for (int k = 0; k < C::L; ++k) v[k] = buf[lane * C::P + k];
+  iir_regs<T, C::L, C::K>(v);
+#pragma unroll
+  for (int j = 0; j < C::S; ++j) buf[lane * C::P + j] = v[C::K + j];
   __syncthreads();
-  for (int k = threadIdx.x; k < 64 * kSeg; k += 64) {
-    const int row = k / 64, col = k - row * 64;
-    const int gr = s0 + row, gc = c0 + col;
-    if (gr >= nc || gc >= nc) continue;
-    T v = buf[(K + row) * 64 + col];
-    if (BC == kDirichlet && (gr == 0 || gr == nc - 1)) v = T(0);
-    out[(size_t)gr * po + gc] = v;
+  if (lane < C::S) {
+    const int gc = s0 + lane;
+    const bool zero_col = BC == kDirichlet && (gc == 0 || gc == nc - 1);
+#pragma unroll 8
+    for (int r = 0; r < 64; ++r) {
+      const int gr = r0 + r;
+      if (gr < nc && gc < nc) out[(size_t)gr * po + gc] = zero_col ? T(0) : buf[r * C::P + lane];
+    }
   }
 }
 
 // ------------------------------------------------------------------ tail --
 // All levels from side nt down to 5 in one workgroup.  LDS holds u and f of
 // every level (pitch = side) and one scratch grid of the top side.
+
+template <int BC>
+__device__ __forceinline__ int wrap_prev(int i, int n) {
+  return BC == kPeriodic ? (i == 0 ? n - 2 : i - 1) : i - 1;
+}
+template <int BC>
+__device__ __forceinline__ int wrap_next(int i, int n) {
+  return BC == kPeriodic ? (i == n - 2 ? 0 : i + 1) : i + 1;
+}
+
+// The tail's 1024 threads form a 32 x 32 layout; a grid of side n <= 65 is
+// covered by visiting nodes (ty + 32a, tx + 32b), a, b < 3.
+#define MG_TAIL_FOR(n, i, j, ...)                         \
+  do {                                                    \
+    _Pragma("unroll") for (int a_ = 0; a_ < 3; ++a_) {    \
+      const int i = (int)threadIdx.y + 32 * a_;           \
+      if (i < (n)) {                                      \
+        _Pragma("unroll") for (int b_ = 0; b_ < 3; ++b_) { \
+          const int j = (int)threadIdx.x + 32 * b_;       \
+          if (j < (n)) {                                  \
+            __VA_ARGS__                                   \
+          }                                               \
+        }                                                 \
+      }                                                   \
+    }                                                     \
+  } while (0)
+
+template <int BC>
+__device__ __forceinline__ bool tail_unknown(int i, int j, int n) {
+  return BC == kPeriodic ? (i < n - 1 && j < n - 1) : (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2);
+}
+
+template <typename T, int BC>
+__device__ void tail_sweeps(T* u, const T* f, int n, int count) {
+  const double hd = 1.0 / (double)(n - 1);
+  const T h2 = T(hd * hd);
+  for (int s = 0; s < count; ++s) {
+    const int colour = s & 1;
+    MG_TAIL_FOR(n, i, j, {
+      if (tail_unknown<BC>(i, j, n) && ((i + j) & 1) == colour) {
+        const T sum = ((u[wrap_prev<BC>(i, n) * n + j] + u[wrap_next<BC>(i, n) * n + j]) +
+                       u[i * n + wrap_prev<BC>(j, n)]) +
+                      u[i * n + wrap_next<BC>(j, n)];
+        u[i * n + j] = (h2 * f[i * n + j] + sum) * T(0.25);
+      }
+    });
+    __syncthreads();
+  }
+}
+
+// r = f - A u into r (pitch n, unknown nodes only), then f_c = FW(r).
+template <typename T, int BC>
+__device__ void tail_restrict(const T* u, const T* f, T* r, T* fc, int n) {
+  const T inv_h2 = T((double)(n - 1) * (double)(n - 1));
+  MG_TAIL_FOR(n, i, j, {
+    T v = T(0);
+    if (tail_unknown<BC>(i, j, n)) {
+      const T s = ((u[wrap_prev<BC>(i, n) * n + j] + u[wrap_next<BC>(i, n) * n + j]) +
+                   u[i * n + wrap_prev<BC>(j, n)]) +
+                  u[i * n + wrap_next<BC>(j, n)];
+      v = f[i * n + j] - (T(4) * u[i * n + j] - s) * inv_h2;
+    }
+    r[i * n + j] = v;
+  });
+  __syncthreads();
+  const int nc = (n - 1) / 2 + 1;
+  MG_TAIL_FOR(nc, I, J, {
+    T v = T(0);
+    if (tail_unknown<BC>(I, J, nc)) {
+      const int i = 2 * I, j = 2 * J;
+      const int im = wrap_prev<BC>(i, n), ip = wrap_next<BC>(i, n);
+      const int jm = wrap_prev<BC>(j, n), jp = wrap_next<BC>(j, n);
+      const T edges = ((r[im * n + j] + r[ip * n + j]) + r[i * n + jm]) + r[i * n + jp];
+      const T corners = ((r[im * n + jm] + r[im * n + jp]) + r[ip * n + jm]) + r[ip * n + jp];
+      v = ((T(4) * r[i * n + j] + T(2) * edges) + corners) * T(0.0625);
+    }
+    fc[I * nc + J] = v;
+  });
+  __syncthreads();
+}
+
+// Prefilter of one line of a tail grid (nc nodes, element stride `ss` in
+// src, `ds` in dst; tmp holds nc values with stride `ts`): the causal and
+// anti-causal recursions run over the whole line plus K nodes of the
+// extended sequence on each side.  dst may alias src.
+template <typename T, int BC, int K>
+__device__ void line_prefilter(const T* src, int ss, T* tmp, int ts, T* dst, int ds, int nc) {
+  const T z = T(kZ), g = T(kG);
+  const int M = BC == kPeriodic ? nc - 1 : nc;  // stored nodes of one period
+  T p = T(0);
+  for (int q = -K; q < 0; ++q) {
+    bool neg;
+    const int j = ext_node_any<BC>(q, nc, &neg);
+    const T x = src[j * ss];
+    p = (neg ? -x : x) + z * p;
+  }
+  for (int q = 0; q < M; ++q) {
+    p = src[q * ss] + z * p;
+    tmp[q * ts] = p;
+  }
+  T w[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    bool neg;
+    const int j = ext_node_any<BC>(M + k, nc, &neg);
+    const T x = src[j * ss];
+    p = (neg ? -x : x) + z * p;
+    w[k] = p;
+  }
+  T m = T(0);
+#pragma unroll
+  for (int k = K - 1; k >= 0; --k) m = w[k] + z * m;
+  for (int q = M - 1; q >= 0; --q) {
+    m = tmp[q * ts] + z * m;
+    T y = g * m;
+    if (BC == kDirichlet && (q == 0 || q == nc - 1)) y = T(0);
+    dst[q * ds] = y;
+  }
+  if (BC == kPeriodic) dst[(nc - 1) * ds] = dst[0];
+}
+
+// Prefilter a tail grid: rows of src (in place into src), then columns into
+// dst (pitch pd).  One thread per line.
+template <typename T, int BC>
+__device__ void tail_prefilter(T* src, T* tmp, T* dst, int pd, int nc) {
+  constexpr int K = sizeof(T) == 8 ? kPrefilterHalfTapsF64 : kPrefilterHalfTapsF32;
+  const int t = threadIdx.y * 32 + threadIdx.x;
+  if (t < nc) line_prefilter<T, BC, K>(src + t * nc, 1, tmp + t * nc, 1, src + t * nc, 1, nc);
+  __syncthreads();
+  if (t < nc) line_prefilter<T, BC, K>(src + t, nc, tmp + t, nc, dst + t, pd, nc);
+  __syncthreads();
+}
+
+// u += P c on a tail grid of side n from coefficients c of side nc.
+template <typename T, int BC>
+__device__ void tail_prolong_add(T* u, const T* c, int n) {
+  const int nc = (n - 1) / 2 + 1;
+  MG_TAIL_FOR(n, i, j, {
+    if (tail_unknown<BC>(i, j, n)) {
+      int bi, bj;
+      T wi[4], wj[4];
+      const int ni = bspline_taps<T>(i, &bi, wi);
+      const int nj = bspline_taps<T>(j, &bj, wj);
+      T v = T(0);
+      for (int a = 0; a < ni; ++a) {
+        bool na;
+        const int I = ext_node<BC>(bi + a, nc, &na);
+        T row = T(0);
+        for (int b = 0; b < nj; ++b) {
+          bool nb;
+          const int J = ext_node<BC>(bj + b, nc, &nb);
+          const T x = c[I * nc + J];
+          row += wj[b] * (nb ? -x : x);
+        }
+        v += wi[a] * (na ? -row : row);
+      }
+      u[i * n + j] += v;
+    }
+  });
+  __syncthreads();
+}
 
 // Level l of the tail has side ((nt - 1) >> l) + 1; its u and f follow the
 // arrays of the levels above it, and the scratch grid follows the last level.
@@ -309,157 +490,28 @@ __device__ __forceinline__ int tail_offf(int nt, int l) {
   return tail_offu(nt, l) + n * n;
 }
 
-template <int BC>
-__device__ __forceinline__ int wrap_prev(int i, int n) {
-  return BC == kPeriodic ? (i == 0 ? n - 2 : i - 1) : i - 1;
-}
-template <int BC>
-__device__ __forceinline__ int wrap_next(int i, int n) {
-  return BC == kPeriodic ? (i == n - 2 ? 0 : i + 1) : i + 1;
-}
-
-template <typename T, int BC>
-__device__ void tail_sweeps(T* u, const T* f, int n, int count) {
-  const int lo = BC == kDirichlet ? 1 : 0, m = n - 1 - lo;
-  const double hd = 1.0 / (double)(n - 1);
-  const T h2 = T(hd * hd);
-  for (int s = 0; s < count; ++s) {
-    const int colour = s & 1;
-    for (int k = threadIdx.x; k < m * m; k += blockDim.x) {
-      const int i = lo + k / m, j = lo + k % m;
-      if (((i + j) & 1) != colour) continue;
-      const T sum = ((u[wrap_prev<BC>(i, n) * n + j] + u[wrap_next<BC>(i, n) * n + j]) +
-                     u[i * n + wrap_prev<BC>(j, n)]) +
-                    u[i * n + wrap_next<BC>(j, n)];
-      u[i * n + j] = (h2 * f[i * n + j] + sum) * T(0.25);
-    }
-    __syncthreads();
-  }
-}
-
-// r = f - A u into r (pitch n, unknown nodes only), then f_c = FW(r).
-template <typename T, int BC>
-__device__ void tail_restrict(const T* u, const T* f, T* r, T* fc, int n) {
-  const int lo = BC == kDirichlet ? 1 : 0, m = n - 1 - lo;
-  const T inv_h2 = T((double)(n - 1) * (double)(n - 1));
-  for (int k = threadIdx.x; k < n * n; k += blockDim.x) {
-    const int i = k / n, j = k % n;
-    T v = T(0);
-    if (i >= lo && i < lo + m && j >= lo && j < lo + m) {
-      const T s = ((u[wrap_prev<BC>(i, n) * n + j] + u[wrap_next<BC>(i, n) * n + j]) +
-                   u[i * n + wrap_prev<BC>(j, n)]) +
-                  u[i * n + wrap_next<BC>(j, n)];
-      v = f[i * n + j] - (T(4) * u[i * n + j] - s) * inv_h2;
-    }
-    r[k] = v;
-  }
-  __syncthreads();
-  const int nc = (n - 1) / 2 + 1;
-  for (int k = threadIdx.x; k < nc * nc; k += blockDim.x) {
-    const int I = k / nc, J = k % nc;
-    const bool ok = BC == kPeriodic ? (I < nc - 1 && J < nc - 1)
-                                    : (I >= 1 && I <= nc - 2 && J >= 1 && J <= nc - 2);
-    T v = T(0);
-    if (ok) {
-      const int i = 2 * I, j = 2 * J;
-      const int im = wrap_prev<BC>(i, n), ip = wrap_next<BC>(i, n);
-      const int jm = wrap_prev<BC>(j, n), jp = wrap_next<BC>(j, n);
-      const T edges = ((r[im * n + j] + r[ip * n + j]) + r[i * n + jm]) + r[i * n + jp];
-      const T corners = ((r[im * n + jm] + r[im * n + jp]) + r[ip * n + jm]) + r[ip * n + jp];
-      v = ((T(4) * r[i * n + j] + T(2) * edges) + corners) * T(0.0625);
-    }
-    fc[k] = v;
-  }
-  __syncthreads();
-}
-
-// Prefilter a tail grid: x pass from `src` into `tmp`, y pass from `tmp`
-// into `dst` (pitch pd), with the exact or truncated inverse kernel.
-template <typename T, int BC>
-__device__ void tail_prefilter(const T* src, T* tmp, T* dst, int pd, int nc,
-                               const PrefilterTaps& tp) {
-  for (int k = threadIdx.x; k < nc * nc; k += blockDim.x) {
-    const int I = k / nc, J = k % nc;
-    T acc = T(0);
-    if (!(BC == kDirichlet && (J == 0 || J == nc - 1))) {
-      for (int t = 0; t < tp.count; ++t) {
-        bool neg;
-        const int q = ext_node<BC>(J + t - tp.offset, nc, &neg);
-        const T x = src[I * nc + q];
-        acc += T(tp.w[t]) * (neg ? -x : x);
-      }
-    }
-    tmp[k] = acc;
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < nc * nc; k += blockDim.x) {
-    const int I = k / nc, J = k % nc;
-    T acc = T(0);
-    if (!(BC == kDirichlet && (I == 0 || I == nc - 1))) {
-      for (int t = 0; t < tp.count; ++t) {
-        bool neg;
-        const int q = ext_node<BC>(I + t - tp.offset, nc, &neg);
-        const T x = tmp[q * nc + J];
-        acc += T(tp.w[t]) * (neg ? -x : x);
-      }
-    }
-    dst[(size_t)I * pd + J] = acc;
-  }
-  __syncthreads();
-}
-
-// u += P c on a tail grid of side n from coefficients c of side nc.
-template <typename T, int BC>
-__device__ void tail_prolong_add(T* u, const T* c, int n) {
-  const int nc = (n - 1) / 2 + 1;
-  for (int k = threadIdx.x; k < n * n; k += blockDim.x) {
-    const int i = k / n, j = k % n;
-    if (!(BC == kPeriodic ? (i < n - 1 && j < n - 1) : (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2)))
-      continue;
-    int bi, bj;
-    T wi[4], wj[4];
-    const int ni = bspline_taps<T>(i, &bi, wi);
-    const int nj = bspline_taps<T>(j, &bj, wj);
-    T v = T(0);
-    for (int a = 0; a < ni; ++a) {
-      bool na;
-      const int I = ext_node<BC>(bi + a, nc, &na);
-      T row = T(0);
-      for (int b = 0; b < nj; ++b) {
-        bool nb;
-        const int J = ext_node<BC>(bj + b, nc, &nb);
-        const T x = c[I * nc + J];
-        row += wj[b] * (nb ? -x : x);
-      }
-      v += wi[a] * (na ? -row : row);
-    }
-    u[k] += v;
-  }
-  __syncthreads();
-}
-
 template <typename T, int BC>
 __global__ void __launch_bounds__(kTailThreads)
     k_tail(int nt, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
            const T* __restrict__ f, int pf, T* __restrict__ cout, int pco,
-           const double* __restrict__ inv, const PrefilterTaps* __restrict__ taps) {
+           const double* __restrict__ inv) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   const int L = tail_levels(nt);
   T* tmp = sm + tail_offu(nt, L);
-  for (int k = threadIdx.x; k < nt * nt; k += blockDim.x) {
-    const int i = k / nt, j = k % nt;
-    sm[k] = uin ? uin[(size_t)i * pui + j] : T(0);
-    sm[nt * nt + k] = f[(size_t)i * pf + j];
-  }
+  MG_TAIL_FOR(nt, i, j, {
+    sm[i * nt + j] = uin ? uin[(size_t)i * pui + j] : T(0);
+    sm[nt * nt + i * nt + j] = f[(size_t)i * pf + j];
+  });
   __syncthreads();
   for (int l = 0; l + 1 < L; ++l) {
     const int n = tail_side(nt, l);
     T* u = sm + tail_offu(nt, l);
     T* ff = sm + tail_offf(nt, l);
-    if (l > 0)
-      for (int k = threadIdx.x; k < n * n; k += blockDim.x) u[k] = T(0);
-    __syncthreads();
+    if (l > 0) {
+      MG_TAIL_FOR(n, i, j, { u[i * n + j] = T(0); });
+      __syncthreads();
+    }
     tail_sweeps<T, BC>(u, ff, n, 4);
     tail_restrict<T, BC>(u, ff, tmp, sm + tail_offf(nt, l + 1), n);
   }
@@ -468,7 +520,7 @@ __global__ void __launch_bounds__(kTailThreads)
     T* u = sm + tail_offu(nt, L - 1);
     const T* ff = sm + tail_offf(nt, L - 1);
     constexpr int m = BC == kDirichlet ? 9 : 16;
-    const int t = threadIdx.x;
+    const int t = threadIdx.y * 32 + threadIdx.x;
     if (t < 25) {
       const int i = t / 5, j = t % 5;
       int k = -1;
@@ -491,20 +543,17 @@ __global__ void __launch_bounds__(kTailThreads)
   for (int l = L - 2; l >= 0; --l) {
     const int n = tail_side(nt, l), nc = tail_side(nt, l + 1);
     T* uc = sm + tail_offu(nt, l + 1);
-    tail_prefilter<T, BC>(uc, tmp, uc, nc, nc, taps[l + 1]);
+    tail_prefilter<T, BC>(uc, tmp, uc, nc, nc);
     tail_prolong_add<T, BC>(sm + tail_offu(nt, l), uc, n);
     tail_sweeps<T, BC>(sm + tail_offu(nt, l), sm + tail_offf(nt, l), n, 4);
   }
   if (uout)
-    for (int k = threadIdx.x; k < nt * nt; k += blockDim.x) {
-      const int i = k / nt, j = k % nt;
-      const bool ok = BC == kPeriodic ? (i < nt - 1 && j < nt - 1)
-                                      : (i >= 1 && i <= nt - 2 && j >= 1 && j <= nt - 2);
-      if (ok) uout[(size_t)i * puo + j] = sm[k];
-    }
+    MG_TAIL_FOR(nt, i, j, {
+      if (tail_unknown<BC>(i, j, nt)) uout[(size_t)i * puo + j] = sm[i * nt + j];
+    });
   if (cout) {
     __syncthreads();
-    tail_prefilter<T, BC>(sm, tmp, cout, pco, nt, taps[0]);
+    tail_prefilter<T, BC>(sm, tmp, cout, pco, nt);
   }
 }
 
@@ -586,15 +635,16 @@ hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uou
 template <typename T>
 hipError_t launch_prefilter_iir(hipStream_t s, int bc, int nc, const T* e, int pe, T* tmp, int pt,
                                 T* c, int pc) {
-  constexpr int K = sizeof(T) == 8 ? kPrefilterHalfTapsF64 : kPrefilterHalfTapsF32;
-  const dim3 gx((nc + kSeg - 1) / kSeg, (nc + 63) / 64);
-  const dim3 gy((nc + 63) / 64, (nc + kSeg - 1) / kSeg);
+  using C = PreCfg<T>;
+  const int nseg = (nc + C::S - 1) / C::S;
+  const dim3 gx(nseg, (nc + 63) / 64);
+  const dim3 gy((nc + 63) / 64, (nseg + 3) / 4);
   if (bc == kDirichlet) {
-    hipLaunchKernelGGL((k_pre_x<T, kDirichlet, K>), gx, dim3(64), 0, s, nc, e, pe, tmp, pt);
-    hipLaunchKernelGGL((k_pre_y<T, kDirichlet, K>), gy, dim3(64), 0, s, nc, tmp, pt, c, pc);
+    hipLaunchKernelGGL((k_pre_x<T, kDirichlet>), gx, dim3(64), 0, s, nc, e, pe, tmp, pt);
+    hipLaunchKernelGGL((k_pre_y<T, kDirichlet>), gy, dim3(256), 0, s, nc, tmp, pt, c, pc, nseg);
   } else {
-    hipLaunchKernelGGL((k_pre_x<T, kPeriodic, K>), gx, dim3(64), 0, s, nc, e, pe, tmp, pt);
-    hipLaunchKernelGGL((k_pre_y<T, kPeriodic, K>), gy, dim3(64), 0, s, nc, tmp, pt, c, pc);
+    hipLaunchKernelGGL((k_pre_x<T, kPeriodic>), gx, dim3(64), 0, s, nc, e, pe, tmp, pt);
+    hipLaunchKernelGGL((k_pre_y<T, kPeriodic>), gy, dim3(256), 0, s, nc, tmp, pt, c, pc, nseg);
   }
   return hipGetLastError();
 }
@@ -604,12 +654,13 @@ hipError_t launch_tail(hipStream_t s, int bc, int nt, const T* uin, int pui, T* 
                        const T* f, int pf, T* cout, int pco, const double* inv,
                        const PrefilterTaps* taps) {
   const size_t bytes = tail_bytes(nt, sizeof(T));
+  (void)taps;
   if (bc == kDirichlet)
-    hipLaunchKernelGGL((k_tail<T, kDirichlet>), dim3(1), dim3(kTailThreads), bytes, s, nt, uin,
-                       pui, uout, puo, f, pf, cout, pco, inv, taps);
+    hipLaunchKernelGGL((k_tail<T, kDirichlet>), dim3(1), dim3(32, 32), bytes, s, nt, uin, pui, uout,
+                       puo, f, pf, cout, pco, inv);
   else
-    hipLaunchKernelGGL((k_tail<T, kPeriodic>), dim3(1), dim3(kTailThreads), bytes, s, nt, uin, pui,
-                       uout, puo, f, pf, cout, pco, inv, taps);
+    hipLaunchKernelGGL((k_tail<T, kPeriodic>), dim3(1), dim3(32, 32), bytes, s, nt, uin, pui, uout,
+                       puo, f, pf, cout, pco, inv);
   return hipGetLastError();
 }
 

@@ -134,7 +134,7 @@ struct TimingRec {
 }  // namespace mg
 
 struct mg_ctx_s {
-  int seg_rows = 64;  // rows per wavefront segment of the streaming passes
+  int seg_rows = 0;  // rows per wavefront segment of the streaming passes (0 = per level)
   bool timing = false;
   std::vector<mg::TimingRec> recs;
   std::vector<hipEvent_t> pool;

@@ -32,13 +32,32 @@ constexpr int kUpHalo = 6;          // up pass: spline support + 4 half-sweeps
 constexpr int kUpOwned = 112;       // owned columns [xw + 6, xw + 118)
 constexpr int kAhead = 6;           // rows loaded this many steps before first use
 
+// Cross-lane moves by one lane with DPP wavefront shifts (GFX9 family):
+// wave_shr:1 gives lane l the value of lane l - 1, wave_shl:1 that of lane
+// l + 1.  Lanes with no source lane receive 0; they are band-edge lanes whose
+// results are never written.  64-bit values move as two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kWaveShr1 = 0x138;
+constexpr int kWaveShl1 = 0x130;
+
 template <typename T>
 __device__ __forceinline__ T from_left(T v) {  // value of lane - 1
-  return __shfl_up(v, 1);
+  return dpp_move<kWaveShr1>(v);
 }
 template <typename T>
-__device__ __forceinline__ T from_right(T v, int d = 1) {  // value of lane + d
-  return __shfl_down(v, d);
+__device__ __forceinline__ T from_right(T v) {  // value of lane + 1
+  return dpp_move<kWaveShl1>(v);
 }
 
 // Column data of one lane.
@@ -213,7 +232,7 @@ __global__ void __launch_bounds__(64 * kWaves)
 // coarse column per lane (lane L holds coefficient column x0/2).
 template <typename T>
 __device__ __forceinline__ void spline_x(T cj, T (&out)[2]) {
-  const T cl = from_left(cj), cr = from_right(cj, 1), cr2 = from_right(cj, 2);
+  const T cl = from_left(cj), cr = from_right(cj), cr2 = from_right(cr);
   out[0] = (T(1.0 / 6.0) * cl + T(4.0 / 6.0) * cj) + T(1.0 / 6.0) * cr;
   out[1] = ((T(1.0 / 48.0) * cl + T(23.0 / 48.0) * cj) + T(23.0 / 48.0) * cr) + T(1.0 / 48.0) * cr2;
 }
@@ -326,10 +345,22 @@ __global__ void __launch_bounds__(64 * kWaves)
 
 }  // namespace
 
+// Rows per wavefront segment: 64 on large grids; on small grids shorter, so
+// that about 1024 wavefronts share the work (each segment also loads ~10 halo
+// rows, which is cheap next to the latency a long serial segment costs).
+int stream_segment_rows(int n, int bc, int owned_cols) {
+  const int extent = bc == kPeriodic ? n - 1 : n;
+  const int nb = (extent + owned_cols - 1) / owned_cols;
+  int hs = 64;
+  while (hs > 8 && (long)nb * ((extent + hs - 1) / hs) < 1024) hs -= 8;
+  return hs;
+}
+
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
                               int puo, const T* f, int pf, T* fc, int pfc, int hs) {
   const int extent = bc == kPeriodic ? n - 1 : n;
+  if (hs <= 0) hs = stream_segment_rows(n, bc, kDownOwned);
   const int nb = (extent + kDownOwned - 1) / kDownOwned;
   const int ns = (extent + hs - 1) / hs;
   const int items = nb * ns;
@@ -349,6 +380,7 @@ template <typename T>
 hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
                             const T* f, int pf, const T* c, int pc, int hs) {
   const int extent = bc == kPeriodic ? n - 1 : n;
+  if (hs <= 0) hs = stream_segment_rows(n, bc, kUpOwned);
   const int nb = (extent + kUpOwned - 1) / kUpOwned;
   const int ns = (extent + hs - 1) / hs;
   const int items = nb * ns;
