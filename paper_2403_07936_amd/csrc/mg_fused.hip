@@ -18,6 +18,8 @@
 // across workgroups would race on halos, so a pass reads one buffer and
 // writes another.
 
+#include <algorithm>
+
 #include "mg_device.h"
 
 namespace mg {
@@ -199,8 +201,8 @@ __global__ void __launch_bounds__(kThreads)
 // segment of S nodes of one line held in registers; both recursions start K
 // nodes outside the segment from a zero state, and the neglected state is
 // below |z|^K of the data.
-constexpr double kZ = -0.26794919243112270647;  // sqrt(3) - 2
-constexpr double kG = 1.60769515458673623882;   // 12 - 6 sqrt(3)
+constexpr double kZ = kPrefZ;
+constexpr double kG = kPrefG;
 
 template <typename T, int L, int K>
 __device__ __forceinline__ void iir_regs(T (&v)[L]) {
@@ -261,47 +263,20 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Along x: a wavefront filters one segment of 64 rows.  The 64 x L tile is
-// loaded and stored row by row (coalesced) through LDS, and each lane runs
-// the recursion of one row in registers.
+// Along x: one wavefront per row, the recursion carried across the row in
+// chunks of 64 columns (wave_line_prefilter); each element is read and
+// written once, coalesced.  The causal values wait in LDS.
 template <typename T, int BC>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
     k_pre_x(int nc, const T* __restrict__ in, int pi, T* __restrict__ out, int po) {
-  using C = PreCfg<T>;
-  __shared__ T buf[64 * C::P];
-  const int lane = threadIdx.x;
-  const int r0 = blockIdx.y * 64, s0 = blockIdx.x * C::S;
-#pragma unroll
-  for (int cp = 0; cp < (C::L + 63) / 64; ++cp) {
-    const int c = lane + 64 * cp;
-    if (c < C::L) {
-      bool neg;
-      const int j = ext_node_any<BC>(s0 - C::K + c, nc, &neg);
-#pragma unroll 8
-      for (int r = 0; r < 64; ++r) {
-        const int gr = r0 + r;
-        const T x = gr < nc ? in[(size_t)gr * pi + j] : T(0);
-        buf[r * C::P + c] = neg ? -x : x;
-      }
-    }
-  }
-  __syncthreads();
-  T v[C::L];
-#pragma unroll
-  for (int k = 0; k < C::L; ++k) v[k] = buf[lane * C::P + k];
-  iir_regs<T, C::L, C::K>(v);
-#pragma unroll
-  for (int j = 0; j < C::S; ++j) buf[lane * C::P + j] = v[C::K + j];
-  __syncthreads();
-  if (lane < C::S) {
-    const int gc = s0 + lane;
-    const bool zero_col = BC == kDirichlet && (gc == 0 || gc == nc - 1);
-#pragma unroll 8
-    for (int r = 0; r < 64; ++r) {
-      const int gr = r0 + r;
-      if (gr < nc && gc < nc) out[(size_t)gr * po + gc] = zero_col ? T(0) : buf[r * C::P + lane];
-    }
-  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int M = BC == kPeriodic ? nc - 1 : nc;
+  T* buf = reinterpret_cast<T*>(smem_raw) + wave * (M + 128);
+  const int r = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (r >= nc) return;
+  const ScanWeights<T> w(lane);
+  wave_line_prefilter<T, BC>(in + (size_t)r * pi, 1, buf, out + (size_t)r * po, 1, nc, w, lane);
 }
 
 // ------------------------------------------------------------------ tail --
@@ -388,55 +363,20 @@ __device__ void tail_restrict(const T* u, const T* f, T* r, T* fc, int n) {
   __syncthreads();
 }
 
-// Prefilter of one line of a tail grid (nc nodes, element stride `ss` in
-// src, `ds` in dst; tmp holds nc values with stride `ts`): the causal and
-// anti-causal recursions run over the whole line plus K nodes of the
-// extended sequence on each side.  dst may alias src.
-template <typename T, int BC, int K>
-__device__ void line_prefilter(const T* src, int ss, T* tmp, int ts, T* dst, int ds, int nc) {
-  const T z = T(kZ), g = T(kG);
-  const int M = BC == kPeriodic ? nc - 1 : nc;  // stored nodes of one period
-  T p = T(0);
-  for (int q = -K; q < 0; ++q) {
-    bool neg;
-    const int j = ext_node_any<BC>(q, nc, &neg);
-    const T x = src[j * ss];
-    p = (neg ? -x : x) + z * p;
-  }
-  for (int q = 0; q < M; ++q) {
-    p = src[q * ss] + z * p;
-    tmp[q * ts] = p;
-  }
-  T w[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    bool neg;
-    const int j = ext_node_any<BC>(M + k, nc, &neg);
-    const T x = src[j * ss];
-    p = (neg ? -x : x) + z * p;
-    w[k] = p;
-  }
-  T m = T(0);
-#pragma unroll
-  for (int k = K - 1; k >= 0; --k) m = w[k] + z * m;
-  for (int q = M - 1; q >= 0; --q) {
-    m = tmp[q * ts] + z * m;
-    T y = g * m;
-    if (BC == kDirichlet && (q == 0 || q == nc - 1)) y = T(0);
-    dst[q * ds] = y;
-  }
-  if (BC == kPeriodic) dst[(nc - 1) * ds] = dst[0];
-}
-
-// Prefilter a tail grid: rows of src (in place into src), then columns into
-// dst (pitch pd).  One thread per line.
+// Prefilter a tail grid: rows of src (in place), then columns into dst
+// (pitch pd); each wavefront takes every 16th line, with its own slice of
+// the scratch grid for the causal values.
 template <typename T, int BC>
 __device__ void tail_prefilter(T* src, T* tmp, T* dst, int pd, int nc) {
-  constexpr int K = sizeof(T) == 8 ? kPrefilterHalfTapsF64 : kPrefilterHalfTapsF32;
   const int t = threadIdx.y * 32 + threadIdx.x;
-  if (t < nc) line_prefilter<T, BC, K>(src + t * nc, 1, tmp + t * nc, 1, src + t * nc, 1, nc);
+  const int lane = t & 63, wave = t >> 6;
+  const ScanWeights<T> w(lane);
+  T* buf = tmp + wave * (nc + 128);
+  for (int line = wave; line < nc; line += 16)
+    wave_line_prefilter<T, BC>(src + line * nc, 1, buf, src + line * nc, 1, nc, w, lane);
   __syncthreads();
-  if (t < nc) line_prefilter<T, BC, K>(src + t, nc, tmp + t, nc, dst + t, pd, nc);
+  for (int line = wave; line < nc; line += 16)
+    wave_line_prefilter<T, BC>(src + line, nc, buf, dst + line, pd, nc, w, lane);
   __syncthreads();
 }
 
@@ -557,13 +497,16 @@ __global__ void __launch_bounds__(kTailThreads)
   }
 }
 
+// u and f of every tail level, then the scratch grid: the residual of the
+// top level, or 16 per-wavefront line buffers of the prefilter.
 size_t tail_bytes(int nt, size_t elem) {
   size_t tot = 0;
   for (int n = nt;; n = (n - 1) / 2 + 1) {
     tot += 2 * (size_t)n * n;
     if (n == 5) break;
   }
-  return (tot + (size_t)nt * nt) * elem;
+  const size_t scratch = std::max((size_t)nt * nt, (size_t)16 * (nt + 128));
+  return (tot + scratch) * elem;
 }
 
 template <typename T, int BC>
@@ -577,6 +520,16 @@ int fused_tile_x() { return 64; }
 int fused_tile_y() { return 32; }
 
 hipError_t fused_init() {
+  // x-pass line buffers: one wavefront per workgroup suffices up to the
+  // largest coarse level (nc = 8193 for n = 16385): (8193 + 128) doubles.
+  const int xmax = (8193 + 128) * 8;
+  hipError_t e0;
+  e0 = hipFuncSetAttribute((const void*)k_pre_x<double, kDirichlet>,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, xmax);
+  if (e0 != hipSuccess) return e0;
+  e0 = hipFuncSetAttribute((const void*)k_pre_x<double, kPeriodic>,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, xmax);
+  if (e0 != hipSuccess) return e0;
   const size_t max64 = tail_bytes(kTailMaxSide, sizeof(double));
   const size_t max32 = tail_bytes(kTailMaxSide, sizeof(float));
   hipError_t e;
@@ -637,13 +590,16 @@ hipError_t launch_prefilter_iir(hipStream_t s, int bc, int nc, const T* e, int p
                                 T* c, int pc) {
   using C = PreCfg<T>;
   const int nseg = (nc + C::S - 1) / C::S;
-  const dim3 gx(nseg, (nc + 63) / 64);
+  int waves = 4;
+  while (waves > 1 && (size_t)waves * (nc + 128) * sizeof(T) > 65536) waves /= 2;
+  const dim3 gx((nc + waves - 1) / waves);
+  const size_t lds = (size_t)waves * (nc + 128) * sizeof(T);
   const dim3 gy((nc + 63) / 64, (nseg + 3) / 4);
   if (bc == kDirichlet) {
-    hipLaunchKernelGGL((k_pre_x<T, kDirichlet>), gx, dim3(64), 0, s, nc, e, pe, tmp, pt);
+    hipLaunchKernelGGL((k_pre_x<T, kDirichlet>), gx, dim3(64 * waves), lds, s, nc, e, pe, tmp, pt);
     hipLaunchKernelGGL((k_pre_y<T, kDirichlet>), gy, dim3(256), 0, s, nc, tmp, pt, c, pc, nseg);
   } else {
-    hipLaunchKernelGGL((k_pre_x<T, kPeriodic>), gx, dim3(64), 0, s, nc, e, pe, tmp, pt);
+    hipLaunchKernelGGL((k_pre_x<T, kPeriodic>), gx, dim3(64 * waves), lds, s, nc, e, pe, tmp, pt);
     hipLaunchKernelGGL((k_pre_y<T, kPeriodic>), gy, dim3(256), 0, s, nc, tmp, pt, c, pc, nseg);
   }
   return hipGetLastError();
