@@ -155,7 +155,7 @@ __device__ __forceinline__ T wave_recursion(T x, T carry, const ScanWeights<T>& 
 // buf (starting 64 nodes before the line from a zero state, and running 64
 // nodes past its end), then the anti-causal pass right to left.
 template <typename T, int BC>
-__device__ void wave_line_prefilter(const T* src, int ss, T* buf, T* dst, int ds, int nc,
+__device__ __forceinline__ void wave_line_prefilter(const T* src, int ss, T* buf, T* dst, int ds, int nc,
                                     const ScanWeights<T>& w, int lane) {
   const int M = BC == kPeriodic ? nc - 1 : nc;
   auto ext = [&](int q) {

@@ -32,7 +32,8 @@ template <typename T, int BC, int W, int HH>
 __device__ __forceinline__ void load_tile(T* s, const T* __restrict__ g, int pg, int n, int gy0,
                                           int gx0, bool zero) {
   const int N = n - 1;
-  for (int k = threadIdx.x; k < W * HH; k += blockDim.x) {
+#pragma unroll
+  for (int k = threadIdx.x; k < W * HH; k += kThreads) {
     const int ly = k / W, lx = k - ly * W;
     int gy = gy0 + ly, gx = gx0 + lx;
     T v = T(0);
@@ -147,7 +148,8 @@ __global__ void __launch_bounds__(kThreads)
   const int cx0 = (gx0 >> 1) - 1, cy0 = (gy0 >> 1) - 1;
   load_tile<T, BC, W, HH>(su, uin, pui, n, gy0, gx0, false);
   load_tile<T, BC, W, HH>(sf, f, pf, n, gy0, gx0, false);
-  for (int k = threadIdx.x; k < CW * CH; k += blockDim.x) {
+#pragma unroll
+  for (int k = threadIdx.x; k < CW * CH; k += kThreads) {
     const int cy = k / CW, cx = k - cy * CW;
     bool ny, nx;
     const int I = ext_node<BC>(cy0 + cy, nc, &ny);
@@ -315,7 +317,7 @@ __device__ __forceinline__ bool tail_unknown(int i, int j, int n) {
 }
 
 template <typename T, int BC>
-__device__ void tail_sweeps(T* u, const T* f, int n, int count) {
+__device__ __forceinline__ void tail_sweeps(T* u, const T* f, int n, int count) {
   const double hd = 1.0 / (double)(n - 1);
   const T h2 = T(hd * hd);
   for (int s = 0; s < count; ++s) {
@@ -334,7 +336,7 @@ __device__ void tail_sweeps(T* u, const T* f, int n, int count) {
 
 // r = f - A u into r (pitch n, unknown nodes only), then f_c = FW(r).
 template <typename T, int BC>
-__device__ void tail_restrict(const T* u, const T* f, T* r, T* fc, int n) {
+__device__ __forceinline__ void tail_restrict(const T* u, const T* f, T* r, T* fc, int n) {
   const T inv_h2 = T((double)(n - 1) * (double)(n - 1));
   MG_TAIL_FOR(n, i, j, {
     T v = T(0);
@@ -367,7 +369,7 @@ __device__ void tail_restrict(const T* u, const T* f, T* r, T* fc, int n) {
 // (pitch pd); each wavefront takes every 16th line, with its own slice of
 // the scratch grid for the causal values.
 template <typename T, int BC>
-__device__ void tail_prefilter(T* src, T* tmp, T* dst, int pd, int nc) {
+__device__ __forceinline__ void tail_prefilter(T* src, T* tmp, T* dst, int pd, int nc) {
   const int t = threadIdx.y * 32 + threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const ScanWeights<T> w(lane);
@@ -382,7 +384,7 @@ __device__ void tail_prefilter(T* src, T* tmp, T* dst, int pd, int nc) {
 
 // u += P c on a tail grid of side n from coefficients c of side nc.
 template <typename T, int BC>
-__device__ void tail_prolong_add(T* u, const T* c, int n) {
+__device__ __forceinline__ void tail_prolong_add(T* u, const T* c, int n) {
   const int nc = (n - 1) / 2 + 1;
   MG_TAIL_FOR(n, i, j, {
     if (tail_unknown<BC>(i, j, n)) {
