@@ -62,6 +62,16 @@ def main() -> int:
     dev = torch.device("cuda:0")
     B.lib()
 
+    # A plain device copy of known size (256 MiB read + 256 MiB written): the
+    # reference dispatch for scaling HBM traffic counters (FETCH_SIZE,
+    # WRITE_SIZE) when this script runs under a counter-collecting profiler.
+    calib = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+    calib_dst = torch.empty_like(calib)
+    calib.fill_(1.0)
+    calib_dst.copy_(calib)
+    torch.cuda.synchronize()
+    del calib, calib_dst
+
     log(f"generating {args.workload} seed {args.seed}")
     n, bc, f = workloads.workload(args.workload, args.seed)
     unknowns = workloads.grid_unknowns(n, bc)
