@@ -29,6 +29,29 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic(kind_name: str, precision: str, bc: int):
+    """HBM bytes per launch of the level-0 kernel from the committed counter
+    summary (profiles/hbm_traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a
+    known-size copy), or None when that kernel's source has changed since the
+    counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    names = {"down": "k_down_s", "up": "k_up_s"}
+    if kind_name not in names or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    t = "float" if precision == "mixed" else "double"
+    prefix = f"{names[kind_name]}<{t}, {bc}>@"
+    cands = [(int(k.split("@")[1]), v) for k, v in rec["per_launch"].items() if k.startswith(prefix)]
+    if not cands:
+        return None
+    return round(max(cands)[1]["bytes"], 0)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,8 +161,8 @@ def main() -> int:
     log(f"level-0 kernels (events): {json.dumps(per_kernel)}")
     roofline = {"bound": "hbm", "kernel": B.mg_kernel_name(kind), "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2),
-                "bytes_per_launch": by / cnt}
+                "traffic": measured_traffic(B.mg_kernel_name(kind), head, bc),
+                "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": by / cnt}
 
     extra = {}
     cpu = None
