@@ -103,6 +103,11 @@ typedef struct {
   int32_t kernel_path;        /* 0: fused register-streaming passes (default);
                                  1: one launch per operation (reference schedule);
                                  2: fused LDS-tiled passes.  Same arithmetic. */
+  int32_t schedule;           /* 0: auto (autotuned at setup, cached in tune_cache_path);
+                                 1: per problem, one graph of per-level kernels per cycle;
+                                 2: one persistent launch per cycle for the whole batch
+                                 (all problems must share the boundary condition; needs
+                                 kernel_path 0, nu_pre = nu_post = 2, inner_cycles = 1). */
 } mg_options;
 
 /* Fill *opt with the defaults listed above.  No-op on NULL. */
@@ -190,6 +195,7 @@ enum {
   MG_K_DOWN = 10,          /* fused: 2 sweeps + residual + restriction */
   MG_K_UP = 11,            /* fused: spline correction + 2 sweeps */
   MG_K_TAIL = 12,          /* fused: all levels <= 65 x 65 in one workgroup */
+  MG_K_PERSISTENT = 13,    /* persistent schedule: one whole step of the batch */
   MG_K_COUNT = 16
 };
 

@@ -60,6 +60,7 @@ class mg_options(ctypes.Structure):
         ("use_graph", i32),
         ("tune_cache_path", ctypes.c_char_p),
         ("kernel_path", i32),
+        ("schedule", i32),
     ]
 
 

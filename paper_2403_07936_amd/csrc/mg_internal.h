@@ -126,4 +126,71 @@ hipError_t launch_tail(hipStream_t s, int bc, int nt, const T* uin, int pui, T* 
                        const T* f, int pf, T* cout, int pco, const double* inv,
                        const PrefilterTaps* taps);
 
+// ---- persistent cycle kernel (mg_persist.hip) -------------------------------
+constexpr int kMaxLevels = 13;   // 16385 -> 5
+constexpr int kPersistThreads = 512;
+constexpr int kRowsPerItem = 8;  // rows of a residual / update item
+
+// One level of one problem as the persistent kernel sees it.  Arrays are of
+// the cycle's precision except where noted.
+struct PLevel {
+  void* u;    // final u of the level (level 0: the correction e, or the caller's u in FP64)
+  void* f;    // right-hand side (level 0 in mixed: the FP32 residual)
+  void* b;    // pre-smoothed u (written by the down pass, read by the up pass)
+  void* c;    // spline coefficients of u (levels >= 1)
+  void* tmp;  // x-filtered u (levels >= 1)
+  int n, pitch;        // side; pitch of b, c, tmp (and of u, f above level 0)
+  int pitch_u, pitch_f;  // pitches of u and f (differ at level 0 in FP64)
+  int hs_down, nb_down, hs_up, nb_up;  // streaming-pass geometry
+};
+
+struct PProblem {
+  int levels, tail, bc, active;
+  double* u64;          // caller's FP64 u (mixed: refined in place)
+  const double* f64;    // caller's FP64 f
+  int pitch64, zero_guess;  // zero_guess: level-0 down pass starts from u = 0
+  PLevel lv[kMaxLevels];
+};
+
+enum PKind : int {
+  kItemRes = 0,   // FP64 residual rows -> FP32 right-hand side (a = first row)
+  kItemDown = 1,  // a = band, b = segment
+  kItemTail = 2,  // workgroup item
+  kItemPreX = 3,  // a = row
+  kItemPreY = 4,  // a = first column, b = segment
+  kItemUp = 5,    // a = band, b = segment
+  kItemUpd = 6    // u64 += e rows (a = first row)
+};
+
+struct PItem {
+  int prob, level, a, b;
+};
+
+struct PPhase {
+  int kind, first, count, pad;
+};
+
+struct PBarrier {
+  unsigned count, gen, error, pad;
+};
+
+// One launch of the whole phase list.  T = cycle precision.
+template <typename T>
+hipError_t launch_persistent(hipStream_t s, int bc, const PProblem* probs, const PPhase* phases,
+                             int nphases, const PItem* items, PBarrier* bar, const double* inv,
+                             int blocks, size_t lds);
+// Largest number of co-resident workgroups of the persistent kernel.
+template <typename T>
+hipError_t persistent_blocks(int bc, size_t lds, int* blocks);
+hipError_t persistent_init(size_t lds64, size_t lds32);
+// Batched helpers over a device problem table: per-problem partial sums of
+// (f - A u)^2 and f^2 at level 0 (FP64), then their fixed-order reduction.
+hipError_t launch_resnorm_batched(hipStream_t s, int bc, const PProblem* probs, int nprob,
+                                  double* partials, int slots, double* sums);
+hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob);
+// Segment rows / band count of the streaming passes for a level.
+int stream_segment_rows(int n, int bc, int owned_cols);
+int stream_down_owned();
+int stream_up_owned();
+
 }  // namespace mg

@@ -1,0 +1,332 @@
+// Persistent cycle kernel: one launch runs a whole step (for the mixed path:
+// FP64 residual, the FP32 V-cycle, FP64 update) for every problem of a batch.
+//
+// The host flattens the step into phases (mg_runtime.hip): a phase is a list
+// of items of one kind, and every item of a phase is independent of the
+// others.  Phases are aligned from the coarsest level, so the tails of all
+// problems fall in one phase whatever their sizes.  Workgroups take items
+// round-robin (wavefront items by global wavefront index, tail items by
+// workgroup index) and meet at a device-wide barrier between phases.  The
+// grid is at most the number of co-resident workgroups; the barrier spins a
+// bounded number of times, and on timeout sets an error flag and every
+// workgroup leaves, so the kernel always ends.
+
+#include "mg_stream_dev.h"
+#include "mg_tail_dev.h"
+
+namespace mg {
+namespace {
+
+using namespace stream;
+using namespace dev;
+
+constexpr int kWavesPerBlock = kPersistThreads / 64;
+constexpr long kSpinLimit = 1L << 24;  // ~1 s of s_sleep: far longer than any phase
+
+// Sense-reversing device-wide barrier.  Returns false (and every later call
+// returns false) once any workgroup has timed out.
+__device__ bool grid_barrier(PBarrier* bar, unsigned* gen_local) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int good = 1;
+    __threadfence();
+    const unsigned g = *gen_local;
+    if (atomicAdd(&bar->count, 1u) == gridDim.x - 1) {
+      atomicExch(&bar->count, 0u);
+      __threadfence();
+      atomicAdd(&bar->gen, 1u);
+    } else {
+      long k = 0;
+      while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(&bar->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+            ++k > kSpinLimit) {
+          atomicOr(&bar->error, 1u);
+          good = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    *gen_local = g + 1;
+    __threadfence();
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+template <int BC>
+__device__ __forceinline__ int wrap_n(int i, int N) {
+  return i < 0 ? i + N : (i >= N ? i - N : i);
+}
+
+// FP64 residual of level 0 stored as the FP32 right-hand side, rows
+// [r0, r0 + kRowsPerItem); Dirichlet boundary 0, periodic seam = node 0.
+template <int BC>
+__device__ __forceinline__ void res_rows(const PProblem& p, int r0, int lane) {
+  const int n = p.lv[0].n, pu = p.pitch64, pr = p.lv[0].pitch_f;
+  const double* u = p.u64;
+  const double* f = p.f64;
+  float* r = static_cast<float*>(p.lv[0].f);
+  const double inv_h2 = (double)(n - 1) * (double)(n - 1);
+  for (int i = r0; i < r0 + kRowsPerItem && i < n; ++i) {
+    for (int j = lane; j < n; j += 64) {
+      double v = 0.0;
+      if (BC == kPeriodic) {
+        const int N = n - 1;
+        const int ii = i == N ? 0 : i, jj = j == N ? 0 : j;
+        const int im = ii == 0 ? N - 1 : ii - 1, ip = ii == N - 1 ? 0 : ii + 1;
+        const int jm = jj == 0 ? N - 1 : jj - 1, jp = jj == N - 1 ? 0 : jj + 1;
+        const double s = ((u[(size_t)im * pu + jj] + u[(size_t)ip * pu + jj]) +
+                          u[(size_t)ii * pu + jm]) + u[(size_t)ii * pu + jp];
+        v = f[(size_t)ii * pu + jj] - (4.0 * u[(size_t)ii * pu + jj] - s) * inv_h2;
+      } else if (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) {
+        const double s = ((u[(size_t)(i - 1) * pu + j] + u[(size_t)(i + 1) * pu + j]) +
+                          u[(size_t)i * pu + j - 1]) + u[(size_t)i * pu + j + 1];
+        v = f[(size_t)i * pu + j] - (4.0 * u[(size_t)i * pu + j] - s) * inv_h2;
+      }
+      r[(size_t)i * pr + j] = (float)v;
+    }
+  }
+}
+
+// u64 += e on the unknowns of rows [r0, r0 + kRowsPerItem).
+template <int BC>
+__device__ __forceinline__ void upd_rows(const PProblem& p, int r0, int lane) {
+  const int n = p.lv[0].n, pu = p.pitch64, pe = p.lv[0].pitch_u;
+  const float* e = static_cast<const float*>(p.lv[0].u);
+  const int lo = BC == kDirichlet ? 1 : 0;
+  for (int i = r0 < lo ? lo : r0; i < r0 + kRowsPerItem && i <= n - 2; ++i)
+    for (int j = lo + lane; j <= n - 2; j += 64)
+      p.u64[(size_t)i * pu + j] += (double)e[(size_t)i * pe + j];
+}
+
+template <typename T, int BC>
+__global__ void __launch_bounds__(kPersistThreads)
+    k_persistent(const PProblem* __restrict__ probs, const PPhase* __restrict__ phases,
+                 int nphases, const PItem* __restrict__ items, PBarrier* bar,
+                 const double* __restrict__ inv) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gwave = blockIdx.x * kWavesPerBlock + wave;
+  const int nwaves = gridDim.x * kWavesPerBlock;
+  __shared__ unsigned gen_local;
+  if (threadIdx.x == 0)
+    gen_local = __hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (__hip_atomic_load(&bar->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  for (int ph = 0; ph < nphases; ++ph) {
+    const PPhase P = phases[ph];
+    if (P.kind == kItemTail) {
+      for (int i = blockIdx.x; i < P.count; i += gridDim.x) {
+        const PItem it = items[P.first + i];
+        const PProblem& p = probs[it.prob];
+        if (!p.active) continue;
+        const int t = it.level;
+        const PLevel& L = p.lv[t];
+        const bool top = t == 0;
+        const T* uin = (top && !p.zero_guess) ? static_cast<const T*>(L.u) : nullptr;
+        tail_block<T, BC, kPersistThreads / 32>(
+            L.n, uin, L.pitch_u, top ? static_cast<T*>(L.u) : nullptr, L.pitch_u,
+            static_cast<const T*>(L.f), L.pitch_f, top ? nullptr : static_cast<T*>(L.c), L.pitch,
+            inv, sm);
+        __syncthreads();
+      }
+    } else {
+      for (int i = gwave; i < P.count; i += nwaves) {
+        const PItem it = items[P.first + i];
+        const PProblem& p = probs[it.prob];
+        if (!p.active) continue;
+        const PLevel& L = p.lv[it.level];
+        switch (P.kind) {
+          case kItemRes:
+            res_rows<BC>(p, it.a, lane);
+            break;
+          case kItemUpd:
+            upd_rows<BC>(p, it.a, lane);
+            break;
+          case kItemDown: {
+            const PLevel& C = p.lv[it.level + 1];
+            const double hd = 1.0 / (double)(L.n - 1);
+            const T* uin = (it.level == 0 && !p.zero_guess) ? static_cast<const T*>(L.u) : nullptr;
+            down_wave<T, BC>(L.n, uin, L.pitch_u, static_cast<T*>(L.b), L.pitch,
+                             static_cast<const T*>(L.f), L.pitch_f, static_cast<T*>(C.f), C.pitch_f,
+                             it.a, it.b, L.hs_down, T(hd * hd),
+                             T((double)(L.n - 1) * (double)(L.n - 1)), lane);
+            break;
+          }
+          case kItemUp: {
+            const PLevel& C = p.lv[it.level + 1];
+            const double hd = 1.0 / (double)(L.n - 1);
+            up_wave<T, BC>(L.n, static_cast<const T*>(L.b), L.pitch, static_cast<T*>(L.u),
+                           L.pitch_u, static_cast<const T*>(L.f), L.pitch_f,
+                           static_cast<const T*>(C.c), C.pitch, it.a, it.b, L.hs_up,
+                           T(hd * hd), lane);
+            break;
+          }
+          case kItemPreX: {
+            const ScanWeights<T> w(lane);
+            const int M = BC == kPeriodic ? L.n - 1 : L.n;
+            T* buf = sm + wave * (M + 128);
+            const T* src = static_cast<const T*>(L.u) + (size_t)it.a * L.pitch_u;
+            T* dst = static_cast<T*>(L.tmp) + (size_t)it.a * L.pitch;
+            wave_line_prefilter<T, BC>(src, 1, buf, dst, 1, L.n, w, lane);
+            break;
+          }
+          case kItemPreY:
+            prey_wave<T, BC>(L.n, static_cast<const T*>(L.tmp), L.pitch, static_cast<T*>(L.c),
+                             L.pitch, it.a, it.b, lane);
+            break;
+          default:
+            break;
+        }
+      }
+    }
+    if (ph + 1 < nphases && !grid_barrier(bar, &gen_local)) return;
+  }
+}
+
+__global__ void k_resnorm_batched(int bc, const PProblem* __restrict__ probs, double* partials,
+                                  int slots) {
+  // Workgroup (256 threads) = (problem, slot); rows slot, slot + slots, ...
+  __shared__ double sr[256], sf[256];
+  const int pi = blockIdx.y, slot = blockIdx.x, t = threadIdx.x;
+  const PProblem& p = probs[pi];
+  double rr = 0.0, ff = 0.0;
+  {
+    const int n = p.lv[0].n, pu = p.pitch64;
+    const double* u = p.u64;
+    const double* f = p.f64;
+    const double inv_h2 = (double)(n - 1) * (double)(n - 1);
+    const int lo = bc == kDirichlet ? 1 : 0, N = n - 1;
+    for (int i = lo + slot; i <= n - 2; i += slots)
+      for (int j = lo + t; j <= n - 2; j += 256) {
+        int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
+        if (bc == kPeriodic) {
+          im = i == 0 ? N - 1 : im;
+          ip = i == N - 1 ? 0 : ip;
+          jm = j == 0 ? N - 1 : jm;
+          jp = j == N - 1 ? 0 : jp;
+        }
+        const double s = ((u[(size_t)im * pu + j] + u[(size_t)ip * pu + j]) + u[(size_t)i * pu + jm]) +
+                         u[(size_t)i * pu + jp];
+        const double fv = f[(size_t)i * pu + j];
+        const double r = fv - (4.0 * u[(size_t)i * pu + j] - s) * inv_h2;
+        rr += r * r;
+        ff += fv * fv;
+      }
+  }
+  sr[t] = rr;
+  sf[t] = ff;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (t < s2) {
+      sr[t] += sr[t + s2];
+      sf[t] += sf[t + s2];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    partials[((size_t)pi * slots + slot) * 2] = sr[0];
+    partials[((size_t)pi * slots + slot) * 2 + 1] = sf[0];
+  }
+}
+
+__global__ void k_reduce_problem(const double* __restrict__ partials, int slots, int nprob,
+                                 double* sums) {
+  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pi >= nprob) return;
+  double rr = 0.0, ff = 0.0;
+  for (int s = 0; s < slots; ++s) {
+    rr += partials[((size_t)pi * slots + s) * 2];
+    ff += partials[((size_t)pi * slots + s) * 2 + 1];
+  }
+  sums[2 * pi] = rr;
+  sums[2 * pi + 1] = ff;
+}
+
+__global__ void k_seam_batched(const PProblem* __restrict__ probs) {
+  const PProblem& p = probs[blockIdx.x];
+  if (p.bc != kPeriodic) return;
+  const int n = p.lv[0].n, pu = p.pitch64;
+  double* u = p.u64;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    if (t < n - 1) {
+      u[(size_t)t * pu + (n - 1)] = u[(size_t)t * pu];
+      u[(size_t)(n - 1) * pu + t] = u[t];
+    } else {
+      u[(size_t)(n - 1) * pu + (n - 1)] = u[0];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t persistent_init(size_t lds64, size_t lds32) {
+  hipError_t e;
+  e = hipFuncSetAttribute((const void*)k_persistent<double, kDirichlet>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds64);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_persistent<double, kPeriodic>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds64);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_persistent<float, kDirichlet>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds32);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_persistent<float, kPeriodic>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds32);
+}
+
+template <typename T>
+hipError_t persistent_blocks(int bc, size_t lds, int* blocks) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const void* fn = bc == kDirichlet ? (const void*)k_persistent<T, kDirichlet>
+                                    : (const void*)k_persistent<T, kPeriodic>;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kPersistThreads, lds);
+  if (e != hipSuccess) return e;
+  *blocks = cus * (per > 0 ? per : 0);
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_persistent(hipStream_t s, int bc, const PProblem* probs, const PPhase* phases,
+                             int nphases, const PItem* items, PBarrier* bar, const double* inv,
+                             int blocks, size_t lds) {
+  if (bc == kDirichlet)
+    hipLaunchKernelGGL((k_persistent<T, kDirichlet>), dim3(blocks), dim3(kPersistThreads), lds, s,
+                       probs, phases, nphases, items, bar, inv);
+  else
+    hipLaunchKernelGGL((k_persistent<T, kPeriodic>), dim3(blocks), dim3(kPersistThreads), lds, s,
+                       probs, phases, nphases, items, bar, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_resnorm_batched(hipStream_t s, int bc, const PProblem* probs, int nprob,
+                                  double* partials, int slots, double* sums) {
+  hipLaunchKernelGGL(k_resnorm_batched, dim3(slots, nprob), dim3(256), 0, s, bc, probs, partials,
+                     slots);
+  hipLaunchKernelGGL(k_reduce_problem, dim3((nprob + 63) / 64), dim3(64), 0, s, partials, slots,
+                     nprob, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob) {
+  hipLaunchKernelGGL(k_seam_batched, dim3(nprob), dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
+
+template hipError_t launch_persistent<double>(hipStream_t, int, const PProblem*, const PPhase*,
+                                              int, const PItem*, PBarrier*, const double*, int,
+                                              size_t);
+template hipError_t launch_persistent<float>(hipStream_t, int, const PProblem*, const PPhase*, int,
+                                             const PItem*, PBarrier*, const double*, int, size_t);
+template hipError_t persistent_blocks<double>(int, size_t, int*);
+template hipError_t persistent_blocks<float>(int, size_t, int*);
+
+}  // namespace mg

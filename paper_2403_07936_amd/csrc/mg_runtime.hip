@@ -16,6 +16,7 @@
 
 #include "mg.h"
 #include "mg_internal.h"
+#include "mg_tail_dev.h"
 
 namespace mg {
 
@@ -133,7 +134,29 @@ struct TimingRec {
 };
 }  // namespace mg
 
+namespace mg {
+// State of the persistent schedule (one launch per step for the batch).
+struct Persist {
+  bool on = false;
+  int bc = 0;
+  std::vector<PProblem> h_probs;
+  PProblem* d_probs = nullptr;
+  bool dirty = true;
+  PPhase* d_phases = nullptr;
+  int nphases = 0;
+  PItem* d_items = nullptr;
+  PBarrier* d_bar = nullptr;
+  int blocks = 0;
+  size_t lds = 0;
+  hipGraphExec_t graph = nullptr;
+  double* d_partials = nullptr;
+  double* d_sums = nullptr;
+  int slots = 32;
+};
+}  // namespace mg
+
 struct mg_ctx_s {
+  mg::Persist ps;
   int seg_rows = 0;  // rows per wavefront segment of the streaming passes (0 = per level)
   bool timing = false;
   std::vector<mg::TimingRec> recs;
@@ -416,12 +439,258 @@ int32_t enqueue_resnorm(mg_ctx_s* ctx, Problem& p, const double* u, const double
   return MG_OK;
 }
 
+// ---------------------------------------------------------------- persistent
+
+template <typename T>
+const Hierarchy<T>& hier(const Problem& p);
+template <>
+const Hierarchy<double>& hier<double>(const Problem& p) {
+  return p.h64;
+}
+template <>
+const Hierarchy<float>& hier<float>(const Problem& p) {
+  return p.h32;
+}
+
+bool persistent_eligible(const mg_ctx_s* ctx, std::string* why) {
+  const auto& o = ctx->opt;
+  if (o.kernel_path != 0 || o.nu_pre != 2 || o.nu_post != 2) {
+    *why = "the persistent schedule needs kernel_path 0 and nu_pre = nu_post = 2";
+    return false;
+  }
+  if (o.precision == MG_MIXED && o.inner_cycles != 1) {
+    *why = "the persistent schedule needs inner_cycles = 1";
+    return false;
+  }
+  for (const auto& p : ctx->probs)
+    if (p.bc != ctx->probs[0].bc) {
+      *why = "the persistent schedule needs one boundary condition for the whole batch";
+      return false;
+    }
+  return true;
+}
+
+// Flattens one step of every problem into phases aligned from the coarsest
+// level and uploads the tables.
+template <typename T>
+int32_t build_persistent(mg_ctx_s* ctx) {
+  Persist& P = ctx->ps;
+  const bool mixed = ctx->opt.precision == MG_MIXED;
+  const int B = (int)ctx->probs.size();
+  P.bc = ctx->probs[0].bc;
+  P.h_probs.assign(B, PProblem{});
+  int K = 0;
+  size_t lds = 0;
+  for (int b = 0; b < B; ++b) {
+    const Problem& p = ctx->probs[b];
+    const Hierarchy<T>& h = hier<T>(p);
+    PProblem& q = P.h_probs[b];
+    q.levels = p.levels;
+    q.tail = p.tail;
+    q.bc = p.bc;
+    q.active = 1;
+    q.pitch64 = p.pitch0;
+    q.zero_guess = mixed ? 1 : 0;
+    for (int l = 0; l < p.levels; ++l) {
+      PLevel& L = q.lv[l];
+      L.u = h.u[l];
+      L.f = h.f[l];
+      L.b = h.r[l];
+      L.c = h.c[l];
+      L.tmp = h.tmp[l];
+      L.n = p.side[l];
+      L.pitch = L.pitch_u = L.pitch_f = p.pitch[l];
+      if (l == 0 && !mixed) L.pitch_u = L.pitch_f = p.pitch0;
+      L.hs_down = stream_segment_rows(L.n, p.bc, stream_down_owned());
+      L.hs_up = stream_segment_rows(L.n, p.bc, stream_up_owned());
+      const int extent = p.bc == kPeriodic ? L.n - 1 : L.n;
+      L.nb_down = (extent + stream_down_owned() - 1) / stream_down_owned();
+      L.nb_up = (extent + stream_up_owned() - 1) / stream_up_owned();
+      if (l > 0 && l < p.tail)
+        lds = std::max(lds, (size_t)(kPersistThreads / 64) * (L.n + 128) * sizeof(T));
+    }
+    K = std::max(K, p.tail);
+    lds = std::max(lds, dev::tail_bytes(p.side[p.tail], sizeof(T)));
+  }
+  std::vector<PPhase> phases;
+  std::vector<PItem> items;
+  auto close_phase = [&](int kind, size_t first) {
+    if (items.size() > first) phases.push_back({kind, (int)first, (int)(items.size() - first), 0});
+  };
+  auto rows_items = [&](int kind) {
+    const size_t first = items.size();
+    for (int b = 0; b < B; ++b)
+      for (int r = 0; r < ctx->probs[b].n; r += kRowsPerItem) items.push_back({b, 0, r, 0});
+    close_phase(kind, first);
+  };
+  auto band_items = [&](int b, int l, bool down) {
+    const PLevel& L = P.h_probs[b].lv[l];
+    const int extent = P.bc == kPeriodic ? L.n - 1 : L.n;
+    const int hs = down ? L.hs_down : L.hs_up, nb = down ? L.nb_down : L.nb_up;
+    const int ns = (extent + hs - 1) / hs;
+    for (int sg = 0; sg < ns; ++sg)
+      for (int bd = 0; bd < nb; ++bd) items.push_back({b, l, bd, sg});
+  };
+  if (mixed) rows_items(kItemRes);
+  for (int k = K - 1; k >= 0; --k) {
+    const size_t first = items.size();
+    for (int b = 0; b < B; ++b) {
+      const int l = ctx->probs[b].tail - 1 - k;
+      if (l >= 0) band_items(b, l, true);
+    }
+    close_phase(kItemDown, first);
+  }
+  {
+    const size_t first = items.size();
+    for (int b = 0; b < B; ++b) items.push_back({b, ctx->probs[b].tail, 0, 0});
+    close_phase(kItemTail, first);
+  }
+  for (int k = 0; k < K; ++k) {
+    size_t first = items.size();
+    for (int b = 0; b < B; ++b) {
+      const int l = ctx->probs[b].tail - 1 - k;
+      if (l >= 0 && l + 1 < ctx->probs[b].tail)
+        for (int r = 0; r < ctx->probs[b].side[l + 1]; ++r) items.push_back({b, l + 1, r, 0});
+    }
+    close_phase(kItemPreX, first);
+    first = items.size();
+    for (int b = 0; b < B; ++b) {
+      const int l = ctx->probs[b].tail - 1 - k;
+      if (l >= 0 && l + 1 < ctx->probs[b].tail) {
+        const int nc = ctx->probs[b].side[l + 1];
+        const int S = sizeof(T) == 8 ? 16 : 32;
+        for (int sg = 0; sg * S < nc; ++sg)
+          for (int c0 = 0; c0 < nc; c0 += 64) items.push_back({b, l + 1, c0, sg});
+      }
+    }
+    close_phase(kItemPreY, first);
+    first = items.size();
+    for (int b = 0; b < B; ++b) {
+      const int l = ctx->probs[b].tail - 1 - k;
+      if (l >= 0) band_items(b, l, false);
+    }
+    close_phase(kItemUp, first);
+  }
+  if (mixed) rows_items(kItemUpd);
+
+  P.lds = lds;
+  MG_HIP(persistent_init(std::max(lds, (size_t)65536), std::max(lds, (size_t)65536)));
+  MG_HIP(persistent_blocks<T>(P.bc, lds, &P.blocks));
+  if (P.blocks <= 0) return fail(MG_ERR_UNSUPPORTED, "persistent kernel does not fit on a CU");
+  unsigned char* d = nullptr;
+  MG_TRY(alloc_level<unsigned char>(ctx, 1, (int)(sizeof(PProblem) * B), &d));
+  P.d_probs = reinterpret_cast<PProblem*>(d);
+  MG_TRY(alloc_level<unsigned char>(ctx, 1, (int)(sizeof(PPhase) * phases.size()), &d));
+  P.d_phases = reinterpret_cast<PPhase*>(d);
+  MG_TRY(alloc_level<unsigned char>(ctx, 1, (int)(sizeof(PItem) * items.size()), &d));
+  P.d_items = reinterpret_cast<PItem*>(d);
+  MG_TRY(alloc_level<unsigned char>(ctx, 1, (int)sizeof(PBarrier), &d));
+  P.d_bar = reinterpret_cast<PBarrier*>(d);
+  MG_TRY(alloc_level<double>(ctx, 2 * B, P.slots, &P.d_partials));
+  MG_TRY(alloc_level<double>(ctx, 2, B, &P.d_sums));
+  MG_HIP(hipMemcpyAsync(P.d_phases, phases.data(), sizeof(PPhase) * phases.size(),
+                        hipMemcpyHostToDevice, ctx->stream));
+  MG_HIP(hipMemcpyAsync(P.d_items, items.data(), sizeof(PItem) * items.size(),
+                        hipMemcpyHostToDevice, ctx->stream));
+  MG_HIP(hipStreamSynchronize(ctx->stream));
+  P.nphases = (int)phases.size();
+  P.on = true;
+  P.dirty = true;
+  return MG_OK;
+}
+
+// Points the problem table at the caller's arrays and activity flags, and
+// uploads it if anything changed.
+int32_t persistent_bind(mg_ctx_s* ctx, double* const* u, const double* const* f,
+                        const std::vector<int>& active) {
+  Persist& P = ctx->ps;
+  const bool mixed = ctx->opt.precision == MG_MIXED;
+  for (size_t b = 0; b < P.h_probs.size(); ++b) {
+    PProblem& q = P.h_probs[b];
+    const int act = active.empty() ? 1 : active[b];
+    if (q.u64 != u[b] || q.f64 != f[b] || q.active != act) P.dirty = true;
+    q.u64 = u[b];
+    q.f64 = f[b];
+    q.active = act;
+    if (!mixed) {
+      q.lv[0].u = u[b];
+      q.lv[0].f = const_cast<double*>(f[b]);
+    }
+  }
+  if (P.dirty) {
+    MG_HIP(hipMemcpyAsync(P.d_probs, P.h_probs.data(), sizeof(PProblem) * P.h_probs.size(),
+                          hipMemcpyHostToDevice, ctx->stream));
+    P.dirty = false;
+  }
+  return MG_OK;
+}
+
+int32_t persistent_launch(mg_ctx_s* ctx) {
+  Persist& P = ctx->ps;
+  auto launch = [&](hipStream_t s) {
+    return ctx->opt.precision == MG_MIXED
+               ? launch_persistent<float>(s, P.bc, P.d_probs, P.d_phases, P.nphases, P.d_items,
+                                          P.d_bar, ctx->inv[P.bc], P.blocks, P.lds)
+               : launch_persistent<double>(s, P.bc, P.d_probs, P.d_phases, P.nphases, P.d_items,
+                                           P.d_bar, ctx->inv[P.bc], P.blocks, P.lds);
+  };
+  if (!ctx->opt.use_graph || ctx->timing) {
+    MG_TRY(timed(ctx, ctx->stream, MG_K_PERSISTENT, 0, 0.0, [&] { return launch(ctx->stream); }));
+    return MG_OK;
+  }
+  if (!P.graph) {
+    hipGraph_t g = nullptr;
+    MG_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
+    const hipError_t le = launch(ctx->capture);
+    hipError_t e = hipStreamEndCapture(ctx->capture, &g);
+    if (le != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(MG_ERR_HIP, std::string("persistent launch: ") + hipGetErrorString(le));
+    }
+    if (e != hipSuccess) return fail(MG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      P.graph = nullptr;
+      return fail(MG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+  }
+  MG_HIP(hipGraphLaunch(P.graph, ctx->stream));
+  return MG_OK;
+}
+
+// Relative residuals of all problems from the batched kernels (synchronises);
+// also reports a timed-out device barrier.
+int32_t persistent_relres(mg_ctx_s* ctx, double* rel) {
+  Persist& P = ctx->ps;
+  const int B = (int)ctx->probs.size();
+  MG_HIP(launch_resnorm_batched(ctx->stream, P.bc, P.d_probs, B, P.d_partials, P.slots,
+                                P.d_sums));
+  std::vector<double> sums(2 * B);
+  MG_HIP(hipMemcpyAsync(sums.data(), P.d_sums, sizeof(double) * 2 * B, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  PBarrier bar{};
+  MG_HIP(hipMemcpyAsync(&bar, P.d_bar, sizeof bar, hipMemcpyDeviceToHost, ctx->stream));
+  MG_HIP(hipStreamSynchronize(ctx->stream));
+  if (bar.error) {
+    MG_HIP(hipMemsetAsync(P.d_bar, 0, sizeof(PBarrier), ctx->stream));
+    MG_HIP(hipStreamSynchronize(ctx->stream));
+    return fail(MG_ERR_HIP, "persistent kernel: device-wide barrier timed out");
+  }
+  for (int b = 0; b < B; ++b) {
+    const double rr = sums[2 * b], ff = sums[2 * b + 1];
+    rel[b] = ff > 0.0 ? std::sqrt(rr) / std::sqrt(ff) : std::sqrt(rr);
+  }
+  return MG_OK;
+}
+
 int32_t destroy_ctx(mg_ctx_s* ctx) {
   if (!ctx) return MG_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& p : ctx->probs)
     if (p.graph) (void)hipGraphExecDestroy(p.graph);
+  if (ctx->ps.graph) (void)hipGraphExecDestroy(ctx->ps.graph);
   for (void* q : ctx->owned) (void)hipFree(q);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->host) (void)hipHostFree(ctx->host);
@@ -447,6 +716,8 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
   if (opt->check_every < 0) return fail(MG_ERR_INVALID_ARG, "check_every must be >= 0");
   if (opt->kernel_path < 0 || opt->kernel_path > 2)
     return fail(MG_ERR_INVALID_ARG, "kernel_path must be 0, 1 or 2");
+  if (opt->schedule < 0 || opt->schedule > 2)
+    return fail(MG_ERR_INVALID_ARG, "schedule must be 0, 1 or 2");
   for (int b = 0; b < batch; ++b) {
     const mg_grid& g = grids[b];
     if (!valid_side(g.n))
@@ -573,6 +844,13 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
   }
   if (hipStreamSynchronize(ctx->stream) != hipSuccess)
     return bail(fail(MG_ERR_HIP, "hipStreamSynchronize after setup"));
+  if (opt->schedule == 2) {
+    std::string why;
+    if (!persistent_eligible(ctx, &why)) return bail(fail(MG_ERR_UNSUPPORTED, why));
+    const int32_t st = opt->precision == MG_MIXED ? build_persistent<float>(ctx)
+                                                  : build_persistent<double>(ctx);
+    if (st != MG_OK) return bail(st);
+  }
   *out = ctx;
   return MG_OK;
 }
@@ -604,6 +882,17 @@ int32_t vcycle_impl(mg_ctx ctx, double* const* u, const double* const* f, int32_
   if (ncycles < 0) return fail(MG_ERR_INVALID_ARG, "ncycles < 0");
   MG_HIP(hipSetDevice(ctx->device));
   const int B = (int)ctx->probs.size();
+  if (ctx->ps.on) {
+    MG_TRY(persistent_bind(ctx, u, f, {}));
+    for (int c = 0; c < ncycles; ++c) MG_TRY(persistent_launch(ctx));
+    if (ctx->ps.bc == kPeriodic && ncycles > 0)
+      MG_HIP(launch_seam_batched(ctx->stream, ctx->ps.d_probs, B));
+    if (!relres_out) return MG_OK;
+    MG_TRY(persistent_relres(ctx, relres_out));
+    for (int b = 0; b < B; ++b)
+      if (!std::isfinite(relres_out[b])) return fail(MG_ERR_NONFINITE, "non-finite residual");
+    return MG_OK;
+  }
   for (int c = 0; c < ncycles; ++c)
     for (int b = 0; b < B; ++b) MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b]));
   if (!relres_out) return MG_OK;
@@ -657,11 +946,15 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
   std::vector<int> cycles(B, 0), state(B, 1);  // state: 1 active, 0 converged, <0 failure
   std::vector<double> rel(B, 0.0), prev(B, -1.0);
   std::vector<int> prev_cycles(B, 0), slow(B, 0), next_check(B, 1), all(B);
-  for (int b = 0; b < B; ++b) {
-    all[b] = b;
-    MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
+  const bool pers = ctx->ps.on;
+  for (int b = 0; b < B; ++b) all[b] = b;
+  if (pers) {
+    MG_TRY(persistent_bind(ctx, u, f, {}));
+    MG_TRY(persistent_relres(ctx, rel.data()));
+  } else {
+    for (int b = 0; b < B; ++b) MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
+    MG_TRY(read_relres(ctx, all, rel.data()));
   }
-  MG_TRY(read_relres(ctx, all, rel.data()));
   for (int b = 0; b < B; ++b) {
     if (!std::isfinite(rel[b])) state[b] = MG_ERR_NONFINITE;
     else if (rel[b] <= rtol) state[b] = 0;
@@ -678,18 +971,40 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
     int steps = 1 << 30;
     for (int b : act) steps = std::min(steps, next_check[b] - cycles[b]);
     steps = std::max(steps, 1);
-    for (int k = 0; k < steps; ++k)
+    for (int k = 0; k < steps; ++k) {
+      if (pers) {
+        std::vector<int> on(B, 0);
+        bool any = false;
+        for (int b : act)
+          if (cycles[b] < max_cycles && cycles[b] < next_check[b]) {
+            on[b] = 1;
+            any = true;
+            ++cycles[b];
+          }
+        if (any) {
+          MG_TRY(persistent_bind(ctx, u, f, on));
+          MG_TRY(persistent_launch(ctx));
+        }
+        continue;
+      }
       for (int b : act)
         if (cycles[b] < max_cycles && cycles[b] < next_check[b]) {
           MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b]));
           ++cycles[b];
         }
+    }
     std::vector<int> chk;
     for (int b : act)
       if (cycles[b] >= next_check[b] || cycles[b] >= max_cycles) chk.push_back(b);
-    for (int b : chk) MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
     std::vector<double> r(chk.size());
-    MG_TRY(read_relres(ctx, chk, r.data()));
+    if (pers) {
+      std::vector<double> rall(B);
+      MG_TRY(persistent_relres(ctx, rall.data()));
+      for (size_t k = 0; k < chk.size(); ++k) r[k] = rall[chk[k]];
+    } else {
+      for (int b : chk) MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
+      MG_TRY(read_relres(ctx, chk, r.data()));
+    }
     for (size_t k = 0; k < chk.size(); ++k) {
       const int b = chk[k];
       const double rr = r[k], last = prev[b];
@@ -854,6 +1169,7 @@ void mg_options_default(mg_options* opt) {
   opt->use_graph = 1;
   opt->tune_cache_path = nullptr;
   opt->kernel_path = 0;
+  opt->schedule = 0;
 }
 
 int32_t mg_setup(const mg_grid* grids, int32_t batch, const mg_options* opt, void* hip_stream,
@@ -963,6 +1279,7 @@ const char* mg_kernel_name(int32_t kind) {
     case MG_K_DOWN: return "down";
     case MG_K_UP: return "up";
     case MG_K_TAIL: return "tail";
+    case MG_K_PERSISTENT: return "persistent";
     default: return "?";
   }
 }

@@ -1,249 +1,21 @@
-// Register-streaming down and up passes for gfx950.
-//
-// Each 64-lane wavefront owns a band of columns, two adjacent columns per
-// lane (x0 = even, x1 = x0 + 1), and marches down a segment of rows.  With
-// two columns per lane every red-black half-sweep updates exactly one node
-// per lane per row, and which of the two it is depends only on the row, so
-// the wavefront never diverges.  The steps of a pass are pipelined over the
-// rows with fixed lags, each row held in registers for the few steps that
-// need it:
-//   down pass, at the step that loads row t:
-//     red sweep on row t-1, black on t-2, red on t-3, black on t-4 (u final),
-//     residual on row t-5, full weighting on the coarse row at fine row t-6;
-//   up pass, at the step that loads row t:
-//     u += P e_c on row t, red sweep on t-1, black on t-2, red on t-3,
-//     black on t-4 (u final).
-// Horizontal neighbours come from the adjacent lane by a cross-lane shuffle.
-// The lanes at the band edges see no neighbour, and the error this causes
-// moves inward one column per step, so only the inner columns of a band are
-// written (the rest is a halo that the neighbouring band owns); the top and
-// bottom of a segment likewise load halo rows.  The arithmetic and its
-// order are those of the per-operation kernels.
+// Standalone register-streaming down and up kernels: one wavefront per
+// (band, row segment) item; the work itself is in mg_stream_dev.h.
 
-#include "mg_device.h"
+#include "mg_stream_dev.h"
 
 namespace mg {
+using namespace stream;
 namespace {
-
-constexpr int kWaves = 4;           // independent wavefronts per workgroup
-constexpr int kDownHalo = 6;        // columns on each side a down band does not own
-constexpr int kDownOwned = 128 - 2 * kDownHalo;
-constexpr int kUpHalo = 6;          // up pass: spline support + 4 half-sweeps
-constexpr int kUpOwned = 112;       // owned columns [xw + 6, xw + 118)
-constexpr int kAhead = 6;           // rows loaded this many steps before first use
-
-// Cross-lane moves by one lane with DPP wavefront shifts (GFX9 family):
-// wave_shr:1 gives lane l the value of lane l - 1, wave_shl:1 that of lane
-// l + 1.  Lanes with no source lane receive 0; they are band-edge lanes whose
-// results are never written.  64-bit values move as two 32-bit halves.
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-constexpr int kWaveShr1 = 0x138;
-constexpr int kWaveShl1 = 0x130;
-
-template <typename T>
-__device__ __forceinline__ T from_left(T v) {  // value of lane - 1
-  return dpp_move<kWaveShr1>(v);
-}
-template <typename T>
-__device__ __forceinline__ T from_right(T v) {  // value of lane + 1
-  return dpp_move<kWaveShl1>(v);
-}
-
-// Column data of one lane.
-template <int BC>
-struct Cols {
-  int c0, c1;        // stored column indices used for loads
-  bool in0, in1;     // column exists in the array (Dirichlet)
-  bool unk0, unk1;   // column holds unknowns
-  __device__ Cols(int x0, int n) {
-    const int x1 = x0 + 1;
-    if constexpr (BC == kPeriodic) {
-      const int N = n - 1;
-      c0 = x0 < 0 ? x0 + N : (x0 >= N ? x0 - N : x0);
-      c1 = x1 < 0 ? x1 + N : (x1 >= N ? x1 - N : x1);
-      in0 = in1 = unk0 = unk1 = true;
-    } else {
-      in0 = x0 >= 0 && x0 < n;
-      in1 = x1 >= 0 && x1 < n;
-      c0 = in0 ? x0 : 0;
-      c1 = in1 ? x1 : 0;
-      unk0 = x0 >= 1 && x0 <= n - 2;
-      unk1 = x1 >= 1 && x1 <= n - 2;
-    }
-  }
-};
-
-template <int BC>
-__device__ __forceinline__ int row_index(int t, int n, bool* in) {
-  if constexpr (BC == kPeriodic) {
-    const int N = n - 1;
-    *in = true;
-    return t < 0 ? t + N : (t >= N ? t - N : t);
-  } else {
-    *in = t >= 0 && t < n;
-    return *in ? t : 0;
-  }
-}
-
-template <int BC>
-__device__ __forceinline__ bool row_unknown(int t, int n) {
-  return BC == kPeriodic || (t >= 1 && t <= n - 2);
-}
-
-template <typename T, int BC>
-__device__ __forceinline__ void load_row(T (&dst)[2], const T* __restrict__ a, int pa, int t, int n,
-                                         const Cols<BC>& col) {
-  bool rin;
-  const int r = row_index<BC>(t, n, &rin);
-  const T* p = a + (size_t)r * pa;
-  dst[0] = (rin && col.in0) ? p[col.c0] : T(0);
-  dst[1] = (rin && col.in1) ? p[col.c1] : T(0);
-}
-
-// Red-black half-sweep on one row: the node of colour `colour` among the
-// lane's two columns solves its equation with its four neighbours fixed.
-template <typename T, int BC>
-__device__ __forceinline__ void sweep_row(const T (&um)[2], T (&u0)[2], const T (&up)[2],
-                                          const T (&f0)[2], int row, int colour, int n,
-                                          const Cols<BC>& col, T h2) {
-  const bool rok = row_unknown<BC>(row, n);
-  if (((colour + row) & 1) == 0) {
-    const T left = from_left(u0[1]);
-    const T s = ((um[0] + up[0]) + left) + u0[1];
-    const T v = (h2 * f0[0] + s) * T(0.25);
-    if (rok && col.unk0) u0[0] = v;
-  } else {
-    const T right = from_right(u0[0]);
-    const T s = ((um[1] + up[1]) + u0[0]) + right;
-    const T v = (h2 * f0[1] + s) * T(0.25);
-    if (rok && col.unk1) u0[1] = v;
-  }
-}
-
-template <typename T, int BC>
-__device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2], const T (&up)[2],
-                                             const T (&f0)[2], T (&r)[2], int row, int n,
-                                             const Cols<BC>& col, T inv_h2) {
-  const T left = from_left(u0[1]);
-  const T right = from_right(u0[0]);
-  const T s0 = ((um[0] + up[0]) + left) + u0[1];
-  const T s1 = ((um[1] + up[1]) + u0[0]) + right;
-  const T r0 = f0[0] - (T(4) * u0[0] - s0) * inv_h2;
-  const T r1 = f0[1] - (T(4) * u0[1] - s1) * inv_h2;
-  const bool rok = row_unknown<BC>(row, n);
-  r[0] = (rok && col.unk0) ? r0 : T(0);
-  r[1] = (rok && col.unk1) ? r1 : T(0);
-}
 
 template <typename T, int BC>
 __global__ void __launch_bounds__(64 * kWaves)
     k_down_s(int n, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
              const T* __restrict__ f, int pf, T* __restrict__ fc, int pfc, int nbands, int nitems,
              int hs, T h2, T inv_h2) {
-  const int lane = threadIdx.x & 63;
   const int item = xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
   if (item >= nitems) return;
-  const int band = item % nbands, seg = item / nbands;
-  const int xw = band * kDownOwned - kDownHalo;
-  const int x0 = xw + 2 * lane;
-  const int ys = seg * hs;
-  const Cols<BC> col(x0, n);
-  const int N = n - 1, nc = (n - 1) / 2 + 1;
-  const bool lane_owns = lane >= kDownHalo / 2 && lane < 64 - kDownHalo / 2;
-  const bool wr0 = lane_owns && (BC == kPeriodic ? x0 < N : col.unk0);
-  const bool wr1 = lane_owns && (BC == kPeriodic ? x0 + 1 < N : col.unk1);
-  const int J = x0 >> 1;
-  const bool wrc = lane_owns && (BC == kPeriodic ? J < nc - 1 : (J >= 1 && J <= nc - 2));
-  const int row_end = BC == kPeriodic ? N : n;  // rows [0, row_end) are owned by some segment
-
-  // Rows live in a ring of 16 register slots; row t0 + s is in slot s & 15
-  // and is loaded kAhead steps before the step that first uses it.
-  T U[16][2], F[16][2], R[4][2];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) U[k][0] = U[k][1] = F[k][0] = F[k][1] = T(0);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) R[k][0] = R[k][1] = T(0);
-
-  const int t0 = ys - 6;
-  const int steps = hs + 11;
-#pragma unroll
-  for (int k = 0; k < kAhead; ++k) {
-    if (uin) load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
-    load_row<T, BC>(F[k], f, pf, t0 + k, n, col);
-  }
-  for (int sb = 0; sb < steps; sb += 16) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int s = sb + k;
-      if (s >= steps) break;
-      const int t = t0 + s;
-      if (s + kAhead < steps) {
-        T(&nu)[2] = U[(k + kAhead) & 15];
-        if (uin) load_row<T, BC>(nu, uin, pui, t + kAhead, n, col);
-        else nu[0] = nu[1] = T(0);
-        load_row<T, BC>(F[(k + kAhead) & 15], f, pf, t + kAhead, n, col);
-      }
-      // red (sweep 1) on t-1, black on t-2, red (sweep 2) on t-3, black on t-4
-      sweep_row<T, BC>(U[(k + 14) & 15], U[(k + 15) & 15], U[k], F[(k + 15) & 15], t - 1, 0, n,
-                       col, h2);
-      sweep_row<T, BC>(U[(k + 13) & 15], U[(k + 14) & 15], U[(k + 15) & 15], F[(k + 14) & 15],
-                       t - 2, 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 12) & 15], U[(k + 13) & 15], U[(k + 14) & 15], F[(k + 13) & 15],
-                       t - 3, 0, n, col, h2);
-      sweep_row<T, BC>(U[(k + 11) & 15], U[(k + 12) & 15], U[(k + 13) & 15], F[(k + 12) & 15],
-                       t - 4, 1, n, col, h2);
-      const int tu = t - 4;
-      if (tu >= ys && tu < ys + hs && tu < row_end) {
-        T* p = uout + (size_t)tu * puo;
-        if (wr0) p[x0] = U[(k + 12) & 15][0];
-        if (wr1) p[x0 + 1] = U[(k + 12) & 15][1];
-      }
-      residual_row<T, BC>(U[(k + 10) & 15], U[(k + 11) & 15], U[(k + 12) & 15], F[(k + 11) & 15],
-                          R[(k + 3) & 3], t - 5, n, col, inv_h2);
-      const int i = t - 6;
-      if ((i & 1) == 0 && i >= ys && i < ys + hs) {
-        const int I = i >> 1;
-        const bool rowc = BC == kPeriodic ? I < nc - 1 : (I >= 1 && I <= nc - 2);
-        const T(&rm)[2] = R[(k + 1) & 3];
-        const T(&r0)[2] = R[(k + 2) & 3];
-        const T(&rp)[2] = R[(k + 3) & 3];
-        const T am = from_left(rm[1]), a0 = from_left(r0[1]), ap = from_left(rp[1]);
-        const T edges = ((rm[0] + rp[0]) + a0) + r0[1];
-        const T corners = ((am + rm[1]) + ap) + rp[1];
-        const T v = ((T(4) * r0[0] + T(2) * edges) + corners) * T(0.0625);
-        if (rowc && wrc) fc[(size_t)I * pfc + J] = v;
-      }
-    }
-  }
-}
-
-// Spline along x at the lane's two columns from coarse row values held one
-// coarse column per lane (lane L holds coefficient column x0/2).
-template <typename T>
-__device__ __forceinline__ void spline_x(T cj, T (&out)[2]) {
-  const T cl = from_left(cj), cr = from_right(cj), cr2 = from_right(cr);
-  out[0] = (T(1.0 / 6.0) * cl + T(4.0 / 6.0) * cj) + T(1.0 / 6.0) * cr;
-  out[1] = ((T(1.0 / 48.0) * cl + T(23.0 / 48.0) * cj) + T(23.0 / 48.0) * cr) + T(1.0 / 48.0) * cr2;
-}
-
-template <typename T, int BC>
-__device__ __forceinline__ T load_coef(const T* __restrict__ c, int pc, int I, int J, int nc) {
-  bool ni, nj;
-  const int ii = ext_node_any<BC>(I, nc, &ni);
-  const int jj = ext_node_any<BC>(J, nc, &nj);
-  const T v = c[(size_t)ii * pc + jj];
-  return (ni != nj) ? -v : v;
+  down_wave<T, BC>(n, uin, pui, uout, puo, f, pf, fc, pfc, item % nbands, item / nbands, hs, h2,
+                   inv_h2, threadIdx.x & 63);
 }
 
 template <typename T, int BC>
@@ -251,96 +23,10 @@ __global__ void __launch_bounds__(64 * kWaves)
     k_up_s(int n, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
            const T* __restrict__ f, int pf, const T* __restrict__ c, int pc, int nbands,
            int nitems, int hs, T h2) {
-  const int lane = threadIdx.x & 63;
   const int item = xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
   if (item >= nitems) return;
-  const int band = item % nbands, seg = item / nbands;
-  const int xw = band * kUpOwned - kUpHalo;
-  const int x0 = xw + 2 * lane;
-  const int ys = seg * hs;
-  const Cols<BC> col(x0, n);
-  const int N = n - 1, nc = (n - 1) / 2 + 1;
-  const bool lane_owns = lane >= kUpHalo / 2 && lane < kUpHalo / 2 + kUpOwned / 2;
-  const bool wr0 = lane_owns && (BC == kPeriodic ? x0 < N : col.unk0);
-  const bool wr1 = lane_owns && (BC == kPeriodic ? x0 + 1 < N : col.unk1);
-  const int Jc = x0 >> 1;
-  const int row_end = BC == kPeriodic ? N : n;
-
-  T U[16][2], F[16][2], CX[4][2], CR[8];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) U[k][0] = U[k][1] = F[k][0] = F[k][1] = T(0);
-
-  const int t0 = ys - 4;            // even
-  const int cbase = (t0 >> 1) - 1;  // coarse row q = 0 of the ring
-  // Raw coefficients (lane L: column x0/2) of coarse row cbase + q live in
-  // CR[q & 7], loaded 4 coarse rows ahead; CX[q & 3] holds their spline
-  // along x at the lane's two columns.
-#pragma unroll
-  for (int q = 0; q < 7; ++q) CR[q] = load_coef<T, BC>(c, pc, cbase + q, Jc, nc);
-  CR[7] = T(0);
-#pragma unroll
-  for (int q = 0; q < 3; ++q) spline_x<T>(CR[q], CX[q]);
-  CX[3][0] = CX[3][1] = T(0);
-  const int steps = hs + 8;
-#pragma unroll
-  for (int k = 0; k < kAhead; ++k) {
-    load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
-    load_row<T, BC>(F[k], f, pf, t0 + k, n, col);
-  }
-  for (int sb = 0; sb < steps; sb += 16) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int s = sb + k;
-      if (s >= steps) break;
-      const int t = t0 + s;
-      if (s + kAhead < steps) {
-        load_row<T, BC>(U[(k + kAhead) & 15], uin, pui, t + kAhead, n, col);
-        load_row<T, BC>(F[(k + kAhead) & 15], f, pf, t + kAhead, n, col);
-      }
-      // coarse row q = (s - 1)/2 + 3 is needed from the first odd step on
-      if (k & 1) {
-        const int qk = ((k - 1) >> 1) + 3;  // q mod 8
-        spline_x<T>(CR[qk & 7], CX[qk & 3]);
-        CR[(qk + 4) & 7] = load_coef<T, BC>(c, pc, cbase + ((s - 1) >> 1) + 7, Jc, nc);
-      }
-      {
-        // u += P e_c on row t: coincident rows (1, 4, 1)/6 on coarse rows
-        // base..base+2, midpoints (1, 23, 23, 1)/48 on base..base+3.
-        const int qb = (k >> 1);  // coarse row (t >> 1) - 1 relative to cbase, mod 8
-        T v0, v1;
-        const T(&a)[2] = CX[qb & 3];
-        const T(&b)[2] = CX[(qb + 1) & 3];
-        const T(&d)[2] = CX[(qb + 2) & 3];
-        if ((k & 1) == 0) {
-          v0 = (T(1.0 / 6.0) * a[0] + T(4.0 / 6.0) * b[0]) + T(1.0 / 6.0) * d[0];
-          v1 = (T(1.0 / 6.0) * a[1] + T(4.0 / 6.0) * b[1]) + T(1.0 / 6.0) * d[1];
-        } else {
-          const T(&e)[2] = CX[(qb + 3) & 3];
-          v0 = ((T(1.0 / 48.0) * a[0] + T(23.0 / 48.0) * b[0]) + T(23.0 / 48.0) * d[0]) +
-               T(1.0 / 48.0) * e[0];
-          v1 = ((T(1.0 / 48.0) * a[1] + T(23.0 / 48.0) * b[1]) + T(23.0 / 48.0) * d[1]) +
-               T(1.0 / 48.0) * e[1];
-        }
-        const bool rok = row_unknown<BC>(t, n);
-        if (rok && col.unk0) U[k][0] += v0;
-        if (rok && col.unk1) U[k][1] += v1;
-      }
-      sweep_row<T, BC>(U[(k + 14) & 15], U[(k + 15) & 15], U[k], F[(k + 15) & 15], t - 1, 0, n,
-                       col, h2);
-      sweep_row<T, BC>(U[(k + 13) & 15], U[(k + 14) & 15], U[(k + 15) & 15], F[(k + 14) & 15],
-                       t - 2, 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 12) & 15], U[(k + 13) & 15], U[(k + 14) & 15], F[(k + 13) & 15],
-                       t - 3, 0, n, col, h2);
-      sweep_row<T, BC>(U[(k + 11) & 15], U[(k + 12) & 15], U[(k + 13) & 15], F[(k + 12) & 15],
-                       t - 4, 1, n, col, h2);
-      const int tu = t - 4;
-      if (tu >= ys && tu < ys + hs && tu < row_end) {
-        T* p = uout + (size_t)tu * puo;
-        if (wr0) p[x0] = U[(k + 12) & 15][0];
-        if (wr1) p[x0 + 1] = U[(k + 12) & 15][1];
-      }
-    }
-  }
+  up_wave<T, BC>(n, uin, pui, uout, puo, f, pf, c, pc, item % nbands, item / nbands, hs, h2,
+                 threadIdx.x & 63);
 }
 
 }  // namespace
@@ -355,6 +41,9 @@ int stream_segment_rows(int n, int bc, int owned_cols) {
   while (hs > 8 && (long)nb * ((extent + hs - 1) / hs) < 1024) hs -= 8;
   return hs;
 }
+
+int stream_down_owned() { return kDownOwned; }
+int stream_up_owned() { return kUpOwned; }
 
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,

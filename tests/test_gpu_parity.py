@@ -390,3 +390,99 @@ def test_unreachable_tolerance_reports_stagnation(B, dev):
         assert rel[0] < 1e-12 and cyc[0] < 60
     finally:
         B.mg_destroy(ctx)
+
+
+# ------------------------------------------------------- persistent schedule --
+
+def batch_ctx(B, specs, precision, schedule):
+    o = B.mg_options_default()
+    o.precision = precision
+    o.schedule = schedule
+    return B.mg_setup([(n, bc, 0) for n, bc in specs], o, torch.cuda.current_stream().cuda_stream)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("bc,sizes", [(P, [33, 129, 65, 257, 513, 9]), (D, [257, 65, 1025, 129])])
+def test_persistent_batch_step_parity(B, dev, precision, bc, sizes):
+    """One persistent launch steps every problem of an uneven batch; each
+    problem's step matches the oracle's."""
+    say(f"persistent batch precision={precision} bc={bc} sizes={sizes}")
+    specs = [(n, bc) for n in sizes]
+    fs = [make_rhs(n, bc, 20 + k) for k, n in enumerate(sizes)]
+    ctx = batch_ctx(B, specs, precision, 2)
+    try:
+        fts = [gpu(f, dev) for f in fs]
+        us = [np.zeros_like(f) for f in fs]
+        for step in range(2):
+            uts = [gpu(u, dev) for u in us]
+            B.mg_vcycle(ctx, [t.data_ptr() for t in uts], [t.data_ptr() for t in fts], 1)
+            for k, (n, _) in enumerate(specs):
+                got = host(uts[k])
+                if precision == 0:
+                    ref = oracle.vcycle(us[k], fs[k], bc)
+                    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+                    bound = 1e-12
+                else:
+                    ref = oracle.refine_step(us[k], fs[k], bc)
+                    err = np.linalg.norm(got - ref) / np.linalg.norm(ref - us[k])
+                    bound = 1e-5
+                say(f"  step {step + 1} n={n}: {err:.2e}")
+                assert err <= bound
+                us[k] = ref
+    finally:
+        B.mg_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_batch_solve(B, dev, precision):
+    """Batched solve with the persistent schedule: every problem reaches
+    1e-10 in the oracle's number of cycles (+-1), problems stopping
+    independently, and matches the oracle's solution."""
+    sizes = [129, 1025, 257, 129, 513, 257, 1025, 513]
+    say(f"persistent batch solve precision={precision}")
+    specs = [(n, P) for n in sizes]
+    fs = [workloads.rhs_divu_periodic(n, 1000 + k) for k, n in enumerate(sizes)]
+    ctx = batch_ctx(B, specs, precision, 2)
+    try:
+        fts = [gpu(f, dev) for f in fs]
+        uts = [torch.zeros_like(t) for t in fts]
+        st, cyc, rel = B.mg_solve(ctx, [t.data_ptr() for t in uts], [t.data_ptr() for t in fts],
+                                  1e-10, 30)
+        assert st == 0
+        for k, f in enumerate(fs):
+            if precision == 0:
+                uo, co, ho = oracle.solve(f, P, rtol=1e-10, max_cycles=30)
+            else:
+                uo, co, ho = oracle.solve_mixed(f, P, rtol=1e-10, max_steps=30)
+            say(f"  n={sizes[k]} cycles={cyc[k]} (oracle {co}) relres={rel[k]:.2e}")
+            assert rel[k] <= 1e-10 and abs(cyc[k] - co) <= 1
+            got = host(uts[k])
+            uo = zero_mean(uo)
+            assert np.linalg.norm(got - uo) <= 1e-9 * np.linalg.norm(uo)
+    finally:
+        B.mg_destroy(ctx)
+
+
+def test_persistent_matches_per_problem_schedule(B, dev):
+    sizes = [257, 65, 513]
+    specs = [(n, P) for n in sizes]
+    fs = [workloads.rhs_divu_periodic(n, 7 + k) for k, n in enumerate(sizes)]
+    outs = []
+    for schedule in (1, 2):
+        ctx = batch_ctx(B, specs, 1, schedule)
+        fts = [gpu(f, dev) for f in fs]
+        uts = [torch.zeros_like(t) for t in fts]
+        rel = B.mg_vcycle(ctx, [t.data_ptr() for t in uts], [t.data_ptr() for t in fts], 3, True)
+        outs.append(([host(t) for t in uts], rel))
+        B.mg_destroy(ctx)
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(a)
+    np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=1e-6)
+
+
+def test_persistent_rejects_mixed_boundary_conditions(B, dev):
+    o = B.mg_options_default()
+    o.schedule = 2
+    with pytest.raises(B.MGError) as ei:
+        B.mg_setup([(65, P, 0), (65, D, 0)], o, 0)
+    assert ei.value.status == B.MG_ERR_UNSUPPORTED
