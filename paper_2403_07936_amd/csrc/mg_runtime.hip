@@ -10,6 +10,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -122,6 +124,9 @@ struct Problem {
   hipGraphExec_t graph = nullptr;
   const double* graph_u = nullptr;
   const double* graph_f = nullptr;
+  // Kernel choice per level (autotuned): variant 0 = register streaming with
+  // `hs` rows per segment (0 = default), 1 = LDS tiles.
+  std::vector<int> down_var, down_hs, up_var, up_hs;
 };
 
 }  // namespace mg
@@ -157,7 +162,6 @@ struct Persist {
 
 struct mg_ctx_s {
   mg::Persist ps;
-  int seg_rows = 0;  // rows per wavefront segment of the streaming passes (0 = per level)
   bool timing = false;
   std::vector<mg::TimingRec> recs;
   std::vector<hipEvent_t> pool;
@@ -320,11 +324,11 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
     const T* uin = (l == 0 && !zero_guess) ? u0 : nullptr;
     const double bytes = ((uin ? 3 : 2) * m * m + mc * mc) * sz;
     MG_TRY(timed(ctx, s, MG_K_DOWN, l, bytes, [&] {
-      if (ctx->opt.kernel_path == 2)
+      if (ctx->opt.kernel_path == 2 || p.down_var[l] == 1)
         return launch_down<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l), h.f[l + 1],
                               p.pitch[l + 1]);
       return launch_down_stream<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l),
-                                   h.f[l + 1], p.pitch[l + 1], ctx->seg_rows);
+                                   h.f[l + 1], p.pitch[l + 1], p.down_hs[l]);
     }));
   }
   {
@@ -348,10 +352,10 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
     T* uout = l == 0 ? u0 : h.u[l];
     const int puo = l == 0 ? pu0 : p.pitch[l];
     MG_TRY(timed(ctx, s, MG_K_UP, l, (3 * m * m + ncc) * sz, [&] {
-      if (ctx->opt.kernel_path == 2)
+      if (ctx->opt.kernel_path == 2 || p.up_var[l] == 1)
         return launch_up<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l), h.c[l + 1], pc);
       return launch_up_stream<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l),
-                                 h.c[l + 1], pc, ctx->seg_rows);
+                                 h.c[l + 1], pc, p.up_hs[l]);
     }));
   }
   return MG_OK;
@@ -684,6 +688,303 @@ int32_t persistent_relres(mg_ctx_s* ctx, double* rel) {
   return MG_OK;
 }
 
+// ----------------------------------------------------------------- autotuner
+//
+// Choices are keyed by (GPU architecture, cycle precision, boundary
+// condition, level side) for the per-level kernels, and by the batch's
+// signature for the schedule.  They live in a process-wide table and, when
+// tune_cache_path is set, in a text file of lines
+//   L <arch> <fp32|fp64> <bc> <n> <down_var> <down_hs> <up_var> <up_hs> <us>
+//   S <arch> <fp32|fp64> <bc> <batch signature> <schedule>
+// read at setup and appended when new choices are measured.
+
+struct LevelChoice {
+  int down_var = 0, down_hs = 0, up_var = 0, up_hs = 0;
+};
+
+std::mutex& tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+std::map<std::string, LevelChoice>& level_table() {
+  static std::map<std::string, LevelChoice> t;
+  return t;
+}
+std::map<std::string, int>& schedule_table() {
+  static std::map<std::string, int> t;
+  return t;
+}
+
+std::string device_arch(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+void load_tune_file(const char* path) {
+  if (!path) return;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, fp)) {
+    char kind[4], arch[64], prec[8], sig[256];
+    int bc = 0, n = 0, dv = 0, dh = 0, uv = 0, uh = 0, sched = 0;
+    double us = 0.0;
+    if (std::sscanf(line, "%3s", kind) != 1) continue;
+    if (kind[0] == 'L' &&
+        std::sscanf(line, "L %63s %7s %d %d %d %d %d %d %lf", arch, prec, &bc, &n, &dv, &dh, &uv,
+                    &uh, &us) == 9) {
+      LevelChoice c;
+      c.down_var = dv;
+      c.down_hs = dh;
+      c.up_var = uv;
+      c.up_hs = uh;
+      level_table()[std::string(arch) + " " + prec + " " + std::to_string(bc) + " " +
+                    std::to_string(n)] = c;
+    } else if (kind[0] == 'S' &&
+               std::sscanf(line, "S %63s %7s %d %255s %d", arch, prec, &bc, sig, &sched) == 5) {
+      schedule_table()[std::string(arch) + " " + prec + " " + std::to_string(bc) + " " + sig] =
+          sched;
+    }
+  }
+  std::fclose(fp);
+}
+
+void append_tune_file(const char* path, const std::string& line) {
+  if (!path) return;
+  FILE* fp = std::fopen(path, "a");
+  if (!fp) return;
+  std::fputs(line.c_str(), fp);
+  std::fclose(fp);
+}
+
+// Mean time of `reps` launches of `launch` on the context's stream (ms).
+template <class Launch>
+int32_t time_launches(mg_ctx_s* ctx, int reps, Launch&& launch, float* ms) {
+  hipEvent_t a = take_event(ctx), b = take_event(ctx);
+  if (!a || !b) return fail(MG_ERR_HIP, "hipEventCreate failed");
+  MG_HIP(launch());  // warm-up
+  MG_HIP(hipEventRecord(a, ctx->stream));
+  for (int r = 0; r < reps; ++r) MG_HIP(launch());
+  MG_HIP(hipEventRecord(b, ctx->stream));
+  MG_HIP(hipEventSynchronize(b));
+  MG_HIP(hipEventElapsedTime(ms, a, b));
+  *ms /= reps;
+  ctx->pool_used -= 2;
+  return MG_OK;
+}
+
+// Per-level kernel choice: the streaming passes with several segment heights
+// against the LDS-tiled passes, each timed on the level's own arrays (the
+// level-0 caller arrays are stood in for by library arrays of the same
+// shape).  Values do not matter to the timing.
+template <typename T>
+int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scratch_u, T* scratch_f,
+                    int pitch0) {
+  const Hierarchy<T>& h = hier<T>(p);
+  const bool mixed = ctx->opt.precision == MG_MIXED;
+  const char* prec = sizeof(T) == 8 ? "fp64" : "fp32";
+  for (int l = 0; l < p.tail; ++l) {
+    const int n = p.side[l];
+    const std::string key = arch + " " + prec + " " + std::to_string(p.bc) + " " + std::to_string(n);
+    {
+      std::lock_guard<std::mutex> lk(tune_mutex());
+      auto it = level_table().find(key);
+      if (it != level_table().end()) {
+        p.down_var[l] = it->second.down_var;
+        p.down_hs[l] = it->second.down_hs;
+        p.up_var[l] = it->second.up_var;
+        p.up_hs[l] = it->second.up_hs;
+        continue;
+      }
+    }
+    T* u = l == 0 ? scratch_u : h.u[l];
+    const T* f = l == 0 ? scratch_f : h.f[l];
+    const int pu = l == 0 ? pitch0 : p.pitch[l];
+    const T* uin = (l == 0 && !mixed) ? u : nullptr;
+    const int reps = n >= 2049 ? 3 : 6;
+    const int hs_cands[] = {0, 8, 16, 32, 64};
+    float best_d = 1e30f, best_u = 1e30f, us_total = 0.f;
+    LevelChoice c;
+    for (int var = 0; var < 2; ++var)
+      for (int hs : hs_cands) {
+        if (var == 1 && hs != 0) continue;
+        float md = 0.f, mu = 0.f;
+        MG_TRY(time_launches(ctx, reps, [&] {
+          return var == 1 ? launch_down<T>(ctx->stream, p.bc, n, uin, pu, h.r[l], p.pitch[l], f, pu,
+                                           h.f[l + 1], p.pitch[l + 1])
+                          : launch_down_stream<T>(ctx->stream, p.bc, n, uin, pu, h.r[l],
+                                                  p.pitch[l], f, pu, h.f[l + 1], p.pitch[l + 1], hs);
+        }, &md));
+        MG_TRY(time_launches(ctx, reps, [&] {
+          return var == 1 ? launch_up<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu, f, pu,
+                                         h.c[l + 1], p.pitch[l + 1])
+                          : launch_up_stream<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu, f,
+                                                pu, h.c[l + 1], p.pitch[l + 1], hs);
+        }, &mu));
+        if (md < best_d) {
+          best_d = md;
+          c.down_var = var;
+          c.down_hs = hs;
+        }
+        if (mu < best_u) {
+          best_u = mu;
+          c.up_var = var;
+          c.up_hs = hs;
+        }
+      }
+    us_total = 1e3f * (best_d + best_u);
+    p.down_var[l] = c.down_var;
+    p.down_hs[l] = c.down_hs;
+    p.up_var[l] = c.up_var;
+    p.up_hs[l] = c.up_hs;
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    level_table()[key] = c;
+    char line[256];
+    std::snprintf(line, sizeof line, "L %s %s %d %d %d %d %d %d %.2f\n", arch.c_str(), prec, p.bc,
+                  n, c.down_var, c.down_hs, c.up_var, c.up_hs, us_total);
+    append_tune_file(ctx->opt.tune_cache_path, line);
+  }
+  // The level arrays used as stand-ins were overwritten: clear them again.
+  for (int l = 0; l < p.levels; ++l) {
+    if (h.u[l]) MG_HIP(launch_zero<T>(ctx->stream, p.side[l], h.u[l], p.pitch[l]));
+    if (h.r[l]) MG_HIP(launch_zero<T>(ctx->stream, p.side[l], h.r[l], p.pitch[l]));
+  }
+  return MG_OK;
+}
+
+// Runs the autotuner for every problem (per-level kernels), then, for
+// batches that may use it, picks the schedule by timing a few steps of each.
+int32_t autotune(mg_ctx_s* ctx) {
+  const bool mixed = ctx->opt.precision == MG_MIXED;
+  const std::string arch = device_arch(ctx->device);
+  {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    static std::string loaded;
+    if (ctx->opt.tune_cache_path && loaded != ctx->opt.tune_cache_path) {
+      load_tune_file(ctx->opt.tune_cache_path);
+      loaded = ctx->opt.tune_cache_path;
+    }
+  }
+  // Level-0 stand-ins: the largest level-0 shape of the batch.
+  size_t elems = 0;
+  int pitch0 = 0;
+  for (const auto& p : ctx->probs) {
+    elems = std::max(elems, (size_t)p.n * p.pitch[0]);
+    pitch0 = std::max(pitch0, p.pitch[0]);
+  }
+  void* su = nullptr;
+  void* sf = nullptr;
+  const size_t bytes = elems * (mixed ? sizeof(float) : sizeof(double));
+  if (hipMalloc(&su, bytes) != hipSuccess || hipMalloc(&sf, bytes) != hipSuccess) {
+    if (su) (void)hipFree(su);
+    (void)hipGetLastError();
+    return fail(MG_ERR_OOM, "autotuner scratch allocation failed");
+  }
+  int32_t st = MG_OK;
+  if (hipMemsetAsync(su, 0, bytes, ctx->stream) != hipSuccess ||
+      hipMemsetAsync(sf, 0, bytes, ctx->stream) != hipSuccess)
+    st = fail(MG_ERR_HIP, "autotuner scratch clear failed");
+  for (auto& p : ctx->probs) {
+    if (st != MG_OK) break;
+    st = mixed ? tune_levels<float>(ctx, p, arch, (float*)su, (float*)sf, p.pitch[0])
+               : tune_levels<double>(ctx, p, arch, (double*)su, (double*)sf, p.pitch[0]);
+  }
+  if (st == MG_OK && hipStreamSynchronize(ctx->stream) != hipSuccess)
+    st = fail(MG_ERR_HIP, "autotuner synchronisation failed");
+  (void)hipFree(su);
+  (void)hipFree(sf);
+  return st;
+}
+
+// Batch schedule: per-problem graphs against the persistent launch, each
+// timed over a few steps on library-owned arrays of the callers' shapes.
+int32_t tune_schedule(mg_ctx_s* ctx) {
+  const int B = (int)ctx->probs.size();
+  std::string why;
+  if (B < 2 || !persistent_eligible(ctx, &why)) return MG_OK;
+  const bool mixed = ctx->opt.precision == MG_MIXED;
+  unsigned long long hsh = 1469598103934665603ULL;  // FNV-1a over the sizes
+  for (const auto& p : ctx->probs) {
+    hsh ^= (unsigned long long)p.n;
+    hsh *= 1099511628211ULL;
+  }
+  char sig[64];
+  std::snprintf(sig, sizeof sig, "B%d:%016llx", B, hsh);
+  const std::string arch = device_arch(ctx->device);
+  const char* prec = mixed ? "fp32" : "fp64";
+  const int bc = ctx->probs[0].bc;
+  const std::string key = arch + " " + prec + " " + std::to_string(bc) + " " + sig;
+  int choice = -1;
+  {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    auto it = schedule_table().find(key);
+    if (it != schedule_table().end()) choice = it->second;
+  }
+  if (choice == 1) return MG_OK;
+  MG_TRY(mixed ? build_persistent<float>(ctx) : build_persistent<double>(ctx));
+  if (choice == 2) return MG_OK;
+
+  // Stand-in arrays (zeros: the work per step does not depend on values).
+  std::vector<size_t> off(B + 1, 0);
+  for (int b = 0; b < B; ++b)
+    off[b + 1] = off[b] + ((size_t)ctx->probs[b].n * ctx->probs[b].pitch0 + 63) / 64 * 64;
+  double* buf = nullptr;
+  if (hipMalloc(&buf, 2 * off[B] * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return MG_OK;  // not enough memory to measure: keep the persistent schedule
+  }
+  std::vector<double*> us(B);
+  std::vector<const double*> fs(B);
+  for (int b = 0; b < B; ++b) {
+    us[b] = buf + off[b];
+    fs[b] = buf + off[B] + off[b];
+  }
+  int32_t st = MG_OK;
+  float t_graph = 0.f, t_pers = 0.f;
+  auto per_problem = [&]() -> hipError_t {
+    for (int b = 0; b < B; ++b)
+      if (run_step(ctx, ctx->probs[b], us[b], fs[b]) != MG_OK) return hipErrorUnknown;
+    return hipSuccess;
+  };
+  auto persistent = [&]() -> hipError_t {
+    if (persistent_bind(ctx, us.data(), fs.data(), {}) != MG_OK ||
+        persistent_launch(ctx) != MG_OK)
+      return hipErrorUnknown;
+    return hipSuccess;
+  };
+  if (hipMemsetAsync(buf, 0, 2 * off[B] * sizeof(double), ctx->stream) != hipSuccess)
+    st = fail(MG_ERR_HIP, "clear of the schedule stand-ins failed");
+  if (st == MG_OK) st = time_launches(ctx, 2, per_problem, &t_graph);
+  if (st == MG_OK) st = time_launches(ctx, 2, persistent, &t_pers);
+  if (st == MG_OK) {
+    std::vector<double> rel(B);
+    st = persistent_relres(ctx, rel.data());  // also reports a timed-out barrier
+  }
+  for (auto& p : ctx->probs)
+    if (p.graph) {
+      (void)hipGraphExecDestroy(p.graph);
+      p.graph = nullptr;
+    }
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(buf);
+  if (st != MG_OK) return st;
+  choice = t_pers < t_graph ? 2 : 1;
+  if (choice == 1) {
+    if (ctx->ps.graph) (void)hipGraphExecDestroy(ctx->ps.graph);
+    ctx->ps.graph = nullptr;
+    ctx->ps.on = false;
+  }
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  schedule_table()[key] = choice;
+  char line[256];
+  std::snprintf(line, sizeof line, "S %s %s %d %s %d\n", arch.c_str(), prec, bc, sig, choice);
+  append_tune_file(ctx->opt.tune_cache_path, line);
+  return MG_OK;
+}
+
 int32_t destroy_ctx(mg_ctx_s* ctx) {
   if (!ctx) return MG_OK;
   (void)hipSetDevice(ctx->device);
@@ -792,6 +1093,10 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
     }
     p.tail = 0;
     while (p.side[p.tail] > kTailMaxSide) ++p.tail;
+    p.down_var.assign(L, 0);
+    p.up_var.assign(L, 0);
+    p.down_hs.assign(L, 0);
+    p.up_hs.assign(L, 0);
     {
       const size_t tb = sizeof(PrefilterTaps) * (size_t)L;
       unsigned char* d = nullptr;
@@ -844,6 +1149,11 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
   }
   if (hipStreamSynchronize(ctx->stream) != hipSuccess)
     return bail(fail(MG_ERR_HIP, "hipStreamSynchronize after setup"));
+  if (opt->schedule == 0 && opt->kernel_path == 0) {
+    int32_t st = autotune(ctx);
+    if (st == MG_OK) st = tune_schedule(ctx);
+    if (st != MG_OK) return bail(st);
+  }
   if (opt->schedule == 2) {
     std::string why;
     if (!persistent_eligible(ctx, &why)) return bail(fail(MG_ERR_UNSUPPORTED, why));

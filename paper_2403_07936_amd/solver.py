@@ -18,9 +18,12 @@ BCS = {"dirichlet": B.MG_BC_DIRICHLET0, "periodic": B.MG_BC_PERIODIC}
 class Solver:
     def __init__(self, grids, precision: str = "fp64", nu_pre: int = 2, nu_post: int = 2,
                  inner_cycles: int = 1, use_graph: bool = True, check_every: int = 0,
-                 pitch=None, stream: torch.cuda.Stream | None = None):
+                 pitch=None, stream: torch.cuda.Stream | None = None, schedule: int = 0,
+                 kernel_path: int = 0, tune_cache_path: str | None = None):
         """grids: sequence of (n, bc) with bc 0/1 or "dirichlet"/"periodic".
-        pitch: optional sequence of row pitches (elements) of the level-0 arrays."""
+        pitch: optional sequence of row pitches (elements) of the level-0 arrays.
+        schedule: 0 autotuned, 1 per-problem graphs, 2 one persistent launch per step.
+        tune_cache_path: optional text file the autotuner reads and appends to."""
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = B.mg_options_default()
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -28,6 +31,10 @@ class Solver:
         opt.inner_cycles = inner_cycles
         opt.use_graph = int(bool(use_graph))
         opt.check_every = check_every
+        opt.schedule = schedule
+        opt.kernel_path = kernel_path
+        self._cache_path = tune_cache_path.encode() if tune_cache_path else None
+        opt.tune_cache_path = self._cache_path
         self.grids = [(int(n), BCS[bc] if isinstance(bc, str) else int(bc)) for n, bc in grids]
         pitches = list(pitch) if pitch is not None else [0] * len(self.grids)
         self.pitch = [p if p else n for (n, _), p in zip(self.grids, pitches)]

@@ -486,3 +486,98 @@ def test_persistent_rejects_mixed_boundary_conditions(B, dev):
     with pytest.raises(B.MGError) as ei:
         B.mg_setup([(65, P, 0), (65, D, 0)], o, 0)
     assert ei.value.status == B.MG_ERR_UNSUPPORTED
+
+
+# ----------------------------------------------------------------- autotuner --
+
+def device_arch():
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def read_tune_file(path):
+    lines = [ln.split() for ln in open(path).read().splitlines() if ln.strip()]
+    return [ln for ln in lines if ln[0] == "L"], [ln for ln in lines if ln[0] == "S"]
+
+
+def run_cycles(B, ctx, fs, dev, k):
+    fts = [gpu(f, dev) for f in fs]
+    uts = [torch.zeros_like(t) for t in fts]
+    B.mg_vcycle(ctx, [t.data_ptr() for t in uts], [t.data_ptr() for t in fts], k)
+    return [host(t) for t in uts]
+
+
+def test_autotune_writes_and_reuses_cache(B, dev, tmp_path):
+    """schedule 0 measures a kernel choice for every streamed level and a
+    schedule for the batch, records them in the cache file, reuses them on
+    the next setup, and steps the same as the untuned per-problem schedule."""
+    path = str(tmp_path / "tune.txt")
+    sizes = [1025, 257, 513]
+    specs = [(n, D) for n in sizes]
+    fs = [make_rhs(n, D, 40 + k) for k, n in enumerate(sizes)]
+    o = B.mg_options_default()
+    o.tune_cache_path = path.encode()
+    ctx = B.mg_setup([(n, bc, 0) for n, bc in specs], o, torch.cuda.current_stream().cuda_stream)
+    try:
+        tuned = run_cycles(B, ctx, fs, dev, 2)
+    finally:
+        B.mg_destroy(ctx)
+    lv, sc = read_tune_file(path)
+    arch = device_arch()
+    tuned_sides = {int(ln[4]) for ln in lv if ln[1] == arch and ln[2] == "fp64" and ln[3] == "0"}
+    # Every level above the single-workgroup tail (65) was measured, unless an
+    # earlier setup in this process already had it.
+    assert tuned_sides <= {1025, 513, 257, 129}
+    for ln in lv:
+        assert ln[5] in ("0", "1") and ln[7] in ("0", "1")
+        assert int(ln[6]) in (0, 8, 16, 32, 64) and int(ln[8]) in (0, 8, 16, 32, 64)
+    assert len(sc) == 1 and sc[0][1] == arch and sc[0][4].startswith("B3:")
+    assert sc[0][5] in ("1", "2")
+    say(f"tuned: {[' '.join(ln) for ln in lv + sc]}")
+    # Second setup: everything comes from the cache, nothing is appended.
+    before = open(path).read()
+    ctx = B.mg_setup([(n, bc, 0) for n, bc in specs], o, torch.cuda.current_stream().cuda_stream)
+    B.mg_destroy(ctx)
+    assert open(path).read() == before
+    ctx = batch_ctx(B, specs, 0, 1)
+    try:
+        ref = run_cycles(B, ctx, fs, dev, 2)
+    finally:
+        B.mg_destroy(ctx)
+    for a, b in zip(tuned, ref):
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotune_cache_forces_variants(B, dev, tmp_path, precision):
+    """Choices read from a cache file are applied: the LDS-tiled down pass
+    and fixed segment heights on the streamed levels give the oracle's
+    cycle."""
+    n, bc = 2049, P
+    prec = "fp64" if precision == 0 else "fp32"
+    path = tmp_path / "tune.txt"
+    text = "".join(f"L {device_arch()} {prec} {bc} {m} 1 0 0 {hs} 0\n"
+                   for m, hs in ((2049, 16), (1025, 8), (513, 32), (257, 64), (129, 8)))
+    path.write_text(text)
+    o = B.mg_options_default()
+    o.precision = precision
+    o.tune_cache_path = str(path).encode()
+    f = make_rhs(n, bc, 77)
+    u0 = zero_mean(make_rhs(n, bc, 78))
+    ctx = B.mg_setup([(n, bc, 0)], o, torch.cuda.current_stream().cuda_stream)
+    try:
+        ut, ft = gpu(u0, dev), gpu(f, dev)
+        B.mg_vcycle(ctx, [ut.data_ptr()], [ft.data_ptr()], 1)
+        got = host(ut)
+    finally:
+        B.mg_destroy(ctx)
+    assert path.read_text() == text  # nothing measured: all came from the file
+    if precision == 0:
+        ref = oracle.vcycle(u0, f, bc)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        bound = 1e-12
+    else:
+        ref = oracle.refine_step(u0, f, bc)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref - u0)
+        bound = 1e-5
+    say(f"forced variants n={n} precision={precision}: {err:.2e}")
+    assert err <= bound
