@@ -41,15 +41,16 @@ def measured_traffic(kind_name: str, precision: str, bc: int):
     if kind_name not in names or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, rec["source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+    if "sources" not in rec:
+        return None
+    hh = hashlib.sha256()
+    for src in rec["sources"]:
+        hh.update(open(os.path.join(ROOT, src), "rb").read())
+    if hh.hexdigest() != rec["sources_sha256"]:
         return None
     t = "float" if precision == "mixed" else "double"
-    prefix = f"{names[kind_name]}<{t}, {bc}>@"
-    cands = [(int(k.split("@")[1]), v) for k, v in rec["per_launch"].items() if k.startswith(prefix)]
-    if not cands:
-        return None
-    return round(max(cands)[1]["bytes"], 0)
+    ent = rec["per_launch"].get(f"{names[kind_name]}<{t}, {bc}>")
+    return None if ent is None else round(ent["bytes"], 0)
 
 
 def parse():

@@ -824,12 +824,14 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
                           : launch_up_stream<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu, f,
                                                 pu, h.c[l + 1], p.pitch[l + 1], hs);
         }, &mu));
-        if (md < best_d) {
+        // A candidate replaces the current best only when it is more than 3%
+        // faster, so that near-ties keep the default and choices stay stable.
+        if (md < 0.97f * best_d) {
           best_d = md;
           c.down_var = var;
           c.down_hs = hs;
         }
-        if (mu < best_u) {
+        if (mu < 0.97f * best_u) {
           best_u = mu;
           c.up_var = var;
           c.up_hs = hs;
