@@ -149,8 +149,11 @@ def coarsest_inverse(bc: int) -> np.ndarray:
     return np.linalg.inv(A) if bc == DIRICHLET else np.linalg.pinv(A)
 
 
-def vcycle(u: np.ndarray, f: np.ndarray, n: int, bc: int, nu1: int = 2, nu2: int = 2) -> np.ndarray:
-    """One V(nu1, nu2) cycle from the dense pieces above."""
+def vcycle(u: np.ndarray, f: np.ndarray, n: int, bc: int, nu1: int = 2, nu2: int = 2,
+           prolong=None, levels: int = 0) -> np.ndarray:
+    """One V(nu1, nu2) cycle from the dense pieces above.  prolong (optional):
+    a function (coarse vector, nc) -> fine vector used instead of the spline
+    on the `levels` finest prolongations."""
     if n == 5:
         return coarsest_inverse(bc) @ f
     for _ in range(nu1):
@@ -159,8 +162,11 @@ def vcycle(u: np.ndarray, f: np.ndarray, n: int, bc: int, nu1: int = 2, nu2: int
     r = f - operator(n, bc) @ u
     fc = full_weighting(n, bc) @ r
     nc = (n - 1) // 2 + 1
-    uc = vcycle(np.zeros_like(fc), fc, nc, bc, nu1, nu2)
-    u = u + spline_prolong(nc, bc) @ uc
+    uc = vcycle(np.zeros_like(fc), fc, nc, bc, nu1, nu2, prolong, levels - 1)
+    if prolong is not None and levels > 0:
+        u = u + prolong(uc, nc)
+    else:
+        u = u + spline_prolong(nc, bc) @ uc
     for _ in range(nu2):
         u = half_sweep(u, f, n, bc, 0)
         u = half_sweep(u, f, n, bc, 1)
