@@ -95,8 +95,9 @@ typedef struct {
   int32_t inner_cycles;       /* MG_MIXED: FP32 cycles per refinement step (1) */
   int32_t prolong;            /* MG_PROLONG_SPLINE (default) or MG_PROLONG_SRCNN */
   int32_t cnn_levels;         /* SR-CNN on this many finest prolongations (2) */
-  const void* cnn_weights;    /* host blob of SR-CNN weights, copied at setup */
-  size_t cnn_weights_bytes;
+  const void* cnn_weights;    /* host blob of SR-CNN weights, copied at setup:
+                                 MG_SRCNN_WEIGHT_COUNT float32 values (see below) */
+  size_t cnn_weights_bytes;   /* 4 * MG_SRCNN_WEIGHT_COUNT */
   int32_t check_every;        /* mg_solve: cycles between norm checks; 0 = auto */
   int32_t use_graph;          /* capture each cycle into a hipGraph (1) */
   const char* tune_cache_path; /* autotuner cache file; NULL = built-in choices */
@@ -108,7 +109,18 @@ typedef struct {
                                  2: one persistent launch per cycle for the whole batch
                                  (all problems must share the boundary condition; needs
                                  kernel_path 0, nu_pre = nu_post = 2, inner_cycles = 1). */
+  double cnn_max_ratio;       /* mg_solve with SR-CNN: after a network-prolongated cycle whose
+                                 residual ratio exceeds this (0.5), use the spline from then on */
+  double cnn_min_relres;      /* ... and likewise once the relative residual is <= this (1e-7) */
 } mg_options;
+
+/* SR-CNN weights (Section 3.1, generator after Ledig et al.; no biases):
+ * float32, PyTorch (out, in, ky, kx) order, concatenated as
+ *   stem 64x1x3x3, then for each of 8 residual blocks conv1 64x64x3x3 and
+ *   conv2 64x64x3x3, then 256x64x3x3 (followed by the x2 pixel shuffle:
+ *   channel 4c + 2a + b -> channel c at fine offset (a, b)), then 1x64x3x3.
+ * The library rounds them to bfloat16 (nearest even) at setup. */
+#define MG_SRCNN_WEIGHT_COUNT 738432
 
 /* Fill *opt with the defaults listed above.  No-op on NULL. */
 MG_API void mg_options_default(mg_options* opt);
@@ -120,8 +132,9 @@ MG_API void mg_options_default(mg_options* opt);
  * hipStream_t (NULL = default stream) used by every later call.
  * Errors: INVALID_ARG (NULL out/grids/opt, batch <= 0, n not 4*2^k+1,
  * pitch < n, bad enum, nu_pre/nu_post outside 0..8, inner_cycles outside
- * 1..8), UNSUPPORTED (SR-CNN requested without weights or on Dirichlet),
- * OOM, HIP.  On error *out is set to NULL and nothing is leaked. */
+ * 1..8, SR-CNN weights of the wrong size), UNSUPPORTED (SR-CNN requested
+ * without weights, on Dirichlet grids, or with a network level whose coarse
+ * side is below 129), OOM, HIP.  On error *out is set to NULL and nothing is leaked. */
 MG_API int32_t mg_setup(const mg_grid* grids, int32_t batch, const mg_options* opt,
                  void* hip_stream, mg_ctx* out);
 
@@ -132,7 +145,9 @@ MG_API int32_t mg_setup(const mg_grid* grids, int32_t batch, const mg_options* o
  * appendix's V-CYCLE(p, r) is one call with ncycles = 1.  If relres_out is
  * not NULL (host array [batch]) the call synchronises and writes
  * ||f - A u||_2 / ||f||_2 over the unknowns after the last cycle; otherwise
- * it returns after queueing.  Periodic seams of u are rewritten.
+ * it returns after queueing.  Periodic seams of u are rewritten.  With
+ * MG_PROLONG_SRCNN every cycle uses the network on the cnn_levels finest
+ * prolongations.
  * Errors: INVALID_ARG (NULL ctx/u/f or entries, ncycles < 0), HIP,
  * NONFINITE (only when relres_out is given). */
 MG_API int32_t mg_vcycle(mg_ctx ctx, double* const* u, const double* const* f, int32_t ncycles,
@@ -147,7 +162,12 @@ MG_API int32_t mg_vcycle(mg_ctx ctx, double* const* u, const double* const* f, i
  * Returns OK when every problem converged, else the first failure among
  * NOT_CONVERGED (max_cycles hit), STAGNATED (ratio > 0.9 over 3 checks),
  * NONFINITE, INCOMPATIBLE_RHS (periodic f with nonzero mean; nothing run).
- * Problems that converge stop cycling while others continue. */
+ * Problems that converge stop cycling while others continue.  With
+ * MG_PROLONG_SRCNN each problem starts with network-prolongated cycles,
+ * checked after every cycle, and falls back to the spline for the rest of
+ * the solve after a cycle whose residual ratio exceeds cnn_max_ratio or
+ * once the relative residual is <= cnn_min_relres (the paper's switching
+ * threshold S_thres, Table 1 and the appendix's V-CYCLE). */
 MG_API int32_t mg_solve(mg_ctx ctx, double* const* u, const double* const* f, double rtol,
                  int32_t max_cycles, int32_t* cycles_out, double* relres_out);
 
@@ -156,9 +176,11 @@ MG_API int32_t mg_solve(mg_ctx ctx, double* const* u, const double* const* f, do
  * `problem`, from level `coarse_level` (>= 1) to level coarse_level - 1.
  * coarse and fine are device arrays of that problem's level sides, pitch =
  * side, dtype MG_DT_F64 or MG_DT_F32.  kind MG_PROLONG_SPLINE interpolates
- * with the cubic spline; MG_PROLONG_SRCNN applies the SR-CNN.  The result
+ * with the cubic spline; MG_PROLONG_SRCNN applies the SR-CNN (the coarse
+ * unique side nc - 1 must be a multiple of 32, at least 32).  The result
  * is written, not added; periodic seams are written.  Asynchronous.
- * Errors: INVALID_ARG, UNSUPPORTED (SRCNN without weights/Dirichlet), HIP. */
+ * Errors: INVALID_ARG, UNSUPPORTED (SRCNN without weights at setup, or a
+ * coarse side the network kernels do not tile), HIP. */
 MG_API int32_t mg_prolong(mg_ctx ctx, int32_t problem, int32_t coarse_level, int32_t kind,
                    const void* coarse, void* fine, int32_t dtype);
 
@@ -196,6 +218,8 @@ enum {
   MG_K_UP = 11,            /* fused: spline correction + 2 sweeps */
   MG_K_TAIL = 12,          /* fused: all levels <= 65 x 65 in one workgroup */
   MG_K_PERSISTENT = 13,    /* persistent schedule: one whole step of the batch */
+  MG_K_CNN = 14,           /* SR-CNN 64-channel convolutions (matrix cores) */
+  MG_K_CNN_AUX = 15,       /* SR-CNN scale, stem and final convolution */
   MG_K_COUNT = 16
 };
 

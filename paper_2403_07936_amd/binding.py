@@ -61,6 +61,8 @@ class mg_options(ctypes.Structure):
         ("tune_cache_path", ctypes.c_char_p),
         ("kernel_path", i32),
         ("schedule", i32),
+        ("cnn_max_ratio", ctypes.c_double),
+        ("cnn_min_relres", ctypes.c_double),
     ]
 
 
@@ -194,7 +196,14 @@ def mg_num_levels(ctx: int, problem: int) -> int:
     return v
 
 
+MG_K_DOWN = 10
+MG_K_UP = 11
+MG_K_TAIL = 12
+MG_K_PERSISTENT = 13
+MG_K_CNN = 14
+MG_K_CNN_AUX = 15
 MG_K_COUNT = 16
+MG_SRCNN_WEIGHT_COUNT = 738432
 
 
 def mg_timing_enable(ctx: int, enable: bool) -> None:

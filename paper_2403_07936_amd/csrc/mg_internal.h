@@ -126,6 +126,31 @@ hipError_t launch_tail(hipStream_t s, int bc, int nt, const T* uin, int pui, T* 
                        const T* f, int pf, T* cout, int pco, const double* inv,
                        const PrefilterTaps* taps);
 
+// ---- SR-CNN prolongation (mg_srcnn.hip) ------------------------------------
+// Activations are bf16 (stored as unsigned short) in NHWC order with 64
+// channels; N = unique nodes per side of the coarse level (a multiple of 32).
+constexpr int kCnnBlocks = 8;
+constexpr int kCnnWidth = 64;
+constexpr int kCnnConvSet = 9 * kCnnWidth * kCnnWidth;  // bf16 values of one 64x64 conv
+hipError_t cnn_init();  // LDS limits of the convolution kernels
+int cnn_partials();     // floats of the max-abs partials buffer
+// partials <- per-block max |e|; h = bf16(relu(stem(bf16(e / s)))) with
+// s = max |e| also stored in scale[0].  stem_w: [64][9] floats.
+template <typename T>
+hipError_t launch_cnn_head(hipStream_t s, int N, const T* e, int pe, float* partials,
+                           const float* stem_w, unsigned short* h, float* scale);
+// mode 0: out = bf16(relu(conv(in))); 1: out = bf16(skip + conv(in)) (out
+// may alias skip); 2: the 64 -> 256 conv followed by the x2 pixel shuffle and
+// ReLU into out [2N][2N][64], w holding 4 sets (one per sub-pixel offset).
+// w: [9 taps][64 out][64 in] bf16 per set.
+hipError_t launch_cnn_conv(hipStream_t s, int mode, int N, const unsigned short* in,
+                           const unsigned short* w, unsigned short* out, const unsigned short* skip);
+// uout = uin (nullable: 0) + scale[0] * conv_fin(z) on the (2N+1)^2 fine grid,
+// seam included.  fin_w: [9][64] floats.
+template <typename T>
+hipError_t launch_cnn_final(hipStream_t s, int N, const unsigned short* z, const float* fin_w,
+                            const float* scale, const T* uin, int pui, T* uout, int puo);
+
 // ---- persistent cycle kernel (mg_persist.hip) -------------------------------
 constexpr int kMaxLevels = 13;   // 16385 -> 5
 constexpr int kPersistThreads = 512;

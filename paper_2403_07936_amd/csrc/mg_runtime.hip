@@ -121,9 +121,11 @@ struct Problem {
   double* partials = nullptr;  // 2 * blocks_for(n) doubles
   double* sums = nullptr;      // 4 doubles of reduced results
   int nblocks = 0;
-  hipGraphExec_t graph = nullptr;
-  const double* graph_u = nullptr;
-  const double* graph_f = nullptr;
+  // Captured step per prolongation kind (0 spline, 1 SR-CNN) and the
+  // caller arrays it was captured with.
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  const double* graph_u[2] = {nullptr, nullptr};
+  const double* graph_f[2] = {nullptr, nullptr};
   // Kernel choice per level (autotuned): variant 0 = register streaming with
   // `hs` rows per segment (0 = default), 1 = LDS tiles.
   std::vector<int> down_var, down_hs, up_var, up_hs;
@@ -160,8 +162,26 @@ struct Persist {
 };
 }  // namespace mg
 
+namespace mg {
+// SR-CNN prolongation state: weights (bf16 sets for the 64-channel convs,
+// bf16-valued floats for the stem and the final conv) and activation
+// buffers sized for the largest coarse level of the batch.
+struct Cnn {
+  bool on = false;   // weights loaded
+  int levels = 0;    // finest prolongations that use the network in cycles
+  unsigned short* w = nullptr;  // 2 * kCnnBlocks body sets, then 4 sub-pixel sets
+  float* stem = nullptr;        // [64][9]
+  float* fin = nullptr;         // [9][64]
+  unsigned short *h = nullptr, *t = nullptr, *z = nullptr;
+  float* partials = nullptr;
+  float* scale = nullptr;
+  int max_n = 0;  // largest coarse unique side the buffers hold
+};
+}  // namespace mg
+
 struct mg_ctx_s {
   mg::Persist ps;
+  mg::Cnn cnn;
   bool timing = false;
   std::vector<mg::TimingRec> recs;
   std::vector<hipEvent_t> pool;
@@ -227,6 +247,35 @@ int32_t timed(mg_ctx_s* ctx, hipStream_t s, int kind, int level, double bytes, L
 
 double unknowns_side(int n, int bc) { return bc == kDirichlet ? n - 2 : n - 1; }
 
+// SR-CNN prolongation of a coarse correction ec (N x N unique nodes of a
+// periodic level, pitch pec) onto fine level `level`: uout = uin + network
+// output (uin nullable).  Uses the context's activation buffers.
+template <typename T>
+int32_t enqueue_cnn(mg_ctx_s* ctx, hipStream_t s, int level, int N, const T* ec, int pec,
+                    const T* uin, int pui, T* uout, int puo) {
+  const mg::Cnn& c = ctx->cnn;
+  const double px = (double)N * N, conv = 2.0 * px * kCnnWidth * kCnnWidth * 9;
+  MG_TRY(timed(ctx, s, MG_K_CNN_AUX, level, 2.0 * px * 2 * sizeof(T) + px * 128, [&] {
+    return launch_cnn_head<T>(s, N, ec, pec, c.partials, c.stem, c.h, c.scale);
+  }));
+  for (int b = 0; b < kCnnBlocks; ++b) {
+    const unsigned short* w1 = c.w + (size_t)(2 * b) * kCnnConvSet;
+    const unsigned short* w2 = w1 + kCnnConvSet;
+    MG_TRY(timed(ctx, s, MG_K_CNN, level, conv,
+                 [&] { return launch_cnn_conv(s, 0, N, c.h, w1, c.t, nullptr); }));
+    MG_TRY(timed(ctx, s, MG_K_CNN, level, conv,
+                 [&] { return launch_cnn_conv(s, 1, N, c.t, w2, c.h, c.h); }));
+  }
+  MG_TRY(timed(ctx, s, MG_K_CNN, level, 4 * conv, [&] {
+    return launch_cnn_conv(s, 2, N, c.h, c.w + (size_t)(2 * kCnnBlocks) * kCnnConvSet, c.z,
+                           nullptr);
+  }));
+  MG_TRY(timed(ctx, s, MG_K_CNN_AUX, level, 4 * px * (128 + 2 * sizeof(T)), [&] {
+    return launch_cnn_final<T>(s, N, c.z, c.fin, c.scale, uin, pui, uout, puo);
+  }));
+  return MG_OK;
+}
+
 bool valid_side(int n) {
   if (n < 5 || n > 16385) return false;
   const int m = (n - 1) / 4;
@@ -253,7 +302,7 @@ int32_t alloc_level(mg_ctx_s* ctx, int n, int pitch, T** out) {
 template <typename T>
 int32_t enqueue_cycle(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
                       const std::vector<PrefilterTaps>& taps, T* u0, int pu0, const T* f0,
-                      int pf0, hipStream_t s) {
+                      int pf0, hipStream_t s, bool cnn) {
   const int L = p.levels;
   const double* inv = ctx->inv[p.bc];
   auto U = [&](int l) { return l == 0 ? u0 : h.u[l]; };
@@ -295,13 +344,17 @@ int32_t enqueue_cycle(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
   for (int l = L - 2; l >= 0; --l) {
     const int n = p.side[l], nc = p.side[l + 1], pc = p.pitch[l + 1];
     const double m = unknowns_side(n, bc), ncc = (double)nc * nc;
-    MG_TRY(timed(ctx, s, MG_K_PREFILTER, l + 1, 4 * ncc * sz, [&] {
-      return launch_prefilter<T>(s, bc, nc, taps[l + 1], h.u[l + 1], pc, h.tmp[l + 1], pc,
-                                 h.c[l + 1], pc);
-    }));
-    MG_TRY(timed(ctx, s, MG_K_PROLONG, l, (2 * m * m + ncc) * sz, [&] {
-      return launch_prolong<T>(s, bc, n, U(l), PU(l), h.c[l + 1], pc, true);
-    }));
+    if (cnn && l < ctx->cnn.levels) {
+      MG_TRY(enqueue_cnn<T>(ctx, s, l, nc - 1, h.u[l + 1], pc, U(l), PU(l), U(l), PU(l)));
+    } else {
+      MG_TRY(timed(ctx, s, MG_K_PREFILTER, l + 1, 4 * ncc * sz, [&] {
+        return launch_prefilter<T>(s, bc, nc, taps[l + 1], h.u[l + 1], pc, h.tmp[l + 1], pc,
+                                   h.c[l + 1], pc);
+      }));
+      MG_TRY(timed(ctx, s, MG_K_PROLONG, l, (2 * m * m + ncc) * sz, [&] {
+        return launch_prolong<T>(s, bc, n, U(l), PU(l), h.c[l + 1], pc, true);
+      }));
+    }
     MG_TRY(sweeps(l, 2 * nu2));
   }
   return MG_OK;
@@ -313,7 +366,7 @@ int32_t enqueue_cycle(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
 template <typename T>
 int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
                             const PrefilterTaps* taps_dev, T* u0, int pu0, const T* f0, int pf0,
-                            bool zero_guess, hipStream_t s) {
+                            bool zero_guess, hipStream_t s, bool cnn) {
   const int t = p.tail, bc = p.bc;
   const double sz = sizeof(T);
   auto F = [&](int l) { return l == 0 ? f0 : (const T*)h.f[l]; };
@@ -345,12 +398,22 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
   for (int l = t - 1; l >= 0; --l) {
     const int n = p.side[l], nc = p.side[l + 1], pc = p.pitch[l + 1];
     const double m = unknowns_side(n, bc), ncc = (double)nc * nc;
+    T* uout = l == 0 ? u0 : h.u[l];
+    const int puo = l == 0 ? pu0 : p.pitch[l];
+    if (cnn && l < ctx->cnn.levels) {
+      // Network prolongation of the coarse result (level l + 1 lies above
+      // the tail, so its values are in h.u), added to the pre-smoothed u,
+      // then the post-smoothing sweeps.
+      MG_TRY(enqueue_cnn<T>(ctx, s, l, nc - 1, h.u[l + 1], pc, h.r[l], p.pitch[l], uout, puo));
+      MG_TRY(timed(ctx, s, MG_K_RELAX, l, 3 * m * m * sz * ctx->opt.nu_post, [&] {
+        return launch_relax<T>(s, bc, n, uout, puo, F(l), PF(l), 0, 2 * ctx->opt.nu_post);
+      }));
+      continue;
+    }
     if (l + 1 < t)
       MG_TRY(timed(ctx, s, MG_K_PREFILTER, l + 1, 4 * ncc * sz, [&] {
         return launch_prefilter_iir<T>(s, bc, nc, h.u[l + 1], pc, h.tmp[l + 1], pc, h.c[l + 1], pc);
       }));
-    T* uout = l == 0 ? u0 : h.u[l];
-    const int puo = l == 0 ? pu0 : p.pitch[l];
     MG_TRY(timed(ctx, s, MG_K_UP, l, (3 * m * m + ncc) * sz, [&] {
       if (ctx->opt.kernel_path == 2 || p.up_var[l] == 1)
         return launch_up<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l), h.c[l + 1], pc);
@@ -368,15 +431,15 @@ bool use_fused(const mg_ctx_s* ctx) {
 // One step of the outer iteration for one problem: an FP64 V-cycle, or one
 // refinement step around inner FP32 cycles.
 int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f,
-                     hipStream_t s) {
+                     hipStream_t s, bool cnn) {
   const double m = unknowns_side(p.n, p.bc), nn = (double)p.n * p.n;
   const bool fused = use_fused(ctx);
   if (ctx->opt.precision == MG_FP64) {
     if (fused)
       MG_TRY(enqueue_cycle_fused<double>(ctx, p, p.h64, p.taps64_dev, u, p.pitch0, f, p.pitch0,
-                                         false, s));
+                                         false, s, cnn));
     else
-      MG_TRY(enqueue_cycle<double>(ctx, p, p.h64, p.taps64, u, p.pitch0, f, p.pitch0, s));
+      MG_TRY(enqueue_cycle<double>(ctx, p, p.h64, p.taps64, u, p.pitch0, f, p.pitch0, s, cnn));
   } else {
     int nb = 0;
     float* e0 = p.h32.u[0];
@@ -388,12 +451,13 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
     if (fused) {
       for (int k = 0; k < ctx->opt.inner_cycles; ++k)
         MG_TRY(enqueue_cycle_fused<float>(ctx, p, p.h32, p.taps32_dev, e0, p.pitch[0], r0,
-                                          p.pitch[0], k == 0, s));
+                                          p.pitch[0], k == 0, s, cnn));
     } else {
       MG_TRY(timed(ctx, s, MG_K_ZERO, 0, 4 * nn,
                    [&] { return launch_zero<float>(s, p.n, e0, p.pitch[0]); }));
       for (int k = 0; k < ctx->opt.inner_cycles; ++k)
-        MG_TRY(enqueue_cycle<float>(ctx, p, p.h32, p.taps32, e0, p.pitch[0], r0, p.pitch[0], s));
+        MG_TRY(enqueue_cycle<float>(ctx, p, p.h32, p.taps32, e0, p.pitch[0], r0, p.pitch[0], s,
+                                    cnn));
     }
     MG_TRY(timed(ctx, s, MG_K_UPDATE_MIXED, 0, 20 * m * m, [&] {
       return launch_update_mixed(s, p.bc, p.n, u, p.pitch0, e0, p.pitch[0]);
@@ -403,32 +467,33 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
   return MG_OK;
 }
 
-int32_t run_step(mg_ctx_s* ctx, Problem& p, double* u, const double* f) {
-  if (!ctx->opt.use_graph || ctx->timing) return enqueue_step(ctx, p, u, f, ctx->stream);
-  if (p.graph && (p.graph_u != u || p.graph_f != f)) {
-    MG_HIP(hipGraphExecDestroy(p.graph));
-    p.graph = nullptr;
+int32_t run_step(mg_ctx_s* ctx, Problem& p, double* u, const double* f, bool cnn = false) {
+  if (!ctx->opt.use_graph || ctx->timing) return enqueue_step(ctx, p, u, f, ctx->stream, cnn);
+  const int k = cnn ? 1 : 0;
+  if (p.graph[k] && (p.graph_u[k] != u || p.graph_f[k] != f)) {
+    MG_HIP(hipGraphExecDestroy(p.graph[k]));
+    p.graph[k] = nullptr;
   }
-  if (!p.graph) {
+  if (!p.graph[k]) {
     hipGraph_t g = nullptr;
     MG_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
-    const int32_t st = enqueue_step(ctx, p, u, f, ctx->capture);
+    const int32_t st = enqueue_step(ctx, p, u, f, ctx->capture, cnn);
     hipError_t e = hipStreamEndCapture(ctx->capture, &g);
     if (st != MG_OK) {
       if (g) (void)hipGraphDestroy(g);
       return st;
     }
     if (e != hipSuccess) return fail(MG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&p.graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&p.graph[k], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-      p.graph = nullptr;
+      p.graph[k] = nullptr;
       return fail(MG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
-    p.graph_u = u;
-    p.graph_f = f;
+    p.graph_u[k] = u;
+    p.graph_f[k] = f;
   }
-  MG_HIP(hipGraphLaunch(p.graph, ctx->stream));
+  MG_HIP(hipGraphLaunch(p.graph[k], ctx->stream));
   return MG_OK;
 }
 
@@ -456,8 +521,14 @@ const Hierarchy<float>& hier<float>(const Problem& p) {
   return p.h32;
 }
 
+bool cnn_cycles(const mg_ctx_s* ctx) { return ctx->cnn.on && ctx->cnn.levels > 0; }
+
 bool persistent_eligible(const mg_ctx_s* ctx, std::string* why) {
   const auto& o = ctx->opt;
+  if (o.prolong == MG_PROLONG_SRCNN) {
+    *why = "the persistent schedule uses the spline prolongation only";
+    return false;
+  }
   if (o.kernel_path != 0 || o.nu_pre != 2 || o.nu_post != 2) {
     *why = "the persistent schedule needs kernel_path 0 and nu_pre = nu_post = 2";
     return false;
@@ -685,6 +756,87 @@ int32_t persistent_relres(mg_ctx_s* ctx, double* rel) {
     const double rr = sums[2 * b], ff = sums[2 * b + 1];
     rel[b] = ff > 0.0 ? std::sqrt(rr) / std::sqrt(ff) : std::sqrt(rr);
   }
+  return MG_OK;
+}
+
+// ----------------------------------------------------------------- SR-CNN setup
+
+// bfloat16 nearest-even rounding of a finite float (bit pattern).
+unsigned short bf16_bits(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, 4);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (unsigned short)(b >> 16);
+}
+float bf16_float(float x) {
+  const uint32_t b = (uint32_t)bf16_bits(x) << 16;
+  float f;
+  std::memcpy(&f, &b, 4);
+  return f;
+}
+
+// Validates the network levels against every problem, converts the weight
+// blob (PyTorch order, see MG_SRCNN_WEIGHT_COUNT) to the kernels' layouts and
+// allocates the activation buffers for the largest coarse level.
+int32_t cnn_setup(mg_ctx_s* ctx, const float* blob) {
+  Cnn& c = ctx->cnn;
+  c.levels = ctx->opt.cnn_levels;
+  for (size_t b = 0; b < ctx->probs.size(); ++b) {
+    const Problem& p = ctx->probs[b];
+    if (c.levels > p.levels - 1)
+      return fail(MG_ERR_UNSUPPORTED, "problem " + std::to_string(b) + ": cnn_levels exceeds the hierarchy");
+    for (int l = 0; l < c.levels; ++l)
+      if (p.side[l + 1] < 129)
+        return fail(MG_ERR_UNSUPPORTED, "problem " + std::to_string(b) +
+                                             ": SR-CNN levels need a coarse side of at least 129");
+    if (p.levels > 1 && p.side[1] - 1 >= 32) c.max_n = std::max(c.max_n, p.side[1] - 1);
+  }
+  for (size_t k = 0; k < (size_t)MG_SRCNN_WEIGHT_COUNT; ++k)
+    if (!std::isfinite(blob[k])) return fail(MG_ERR_INVALID_ARG, "non-finite SR-CNN weight");
+  constexpr int W = kCnnWidth;
+  const size_t set = kCnnConvSet;
+  std::vector<unsigned short> w((2 * kCnnBlocks + 4) * set);
+  std::vector<float> stem(W * 9), fin(9 * W);
+  const float* src_stem = blob;
+  const float* src_body = blob + W * 9;
+  const float* src_up = src_body + 2 * kCnnBlocks * set;
+  const float* src_fin = src_up + 4 * set;
+  for (int o = 0; o < W; ++o)
+    for (int t = 0; t < 9; ++t) stem[o * 9 + t] = bf16_float(src_stem[o * 9 + t]);
+  for (int k = 0; k < 2 * kCnnBlocks; ++k)
+    for (int o = 0; o < W; ++o)
+      for (int i = 0; i < W; ++i)
+        for (int t = 0; t < 9; ++t)
+          w[k * set + ((size_t)t * W + o) * W + i] = bf16_bits(src_body[k * set + ((size_t)o * W + i) * 9 + t]);
+  for (int ab = 0; ab < 4; ++ab)
+    for (int ch = 0; ch < W; ++ch)
+      for (int i = 0; i < W; ++i)
+        for (int t = 0; t < 9; ++t)
+          w[(2 * kCnnBlocks + ab) * set + ((size_t)t * W + ch) * W + i] =
+              bf16_bits(src_up[((size_t)(4 * ch + ab) * W + i) * 9 + t]);
+  for (int i = 0; i < W; ++i)
+    for (int t = 0; t < 9; ++t) fin[t * W + i] = bf16_float(src_fin[i * 9 + t]);
+
+  MG_TRY(alloc_level<unsigned short>(ctx, 2 * kCnnBlocks + 4, (int)set, &c.w));
+  MG_TRY(alloc_level<float>(ctx, 1, W * 9, &c.stem));
+  MG_TRY(alloc_level<float>(ctx, 1, 9 * W, &c.fin));
+  MG_TRY(alloc_level<float>(ctx, 1, cnn_partials() + 1, &c.partials));
+  c.scale = c.partials + cnn_partials();
+  if (c.max_n > 0) {
+    const int N = c.max_n;
+    MG_TRY(alloc_level<unsigned short>(ctx, N * N, W, &c.h));
+    MG_TRY(alloc_level<unsigned short>(ctx, N * N, W, &c.t));
+    MG_TRY(alloc_level<unsigned short>(ctx, 4 * N * N, W, &c.z));
+  }
+  MG_HIP(hipMemcpyAsync(c.w, w.data(), w.size() * sizeof(unsigned short), hipMemcpyHostToDevice,
+                        ctx->stream));
+  MG_HIP(hipMemcpyAsync(c.stem, stem.data(), stem.size() * sizeof(float), hipMemcpyHostToDevice,
+                        ctx->stream));
+  MG_HIP(hipMemcpyAsync(c.fin, fin.data(), fin.size() * sizeof(float), hipMemcpyHostToDevice,
+                        ctx->stream));
+  MG_HIP(hipStreamSynchronize(ctx->stream));  // the host staging vectors go out of scope
+  MG_HIP(cnn_init());
+  c.on = true;
   return MG_OK;
 }
 
@@ -966,10 +1118,11 @@ int32_t tune_schedule(mg_ctx_s* ctx) {
     st = persistent_relres(ctx, rel.data());  // also reports a timed-out barrier
   }
   for (auto& p : ctx->probs)
-    if (p.graph) {
-      (void)hipGraphExecDestroy(p.graph);
-      p.graph = nullptr;
-    }
+    for (auto& g : p.graph)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipFree(buf);
   if (st != MG_OK) return st;
@@ -992,7 +1145,8 @@ int32_t destroy_ctx(mg_ctx_s* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& p : ctx->probs)
-    if (p.graph) (void)hipGraphExecDestroy(p.graph);
+    for (auto g : p.graph)
+      if (g) (void)hipGraphExecDestroy(g);
   if (ctx->ps.graph) (void)hipGraphExecDestroy(ctx->ps.graph);
   for (void* q : ctx->owned) (void)hipFree(q);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -1035,8 +1189,15 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
   }
   if (opt->prolong == MG_PROLONG_SRCNN && (!opt->cnn_weights || opt->cnn_weights_bytes == 0))
     return fail(MG_ERR_UNSUPPORTED, "SR-CNN prolongation needs weights");
-  if (opt->prolong == MG_PROLONG_SRCNN)
-    return fail(MG_ERR_UNSUPPORTED, "SR-CNN prolongation is not available in this build");
+  if (opt->prolong == MG_PROLONG_SRCNN) {
+    if (opt->cnn_weights_bytes != sizeof(float) * (size_t)MG_SRCNN_WEIGHT_COUNT)
+      return fail(MG_ERR_INVALID_ARG, "SR-CNN weights must be " +
+                                          std::to_string(MG_SRCNN_WEIGHT_COUNT) + " float32 values");
+    if (opt->cnn_levels < 0 || opt->cnn_levels > kMaxLevels)
+      return fail(MG_ERR_INVALID_ARG, "cnn_levels out of range");
+    if (!(opt->cnn_max_ratio >= 0.0) || !(opt->cnn_min_relres >= 0.0))
+      return fail(MG_ERR_INVALID_ARG, "cnn_max_ratio and cnn_min_relres must be >= 0");
+  }
 
   int ndev = 0;
   MG_HIP(hipGetDeviceCount(&ndev));
@@ -1149,6 +1310,11 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
     if (st == MG_OK) st = alloc_level<double>(ctx, 1, 4, &p.sums);
     if (st != MG_OK) return bail(st);
   }
+  if (opt->prolong == MG_PROLONG_SRCNN) {
+    const int32_t st = cnn_setup(ctx, static_cast<const float*>(opt->cnn_weights));
+    if (st != MG_OK) return bail(st);
+  }
+  ctx->opt.cnn_weights = nullptr;  // copied; the caller's blob is not retained
   if (hipStreamSynchronize(ctx->stream) != hipSuccess)
     return bail(fail(MG_ERR_HIP, "hipStreamSynchronize after setup"));
   if (opt->schedule == 0 && opt->kernel_path == 0) {
@@ -1206,7 +1372,7 @@ int32_t vcycle_impl(mg_ctx ctx, double* const* u, const double* const* f, int32_
     return MG_OK;
   }
   for (int c = 0; c < ncycles; ++c)
-    for (int b = 0; b < B; ++b) MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b]));
+    for (int b = 0; b < B; ++b) MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b], cnn_cycles(ctx)));
   if (!relres_out) return MG_OK;
   std::vector<int> all(B);
   for (int b = 0; b < B; ++b) {
@@ -1274,6 +1440,10 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
     prev[b] = rel[b];
   }
   const int every = ctx->opt.check_every;
+  // Network-prolongated cycles until a cycle's residual ratio exceeds
+  // cnn_max_ratio or the residual reaches cnn_min_relres; checked after every
+  // such cycle.
+  std::vector<char> cnn_on(B, cnn_cycles(ctx) ? 1 : 0);
   for (;;) {
     std::vector<int> act;
     for (int b = 0; b < B; ++b)
@@ -1301,7 +1471,7 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
       }
       for (int b : act)
         if (cycles[b] < max_cycles && cycles[b] < next_check[b]) {
-          MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b]));
+          MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b], cnn_on[b] != 0));
           ++cycles[b];
         }
     }
@@ -1334,6 +1504,11 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
       // per cycle.
       const double rate = span > 0 && last > 0.0 ? std::pow(rr / last, 1.0 / span) : 1.0;
       slow[b] = rate > 0.9 ? slow[b] + 1 : 0;
+      bool switched = false;
+      if (cnn_on[b] && (rate > ctx->opt.cnn_max_ratio || rr <= ctx->opt.cnn_min_relres)) {
+        cnn_on[b] = 0;
+        switched = true;  // the rate seen so far is not the spline cycle's
+      }
       prev[b] = rr;
       prev_cycles[b] = cycles[b];
       if (slow[b] >= 3) {
@@ -1347,7 +1522,9 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
       // Next check: every `every` cycles, or (auto) at the cycle where the
       // observed rate predicts the tolerance is crossed, at most 8 ahead.
       int gap = 1;
-      if (every > 0) {
+      if (cnn_on[b] || switched) {
+        gap = 1;
+      } else if (every > 0) {
         gap = every;
       } else if (rate > 0.0 && rate < 0.9) {
         const double need = std::log(rtol / rr) / std::log(rate);
@@ -1433,14 +1610,22 @@ int32_t coarse_t(mg_ctx ctx, int32_t problem, const void* f, void* u) {
 }
 
 template <typename T>
-int32_t prolong_t(mg_ctx ctx, int32_t problem, int32_t coarse_level, const void* coarse,
-                  void* fine) {
+int32_t prolong_t(mg_ctx ctx, int32_t problem, int32_t coarse_level, int32_t kind,
+                  const void* coarse, void* fine) {
   Problem* p;
   MG_TRY(step_common<T>(ctx, problem, coarse_level, &p));
   if (coarse_level < 1) return fail(MG_ERR_INVALID_ARG, "coarse_level must be >= 1");
   if (!coarse || !fine) return fail(MG_ERR_INVALID_ARG, "NULL array");
   const int nc = p->side[coarse_level], n = p->side[coarse_level - 1];
   const int pc = p->pitch[coarse_level];
+  if (kind == MG_PROLONG_SRCNN) {
+    if (!ctx->cnn.on) return fail(MG_ERR_UNSUPPORTED, "no SR-CNN weights were given at setup");
+    const int N = nc - 1;
+    if (N < 32 || N % 32 != 0 || N > ctx->cnn.max_n)
+      return fail(MG_ERR_UNSUPPORTED, "SR-CNN needs a coarse unique side that is a multiple of 32");
+    return enqueue_cnn<T>(ctx, ctx->stream, coarse_level - 1, N, (const T*)coarse, nc, nullptr, 0,
+                          (T*)fine, n);
+  }
   // Workspace: the FP64 hierarchy's coefficient arrays of that level (their
   // byte size also covers FP32 data with the same element pitch).
   T* tmp = reinterpret_cast<T*>(p->h64.tmp[coarse_level]);
@@ -1482,6 +1667,8 @@ void mg_options_default(mg_options* opt) {
   opt->tune_cache_path = nullptr;
   opt->kernel_path = 0;
   opt->schedule = 0;
+  opt->cnn_max_ratio = 0.5;
+  opt->cnn_min_relres = 1e-7;
 }
 
 int32_t mg_setup(const mg_grid* grids, int32_t batch, const mg_options* opt, void* hip_stream,
@@ -1505,11 +1692,12 @@ int32_t mg_solve(mg_ctx ctx, double* const* u, const double* const* f, double rt
 int32_t mg_prolong(mg_ctx ctx, int32_t problem, int32_t coarse_level, int32_t kind,
                    const void* coarse, void* fine, int32_t dtype) {
   g_last_error.clear();
-  if (kind == MG_PROLONG_SRCNN)
-    return fail(MG_ERR_UNSUPPORTED, "SR-CNN prolongation is not available in this build");
-  if (kind != MG_PROLONG_SPLINE) return fail(MG_ERR_INVALID_ARG, "unknown prolongation kind");
-  MG_GUARD(if (dtype == MG_DT_F64) return prolong_t<double>(ctx, problem, coarse_level, coarse, fine);
-           if (dtype == MG_DT_F32) return prolong_t<float>(ctx, problem, coarse_level, coarse, fine);
+  if (kind != MG_PROLONG_SPLINE && kind != MG_PROLONG_SRCNN)
+    return fail(MG_ERR_INVALID_ARG, "unknown prolongation kind");
+  MG_GUARD(if (dtype == MG_DT_F64)
+               return prolong_t<double>(ctx, problem, coarse_level, kind, coarse, fine);
+           if (dtype == MG_DT_F32)
+               return prolong_t<float>(ctx, problem, coarse_level, kind, coarse, fine);
            return fail(MG_ERR_INVALID_ARG, "bad dtype");)
 }
 
@@ -1592,6 +1780,8 @@ const char* mg_kernel_name(int32_t kind) {
     case MG_K_UP: return "up";
     case MG_K_TAIL: return "tail";
     case MG_K_PERSISTENT: return "persistent";
+    case MG_K_CNN: return "cnn_conv";
+    case MG_K_CNN_AUX: return "cnn_aux";
     default: return "?";
   }
 }

@@ -19,11 +19,16 @@ class Solver:
     def __init__(self, grids, precision: str = "fp64", nu_pre: int = 2, nu_post: int = 2,
                  inner_cycles: int = 1, use_graph: bool = True, check_every: int = 0,
                  pitch=None, stream: torch.cuda.Stream | None = None, schedule: int = 0,
-                 kernel_path: int = 0, tune_cache_path: str | None = None):
+                 kernel_path: int = 0, tune_cache_path: str | None = None,
+                 cnn_weights=None, cnn_levels: int = 2, cnn_max_ratio: float = 0.5,
+                 cnn_min_relres: float = 1e-7):
         """grids: sequence of (n, bc) with bc 0/1 or "dirichlet"/"periodic".
         pitch: optional sequence of row pitches (elements) of the level-0 arrays.
         schedule: 0 autotuned, 1 per-problem graphs, 2 one persistent launch per step.
-        tune_cache_path: optional text file the autotuner reads and appends to."""
+        tune_cache_path: optional text file the autotuner reads and appends to.
+        cnn_weights: optional flat float32 array of SR-CNN weights (MG_SRCNN_WEIGHT_COUNT
+        values, see include/mg.h); selects the network prolongation on the
+        cnn_levels finest levels."""
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = B.mg_options_default()
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -35,6 +40,17 @@ class Solver:
         opt.kernel_path = kernel_path
         self._cache_path = tune_cache_path.encode() if tune_cache_path else None
         opt.tune_cache_path = self._cache_path
+        self._weights = None
+        if cnn_weights is not None:
+            import numpy as np
+
+            self._weights = np.ascontiguousarray(cnn_weights, dtype=np.float32).reshape(-1)
+            opt.prolong = B.MG_PROLONG_SRCNN
+            opt.cnn_levels = cnn_levels
+            opt.cnn_weights = self._weights.ctypes.data
+            opt.cnn_weights_bytes = self._weights.nbytes
+            opt.cnn_max_ratio = cnn_max_ratio
+            opt.cnn_min_relres = cnn_min_relres
         self.grids = [(int(n), BCS[bc] if isinstance(bc, str) else int(bc)) for n, bc in grids]
         pitches = list(pitch) if pitch is not None else [0] * len(self.grids)
         self.pitch = [p if p else n for (n, _), p in zip(self.grids, pitches)]
