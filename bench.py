@@ -59,11 +59,123 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dirichlet4097",
-                    choices=["dirichlet4097", "periodic1025", "dirichlet65"])
+                    choices=["dirichlet4097", "periodic1025", "dirichlet65", "periodic1025_srcnn"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
+
+
+BF16_PEAK_TFLOPS = 2500.0
+WEIGHTS = os.path.join(ROOT, "paper_2403_07936_amd", "weights", "srcnn_divu_periodic.npy")
+
+
+def bench_srcnn(args) -> int:
+    """1025 x 1025 periodic div-u source, V(2,2) cycles whose two finest
+    prolongations use the SR-CNN (bf16 matrix cores), FP64 cycle.  A step is
+    one such cycle.  Also reported: time to 1e-8 with the network-then-spline
+    schedule, and the spline cycle for comparison."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2403_07936_amd import binding as B
+    from paper_2403_07936_amd.solver import Solver
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    B.lib()
+    n, bc, f = workloads.workload("periodic1025", args.seed)
+    unknowns = workloads.grid_unknowns(n, bc)
+    W = np.load(WEIGHTS)
+    ft = torch.from_numpy(f).to(dev)
+    ut = torch.zeros_like(ft)
+    res = {}
+    for mode in ("srcnn", "spline"):
+        kw = dict(cnn_weights=W, cnn_levels=2) if mode == "srcnn" else {}
+        s = Solver([(n, bc)], precision="fp64", use_graph=True, **kw)
+        ut.zero_()
+        s.vcycle([ut], [ft], args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.vcycle([ut], [ft], args.steps)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        best = None
+        for _ in range(3):
+            ut.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, cyc, rel = s.solve([ut], [ft], rtol=1e-8, max_cycles=60)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, st, cyc[0], rel[0])
+        res[mode] = {"solver": s, "sec": sec, "ttt": best}
+        log(f"{mode}: {sec * 1e3:.3f} ms/cycle; to 1e-8: {best[0] * 1e3:.2f} ms, {best[2]} cycles, "
+            f"relres {best[3]:.2e}")
+    hs = res["srcnn"]["solver"]
+    B.mg_timing_enable(hs.ctx, True)
+    ut.zero_()
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        hs.vcycle([ut], [ft], 1)
+    torch.cuda.synchronize()
+    kern = {}
+    for kind in range(B.MG_K_COUNT):
+        for lvl in range(2):
+            cnt, ms, by = B.mg_timing_read(hs.ctx, kind, lvl)
+            if cnt:
+                kern[f"{B.mg_kernel_name(kind)}@{lvl}"] = (cnt, ms, by)
+    B.mg_timing_enable(hs.ctx, False)
+    cnt, ms, flops = kern["cnn_conv@0"]
+    achieved = flops / (ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": "cnn_conv (level 0, 512^2 coarse, 64->64 and 64->256)",
+                "achieved": round(achieved, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_us": round(ms / cnt * 1e3, 2), "flops_per_launch": flops / cnt}
+    per_kernel = {k: {"launches": c, "avg_us": round(m / c * 1e3, 2)} for k, (c, m, b) in kern.items()}
+    cpu = None
+    if not args.no_cpu:
+        from oracle import srcnn
+
+        layers = srcnn.unpack_weights(W)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        u = np.zeros_like(f)
+        count, t0 = 0, time.perf_counter()
+        while True:
+            u = srcnn.vcycle(u, f, layers, 2)
+            count += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds or count >= 3:
+                break
+        cpu = {"value": round(unknowns * count / el, 1), "unit": "grid-points/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{count} SR-CNN cycles of periodic1025 ({el:.1f} s, oracle: C V-cycle "
+                         f"steps and float64 torch CPU convolutions)"}
+    r = res["srcnn"]
+    out = {
+        "metric": "grid-points/s per V-cycle + time to 1e-10 rel. residual, 4097² Poisson",
+        "value": round(unknowns / r["sec"], 1), "unit": "grid-points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["sec"] * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 network, f64 cycle", "data": "synthetic",
+        "config": {"workload": "periodic1025_srcnn", "n": n, "bc": "periodic",
+                   "unknowns": unknowns, "cnn_levels": 2, "seed": args.seed,
+                   "weights": "paper_2403_07936_amd/weights/srcnn_divu_periodic.npy"},
+        "time_to_1e-8_s": round(r["ttt"][0], 6), "cycles_to_1e-8": r["ttt"][2],
+        "final_relres": r["ttt"][3],
+        "spline": {"ms_per_cycle": round(res["spline"]["sec"] * 1e3, 4),
+                   "time_to_1e-8_s": round(res["spline"]["ttt"][0], 6),
+                   "cycles_to_1e-8": res["spline"]["ttt"][2]},
+        "roofline": roofline, "kernels": per_kernel, "cpu_baseline": cpu,
+    }
+    for v in res.values():
+        v["solver"].close()
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def main() -> int:
@@ -72,6 +184,8 @@ def main() -> int:
         print(f"bench.py runs on exactly one GPU (this build has no multi-GPU path); "
               f"got --gpus {args.gpus}", file=sys.stderr)
         return 2
+    if args.workload == "periodic1025_srcnn":
+        return bench_srcnn(args)
 
     import numpy as np
     import torch

@@ -17,6 +17,8 @@
 
 #include "mg_internal.h"
 
+#include <algorithm>
+
 namespace mg {
 namespace {
 
@@ -39,9 +41,14 @@ __device__ __forceinline__ float from_bf16(unsigned short b) {
   return __builtin_bit_cast(float, (unsigned)b << 16);
 }
 
-// Bank-conflict-free placement of 16-byte chunk c (0..7) of row r: the
-// eight chunks of eight consecutive rows land in distinct bank groups.
-__device__ __forceinline__ int swz(int r, int c) { return r * 8 + (c ^ (r & 7)); }
+// Placement of 16-byte chunk c (0..7) of 128-byte row r.  The LDS serves a
+// 16-byte read of 64 lanes from 64 banks (256 bytes per pass), so the
+// chunks that 16 lanes reading 16 consecutive rows ask for must fill all 64
+// banks: consecutive row pairs share a 256-byte bank row, and XOR-ing the
+// chunk with r/2 spreads the eight pairs over its eight 32-byte slots.
+// (XOR with r itself leaves rows r and r + 8 on the same banks: a 2-way
+// conflict measured with SQ_LDS_BANK_CONFLICT.)
+__device__ __forceinline__ int swz(int r, int c) { return r * 8 + (c ^ ((r >> 1) & 7)); }
 
 // ---------------------------------------------------------------- max |e|
 template <typename T>
@@ -63,29 +70,26 @@ __global__ void __launch_bounds__(256) k_cnn_absmax(int N, const T* __restrict__
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-// Block-wide max of the partials (every thread gets it).
-__device__ float block_scale(const float* __restrict__ partials, float* red) {
+// scale[0] = max of the partials (one workgroup).
+__global__ void __launch_bounds__(256) k_cnn_scale(const float* __restrict__ partials,
+                                                   float* __restrict__ scale) {
+  __shared__ float red[256];
   red[threadIdx.x] = partials[threadIdx.x];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  const float s = red[0];
-  __syncthreads();
-  return s;
+  if (threadIdx.x == 0) scale[0] = red[0];
 }
 
 // ---------------------------------------------------------------- stem
 // Thread = (pixel, group of 8 output channels).  stem_w: [64][9] floats.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_cnn_stem(int N, const T* __restrict__ e, int pe, const float* __restrict__ partials,
-               const float* __restrict__ stem_w, unsigned short* __restrict__ h,
-               float* __restrict__ scale_out) {
-  __shared__ float red[256];
-  const float s = block_scale(partials, red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) scale_out[0] = s;
+    k_cnn_stem(int N, const T* __restrict__ e, int pe, const float* __restrict__ scale,
+               const float* __restrict__ stem_w, unsigned short* __restrict__ h) {
+  const float s = scale[0];
   const long q = (long)blockIdx.x * 256 + threadIdx.x;
   if (q >= (long)N * N * 8) return;
   const int g = (int)(q & 7);
@@ -121,82 +125,155 @@ __global__ void __launch_bounds__(256)
 // MODE 2: sub-pixel ab = blockIdx.y of the x2 shuffle: out[2y+a][2x+b] =
 //         bf16(relu(conv(in))) with the 64 channels of weight set ab  [2N][2N][64]
 // w: weight sets of [9 taps][64 out][64 in] bf16 (set blockIdx.y for MODE 2).
+//
+// Each workgroup keeps its weight set in LDS and walks the tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's input is loaded
+// into registers while the current tile is computed, then written to the
+// other of two LDS tile buffers.  (Copying it with LDS-direct loads instead
+// makes the compiler wait for every outstanding LDS read before each step
+// of the product loop, which costs more than the registers.)
+//
+// LDS layouts are chunk-major: slot (c, row) holds 16-byte chunk c (input
+// channels 8c .. 8c+7) of a weight row (tap * 64 + out channel) or of a
+// tile pixel.  A fragment read by 32 lanes then covers 32 consecutive
+// slots (no bank conflicts), and every read of a step is one per-lane base
+// address plus a compile-time offset.
+constexpr int kWRows = 9 * kC;                  // weight rows (tap, out channel)
+constexpr int kTPix = (kTH + 2) * kHW;          // tile pixels with halo
+constexpr int kWPerThread = kWChunks / kConvThreads;                           // 18
+constexpr int kTPerThread = (kTileChunks + kConvThreads - 1) / kConvThreads;  // 11
+
+struct TileRegs {
+  uint4 v[kTPerThread];
+};
+
+__device__ __forceinline__ TileRegs tile_fetch(const uint4* __restrict__ in, int N, int tile,
+                                               int tid) {
+  TileRegs r;
+  const int tiles_x = N / kTW;
+  const int row0 = (tile / tiles_x) * kTH, col0 = (tile % tiles_x) * kTW;
+#pragma unroll
+  for (int k = 0; k < kTPerThread; ++k) {
+    // Threads past the tile's last slot re-read that slot's chunk (not stored).
+    const int q = min(k * kConvThreads + tid, kTileChunks - 1);
+    const int c = q / kTPix, p = q % kTPix;
+    int gy = row0 - 1 + p / kHW, gx = col0 - 1 + p % kHW;
+    gy = gy < 0 ? gy + N : (gy >= N ? gy - N : gy);
+    gx = gx < 0 ? gx + N : (gx >= N ? gx - N : gx);
+    r.v[k] = in[((size_t)gy * N + gx) * 8 + c];
+  }
+  return r;
+}
+
+__device__ __forceinline__ void tile_store(uint4* buf, int tid, const TileRegs& r) {
+#pragma unroll
+  for (int k = 0; k < kTPerThread - 1; ++k) buf[k * kConvThreads + tid] = r.v[k];
+  const int q = (kTPerThread - 1) * kConvThreads + tid;
+  if (q < kTileChunks) buf[q] = r.v[kTPerThread - 1];
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(kConvThreads)
     k_cnn_conv(int N, const unsigned short* __restrict__ in, const unsigned short* __restrict__ w,
                unsigned short* out, const unsigned short* skip) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  uint4* wl = reinterpret_cast<uint4*>(lds);                    // kWChunks
-  uint4* il = reinterpret_cast<uint4*>(lds) + kWChunks;         // kTileChunks
-  const int tiles_x = N / kTW;
-  const int tile = blockIdx.x;
-  const int row0 = (tile / tiles_x) * kTH, col0 = (tile % tiles_x) * kTW;
-  const uint4* wg = reinterpret_cast<const uint4*>(w) + (size_t)(MODE == 2 ? blockIdx.y : 0) * kWChunks;
-  for (int q = threadIdx.x; q < kWChunks; q += kConvThreads) wl[swz(q >> 3, q & 7)] = wg[q];
-  for (int q = threadIdx.x; q < kTileChunks; q += kConvThreads) {
-    const int p = q >> 3, c = q & 7;
-    const int ty = p / kHW, tx = p % kHW;
-    int gy = row0 - 1 + ty, gx = col0 - 1 + tx;
-    gy = gy < 0 ? gy + N : (gy >= N ? gy - N : gy);
-    gx = gx < 0 ? gx + N : (gx >= N ? gx - N : gx);
-    il[swz(p, c)] = reinterpret_cast<const uint4*>(in)[((size_t)gy * N + gx) * 8 + c];
+  uint4* wl = reinterpret_cast<uint4*>(lds);                         // kWChunks
+  uint4* ib = reinterpret_cast<uint4*>(lds) + kWChunks;              // 2 x kTileChunks
+  const int tid = threadIdx.x;
+  const int tiles_x = N / kTW, tiles = tiles_x * (N / kTH);
+  const uint4* in4 = reinterpret_cast<const uint4*>(in);
+  int tile = blockIdx.x;
+  if (tile >= tiles) return;  // uniform per workgroup
+  {
+    const uint4* wg = reinterpret_cast<const uint4*>(w) + (size_t)(MODE == 2 ? blockIdx.y : 0) * kWChunks;
+    uint4 r[kWPerThread];
+#pragma unroll
+    for (int k = 0; k < kWPerThread; ++k) {
+      const int q = k * kConvThreads + tid;
+      r[k] = wg[(q % kWRows) * 8 + q / kWRows];
+    }
+#pragma unroll
+    for (int k = 0; k < kWPerThread; ++k) wl[k * kConvThreads + tid] = r[k];
   }
+  tile_store(ib, tid, tile_fetch(in4, N, tile, tid));
   __syncthreads();
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
   const int m = lane & 31, kh = lane >> 5;
-  f32x16 acc[2][2];
-  for (int j = 0; j < 2; ++j)
-    for (int i = 0; i < 2; ++i)
-      for (int v = 0; v < 16; ++v) acc[j][i][v] = 0.f;
-#pragma unroll 1
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ky = tap / 3, kx = tap % 3;
-    const int p0 = (2 * wave + ky) * kHW + m + kx;
-    const int p1 = p0 + kHW;
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc) {
-      const int c = kc * 2 + kh;
-      const bf16x8 a0 = __builtin_bit_cast(bf16x8, wl[swz(tap * kC + m, c)]);
-      const bf16x8 a1 = __builtin_bit_cast(bf16x8, wl[swz(tap * kC + 32 + m, c)]);
-      const bf16x8 b0 = __builtin_bit_cast(bf16x8, il[swz(p0, c)]);
-      const bf16x8 b1 = __builtin_bit_cast(bf16x8, il[swz(p1, c)]);
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
-    }
-  }
+  int cur = 0;
+  for (; tile < tiles; tile += gridDim.x) {
+    const int next = tile + gridDim.x;
+    const TileRegs pre = tile_fetch(in4, N, next < tiles ? next : tile, tid);  // last pass: a re-read
+    const uint4* il = ib + cur * kTileChunks;
 
-  // Lane holds pixel column m and output channels 32j + 8g + 4kh + (0..3).
-  for (int i = 0; i < 2; ++i) {
-    const int y = row0 + 2 * wave + i, x = col0 + m;
-    size_t base;
-    if (MODE == 2) {
-      const int a = blockIdx.y >> 1, b = blockIdx.y & 1;
-      base = ((size_t)(2 * y + a) * (2 * N) + (2 * x + b)) * kC;
-    } else {
-      base = ((size_t)y * N + x) * kC;
-    }
+    f32x16 acc[2][2];
     for (int j = 0; j < 2; ++j)
-      for (int g = 0; g < 4; ++g) {
-        const int ch = 32 * j + 8 * g + 4 * kh;
-        float v[4];
-        for (int r = 0; r < 4; ++r) v[r] = acc[j][i][4 * g + r];
-        if (MODE == 1) {
-          const uint2 sk = *reinterpret_cast<const uint2*>(skip + base + ch);
-          v[0] += from_bf16(sk.x & 0xffff);
-          v[1] += from_bf16(sk.x >> 16);
-          v[2] += from_bf16(sk.y & 0xffff);
-          v[3] += from_bf16(sk.y >> 16);
-        } else {
-          for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
-        }
-        uint2 pk;
-        pk.x = to_bf16(v[0]) | ((unsigned)to_bf16(v[1]) << 16);
-        pk.y = to_bf16(v[2]) | ((unsigned)to_bf16(v[3]) << 16);
-        *reinterpret_cast<uint2*>(out + base + ch) = pk;
+      for (int i = 0; i < 2; ++i)
+        for (int v = 0; v < 16; ++v) acc[j][i][v] = 0.f;
+    // K loop of 36 steps (9 taps x 4 chunks of 16 input channels), fully
+    // unrolled, with the four operand fragments of step s + 2 read from LDS
+    // while the four products of step s run.
+    const uint4* wb = wl + kh * kWRows + m;                 // chunk kh, row m
+    const uint4* ibase = il + kh * kTPix + 2 * wave * kHW + m;  // chunk kh, pixel (2 wave, m)
+    auto fetch = [&](int st, bf16x8 (&fr)[4]) {
+      const int tap = st >> 2, kc = st & 3;
+      const int poff = 2 * kc * kTPix + (tap / 3) * kHW + tap % 3;
+      fr[0] = __builtin_bit_cast(bf16x8, wb[2 * kc * kWRows + tap * kC]);
+      fr[1] = __builtin_bit_cast(bf16x8, wb[2 * kc * kWRows + tap * kC + 32]);
+      fr[2] = __builtin_bit_cast(bf16x8, ibase[poff]);
+      fr[3] = __builtin_bit_cast(bf16x8, ibase[poff + kHW]);
+    };
+    bf16x8 fr[3][4];
+    fetch(0, fr[0]);
+    fetch(1, fr[1]);
+#pragma unroll
+    for (int st = 0; st < 36; ++st) {
+      if (st + 2 < 36) fetch(st + 2, fr[(st + 2) % 3]);
+      const bf16x8(&f)[4] = fr[st % 3];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f[0], f[2], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f[0], f[3], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f[1], f[2], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f[1], f[3], acc[1][1], 0, 0, 0);
+      // Nothing moves across step boundaries: the reads of step st + 2 stay
+      // in step st, two steps of products ahead of their use, so the LDS
+      // latency hides behind the matrix pipe.
+      __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // Lane holds pixel column m and output channels 32j + 8g + 4kh + (0..3).
+    const int row0 = (tile / tiles_x) * kTH, col0 = (tile % tiles_x) * kTW;
+    for (int i = 0; i < 2; ++i) {
+      const int y = row0 + 2 * wave + i, x = col0 + m;
+      size_t base;
+      if (MODE == 2) {
+        const int a = blockIdx.y >> 1, b = blockIdx.y & 1;
+        base = ((size_t)(2 * y + a) * (2 * N) + (2 * x + b)) * kC;
+      } else {
+        base = ((size_t)y * N + x) * kC;
       }
+      for (int j = 0; j < 2; ++j)
+        for (int g = 0; g < 4; ++g) {
+          const int ch = 32 * j + 8 * g + 4 * kh;
+          float v[4];
+          for (int r = 0; r < 4; ++r) v[r] = acc[j][i][4 * g + r];
+          if (MODE == 1) {
+            const uint2 sk = *reinterpret_cast<const uint2*>(skip + base + ch);
+            v[0] += from_bf16(sk.x & 0xffff);
+            v[1] += from_bf16(sk.x >> 16);
+            v[2] += from_bf16(sk.y & 0xffff);
+            v[3] += from_bf16(sk.y >> 16);
+          } else {
+            for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
+          }
+          uint2 pk;
+          pk.x = to_bf16(v[0]) | ((unsigned)to_bf16(v[1]) << 16);
+          pk.y = to_bf16(v[2]) | ((unsigned)to_bf16(v[3]) << 16);
+          *reinterpret_cast<uint2*>(out + base + ch) = pk;
+        }
+    }
+    if (next < tiles) tile_store(ib + (cur ^ 1) * kTileChunks, tid, pre);
+    __syncthreads();
+    cur ^= 1;
   }
 }
 
@@ -210,17 +287,28 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_cnn_final(int M, const unsigned short* __restrict__ z, const float* __restrict__ fin_w,
                 const float* __restrict__ scale, const T* uin, int pui, T* uout, int puo) {
-  __shared__ __attribute__((aligned(16))) uint4 tl[kFHW * kFHW * 8];
+  __shared__ __attribute__((aligned(16))) uint4 tl[kFHW * kFHW * 8];  // chunk-major: [c][pixel]
   __shared__ float wf[9 * kC];
   const int tiles_x = M / kFT;
   const int y0 = (blockIdx.x / tiles_x) * kFT, x0 = (blockIdx.x % tiles_x) * kFT;
   for (int q = threadIdx.x; q < 9 * kC; q += 256) wf[q] = fin_w[q];
-  for (int q = threadIdx.x; q < kFHW * kFHW * 8; q += 256) {
-    const int p = q >> 3, c = q & 7;
-    int gy = y0 - 1 + p / kFHW, gx = x0 - 1 + p % kFHW;
-    gy = gy < 0 ? gy + M : (gy >= M ? gy - M : gy);
-    gx = gx < 0 ? gx + M : (gx >= M ? gx - M : gx);
-    tl[swz(p, c)] = reinterpret_cast<const uint4*>(z)[((size_t)gy * M + gx) * 8 + c];
+  {
+    constexpr int kChunks = kFHW * kFHW * 8, kPer = (kChunks + 255) / 256;
+    uint4 r[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int q = min((int)threadIdx.x + k * 256, kChunks - 1);
+      const int p = q >> 3, c = q & 7;
+      int gy = y0 - 1 + p / kFHW, gx = x0 - 1 + p % kFHW;
+      gy = gy < 0 ? gy + M : (gy >= M ? gy - M : gy);
+      gx = gx < 0 ? gx + M : (gx >= M ? gx - M : gx);
+      r[k] = reinterpret_cast<const uint4*>(z)[((size_t)gy * M + gx) * 8 + c];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int q = threadIdx.x + k * 256;
+      if (q < kChunks) tl[(q & 7) * (kFHW * kFHW) + (q >> 3)] = r[k];
+    }
   }
   __syncthreads();
   const int ty = threadIdx.x / kFT, tx = threadIdx.x % kFT;
@@ -228,7 +316,7 @@ __global__ void __launch_bounds__(256)
   for (int tap = 0; tap < 9; ++tap) {
     const int p = (ty + tap / 3) * kFHW + tx + tap % 3;
     for (int c = 0; c < 8; ++c) {
-      const uint4 v = tl[swz(p, c)];
+      const uint4 v = tl[c * (kFHW * kFHW) + p];
       const float* wv = wf + tap * kC + c * 8;
       acc += wv[0] * from_bf16(v.x & 0xffff) + wv[1] * from_bf16(v.x >> 16) +
              wv[2] * from_bf16(v.y & 0xffff) + wv[3] * from_bf16(v.y >> 16) +
@@ -248,12 +336,18 @@ __global__ void __launch_bounds__(256)
   if (x == 0 && y == 0) put(M, M);
 }
 
+int g_cus = 256;  // compute units of the device (set by cnn_init)
+
 }  // namespace
 
-size_t cnn_conv_lds() { return (size_t)(kWChunks + kTileChunks) * 16; }
+size_t cnn_conv_lds() { return (size_t)(kWChunks + 2 * kTileChunks) * 16; }
 
 hipError_t cnn_init() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_cnn_conv<0>,
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_cnn_conv<0>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)cnn_conv_lds());
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_cnn_conv<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -270,15 +364,22 @@ template <typename T>
 hipError_t launch_cnn_head(hipStream_t s, int N, const T* e, int pe, float* partials,
                            const float* stem_w, unsigned short* h, float* scale) {
   hipLaunchKernelGGL(k_cnn_absmax<T>, dim3(kPartials), dim3(256), 0, s, N, e, pe, partials);
+  hipLaunchKernelGGL(k_cnn_scale, dim3(1), dim3(256), 0, s, partials, scale);
   const long threads = (long)N * N * 8;
   hipLaunchKernelGGL(k_cnn_stem<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, N, e,
-                     pe, partials, stem_w, h, scale);
+                     pe, scale, stem_w, h);
   return hipGetLastError();
 }
 
 hipError_t launch_cnn_conv(hipStream_t s, int mode, int N, const unsigned short* in,
                            const unsigned short* w, unsigned short* out, const unsigned short* skip) {
-  const dim3 grid((unsigned)((N / kTW) * (N / kTH)), mode == 2 ? 4 : 1);
+  // One workgroup per compute unit (its LDS holds a whole weight set), each
+  // taking at least two tiles where there are enough.
+  const int sets = mode == 2 ? 4 : 1;
+  const int tiles = (N / kTW) * (N / kTH);
+  int g = std::max(1, g_cus / sets);
+  g = std::min(g, std::max(1, (tiles + 1) / 2));
+  const dim3 grid((unsigned)g, (unsigned)sets);
   const size_t lds = cnn_conv_lds();
   if (mode == 0)
     hipLaunchKernelGGL(k_cnn_conv<0>, grid, dim3(kConvThreads), lds, s, N, in, w, out, skip);
