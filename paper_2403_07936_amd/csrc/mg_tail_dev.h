@@ -163,9 +163,17 @@ __device__ __forceinline__ void tail_restrict(const T* u, const T* f, T* r, T* f
   __syncthreads();
 }
 
+// Node q of the extended sequence of a tail line for q in [-Q - 1, 2Q)
+// (Q the period of the extension; the prolongation reaches one node
+// outside the line).
+template <int BC>
+__device__ __forceinline__ int tail_ext(int q, int nc, bool* neg) {
+  return ext_node<BC>(q, nc, neg);
+}
+
 // Prefilter a tail grid: rows of src (in place), then columns into dst
-// (pitch pd); each wavefront takes every 16th line, with its own slice of
-// the scratch grid for the causal values.
+// (pitch pd); each wavefront takes every (TR/2)-th line, with its own slice
+// of the scratch grid for the causal values.
 template <typename T, int BC, int TR>
 __device__ __forceinline__ void tail_prefilter(T* src, T* tmp, T* dst, int pd, int nc) {
   const int t = tail_tid();
@@ -181,29 +189,38 @@ __device__ __forceinline__ void tail_prefilter(T* src, T* tmp, T* dst, int pd, i
   __syncthreads();
 }
 
-// u += P c on a tail grid of side n from coefficients c of side nc.
+// u += P c on a tail grid of side n from coefficients c of side nc, in two
+// separable passes through the scratch grid t: first along x for every
+// coarse row of the extension that the y taps reach (rows -1 .. nc), then
+// along y.
 template <typename T, int BC, int TR>
-__device__ __forceinline__ void tail_prolong_add(T* u, const T* c, int n) {
+__device__ __forceinline__ void tail_prolong_add(T* u, const T* c, T* t, int n) {
   const int nc = (n - 1) / 2 + 1;
+  const int rows = nc + 2;  // coarse rows -1 .. nc
+  for (int q = tail_tid(); q < rows * n; q += 32 * TR) {
+    const int I = q / n - 1, j = q % n;
+    bool ni;
+    const int Ie = tail_ext<BC>(I, nc, &ni);
+    int bj;
+    T wj[4];
+    const int nj = bspline_taps<T>(j, &bj, wj);
+    T row = T(0);
+    for (int b = 0; b < nj; ++b) {
+      bool nb;
+      const int J = ext_node<BC>(bj + b, nc, &nb);
+      const T x = c[Ie * nc + J];
+      row += wj[b] * (nb ? -x : x);
+    }
+    t[q] = ni ? -row : row;
+  }
+  __syncthreads();
   MG_TAIL_FOR(n, i, j, {
     if (tail_unknown<BC>(i, j, n)) {
-      int bi, bj;
-      T wi[4], wj[4];
+      int bi;
+      T wi[4];
       const int ni = bspline_taps<T>(i, &bi, wi);
-      const int nj = bspline_taps<T>(j, &bj, wj);
       T v = T(0);
-      for (int a = 0; a < ni; ++a) {
-        bool na;
-        const int I = ext_node<BC>(bi + a, nc, &na);
-        T row = T(0);
-        for (int b = 0; b < nj; ++b) {
-          bool nb;
-          const int J = ext_node<BC>(bj + b, nc, &nb);
-          const T x = c[I * nc + J];
-          row += wj[b] * (nb ? -x : x);
-        }
-        v += wi[a] * (na ? -row : row);
-      }
+      for (int a = 0; a < ni; ++a) v += wi[a] * t[(bi + a + 1) * n + j];
       u[i * n + j] += v;
     }
   });
@@ -285,7 +302,7 @@ __device__ __forceinline__ void tail_block(int nt, const T* __restrict__ uin, in
     const int n = tail_side(nt, l), nc = tail_side(nt, l + 1);
     T* uc = sm + tail_offu(nt, l + 1);
     tail_prefilter<T, BC, TR>(uc, tmp, uc, nc, nc);
-    tail_prolong_add<T, BC, TR>(sm + tail_offu(nt, l), uc, n);
+    tail_prolong_add<T, BC, TR>(sm + tail_offu(nt, l), uc, tmp, n);
     tail_sweeps<T, BC, TR>(sm + tail_offu(nt, l), sm + tail_offf(nt, l), n, 4);
   }
   if (uout)
@@ -299,7 +316,9 @@ __device__ __forceinline__ void tail_block(int nt, const T* __restrict__ uin, in
 }
 
 // u and f of every tail level, then the scratch grid: the residual of the
-// top level, or 16 per-wavefront line buffers of the prefilter.
+// top level, the x-interpolated rows of a prolongation ((nt+1)/2 + 2 rows of
+// nt), or the per-wavefront line buffers of the prefilter (TR/2 <= 16 of
+// them).
 __host__ __device__ inline size_t tail_bytes(int nt, size_t elem) {
   size_t tot = 0;
   for (int n = nt;; n = (n - 1) / 2 + 1) {
