@@ -111,9 +111,12 @@ hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uou
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
                               int puo, const T* f, int pf, T* fc, int pfc, int hs);
+// u64 (nullable): instead of writing uout, add the result to this FP64
+// array (pitch p64) over the unknowns (the mixed path's refinement update).
 template <typename T>
 hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
-                            const T* f, int pf, const T* c, int pc, int hs);
+                            const T* f, int pf, const T* c, int pc, int hs,
+                            double* u64 = nullptr, int p64 = 0);
 // c = spline coefficients of e (level with nc nodes), via tmp.
 template <typename T>
 hipError_t launch_prefilter_iir(hipStream_t s, int bc, int nc, const T* e, int pe, T* tmp, int pt,

@@ -366,7 +366,8 @@ int32_t enqueue_cycle(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
 template <typename T>
 int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
                             const PrefilterTaps* taps_dev, T* u0, int pu0, const T* f0, int pf0,
-                            bool zero_guess, hipStream_t s, bool cnn) {
+                            bool zero_guess, hipStream_t s, bool cnn, double* u64 = nullptr,
+                            int p64 = 0, bool* added = nullptr) {
   const int t = p.tail, bc = p.bc;
   const double sz = sizeof(T);
   auto F = [&](int l) { return l == 0 ? f0 : (const T*)h.f[l]; };
@@ -414,11 +415,16 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
       MG_TRY(timed(ctx, s, MG_K_PREFILTER, l + 1, 4 * ncc * sz, [&] {
         return launch_prefilter_iir<T>(s, bc, nc, h.u[l + 1], pc, h.tmp[l + 1], pc, h.c[l + 1], pc);
       }));
-    MG_TRY(timed(ctx, s, MG_K_UP, l, (3 * m * m + ncc) * sz, [&] {
-      if (ctx->opt.kernel_path == 2 || p.up_var[l] == 1)
+    // Level 0 of the mixed path's last inner cycle: the streaming up pass
+    // adds its result straight into the FP64 iterate (no separate update).
+    const bool tile = ctx->opt.kernel_path == 2 || p.up_var[l] == 1;
+    const bool add = l == 0 && u64 && !tile;
+    if (add && added) *added = true;
+    MG_TRY(timed(ctx, s, MG_K_UP, l, (3 * m * m + ncc) * sz + (add ? 16 * m * m - 4 * m * m : 0), [&] {
+      if (tile)
         return launch_up<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l), h.c[l + 1], pc);
       return launch_up_stream<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l),
-                                 h.c[l + 1], pc, p.up_hs[l]);
+                                 h.c[l + 1], pc, p.up_hs[l], add ? u64 : nullptr, p64);
     }));
   }
   return MG_OK;
@@ -448,10 +454,13 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
       return launch_residual_mixed(s, p.bc, p.n, u, p.pitch0, f, p.pitch0, r0, p.pitch[0],
                                    p.partials, &nb);
     }));
+    bool added = false;
     if (fused) {
-      for (int k = 0; k < ctx->opt.inner_cycles; ++k)
+      const int K = ctx->opt.inner_cycles;
+      for (int k = 0; k < K; ++k)
         MG_TRY(enqueue_cycle_fused<float>(ctx, p, p.h32, p.taps32_dev, e0, p.pitch[0], r0,
-                                          p.pitch[0], k == 0, s, cnn));
+                                          p.pitch[0], k == 0, s, cnn, k == K - 1 ? u : nullptr,
+                                          p.pitch0, &added));
     } else {
       MG_TRY(timed(ctx, s, MG_K_ZERO, 0, 4 * nn,
                    [&] { return launch_zero<float>(s, p.n, e0, p.pitch[0]); }));
@@ -459,9 +468,10 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
         MG_TRY(enqueue_cycle<float>(ctx, p, p.h32, p.taps32, e0, p.pitch[0], r0, p.pitch[0], s,
                                     cnn));
     }
-    MG_TRY(timed(ctx, s, MG_K_UPDATE_MIXED, 0, 20 * m * m, [&] {
-      return launch_update_mixed(s, p.bc, p.n, u, p.pitch0, e0, p.pitch[0]);
-    }));
+    if (!added)
+      MG_TRY(timed(ctx, s, MG_K_UPDATE_MIXED, 0, 20 * m * m, [&] {
+        return launch_update_mixed(s, p.bc, p.n, u, p.pitch0, e0, p.pitch[0]);
+      }));
   }
   if (p.bc == kPeriodic) MG_HIP(launch_seam<double>(s, p.n, u, p.pitch0));
   return MG_OK;

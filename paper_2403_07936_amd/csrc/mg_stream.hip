@@ -18,15 +18,15 @@ __global__ void __launch_bounds__(64 * kWaves)
                    inv_h2, threadIdx.x & 63);
 }
 
-template <typename T, int BC>
+template <typename T, int BC, bool ADD>
 __global__ void __launch_bounds__(64 * kWaves)
     k_up_s(int n, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
            const T* __restrict__ f, int pf, const T* __restrict__ c, int pc, int nbands,
-           int nitems, int hs, T h2) {
+           int nitems, int hs, T h2, double* __restrict__ u64, int p64) {
   const int item = xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
   if (item >= nitems) return;
-  up_wave<T, BC>(n, uin, pui, uout, puo, f, pf, c, pc, item % nbands, item / nbands, hs, h2,
-                 threadIdx.x & 63);
+  up_wave<T, BC, ADD>(n, uin, pui, uout, puo, f, pf, c, pc, item % nbands, item / nbands, hs, h2,
+                      threadIdx.x & 63, u64, p64);
 }
 
 }  // namespace
@@ -67,7 +67,8 @@ hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pu
 
 template <typename T>
 hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
-                            const T* f, int pf, const T* c, int pc, int hs) {
+                            const T* f, int pf, const T* c, int pc, int hs, double* u64,
+                            int p64) {
   const int extent = bc == kPeriodic ? n - 1 : n;
   if (hs <= 0) hs = stream_segment_rows(n, bc, kUpOwned);
   const int nb = (extent + kUpOwned - 1) / kUpOwned;
@@ -76,12 +77,18 @@ hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui,
   const int blocks = (items + kWaves - 1) / kWaves;
   const double hd = 1.0 / (double)(n - 1);
   const T h2 = T(hd * hd);
-  if (bc == kDirichlet)
-    hipLaunchKernelGGL((k_up_s<T, kDirichlet>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin, pui,
-                       uout, puo, f, pf, c, pc, nb, items, hs, h2);
+  if (bc == kDirichlet && u64)
+    hipLaunchKernelGGL((k_up_s<T, kDirichlet, true>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
+                       pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64);
+  else if (bc == kDirichlet)
+    hipLaunchKernelGGL((k_up_s<T, kDirichlet, false>), dim3(blocks), dim3(64 * kWaves), 0, s, n,
+                       uin, pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64);
+  else if (u64)
+    hipLaunchKernelGGL((k_up_s<T, kPeriodic, true>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
+                       pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64);
   else
-    hipLaunchKernelGGL((k_up_s<T, kPeriodic>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin, pui,
-                       uout, puo, f, pf, c, pc, nb, items, hs, h2);
+    hipLaunchKernelGGL((k_up_s<T, kPeriodic, false>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
+                       pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64);
   return hipGetLastError();
 }
 
@@ -89,7 +96,7 @@ hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui,
   template hipError_t launch_down_stream<T>(hipStream_t, int, int, const T*, int, T*, int,      \
                                             const T*, int, T*, int, int);                        \
   template hipError_t launch_up_stream<T>(hipStream_t, int, int, const T*, int, T*, int,        \
-                                          const T*, int, const T*, int, int);
+                                          const T*, int, const T*, int, int, double*, int);
 
 MG_STREAM_INSTANTIATE(double)
 MG_STREAM_INSTANTIATE(float)

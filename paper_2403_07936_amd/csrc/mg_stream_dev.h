@@ -248,12 +248,15 @@ __device__ __forceinline__ T load_coef(const T* __restrict__ c, int pc, int I, i
   return (ni != nj) ? -v : v;
 }
 
-// Up pass of one wavefront item (see down_wave).
-template <typename T, int BC>
+// Up pass of one wavefront item (see down_wave).  With ADD, the finished
+// rows are added to u64 (the FP64 iterate of the mixed path, pitch p64) over
+// the unknowns -- the refinement update -- instead of being written to uout.
+template <typename T, int BC, bool ADD = false>
 __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pui,
                                         T* __restrict__ uout, int puo, const T* __restrict__ f,
                                         int pf, const T* __restrict__ c, int pc, int band, int seg,
-                                        int hs, T h2, int lane) {
+                                        int hs, T h2, int lane, double* __restrict__ u64 = nullptr,
+                                        int p64 = 0) {
   const int xw = band * kUpOwned - kUpHalo;
   const int x0 = xw + 2 * lane;
   const int ys = seg * hs;
@@ -281,10 +284,21 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
   for (int q = 0; q < 3; ++q) spline_x<T>(CR[q], CX[q]);
   CX[3][0] = CX[3][1] = T(0);
   const int steps = hs + 8;
+  // With u64: its row written at step s (row t0 + s - 4) is read kAhead
+  // steps earlier into UR[s & 7].
+  double UR[ADD ? 8 : 1][2];
+  auto load_u64 = [&](int slot, int row) {
+    if (ADD && row >= 0 && row < row_end) {
+      const double* q = u64 + (size_t)row * p64;
+      UR[slot][0] = wr0 ? q[x0] : 0.0;
+      UR[slot][1] = wr1 ? q[x0 + 1] : 0.0;
+    }
+  };
 #pragma unroll
   for (int k = 0; k < kAhead; ++k) {
     load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
     load_row<T, BC>(F[k], f, pf, t0 + k, n, col);
+    load_u64(k & 7, t0 - 4 + k);
   }
   for (int sb = 0; sb < steps; sb += 16) {
 #pragma unroll
@@ -295,6 +309,7 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
       if (s + kAhead < steps) {
         load_row<T, BC>(U[(k + kAhead) & 15], uin, pui, t + kAhead, n, col);
         load_row<T, BC>(F[(k + kAhead) & 15], f, pf, t + kAhead, n, col);
+        load_u64((k + kAhead) & 7, t - 4 + kAhead);
       }
       // coarse row q = (s - 1)/2 + 3 is needed from the first odd step on
       if (k & 1) {
@@ -334,9 +349,16 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
                        t - 4, 1, n, col, h2);
       const int tu = t - 4;
       if (tu >= ys && tu < ys + hs && tu < row_end) {
-        T* p = uout + (size_t)tu * puo;
-        if (wr0) p[x0] = U[(k + 12) & 15][0];
-        if (wr1) p[x0 + 1] = U[(k + 12) & 15][1];
+        if (ADD) {
+          double* q = u64 + (size_t)tu * p64;
+          const bool r = row_unknown<BC>(tu, n);
+          if (wr0 && col.unk0 && r) q[x0] = UR[k & 7][0] + (double)U[(k + 12) & 15][0];
+          if (wr1 && col.unk1 && r) q[x0 + 1] = UR[k & 7][1] + (double)U[(k + 12) & 15][1];
+        } else {
+          T* p = uout + (size_t)tu * puo;
+          if (wr0) p[x0] = U[(k + 12) & 15][0];
+          if (wr1) p[x0 + 1] = U[(k + 12) & 15][1];
+        }
       }
     }
   }
