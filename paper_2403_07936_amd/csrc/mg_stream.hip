@@ -7,15 +7,15 @@ namespace mg {
 using namespace stream;
 namespace {
 
-template <typename T, int BC>
+template <typename T, int BC, int UIN>
 __global__ void __launch_bounds__(64 * kWaves)
     k_down_s(int n, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
              const T* __restrict__ f, int pf, T* __restrict__ fc, int pfc, int nbands, int nitems,
              int hs, T h2, T inv_h2) {
   const int item = xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
   if (item >= nitems) return;
-  down_wave<T, BC>(n, uin, pui, uout, puo, f, pf, fc, pfc, item % nbands, item / nbands, hs, h2,
-                   inv_h2, threadIdx.x & 63);
+  down_wave<T, BC, UIN>(n, uin, pui, uout, puo, f, pf, fc, pfc, item % nbands, item / nbands, hs,
+                        h2, inv_h2, threadIdx.x & 63);
 }
 
 template <typename T, int BC, bool ADD>
@@ -56,12 +56,18 @@ hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pu
   const int blocks = (items + kWaves - 1) / kWaves;
   const double hd = 1.0 / (double)(n - 1);
   const T h2 = T(hd * hd), inv_h2 = T((double)(n - 1) * (double)(n - 1));
-  if (bc == kDirichlet)
-    hipLaunchKernelGGL((k_down_s<T, kDirichlet>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
+  if (bc == kDirichlet && uin)
+    hipLaunchKernelGGL((k_down_s<T, kDirichlet, 1>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
+                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2);
+  else if (bc == kDirichlet)
+    hipLaunchKernelGGL((k_down_s<T, kDirichlet, 0>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
+                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2);
+  else if (uin)
+    hipLaunchKernelGGL((k_down_s<T, kPeriodic, 1>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
                        pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2);
   else
-    hipLaunchKernelGGL((k_down_s<T, kPeriodic>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin, pui,
-                       uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2);
+    hipLaunchKernelGGL((k_down_s<T, kPeriodic, 0>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
+                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2);
   return hipGetLastError();
 }
 

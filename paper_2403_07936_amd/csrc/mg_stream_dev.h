@@ -105,14 +105,20 @@ __device__ __forceinline__ bool row_unknown(int t, int n) {
   return BC == kPeriodic || (t >= 1 && t <= n - 2);
 }
 
+// Loads are unconditional: rows and columns outside a Dirichlet grid are
+// clamped to node 0 of that axis (a boundary node), and such values only
+// feed results at nodes outside the grid or in the halo, which are never
+// written.  Conditional loads would leave the compiler unable to count the
+// loads in flight, and every use of a row would then wait for all of them,
+// the prefetched rows included.
 template <typename T, int BC>
 __device__ __forceinline__ void load_row(T (&dst)[2], const T* __restrict__ a, int pa, int t, int n,
                                          const Cols<BC>& col) {
   bool rin;
   const int r = row_index<BC>(t, n, &rin);
   const T* p = a + (size_t)r * pa;
-  dst[0] = (rin && col.in0) ? p[col.c0] : T(0);
-  dst[1] = (rin && col.in1) ? p[col.c1] : T(0);
+  dst[0] = p[col.c0];
+  dst[1] = p[col.c1];
 }
 
 // Red-black half-sweep on one row: the node of colour `colour` among the
@@ -152,7 +158,9 @@ __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2],
 
 // Down pass of one wavefront item: band `band` (128 columns) and row segment
 // `seg` (hs rows) of a level with n nodes per side.  lane = threadIdx & 63.
-template <typename T, int BC>
+// UIN: 1 reads the initial u from uin, 0 starts from u = 0 (uin unused),
+// -1 decides at run time (uin == nullptr: zero).
+template <typename T, int BC, int UIN = -1>
 __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
@@ -179,9 +187,10 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
 
   const int t0 = ys - 6;
   const int steps = hs + 11;
+  const bool read_u = UIN == 1 || (UIN == -1 && uin != nullptr);
 #pragma unroll
   for (int k = 0; k < kAhead; ++k) {
-    if (uin) load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
+    if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
     load_row<T, BC>(F[k], f, pf, t0 + k, n, col);
   }
   for (int sb = 0; sb < steps; sb += 16) {
@@ -190,9 +199,10 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
       const int s = sb + k;
       if (s >= steps) break;
       const int t = t0 + s;
-      if (s + kAhead < steps) {
+      // Rows kAhead ahead (past the segment's last step too: harmless reads).
+      {
         T(&nu)[2] = U[(k + kAhead) & 15];
-        if (uin) load_row<T, BC>(nu, uin, pui, t + kAhead, n, col);
+        if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(nu, uin, pui, t + kAhead, n, col);
         else nu[0] = nu[1] = T(0);
         load_row<T, BC>(F[(k + kAhead) & 15], f, pf, t + kAhead, n, col);
       }
@@ -288,10 +298,11 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
   // steps earlier into UR[s & 7].
   double UR[ADD ? 8 : 1][2];
   auto load_u64 = [&](int slot, int row) {
-    if (ADD && row >= 0 && row < row_end) {
-      const double* q = u64 + (size_t)row * p64;
-      UR[slot][0] = wr0 ? q[x0] : 0.0;
-      UR[slot][1] = wr1 ? q[x0 + 1] : 0.0;
+    if (ADD) {
+      const int rr = row < 0 ? 0 : (row >= row_end ? row_end - 1 : row);
+      const double* q = u64 + (size_t)rr * p64;
+      UR[slot][0] = q[col.c0];
+      UR[slot][1] = q[col.c1];
     }
   };
 #pragma unroll
@@ -306,7 +317,7 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
       const int s = sb + k;
       if (s >= steps) break;
       const int t = t0 + s;
-      if (s + kAhead < steps) {
+      {  // rows kAhead ahead (past the segment's last step too: harmless reads)
         load_row<T, BC>(U[(k + kAhead) & 15], uin, pui, t + kAhead, n, col);
         load_row<T, BC>(F[(k + kAhead) & 15], f, pf, t + kAhead, n, col);
         load_u64((k + kAhead) & 7, t - 4 + kAhead);
