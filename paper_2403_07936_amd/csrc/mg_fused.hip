@@ -5,10 +5,11 @@
 //             with a 6-node halo, each half-sweep invalidates one more ring).
 //   k_up    : cubic-spline evaluation of the coarse correction, u += P e_c,
 //             then 2 red-black sweeps, in one pass (4-node halo).
-//   k_pre_x / k_pre_y : B-spline prefilter of a coarse level (the non-local
-//             part of the spline), as causal + anti-causal first-order
-//             recursions over 64-node segments with a warm-up run long enough
-//             that the truncated state is below the working precision.
+//   k_pre_tile : B-spline prefilter of a coarse level (the non-local part of
+//             the spline) in one pass over LDS tiles, as causal + anti-causal
+//             first-order recursions over short chunks with a warm-up run
+//             long enough that the truncated state is below the working
+//             precision.
 //   k_tail  : the whole V-cycle below a 65 x 65 level in one workgroup, with
 //             every level resident in LDS, including the 5 x 5 direct solve
 //             (FP64) and the prefilter of the top tail level.
@@ -199,30 +200,12 @@ __global__ void __launch_bounds__(kThreads)
 
 using namespace dev;
 
-// Along y: one thread per (column, segment); lanes are consecutive columns,
-// so every load and store is coalesced (prey_wave).
 template <typename T, int BC>
 __global__ void __launch_bounds__(256)
-    k_pre_y(int nc, const T* __restrict__ in, int pi, T* __restrict__ out, int po, int nseg) {
-  const int seg = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (seg >= nseg) return;
-  prey_wave<T, BC>(nc, in, pi, out, po, blockIdx.x * 64, seg, threadIdx.x & 63);
-}
-
-// Along x: one wavefront per row, the recursion carried across the row in
-// chunks of 64 columns (wave_line_prefilter); each element is read and
-// written once, coalesced.  The causal values wait in LDS.
-template <typename T, int BC>
-__global__ void __launch_bounds__(256)
-    k_pre_x(int nc, const T* __restrict__ in, int pi, T* __restrict__ out, int po) {
+    k_pre_tile(int nc, const T* __restrict__ in, int pi, T* __restrict__ out, int po, int tiles_x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int M = BC == kPeriodic ? nc - 1 : nc;
-  T* buf = reinterpret_cast<T*>(smem_raw) + wave * (M + 128);
-  const int r = blockIdx.x * (blockDim.x >> 6) + wave;
-  if (r >= nc) return;
-  const ScanWeights<T> w(lane);
-  wave_line_prefilter<T, BC>(in + (size_t)r * pi, 1, buf, out + (size_t)r * po, 1, nc, w, lane);
+  pre_tile_block<T, BC, 256>(nc, in, pi, out, po, blockIdx.x, tiles_x,
+                             reinterpret_cast<T*>(smem_raw));
 }
 
 template <typename T, int BC>
@@ -246,15 +229,18 @@ int fused_tile_x() { return 64; }
 int fused_tile_y() { return 32; }
 
 hipError_t fused_init() {
-  // x-pass line buffers: one wavefront per workgroup suffices up to the
-  // largest coarse level (nc = 8193 for n = 16385): (8193 + 128) doubles.
-  const int xmax = (8193 + 128) * 8;
   hipError_t e0;
-  e0 = hipFuncSetAttribute((const void*)k_pre_x<double, kDirichlet>,
-                           hipFuncAttributeMaxDynamicSharedMemorySize, xmax);
+  e0 = hipFuncSetAttribute((const void*)k_pre_tile<double, kDirichlet>,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)PreTile<double>::kLds);
   if (e0 != hipSuccess) return e0;
-  e0 = hipFuncSetAttribute((const void*)k_pre_x<double, kPeriodic>,
-                           hipFuncAttributeMaxDynamicSharedMemorySize, xmax);
+  e0 = hipFuncSetAttribute((const void*)k_pre_tile<double, kPeriodic>,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)PreTile<double>::kLds);
+  if (e0 != hipSuccess) return e0;
+  e0 = hipFuncSetAttribute((const void*)k_pre_tile<float, kDirichlet>,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)PreTile<float>::kLds);
+  if (e0 != hipSuccess) return e0;
+  e0 = hipFuncSetAttribute((const void*)k_pre_tile<float, kPeriodic>,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)PreTile<float>::kLds);
   if (e0 != hipSuccess) return e0;
   const size_t max64 = tail_bytes(kTailMaxSide, sizeof(double));
   const size_t max32 = tail_bytes(kTailMaxSide, sizeof(float));
@@ -314,20 +300,17 @@ hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uou
 template <typename T>
 hipError_t launch_prefilter_iir(hipStream_t s, int bc, int nc, const T* e, int pe, T* tmp, int pt,
                                 T* c, int pc) {
-  using C = PreCfg<T>;
-  const int nseg = (nc + C::S - 1) / C::S;
-  int waves = 4;
-  while (waves > 1 && (size_t)waves * (nc + 128) * sizeof(T) > 65536) waves /= 2;
-  const dim3 gx((nc + waves - 1) / waves);
-  const size_t lds = (size_t)waves * (nc + 128) * sizeof(T);
-  const dim3 gy((nc + 63) / 64, (nseg + 3) / 4);
-  if (bc == kDirichlet) {
-    hipLaunchKernelGGL((k_pre_x<T, kDirichlet>), gx, dim3(64 * waves), lds, s, nc, e, pe, tmp, pt);
-    hipLaunchKernelGGL((k_pre_y<T, kDirichlet>), gy, dim3(256), 0, s, nc, tmp, pt, c, pc, nseg);
-  } else {
-    hipLaunchKernelGGL((k_pre_x<T, kPeriodic>), gx, dim3(64 * waves), lds, s, nc, e, pe, tmp, pt);
-    hipLaunchKernelGGL((k_pre_y<T, kPeriodic>), gy, dim3(256), 0, s, nc, tmp, pt, c, pc, nseg);
-  }
+  using C = PreTile<T>;
+  (void)tmp;
+  (void)pt;
+  const int extent = bc == kPeriodic ? nc - 1 : nc;
+  const int tx = (extent + C::TW - 1) / C::TW, ty = (extent + C::TH - 1) / C::TH;
+  if (bc == kDirichlet)
+    hipLaunchKernelGGL((k_pre_tile<T, kDirichlet>), dim3(tx * ty), dim3(256), C::kLds, s, nc, e, pe,
+                       c, pc, tx);
+  else
+    hipLaunchKernelGGL((k_pre_tile<T, kPeriodic>), dim3(tx * ty), dim3(256), C::kLds, s, nc, e, pe,
+                       c, pc, tx);
   return hipGetLastError();
 }
 

@@ -13,9 +13,13 @@ constexpr int kDirichlet = 0;
 constexpr int kPeriodic = 1;
 
 // Half-width of the truncated spline prefilter (see spline_taps): the
-// neglected weights sum to below the unit roundoff of each precision.
+// neglected weights sum to below the unit roundoff of FP64 (|z|^28 ~ 1e-16)
+// and to ~1/300 of that of FP32 (|z|^18 ~ 2e-10).  Chunked recursions that
+// start from a zero state K nodes out leave steps of that relative size at
+// chunk edges, which the 5-point operator amplifies; at |z|^14 ~ 1e-8 they
+// showed in FP32 residual norms.
 constexpr int kPrefilterHalfTapsF64 = 28;
-constexpr int kPrefilterHalfTapsF32 = 14;
+constexpr int kPrefilterHalfTapsF32 = 18;
 constexpr int kMaxPrefilterTaps = 64;
 
 // Levels with at most this many nodes per side run inside the single-
@@ -184,8 +188,7 @@ enum PKind : int {
   kItemRes = 0,   // FP64 residual rows -> FP32 right-hand side (a = first row)
   kItemDown = 1,  // a = band, b = segment
   kItemTail = 2,  // workgroup item
-  kItemPreX = 3,  // a = row
-  kItemPreY = 4,  // a = first column, b = segment
+  kItemPre = 3,   // workgroup item: prefilter tile a of b tiles along x
   kItemUp = 5,    // a = band, b = segment
   kItemUpd = 6    // u64 += e rows (a = first row)
 };

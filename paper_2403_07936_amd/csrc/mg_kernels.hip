@@ -351,15 +351,37 @@ __global__ void __launch_bounds__(TX* TY)
   }
 }
 
-__global__ void __launch_bounds__(TX* TY)
+// Sum of `count` partials per group (group g at partials + g * stride), one
+// workgroup per group.  Each thread keeps 16 accumulators over its strided
+// share so that 16 loads are in flight at once; the order of every addition
+// is fixed, so the result is deterministic.
+constexpr int kReduceThreads = 1024;
+constexpr int kReduceLanes = 16;
+__global__ void __launch_bounds__(kReduceThreads)
     k_reduce(const double* __restrict__ partials, int count, int stride, double* __restrict__ out) {
-  __shared__ double sh[TX * TY];
-  const int t = threadIdx.y * TX + threadIdx.x;
+  __shared__ double sh[kReduceThreads];
+  const int t = threadIdx.x;
   const double* p = partials + (size_t)blockIdx.x * stride;
-  double acc = 0.0;
-  for (int k = t; k < count; k += TX * TY) acc += p[k];
-  const double s = block_sum(acc, sh);
-  if (t == 0) out[blockIdx.x] = s;
+  double acc[kReduceLanes];
+#pragma unroll
+  for (int q = 0; q < kReduceLanes; ++q) acc[q] = 0.0;
+  int k = t;
+  for (; k + (kReduceLanes - 1) * kReduceThreads < count; k += kReduceLanes * kReduceThreads) {
+#pragma unroll
+    for (int q = 0; q < kReduceLanes; ++q) acc[q] += p[k + q * kReduceThreads];
+  }
+  for (; k < count; k += kReduceThreads) acc[0] += p[k];
+#pragma unroll
+  for (int w = kReduceLanes / 2; w > 0; w >>= 1)
+#pragma unroll
+    for (int q = 0; q < w; ++q) acc[q] += acc[q + w];
+  sh[t] = acc[0];
+  __syncthreads();
+  for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  if (t == 0) out[blockIdx.x] = sh[0];
 }
 
 __global__ void __launch_bounds__(TX* TY)
@@ -543,7 +565,8 @@ hipError_t launch_sum(hipStream_t s, int bc, int n, const double* a, int pa, dou
 
 hipError_t launch_reduce(hipStream_t s, const double* partials, int count, int stride, int groups,
                          double* out) {
-  hipLaunchKernelGGL(k_reduce, dim3(groups), kBlock, 0, s, partials, count, stride, out);
+  hipLaunchKernelGGL(k_reduce, dim3(groups), dim3(kReduceThreads), 0, s, partials, count, stride,
+                     out);
   return hipGetLastError();
 }
 

@@ -134,6 +134,16 @@ __global__ void __launch_bounds__(kPersistThreads)
             inv, sm);
         __syncthreads();
       }
+    } else if (P.kind == kItemPre) {
+      for (int i = blockIdx.x; i < P.count; i += gridDim.x) {
+        const PItem it = items[P.first + i];
+        const PProblem& p = probs[it.prob];
+        if (!p.active) continue;
+        const PLevel& L = p.lv[it.level];
+        pre_tile_block<T, BC, kPersistThreads>(L.n, static_cast<const T*>(L.u), L.pitch_u,
+                                               static_cast<T*>(L.c), L.pitch, it.a, it.b, sm);
+        __syncthreads();
+      }
     } else {
       for (int i = gwave; i < P.count; i += nwaves) {
         const PItem it = items[P.first + i];
@@ -166,19 +176,6 @@ __global__ void __launch_bounds__(kPersistThreads)
                            T(hd * hd), lane);
             break;
           }
-          case kItemPreX: {
-            const ScanWeights<T> w(lane);
-            const int M = BC == kPeriodic ? L.n - 1 : L.n;
-            T* buf = sm + wave * (M + 128);
-            const T* src = static_cast<const T*>(L.u) + (size_t)it.a * L.pitch_u;
-            T* dst = static_cast<T*>(L.tmp) + (size_t)it.a * L.pitch;
-            wave_line_prefilter<T, BC>(src, 1, buf, dst, 1, L.n, w, lane);
-            break;
-          }
-          case kItemPreY:
-            prey_wave<T, BC>(L.n, static_cast<const T*>(L.tmp), L.pitch, static_cast<T*>(L.c),
-                             L.pitch, it.a, it.b, lane);
-            break;
           default:
             break;
         }

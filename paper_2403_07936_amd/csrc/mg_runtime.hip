@@ -591,8 +591,7 @@ int32_t build_persistent(mg_ctx_s* ctx) {
       const int extent = p.bc == kPeriodic ? L.n - 1 : L.n;
       L.nb_down = (extent + stream_down_owned() - 1) / stream_down_owned();
       L.nb_up = (extent + stream_up_owned() - 1) / stream_up_owned();
-      if (l > 0 && l < p.tail)
-        lds = std::max(lds, (size_t)(kPersistThreads / 64) * (L.n + 128) * sizeof(T));
+      if (l > 0 && l < p.tail) lds = std::max(lds, dev::PreTile<T>::kLds);
     }
     K = std::max(K, p.tail);
     lds = std::max(lds, dev::tail_bytes(p.side[p.tail], sizeof(T)));
@@ -634,21 +633,15 @@ int32_t build_persistent(mg_ctx_s* ctx) {
     size_t first = items.size();
     for (int b = 0; b < B; ++b) {
       const int l = ctx->probs[b].tail - 1 - k;
-      if (l >= 0 && l + 1 < ctx->probs[b].tail)
-        for (int r = 0; r < ctx->probs[b].side[l + 1]; ++r) items.push_back({b, l + 1, r, 0});
-    }
-    close_phase(kItemPreX, first);
-    first = items.size();
-    for (int b = 0; b < B; ++b) {
-      const int l = ctx->probs[b].tail - 1 - k;
       if (l >= 0 && l + 1 < ctx->probs[b].tail) {
+        using C = dev::PreTile<T>;
         const int nc = ctx->probs[b].side[l + 1];
-        const int S = sizeof(T) == 8 ? 16 : 32;
-        for (int sg = 0; sg * S < nc; ++sg)
-          for (int c0 = 0; c0 < nc; c0 += 64) items.push_back({b, l + 1, c0, sg});
+        const int extent = P.bc == kPeriodic ? nc - 1 : nc;
+        const int tx = (extent + C::TW - 1) / C::TW, ty = (extent + C::TH - 1) / C::TH;
+        for (int tile = 0; tile < tx * ty; ++tile) items.push_back({b, l + 1, tile, tx});
       }
     }
-    close_phase(kItemPreY, first);
+    close_phase(kItemPre, first);
     first = items.size();
     for (int b = 0; b < B; ++b) {
       const int l = ctx->probs[b].tail - 1 - k;

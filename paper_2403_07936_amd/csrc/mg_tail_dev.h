@@ -12,66 +12,152 @@ namespace dev {
 // extended sequence.  S^-1 = g / ((1 - z q^-1)(1 - z q)), z = sqrt(3) - 2,
 // g = 12 - 6 sqrt(3): a causal recursion p_k = e_k + z p_{k-1} followed by an
 // anti-causal one m_k = p_k + z m_{k+1}, c_k = g m_k.  A thread filters one
-// segment of S nodes of one line held in registers; both recursions start K
-// nodes outside the segment from a zero state, and the neglected state is
-// below |z|^K of the data.
+// chunk of S nodes of one line; both recursions start K nodes outside the
+// chunk from a zero state, and the neglected state is below |z|^K of the
+// data.
 constexpr double kZ = kPrefZ;
 constexpr double kG = kPrefG;
-
-template <typename T, int L, int K>
-__device__ __forceinline__ void iir_regs(T (&v)[L]) {
-  const T z = T(kZ), g = T(kG);
-  T p = T(0);
-#pragma unroll
-  for (int k = 0; k < L; ++k) {
-    p = v[k] + z * p;
-    v[k] = p;
-  }
-  T m = T(0);
-#pragma unroll
-  for (int k = L - 1; k >= K; --k) {
-    m = v[k] + z * m;
-    v[k] = g * m;
-  }
-}
 
 template <typename T>
 struct PreCfg {
   static constexpr int K = sizeof(T) == 8 ? kPrefilterHalfTapsF64 : kPrefilterHalfTapsF32;
-  static constexpr int S = sizeof(T) == 8 ? 16 : 32;  // segment length
-  static constexpr int L = S + 2 * K;
-  // LDS row pitch for the x pass: lanes read rows with this stride, chosen
-  // so that 32 consecutive rows fall on distinct banks.
-  static constexpr int P = sizeof(T) == 8 ? (L + 15) / 16 * 16 + 1 : L + 1 - (L % 2);
 };
 
-// Along y: one wavefront filters 64 consecutive columns [c0, c0 + 64) over
-// one segment of PreCfg<T>::S rows, one column per lane (coalesced).
-template <typename T, int BC>
-__device__ __forceinline__ void prey_wave(int nc, const T* __restrict__ in, int pi,
-                                          T* __restrict__ out, int po, int c0, int seg, int lane) {
-  using C = PreCfg<T>;
-  const int col = c0 + lane;
-  const int r0 = seg * C::S;
-  const bool cok = col < nc;
-  const int cc = cok ? col : 0;
-  T v[C::L];
+// B-spline prefilter of a whole level in one pass.  A workgroup owns a
+// TH x TW tile of coefficients: it loads the tile with a K-node halo of the
+// extended grid (ext_node_any: odd reflection or periodic wrap) into LDS,
+// filters every row of the halo'd tile along x into a second LDS array and
+// then the tile's columns along y.  Each thread of a pass takes S
+// consecutive coefficients of one line; both recursions start K nodes
+// outside its chunk from a zero state (chunk_iir), so the
+// neglected state is below |z|^K of the data.
+template <typename T>
+struct PreTile {
+  static constexpr int K = PreCfg<T>::K;
+  static constexpr int S = sizeof(T) == 8 ? 8 : 16;
+  static constexpr int TW = 64;
+  static constexpr int TH = 4 * S;       // one column chunk per thread
+  static constexpr int HI = TH + 2 * K;  // rows of the halo'd tile
+  static constexpr int WI = TW + 2 * K;  // columns of the halo'd tile
+  static constexpr int PI = WI | 1;      // LDS pitches: odd, so that lanes on
+  static constexpr int PM = TW + 1;      // consecutive rows hit distinct banks
+  static constexpr size_t kLds = (size_t)(HI * PI + HI * PM) * sizeof(T);
+  static_assert(WI <= 128, "a lane loads at most two columns of the halo'd tile");
+};
+
+// S coefficients y from S + 2K consecutive nodes x[0], x[sx], ... of an
+// extended line (chunk at offset K).
+template <typename T, int S, int K>
+__device__ __forceinline__ void chunk_iir(const T* x, int sx, T (&y)[S]) {
+  const T z = T(kZ), g = T(kG);
+  T p = T(0);
 #pragma unroll
-  for (int k = 0; k < C::L; ++k) {
-    bool neg;
-    const int r = ext_node_any<BC>(r0 - C::K + k, nc, &neg);
-    const T x = cok ? in[(size_t)r * pi + cc] : T(0);
-    v[k] = neg ? -x : x;
+  for (int k = 0; k < K; ++k) p = x[k * sx] + z * p;
+  T v[S + K];
+#pragma unroll
+  for (int k = 0; k < S + K; ++k) {
+    p = x[(K + k) * sx] + z * p;
+    v[k] = p;
   }
-  iir_regs<T, C::L, C::K>(v);
-  if (!cok) return;
+  T m = T(0);
 #pragma unroll
-  for (int j = 0; j < C::S; ++j) {
-    const int r = r0 + j;
-    if (r >= nc) break;
-    T y = v[C::K + j];
-    if (BC == kDirichlet && (r == 0 || r == nc - 1)) y = T(0);
-    out[(size_t)r * po + col] = y;
+  for (int k = S + K - 1; k >= 0; --k) {
+    m = v[k] + z * m;
+    if (k < S) y[k] = g * m;
+  }
+}
+
+// One tile of the level prefilter by a workgroup of NT threads (a multiple
+// of 64, at least 256); smem = PreTile<T>::kLds bytes of LDS.
+template <typename T, int BC, int NT>
+__device__ __forceinline__ void pre_tile_block(int nc, const T* __restrict__ in, int pi,
+                                               T* __restrict__ out, int po, int tile, int tiles_x,
+                                               T* smem) {
+  using C = PreTile<T>;
+  static_assert(NT % 64 == 0 && NT >= 256, "pre_tile_block needs whole wavefronts, at least four");
+  constexpr int kWaves = NT / 64;
+  __shared__ int rtab[C::HI], ctab[C::WI];
+  T* si = smem;
+  T* sm = si + C::HI * C::PI;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int y0 = ty * C::TH, x0 = tx * C::TW;
+  // Stored node of every row and column of the halo'd tile, complemented
+  // (~index) where the extension negates the value.
+  for (int k = t; k < C::HI + C::WI; k += NT) {
+    bool neg;
+    if (k < C::HI) {
+      const int r = ext_node_any<BC>(y0 - C::K + k, nc, &neg);
+      rtab[k] = neg ? ~r : r;
+    } else {
+      const int c = ext_node_any<BC>(x0 - C::K + (k - C::HI), nc, &neg);
+      ctab[k - C::HI] = neg ? ~c : c;
+    }
+  }
+  __syncthreads();
+  // Load: a wavefront per row, a lane per column (two for the last lanes).
+  // Every load of the wavefront is issued before the first store to LDS
+  // (rows past the tile repeat its last row and are not stored), so the
+  // tile costs one memory round trip.
+  constexpr int kRows = (C::HI + kWaves - 1) / kWaves;
+  const int lx1 = lane + 64 < C::WI ? lane + 64 : C::WI - 1;
+  const int ce0 = ctab[lane < C::WI ? lane : C::WI - 1], ce1 = ctab[lx1];
+  const int c0 = ce0 < 0 ? ~ce0 : ce0, c1 = ce1 < 0 ? ~ce1 : ce1;
+  T v0[kRows], v1[kRows];
+  int re[kRows];
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const int ly = wave + i * kWaves;
+    re[i] = rtab[ly < C::HI ? ly : C::HI - 1];
+  }
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const T* row = in + (size_t)(re[i] < 0 ? ~re[i] : re[i]) * pi;
+    v0[i] = row[c0];
+    v1[i] = row[c1];
+  }
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const int ly = wave + i * kWaves;
+    if (ly < C::HI) {
+      if (lane < C::WI) si[ly * C::PI + lane] = ((re[i] ^ ce0) < 0) ? -v0[i] : v0[i];
+      if (lane + 64 < C::WI) si[ly * C::PI + lane + 64] = ((re[i] ^ ce1) < 0) ? -v1[i] : v1[i];
+    }
+  }
+  __syncthreads();
+  // Rows of the halo'd tile along x (lanes on consecutive rows).
+  for (int w = t; w < C::HI * (C::TW / C::S); w += NT) {
+    const int ly = w % C::HI, q = (w / C::HI) * C::S;
+    T y[C::S];
+    chunk_iir<T, C::S, C::K>(si + ly * C::PI + q, 1, y);
+#pragma unroll
+    for (int k = 0; k < C::S; ++k) {
+      const int gx = x0 + q + k;
+      sm[ly * C::PM + q + k] = (BC == kDirichlet && (gx == 0 || gx == nc - 1)) ? T(0) : y[k];
+    }
+  }
+  __syncthreads();
+  // Columns along y (lanes on consecutive columns) and the store.
+  const int M = BC == kPeriodic ? nc - 1 : nc;
+  if (t < C::TW * (C::TH / C::S)) {
+    const int x = lane, q = wave * C::S, gx = x0 + x;
+    T y[C::S];
+    chunk_iir<T, C::S, C::K>(sm + q * C::PM + x, C::PM, y);
+    if (gx < M) {
+#pragma unroll
+      for (int k = 0; k < C::S; ++k) {
+        const int gy = y0 + q + k;
+        if (gy < M) {
+          const T v = (BC == kDirichlet && (gy == 0 || gy == nc - 1)) ? T(0) : y[k];
+          out[(size_t)gy * po + gx] = v;
+          if (BC == kPeriodic) {
+            if (gy == 0) out[(size_t)(nc - 1) * po + gx] = v;
+            if (gx == 0) out[(size_t)gy * po + nc - 1] = v;
+            if (gy == 0 && gx == 0) out[(size_t)(nc - 1) * po + nc - 1] = v;
+          }
+        }
+      }
+    }
   }
 }
 
@@ -171,21 +257,84 @@ __device__ __forceinline__ int tail_ext(int q, int nc, bool* neg) {
   return ext_node<BC>(q, nc, neg);
 }
 
-// Prefilter a tail grid: rows of src (in place), then columns into dst
-// (pitch pd); each wavefront takes every (TR/2)-th line, with its own slice
-// of the scratch grid for the causal values.
+// Prefilter of the tail grids by per-thread chunks.  A thread takes S
+// consecutive coefficients q0 .. q0 + S - 1 of one line: the causal
+// recursion starts K nodes before the chunk from a zero state and runs K
+// nodes past it, the anti-causal one starts there from a zero state (the
+// truncation of the level prefilter, chunk_iir).  Extended-sequence
+// nodes come from a table built once per call: entry q + K, q in
+// [-K, nc + S + K), holds the stored node of ext_node_any, complemented
+// (~index) where the extension negates the value.
+template <typename T>
+struct TailPre {
+  static constexpr int K = PreCfg<T>::K;
+  static constexpr int S = sizeof(T) == 8 ? 8 : 16;
+  static constexpr int kTable = kTailMaxSide + S + 2 * K;
+};
+
+template <typename T, int BC>
+__device__ __forceinline__ void tail_chunk(const T* src, int ss, T* dst, int ds, int nc, int q0,
+                                           const int* tbl) {
+  constexpr int K = TailPre<T>::K, S = TailPre<T>::S;
+  const T z = T(kZ), g = T(kG);
+  auto at = [&](int k) {  // node q0 - K + k of the extended line
+    const int e = tbl[q0 + k];
+    const T x = src[(e < 0 ? ~e : e) * ss];
+    return e < 0 ? -x : x;
+  };
+  T p = T(0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) p = at(k) + z * p;
+  T v[S + K];
+#pragma unroll
+  for (int k = 0; k < S + K; ++k) {
+    p = at(K + k) + z * p;
+    v[k] = p;
+  }
+  T m = T(0);
+#pragma unroll
+  for (int k = S + K - 1; k >= 0; --k) {
+    m = v[k] + z * m;
+    v[k] = m;
+  }
+  const int M = BC == kPeriodic ? nc - 1 : nc;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const int q = q0 + k;
+    if (q < M) {
+      T y = g * v[k];
+      if (BC == kDirichlet && (q == 0 || q == nc - 1)) y = T(0);
+      dst[q * ds] = y;
+      if (BC == kPeriodic && q == 0) dst[(nc - 1) * ds] = y;
+    }
+  }
+}
+
+// Prefilter a tail grid src (side nc, pitch nc): rows into the scratch grid
+// tmp, then columns into dst (pitch pd; may be src).
 template <typename T, int BC, int TR>
-__device__ __forceinline__ void tail_prefilter(T* src, T* tmp, T* dst, int pd, int nc) {
+__device__ __forceinline__ void tail_prefilter(const T* src, T* tmp, T* dst, int pd, int nc) {
+  using C = TailPre<T>;
+  __shared__ int tbl[C::kTable];
   const int t = tail_tid();
-  const int lane = t & 63, wave = t >> 6;
-  constexpr int kLineWaves = TR / 2;
-  const ScanWeights<T> w(lane);
-  T* buf = tmp + wave * (nc + 128);
-  for (int line = wave; line < nc; line += kLineWaves)
-    wave_line_prefilter<T, BC>(src + line * nc, 1, buf, src + line * nc, 1, nc, w, lane);
+  for (int q = t; q < nc + C::S + 2 * C::K; q += 32 * TR) {
+    bool neg;
+    const int j = ext_node_any<BC>(q - C::K, nc, &neg);
+    tbl[q] = neg ? ~j : j;
+  }
   __syncthreads();
-  for (int line = wave; line < nc; line += kLineWaves)
-    wave_line_prefilter<T, BC>(src + line, nc, buf, dst + line, pd, nc, w, lane);
+  // Rows: the periodic seam row is never read by the column pass.
+  const int rows = BC == kPeriodic ? nc - 1 : nc;
+  const int chunks = (nc + C::S - 1) / C::S;
+  for (int w = t; w < rows * chunks; w += 32 * TR) {
+    const int line = w % rows, q0 = (w / rows) * C::S;
+    tail_chunk<T, BC>(src + line * nc, 1, tmp + line * nc, 1, nc, q0, tbl);
+  }
+  __syncthreads();
+  for (int w = t; w < nc * chunks; w += 32 * TR) {
+    const int line = w % nc, q0 = (w / nc) * C::S;
+    tail_chunk<T, BC>(tmp + line, nc, dst + line, pd, nc, q0, tbl);
+  }
   __syncthreads();
 }
 
@@ -315,18 +464,16 @@ __device__ __forceinline__ void tail_block(int nt, const T* __restrict__ uin, in
   }
 }
 
-// u and f of every tail level, then the scratch grid: the residual of the
-// top level, the x-interpolated rows of a prolongation ((nt+1)/2 + 2 rows of
-// nt), or the per-wavefront line buffers of the prefilter (TR/2 <= 16 of
-// them).
+// u and f of every tail level, then the scratch grid of nt x nt: the
+// residual of the top level, the x-interpolated rows of a prolongation
+// ((nt+1)/2 + 2 rows of nt), or the row pass of the prefilter.
 __host__ __device__ inline size_t tail_bytes(int nt, size_t elem) {
   size_t tot = 0;
   for (int n = nt;; n = (n - 1) / 2 + 1) {
     tot += 2 * (size_t)n * n;
     if (n == 5) break;
   }
-  const size_t scratch = ((size_t)nt * nt > (size_t)16 * (nt + 128) ? (size_t)nt * nt : (size_t)16 * (nt + 128));
-  return (tot + scratch) * elem;
+  return (tot + (size_t)nt * nt) * elem;
 }
 
 }  // namespace dev
