@@ -30,25 +30,51 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kTailThreads = 1024;
 
+// Loads a W x HH tile whose node (0, 0) is global node (gy0, gx0) into s:
+// periodic wrap, zero outside a Dirichlet grid, all zero if `zero`.  Every
+// load of the thread is issued (from clamped, in-bounds indices) before the
+// first store to LDS, so the tile costs one memory round trip.
 template <typename T, int BC, int W, int HH>
 __device__ __forceinline__ void load_tile(T* s, const T* __restrict__ g, int pg, int n, int gy0,
                                           int gx0, bool zero) {
-  const int N = n - 1;
+  constexpr int kIt = (W * HH + kThreads - 1) / kThreads;
+  if (zero) {
 #pragma unroll
-  for (int k = threadIdx.x; k < W * HH; k += kThreads) {
+    for (int i = 0; i < kIt; ++i) {
+      const int k = threadIdx.x + i * kThreads;
+      if (k < W * HH) s[k] = T(0);
+    }
+    return;
+  }
+  const int N = n - 1;
+  T v[kIt];
+#pragma unroll
+  for (int i = 0; i < kIt; ++i) {
+    const int k0 = threadIdx.x + i * kThreads;
+    const int k = k0 < W * HH ? k0 : W * HH - 1;
     const int ly = k / W, lx = k - ly * W;
     int gy = gy0 + ly, gx = gx0 + lx;
-    T v = T(0);
-    if (!zero) {
-      if constexpr (BC == kPeriodic) {
-        gy = gy < 0 ? gy + N : (gy >= N ? gy - N : gy);
-        gx = gx < 0 ? gx + N : (gx >= N ? gx - N : gx);
-        v = g[(size_t)gy * pg + gx];
-      } else {
-        if (gy >= 0 && gy < n && gx >= 0 && gx < n) v = g[(size_t)gy * pg + gx];
-      }
+    if constexpr (BC == kPeriodic) {
+      gy = gy < 0 ? gy + N : (gy >= N ? gy - N : gy);
+      gx = gx < 0 ? gx + N : (gx >= N ? gx - N : gx);
+    } else {
+      gy = gy < 0 ? 0 : (gy > N ? N : gy);
+      gx = gx < 0 ? 0 : (gx > N ? N : gx);
     }
-    s[k] = v;
+    v[i] = g[(size_t)gy * pg + gx];
+  }
+#pragma unroll
+  for (int i = 0; i < kIt; ++i) {
+    const int k = threadIdx.x + i * kThreads;
+    if (k < W * HH) {
+      T x = v[i];
+      if constexpr (BC == kDirichlet) {
+        const int ly = k / W, lx = k - ly * W;
+        const int gy = gy0 + ly, gx = gx0 + lx;
+        if (gy < 0 || gy > N || gx < 0 || gx > N) x = T(0);
+      }
+      s[k] = x;
+    }
   }
 }
 
@@ -150,14 +176,27 @@ __global__ void __launch_bounds__(kThreads)
   const int cx0 = (gx0 >> 1) - 1, cy0 = (gy0 >> 1) - 1;
   load_tile<T, BC, W, HH>(su, uin, pui, n, gy0, gx0, false);
   load_tile<T, BC, W, HH>(sf, f, pf, n, gy0, gx0, false);
+  {
+    // Coarse coefficients of the tile's spline support (all loads first).
+    constexpr int kIt = (CW * CH + kThreads - 1) / kThreads;
+    T v[kIt];
+    bool neg[kIt];
 #pragma unroll
-  for (int k = threadIdx.x; k < CW * CH; k += kThreads) {
-    const int cy = k / CW, cx = k - cy * CW;
-    bool ny, nx;
-    const int I = ext_node<BC>(cy0 + cy, nc, &ny);
-    const int J = ext_node<BC>(cx0 + cx, nc, &nx);
-    const T v = c[(size_t)I * pc + J];
-    sc[k] = (ny != nx) ? -v : v;
+    for (int i = 0; i < kIt; ++i) {
+      const int k0 = threadIdx.x + i * kThreads;
+      const int k = k0 < CW * CH ? k0 : CW * CH - 1;
+      const int cy = k / CW, cx = k - cy * CW;
+      bool ny, nx;
+      const int I = ext_node<BC>(cy0 + cy, nc, &ny);
+      const int J = ext_node<BC>(cx0 + cx, nc, &nx);
+      v[i] = c[(size_t)I * pc + J];
+      neg[i] = ny != nx;
+    }
+#pragma unroll
+    for (int i = 0; i < kIt; ++i) {
+      const int k = threadIdx.x + i * kThreads;
+      if (k < CW * CH) sc[k] = neg[i] ? -v[i] : v[i];
+    }
   }
   __syncthreads();
   // Spline along x for every coarse row of the tile.

@@ -121,11 +121,12 @@ struct Problem {
   double* partials = nullptr;  // 2 * blocks_for(n) doubles
   double* sums = nullptr;      // 4 doubles of reduced results
   int nblocks = 0;
-  // Captured step per prolongation kind (0 spline, 1 SR-CNN) and the
-  // caller arrays it was captured with.
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-  const double* graph_u[2] = {nullptr, nullptr};
-  const double* graph_f[2] = {nullptr, nullptr};
+  // Captured step per variant (bit 0: SR-CNN prolongation, bit 1: mixed
+  // step whose FP64 residual is already in place) and the caller arrays it
+  // was captured with.
+  hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  const double* graph_u[4] = {nullptr, nullptr, nullptr, nullptr};
+  const double* graph_f[4] = {nullptr, nullptr, nullptr, nullptr};
   // Kernel choice per level (autotuned): variant 0 = register streaming with
   // `hs` rows per segment (0 = default), 1 = LDS tiles.
   std::vector<int> down_var, down_hs, up_var, up_hs;
@@ -436,8 +437,12 @@ bool use_fused(const mg_ctx_s* ctx) {
 
 // One step of the outer iteration for one problem: an FP64 V-cycle, or one
 // refinement step around inner FP32 cycles.
+// One step for problem p: an FP64 V-cycle, or one mixed refinement step
+// (FP64 residual, FP32 inner cycles, FP64 update).  have_res: the mixed
+// step's residual of this u is already in the level-0 right-hand side (left
+// there by enqueue_check_mixed), so the step starts with the inner cycles.
 int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f,
-                     hipStream_t s, bool cnn) {
+                     hipStream_t s, bool cnn, bool have_res = false) {
   const double m = unknowns_side(p.n, p.bc), nn = (double)p.n * p.n;
   const bool fused = use_fused(ctx);
   if (ctx->opt.precision == MG_FP64) {
@@ -450,10 +455,11 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
     int nb = 0;
     float* e0 = p.h32.u[0];
     float* r0 = p.h32.f[0];
-    MG_TRY(timed(ctx, s, MG_K_RESIDUAL_MIXED, 0, 20 * nn, [&] {
-      return launch_residual_mixed(s, p.bc, p.n, u, p.pitch0, f, p.pitch0, r0, p.pitch[0],
-                                   p.partials, &nb);
-    }));
+    if (!have_res)
+      MG_TRY(timed(ctx, s, MG_K_RESIDUAL_MIXED, 0, 20 * nn, [&] {
+        return launch_residual_mixed(s, p.bc, p.n, u, p.pitch0, f, p.pitch0, r0, p.pitch[0],
+                                     p.partials, &nb);
+      }));
     bool added = false;
     if (fused) {
       const int K = ctx->opt.inner_cycles;
@@ -477,9 +483,11 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
   return MG_OK;
 }
 
-int32_t run_step(mg_ctx_s* ctx, Problem& p, double* u, const double* f, bool cnn = false) {
-  if (!ctx->opt.use_graph || ctx->timing) return enqueue_step(ctx, p, u, f, ctx->stream, cnn);
-  const int k = cnn ? 1 : 0;
+int32_t run_step(mg_ctx_s* ctx, Problem& p, double* u, const double* f, bool cnn = false,
+                 bool have_res = false) {
+  if (!ctx->opt.use_graph || ctx->timing)
+    return enqueue_step(ctx, p, u, f, ctx->stream, cnn, have_res);
+  const int k = (cnn ? 1 : 0) + (have_res ? 2 : 0);
   if (p.graph[k] && (p.graph_u[k] != u || p.graph_f[k] != f)) {
     MG_HIP(hipGraphExecDestroy(p.graph[k]));
     p.graph[k] = nullptr;
@@ -487,7 +495,7 @@ int32_t run_step(mg_ctx_s* ctx, Problem& p, double* u, const double* f, bool cnn
   if (!p.graph[k]) {
     hipGraph_t g = nullptr;
     MG_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
-    const int32_t st = enqueue_step(ctx, p, u, f, ctx->capture, cnn);
+    const int32_t st = enqueue_step(ctx, p, u, f, ctx->capture, cnn, have_res);
     hipError_t e = hipStreamEndCapture(ctx->capture, &g);
     if (st != MG_OK) {
       if (g) (void)hipGraphDestroy(g);
@@ -515,6 +523,31 @@ int32_t enqueue_resnorm(mg_ctx_s* ctx, Problem& p, const double* u, const double
     return launch_resnorm(ctx->stream, p.bc, p.n, u, p.pitch0, f, p.pitch0, p.partials, true, &nb);
   }));
   MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 2, p.sums));
+  return MG_OK;
+}
+
+// Mixed path: ||f - A u||^2 into p.sums[0] from the FP64 residual that the
+// next refinement step starts from; its FP32 copy stays in the level-0
+// right-hand side, so that step skips it (run_step with have_res).
+int32_t enqueue_check_mixed(mg_ctx_s* ctx, Problem& p, const double* u, const double* f) {
+  int nb = 0;
+  const double nn = (double)p.n * p.n;
+  MG_TRY(timed(ctx, ctx->stream, MG_K_RESIDUAL_MIXED, 0, 20 * nn, [&] {
+    return launch_residual_mixed(ctx->stream, p.bc, p.n, u, p.pitch0, f, p.pitch0, p.h32.f[0],
+                                 p.pitch[0], p.partials, &nb);
+  }));
+  MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 1, p.sums));
+  return MG_OK;
+}
+
+// ||f||^2 over the unknowns into p.sums[1] (the denominator read_relres
+// uses), through p.sums[2..3].
+int32_t enqueue_fnorm(mg_ctx_s* ctx, Problem& p, const double* f) {
+  int nb = 0;
+  MG_HIP(launch_rhs_moments(ctx->stream, p.bc, p.n, f, p.pitch0, p.partials, &nb));
+  MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 2, p.sums + 2));
+  MG_HIP(hipMemcpyAsync(p.sums + 1, p.sums + 3, sizeof(double), hipMemcpyDeviceToDevice,
+                        ctx->stream));
   return MG_OK;
 }
 
@@ -1428,10 +1461,21 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
   std::vector<double> rel(B, 0.0), prev(B, -1.0);
   std::vector<int> prev_cycles(B, 0), slow(B, 0), next_check(B, 1), all(B);
   const bool pers = ctx->ps.on;
+  // Mixed path: every norm check is the FP64 residual the next step needs
+  // anyway (have_res: the next step of b skips it).
+  const bool mixed_chk = !pers && ctx->opt.precision == MG_MIXED;
+  std::vector<char> have_res(B, 0);
   for (int b = 0; b < B; ++b) all[b] = b;
   if (pers) {
     MG_TRY(persistent_bind(ctx, u, f, {}));
     MG_TRY(persistent_relres(ctx, rel.data()));
+  } else if (mixed_chk) {
+    for (int b = 0; b < B; ++b) {
+      MG_TRY(enqueue_fnorm(ctx, ctx->probs[b], f[b]));
+      MG_TRY(enqueue_check_mixed(ctx, ctx->probs[b], u[b], f[b]));
+      have_res[b] = 1;
+    }
+    MG_TRY(read_relres(ctx, all, rel.data()));
   } else {
     for (int b = 0; b < B; ++b) MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
     MG_TRY(read_relres(ctx, all, rel.data()));
@@ -1474,7 +1518,8 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
       }
       for (int b : act)
         if (cycles[b] < max_cycles && cycles[b] < next_check[b]) {
-          MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b], cnn_on[b] != 0));
+          MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b], cnn_on[b] != 0, have_res[b] != 0));
+          have_res[b] = 0;
           ++cycles[b];
         }
     }
@@ -1486,6 +1531,12 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
       std::vector<double> rall(B);
       MG_TRY(persistent_relres(ctx, rall.data()));
       for (size_t k = 0; k < chk.size(); ++k) r[k] = rall[chk[k]];
+    } else if (mixed_chk) {
+      for (int b : chk) {
+        MG_TRY(enqueue_check_mixed(ctx, ctx->probs[b], u[b], f[b]));
+        have_res[b] = 1;
+      }
+      MG_TRY(read_relres(ctx, chk, r.data()));
     } else {
       for (int b : chk) MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
       MG_TRY(read_relres(ctx, chk, r.data()));
