@@ -49,8 +49,11 @@ def measured_traffic(kind_name: str, precision: str, bc: int):
     if hh.hexdigest() != rec["sources_sha256"]:
         return None
     t = "float" if precision == "mixed" else "double"
-    ent = rec["per_launch"].get(f"{names[kind_name]}<{t}, {bc}>")
-    return None if ent is None else round(ent["bytes"], 0)
+    # Template variants of the kernel (input/accumulation flags); the
+    # level-0 launch is the one with the most traffic.
+    head = f"{names[kind_name]}<{t}, {bc}"
+    ents = [v for k, v in rec["per_launch"].items() if k == head + ">" or k.startswith(head + ",")]
+    return round(max(e["bytes"] for e in ents), 0) if ents else None
 
 
 def parse():
@@ -63,6 +66,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (read, and appended with new choices), so that "
+                         "several runs (e.g. one per profiler counter) use the same launch shapes")
     return ap.parse_args()
 
 
@@ -241,7 +247,7 @@ def main() -> int:
 
     results = {}
     for prec in ("fp64", "mixed"):
-        s = Solver([(n, bc)], precision=prec, use_graph=True)
+        s = Solver([(n, bc)], precision=prec, use_graph=True, tune_cache_path=args.tune_cache)
         sec = timed_steps(s, args.steps, args.warmup)
         tt = time_to_tol(s)
         u_final = ut.clone()
