@@ -23,6 +23,7 @@ namespace mg {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kC = 64;            // channels
@@ -84,19 +85,21 @@ __global__ void __launch_bounds__(256) k_cnn_scale(const float* __restrict__ par
 }
 
 // ---------------------------------------------------------------- stem
-// Thread = (pixel, group of 8 output channels).  stem_w: [64][9] floats.
+// Thread = pixel: its 9 scaled, bf16-rounded inputs, then all 64 output
+// channels (the weight addresses are uniform, so they come through the
+// scalar cache).  stem_w: [64][9] floats.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_cnn_stem(int N, const T* __restrict__ e, int pe, const float* __restrict__ scale,
                const float* __restrict__ stem_w, unsigned short* __restrict__ h) {
   const float s = scale[0];
-  const long q = (long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= (long)N * N * 8) return;
-  const int g = (int)(q & 7);
-  const long pix = q >> 3;
+  const long pix = (long)blockIdx.x * 256 + threadIdx.x;
+  if (pix >= (long)N * N) return;
   const int y = (int)(pix / N), x = (int)(pix % N);
   float xv[9];
+#pragma unroll
   for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
       int yy = y + dy - 1, xx = x + dx - 1;
       yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
@@ -104,19 +107,25 @@ __global__ void __launch_bounds__(256)
       const float v = (float)e[(long)yy * pe + xx];
       xv[dy * 3 + dx] = s > 0.f ? from_bf16(to_bf16(v / s)) : 0.f;
     }
-  unsigned short o[8];
-  for (int c = 0; c < 8; ++c) {
-    const float* w = stem_w + (g * 8 + c) * 9;
-    float acc = 0.f;
-    for (int t = 0; t < 9; ++t) acc += w[t] * xv[t];
-    o[c] = to_bf16(fmaxf(acc, 0.f));
+  uint4* dst = reinterpret_cast<uint4*>(h + pix * kC);
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    unsigned short o[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float* w = stem_w + (g * 8 + c) * 9;
+      float acc = 0.f;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) acc += w[t] * xv[t];
+      o[c] = to_bf16(fmaxf(acc, 0.f));
+    }
+    uint4 pk;
+    pk.x = o[0] | ((unsigned)o[1] << 16);
+    pk.y = o[2] | ((unsigned)o[3] << 16);
+    pk.z = o[4] | ((unsigned)o[5] << 16);
+    pk.w = o[6] | ((unsigned)o[7] << 16);
+    dst[g] = pk;
   }
-  uint4 pk;
-  pk.x = o[0] | ((unsigned)o[1] << 16);
-  pk.y = o[2] | ((unsigned)o[3] << 16);
-  pk.z = o[4] | ((unsigned)o[5] << 16);
-  pk.w = o[6] | ((unsigned)o[7] << 16);
-  *reinterpret_cast<uint4*>(h + pix * kC + g * 8) = pk;
 }
 
 // ---------------------------------------------------------------- 64-channel conv
@@ -205,6 +214,32 @@ __global__ void __launch_bounds__(kConvThreads)
     const int next = tile + gridDim.x;
     const TileRegs pre = tile_fetch(in4, N, next < tiles ? next : tile, tid);  // last pass: a re-read
     const uint4* il = ib + cur * kTileChunks;
+    // Output addresses of this lane (pixel column m of rows 2 wave + i), and
+    // for MODE 1 the skip values there, loaded before the product loop so
+    // that their latency hides behind it (out may alias skip: each value is
+    // read here and written only by this lane's epilogue).
+    const int row0 = (tile / tiles_x) * kTH, col0 = (tile % tiles_x) * kTW;
+    size_t obase[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int y = row0 + 2 * wave + i, x = col0 + m;
+      if (MODE == 2) {
+        const int a = blockIdx.y >> 1, b = blockIdx.y & 1;
+        obase[i] = ((size_t)(2 * y + a) * (2 * N) + (2 * x + b)) * kC;
+      } else {
+        obase[i] = ((size_t)y * N + x) * kC;
+      }
+    }
+    uint2 skv[2][2][4];
+    if (MODE == 1) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int g = 0; g < 4; ++g)
+            skv[i][j][g] = *reinterpret_cast<const uint2*>(skip + obase[i] + 32 * j + 8 * g + 4 * kh);
+    }
 
     f32x16 acc[2][2];
     for (int j = 0; j < 2; ++j)
@@ -241,23 +276,18 @@ __global__ void __launch_bounds__(kConvThreads)
     }
 
     // Lane holds pixel column m and output channels 32j + 8g + 4kh + (0..3).
-    const int row0 = (tile / tiles_x) * kTH, col0 = (tile % tiles_x) * kTW;
+#pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const int y = row0 + 2 * wave + i, x = col0 + m;
-      size_t base;
-      if (MODE == 2) {
-        const int a = blockIdx.y >> 1, b = blockIdx.y & 1;
-        base = ((size_t)(2 * y + a) * (2 * N) + (2 * x + b)) * kC;
-      } else {
-        base = ((size_t)y * N + x) * kC;
-      }
+      const size_t base = obase[i];
+#pragma unroll
       for (int j = 0; j < 2; ++j)
+#pragma unroll
         for (int g = 0; g < 4; ++g) {
           const int ch = 32 * j + 8 * g + 4 * kh;
           float v[4];
           for (int r = 0; r < 4; ++r) v[r] = acc[j][i][4 * g + r];
           if (MODE == 1) {
-            const uint2 sk = *reinterpret_cast<const uint2*>(skip + base + ch);
+            const uint2 sk = skv[i][j][g];
             v[0] += from_bf16(sk.x & 0xffff);
             v[1] += from_bf16(sk.x >> 16);
             v[2] += from_bf16(sk.y & 0xffff);
@@ -288,10 +318,12 @@ __global__ void __launch_bounds__(256)
     k_cnn_final(int M, const unsigned short* __restrict__ z, const float* __restrict__ fin_w,
                 const float* __restrict__ scale, const T* uin, int pui, T* uout, int puo) {
   __shared__ __attribute__((aligned(16))) uint4 tl[kFHW * kFHW * 8];  // chunk-major: [c][pixel]
-  __shared__ float wf[9 * kC];
+  __shared__ __attribute__((aligned(16))) unsigned wf[9 * kC / 2];    // bf16 pairs [tap][ch/2]
   const int tiles_x = M / kFT;
   const int y0 = (blockIdx.x / tiles_x) * kFT, x0 = (blockIdx.x % tiles_x) * kFT;
-  for (int q = threadIdx.x; q < 9 * kC; q += 256) wf[q] = fin_w[q];
+  // The weights are bf16 values (rounded at setup), so packing is exact.
+  for (int q = threadIdx.x; q < 9 * kC / 2; q += 256)
+    wf[q] = to_bf16(fin_w[2 * q]) | ((unsigned)to_bf16(fin_w[2 * q + 1]) << 16);
   {
     constexpr int kChunks = kFHW * kFHW * 8, kPer = (kChunks + 255) / 256;
     uint4 r[kPer];
@@ -312,16 +344,24 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   const int ty = threadIdx.x / kFT, tx = threadIdx.x % kFT;
+  // Products of two bf16 values are exact in FP32; v_dot2 adds a pair of
+  // them to the FP32 accumulator.
   float acc = 0.f;
+#pragma unroll 1
   for (int tap = 0; tap < 9; ++tap) {
     const int p = (ty + tap / 3) * kFHW + tx + tap % 3;
+#pragma unroll
     for (int c = 0; c < 8; ++c) {
       const uint4 v = tl[c * (kFHW * kFHW) + p];
-      const float* wv = wf + tap * kC + c * 8;
-      acc += wv[0] * from_bf16(v.x & 0xffff) + wv[1] * from_bf16(v.x >> 16) +
-             wv[2] * from_bf16(v.y & 0xffff) + wv[3] * from_bf16(v.y >> 16) +
-             wv[4] * from_bf16(v.z & 0xffff) + wv[5] * from_bf16(v.z >> 16) +
-             wv[6] * from_bf16(v.w & 0xffff) + wv[7] * from_bf16(v.w >> 16);
+      const uint4 wv = *reinterpret_cast<const uint4*>(wf + tap * (kC / 2) + c * 4);
+      acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, v.x),
+                                            __builtin_bit_cast(bf16x2, wv.x), acc, false);
+      acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, v.y),
+                                            __builtin_bit_cast(bf16x2, wv.y), acc, false);
+      acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, v.z),
+                                            __builtin_bit_cast(bf16x2, wv.z), acc, false);
+      acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, v.w),
+                                            __builtin_bit_cast(bf16x2, wv.w), acc, false);
     }
   }
   const T d = (T)(scale[0] * acc);
@@ -365,7 +405,7 @@ hipError_t launch_cnn_head(hipStream_t s, int N, const T* e, int pe, float* part
                            const float* stem_w, unsigned short* h, float* scale) {
   hipLaunchKernelGGL(k_cnn_absmax<T>, dim3(kPartials), dim3(256), 0, s, N, e, pe, partials);
   hipLaunchKernelGGL(k_cnn_scale, dim3(1), dim3(256), 0, s, partials, scale);
-  const long threads = (long)N * N * 8;
+  const long threads = (long)N * N;
   hipLaunchKernelGGL(k_cnn_stem<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, N, e,
                      pe, scale, stem_w, h);
   return hipGetLastError();
