@@ -111,7 +111,7 @@ template <typename T>
 hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
                      const T* f, int pf, const T* c, int pc);
 // Register-streaming versions of the two passes (mg_stream.hip); same
-// contracts.  hs = rows per wavefront segment (even, 8..64; 0 = chosen per level).
+// contracts.  hs = rows per wavefront segment (even, 8..128; 0 = chosen per level).
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
                               int puo, const T* f, int pf, T* fc, int pfc, int hs);

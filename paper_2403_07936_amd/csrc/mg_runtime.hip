@@ -967,15 +967,26 @@ int32_t time_launches(mg_ctx_s* ctx, int reps, Launch&& launch, float* ms) {
 // Per-level kernel choice: the streaming passes with several segment heights
 // against the LDS-tiled passes, each timed on the level's own arrays (the
 // level-0 caller arrays are stood in for by library arrays of the same
-// shape).  Values do not matter to the timing.
+// shape).  Values do not matter to the timing.  The mixed path's level-0 up
+// pass adds into the FP64 iterate (a different kernel variant, keyed
+// "fp32a"), so it is timed that way, against a scratch FP64 array, and
+// only among the streaming candidates.
 template <typename T>
 int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scratch_u, T* scratch_f,
                     int pitch0) {
   const Hierarchy<T>& h = hier<T>(p);
   const bool mixed = ctx->opt.precision == MG_MIXED;
-  const char* prec = sizeof(T) == 8 ? "fp64" : "fp32";
+  double* u64 = nullptr;
+  struct Free {
+    double*& q;
+    ~Free() {
+      if (q) (void)hipFree(q);
+    }
+  } free_u64{u64};
   for (int l = 0; l < p.tail; ++l) {
     const int n = p.side[l];
+    const bool add = mixed && l == 0;
+    const char* prec = sizeof(T) == 8 ? "fp64" : (add ? "fp32a" : "fp32");
     const std::string key = arch + " " + prec + " " + std::to_string(p.bc) + " " + std::to_string(n);
     {
       std::lock_guard<std::mutex> lk(tune_mutex());
@@ -993,7 +1004,13 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
     const int pu = l == 0 ? pitch0 : p.pitch[l];
     const T* uin = (l == 0 && !mixed) ? u : nullptr;
     const int reps = n >= 2049 ? 3 : 6;
-    const int hs_cands[] = {0, 8, 16, 32, 64};
+    const int hs_cands[] = {0, 8, 16, 32, 64, 96, 128};
+    if (add && !u64) {
+      if (hipMalloc(&u64, sizeof(double) * (size_t)n * p.pitch[0]) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MG_ERR_OOM, "scratch FP64 array for tuning");
+      }
+    }
     float best_d = 1e30f, best_u = 1e30f, us_total = 0.f;
     LevelChoice c;
     for (int var = 0; var < 2; ++var)
@@ -1006,12 +1023,17 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
                           : launch_down_stream<T>(ctx->stream, p.bc, n, uin, pu, h.r[l],
                                                   p.pitch[l], f, pu, h.f[l + 1], p.pitch[l + 1], hs);
         }, &md));
-        MG_TRY(time_launches(ctx, reps, [&] {
-          return var == 1 ? launch_up<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu, f, pu,
-                                         h.c[l + 1], p.pitch[l + 1])
-                          : launch_up_stream<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu, f,
-                                                pu, h.c[l + 1], p.pitch[l + 1], hs);
-        }, &mu));
+        if (add && var == 1) {
+          mu = 1e30f;  // the tiled up pass does not add into the FP64 iterate
+        } else {
+          MG_TRY(time_launches(ctx, reps, [&] {
+            return var == 1 ? launch_up<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu, f, pu,
+                                           h.c[l + 1], p.pitch[l + 1])
+                            : launch_up_stream<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu,
+                                                  f, pu, h.c[l + 1], p.pitch[l + 1], hs,
+                                                  add ? u64 : nullptr, p.pitch[0]);
+          }, &mu));
+        }
         // A candidate replaces the current best only when it is more than 3%
         // faster, so that near-ties keep the default and choices stay stable.
         if (md < 0.97f * best_d) {

@@ -554,8 +554,11 @@ def test_autotune_cache_forces_variants(B, dev, tmp_path, precision):
     cycle."""
     n, bc = 2049, P
     prec = "fp64" if precision == 0 else "fp32"
+    # The mixed path's level-0 up pass adds into the FP64 iterate, a kernel
+    # variant of its own, tuned under the key "fp32a".
+    top = "fp32a" if precision == 1 else prec
     path = tmp_path / "tune.txt"
-    text = "".join(f"L {device_arch()} {prec} {bc} {m} 1 0 0 {hs} 0\n"
+    text = "".join(f"L {device_arch()} {top if m == n else prec} {bc} {m} 1 0 0 {hs} 0\n"
                    for m, hs in ((2049, 16), (1025, 8), (513, 32), (257, 64), (129, 8)))
     path.write_text(text)
     o = B.mg_options_default()
