@@ -29,6 +29,9 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kTailThreads = 1024;
+// Tile of the LDS up pass and the coarse support its spline reads.
+constexpr int kUpTX = 64, kUpTY = 32, kUpH = 4;
+constexpr int kUpCW = kUpTX / 2 + kUpH + 3, kUpCH = kUpTY / 2 + kUpH + 3;
 
 // Loads a W x HH tile whose node (0, 0) is global node (gy0, gx0) into s:
 // periodic wrap, zero outside a Dirichlet grid, all zero if `zero`.  Every
@@ -158,13 +161,17 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-template <typename T, int BC, int TX, int TY>
+// PRE: c holds the coarse correction itself, and the tile computes the
+// B-spline coefficients of its own support (prefilter_region) in place of a
+// separate prefilter pass over the level.
+template <typename T, int BC, int TX, int TY, bool PRE>
 __global__ void __launch_bounds__(kThreads)
     k_up(int n, const T* __restrict__ uin, T* __restrict__ uout, int pui, int puo,
          const T* __restrict__ f, int pf, const T* __restrict__ c, int pc, int tiles_x, int ntiles,
          T h2) {
-  constexpr int H = 4, W = TX + 2 * H, HH = TY + 2 * H;
+  constexpr int H = kUpH, W = TX + 2 * H, HH = TY + 2 * H;
   constexpr int CW = TX / 2 + H + 3, CH = TY / 2 + H + 3;
+  static_assert(!PRE || (CW == kUpCW && CH == kUpCH), "launch_up sizes the prefilter LDS");
   __shared__ T su[W * HH];
   __shared__ T sf[W * HH];
   __shared__ T sc[CW * CH];
@@ -176,7 +183,11 @@ __global__ void __launch_bounds__(kThreads)
   const int cx0 = (gx0 >> 1) - 1, cy0 = (gy0 >> 1) - 1;
   load_tile<T, BC, W, HH>(su, uin, pui, n, gy0, gx0, false);
   load_tile<T, BC, W, HH>(sf, f, pf, n, gy0, gx0, false);
-  {
+  if constexpr (PRE) {
+    extern __shared__ __align__(16) unsigned char pre_lds[];
+    dev::prefilter_region<T, BC, kThreads, CH, CW>(nc, c, pc, cy0, cx0, sc, CW,
+                                                   reinterpret_cast<T*>(pre_lds));
+  } else {
     // Coarse coefficients of the tile's spline support (all loads first).
     constexpr int kIt = (CW * CH + kThreads - 1) / kThreads;
     T v[kIt];
@@ -281,6 +292,22 @@ hipError_t fused_init() {
   e0 = hipFuncSetAttribute((const void*)k_pre_tile<float, kPeriodic>,
                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)PreTile<float>::kLds);
   if (e0 != hipSuccess) return e0;
+  {
+    const int l64 = (int)PreRegion<double, kUpCH, kUpCW>::kLds;
+    const int l32 = (int)PreRegion<float, kUpCH, kUpCW>::kLds;
+    hipError_t e1 = hipFuncSetAttribute((const void*)k_up<double, kDirichlet, kUpTX, kUpTY, true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, l64);
+    if (e1 == hipSuccess)
+      e1 = hipFuncSetAttribute((const void*)k_up<double, kPeriodic, kUpTX, kUpTY, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, l64);
+    if (e1 == hipSuccess)
+      e1 = hipFuncSetAttribute((const void*)k_up<float, kDirichlet, kUpTX, kUpTY, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, l32);
+    if (e1 == hipSuccess)
+      e1 = hipFuncSetAttribute((const void*)k_up<float, kPeriodic, kUpTX, kUpTY, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, l32);
+    if (e1 != hipSuccess) return e1;
+  }
   const size_t max64 = tail_bytes(kTailMaxSide, sizeof(double));
   const size_t max32 = tail_bytes(kTailMaxSide, sizeof(float));
   hipError_t e;
@@ -321,18 +348,25 @@ hipError_t launch_down(hipStream_t s, int bc, int n, const T* uin, int pui, T* u
 
 template <typename T>
 hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
-                     const T* f, int pf, const T* c, int pc) {
-  constexpr int TX = 64, TY = 32;
+                     const T* f, int pf, const T* c, int pc, bool pre) {
+  constexpr int TX = kUpTX, TY = kUpTY;
   const int tx = tiles_along(n, bc, TX), ty = tiles_along(n, bc, TY);
   const int nt = tx * ty;
   const double hd = 1.0 / (double)(n - 1);
   const T h2 = T(hd * hd);
-  if (bc == kDirichlet)
-    hipLaunchKernelGGL((k_up<T, kDirichlet, TX, TY>), dim3(nt), dim3(kThreads), 0, s, n, uin, uout,
-                       pui, puo, f, pf, c, pc, tx, nt, h2);
+  const size_t lds = pre ? dev::PreRegion<T, kUpCH, kUpCW>::kLds : 0;
+#define MG_TILE_UP(BCV, PREV)                                                                    \
+  hipLaunchKernelGGL((k_up<T, BCV, TX, TY, PREV>), dim3(nt), dim3(kThreads), lds, s, n, uin, uout, \
+                     pui, puo, f, pf, c, pc, tx, nt, h2)
+  if (bc == kDirichlet && pre)
+    MG_TILE_UP(kDirichlet, true);
+  else if (bc == kDirichlet)
+    MG_TILE_UP(kDirichlet, false);
+  else if (pre)
+    MG_TILE_UP(kPeriodic, true);
   else
-    hipLaunchKernelGGL((k_up<T, kPeriodic, TX, TY>), dim3(nt), dim3(kThreads), 0, s, n, uin, uout,
-                       pui, puo, f, pf, c, pc, tx, nt, h2);
+    MG_TILE_UP(kPeriodic, false);
+#undef MG_TILE_UP
   return hipGetLastError();
 }
 
@@ -372,7 +406,7 @@ hipError_t launch_tail(hipStream_t s, int bc, int nt, const T* uin, int pui, T* 
   template hipError_t launch_down<T>(hipStream_t, int, int, const T*, int, T*, int, const T*,    \
                                      int, T*, int);                                              \
   template hipError_t launch_up<T>(hipStream_t, int, int, const T*, int, T*, int, const T*, int, \
-                                   const T*, int);                                               \
+                                   const T*, int, bool);                                         \
   template hipError_t launch_prefilter_iir<T>(hipStream_t, int, int, const T*, int, T*, int, T*, \
                                               int);                                              \
   template hipError_t launch_tail<T>(hipStream_t, int, int, const T*, int, T*, int, const T*,    \

@@ -106,10 +106,12 @@ template <typename T>
 hipError_t launch_down(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
                        const T* f, int pf, T* fc, int pfc);
 // Up pass: uout = uin + P c (c = prefiltered coarse correction), then 2
-// red-black sweeps.  uout must differ from uin.
+// red-black sweeps.  uout must differ from uin.  pre: c is the coarse
+// correction itself, prefiltered by each tile on its own support.
 template <typename T>
 hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
-                     const T* f, int pf, const T* c, int pc);
+                     const T* f, int pf, const T* c, int pc,
+                     bool pre = false);
 // Register-streaming versions of the two passes (mg_stream.hip); same
 // contracts.  hs = rows per wavefront segment (even, 8..128; 0 = chosen per level).
 template <typename T>

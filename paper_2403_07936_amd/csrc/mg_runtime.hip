@@ -412,18 +412,22 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
       }));
       continue;
     }
-    if (l + 1 < t)
+    // Variant 2: the tiled up pass prefilters its own coarse support (no
+    // prefilter pass over level l + 1).
+    const bool pre = ctx->opt.kernel_path != 2 && p.up_var[l] == 2 && l + 1 < t;
+    if (l + 1 < t && !pre)
       MG_TRY(timed(ctx, s, MG_K_PREFILTER, l + 1, 4 * ncc * sz, [&] {
         return launch_prefilter_iir<T>(s, bc, nc, h.u[l + 1], pc, h.tmp[l + 1], pc, h.c[l + 1], pc);
       }));
     // Level 0 of the mixed path's last inner cycle: the streaming up pass
     // adds its result straight into the FP64 iterate (no separate update).
-    const bool tile = ctx->opt.kernel_path == 2 || p.up_var[l] == 1;
+    const bool tile = ctx->opt.kernel_path == 2 || p.up_var[l] == 1 || pre;
     const bool add = l == 0 && u64 && !tile;
     if (add && added) *added = true;
     MG_TRY(timed(ctx, s, MG_K_UP, l, (3 * m * m + ncc) * sz + (add ? 16 * m * m - 4 * m * m : 0), [&] {
       if (tile)
-        return launch_up<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l), h.c[l + 1], pc);
+        return launch_up<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l),
+                            pre ? h.u[l + 1] : h.c[l + 1], pc, pre);
       return launch_up_stream<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l),
                                  h.c[l + 1], pc, p.up_hs[l], add ? u64 : nullptr, p64);
     }));
@@ -1013,26 +1017,42 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
     }
     float best_d = 1e30f, best_u = 1e30f, us_total = 0.f;
     LevelChoice c;
-    for (int var = 0; var < 2; ++var)
+    // The separate prefilter of level l + 1, charged to the up-pass variants
+    // that need it (variant 2 prefilters inside its tiles).
+    float mp = 0.f;
+    const bool can_pre = !add && l + 1 < p.tail;
+    if (can_pre) {
+      const int nc = p.side[l + 1], pc = p.pitch[l + 1];
+      MG_TRY(time_launches(ctx, reps, [&] {
+        return launch_prefilter_iir<T>(ctx->stream, p.bc, nc, h.u[l + 1], pc, h.tmp[l + 1], pc,
+                                       h.c[l + 1], pc);
+      }, &mp));
+    }
+    for (int var = 0; var < 3; ++var)
       for (int hs : hs_cands) {
-        if (var == 1 && hs != 0) continue;
-        float md = 0.f, mu = 0.f;
-        MG_TRY(time_launches(ctx, reps, [&] {
-          return var == 1 ? launch_down<T>(ctx->stream, p.bc, n, uin, pu, h.r[l], p.pitch[l], f, pu,
-                                           h.f[l + 1], p.pitch[l + 1])
-                          : launch_down_stream<T>(ctx->stream, p.bc, n, uin, pu, h.r[l],
-                                                  p.pitch[l], f, pu, h.f[l + 1], p.pitch[l + 1], hs);
-        }, &md));
-        if (add && var == 1) {
+        if (var >= 1 && hs != 0) continue;
+        if (var == 2 && !can_pre) continue;
+        float md = 1e30f, mu = 0.f;
+        if (var < 2)  // variant 2 concerns the up pass only
+          MG_TRY(time_launches(ctx, reps, [&] {
+            return var == 1 ? launch_down<T>(ctx->stream, p.bc, n, uin, pu, h.r[l], p.pitch[l], f,
+                                             pu, h.f[l + 1], p.pitch[l + 1])
+                            : launch_down_stream<T>(ctx->stream, p.bc, n, uin, pu, h.r[l],
+                                                    p.pitch[l], f, pu, h.f[l + 1], p.pitch[l + 1],
+                                                    hs);
+          }, &md));
+        if (add && var >= 1) {
           mu = 1e30f;  // the tiled up pass does not add into the FP64 iterate
         } else {
           MG_TRY(time_launches(ctx, reps, [&] {
-            return var == 1 ? launch_up<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu, f, pu,
-                                           h.c[l + 1], p.pitch[l + 1])
-                            : launch_up_stream<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu,
-                                                  f, pu, h.c[l + 1], p.pitch[l + 1], hs,
-                                                  add ? u64 : nullptr, p.pitch[0]);
+            if (var >= 1)
+              return launch_up<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu, f, pu,
+                                  var == 2 ? h.u[l + 1] : h.c[l + 1], p.pitch[l + 1], var == 2);
+            return launch_up_stream<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu, f, pu,
+                                       h.c[l + 1], p.pitch[l + 1], hs, add ? u64 : nullptr,
+                                       p.pitch[0]);
           }, &mu));
+          if (var < 2) mu += mp;
         }
         // A candidate replaces the current best only when it is more than 3%
         // faster, so that near-ties keep the default and choices stay stable.

@@ -257,6 +257,94 @@ __device__ __forceinline__ int tail_ext(int q, int nc, bool* neg) {
   return ext_node<BC>(q, nc, neg);
 }
 
+// Coefficients of a coarse region, for an up pass that prefilters its own
+// spline support: c on the extended-grid rows [ry0, ry0 + RH) and columns
+// [rx0, rx0 + RW) (indices may lie outside [0, nc): the extension of c) into
+// out (pitch po), from the coarse values `in` (pitch pi), by the chunked
+// recursions of pre_tile_block; smem = PreRegion<...>::kLds bytes of LDS.
+// On a Dirichlet grid the coefficients of boundary nodes are 0, as there.
+template <typename T, int RH, int RW>
+struct PreRegion {
+  static constexpr int K = PreCfg<T>::K;
+  static constexpr int S = sizeof(T) == 8 ? 8 : 16;
+  static constexpr int CX = (RW + S - 1) / S, CY = (RH + S - 1) / S;  // chunks per line
+  static constexpr int WO = CX * S, HO = CY * S;                      // padded outputs
+  static constexpr int HI = HO + 2 * K, WI = WO + 2 * K;
+  static constexpr int PI = WI | 1, PM = WO + 1;
+  static constexpr size_t kLds = (size_t)(HI * PI + HI * PM) * sizeof(T);
+  static_assert(WI <= 128, "a lane loads at most two columns of the region");
+};
+
+template <typename T, int BC, int NT, int RH, int RW>
+__device__ __forceinline__ void prefilter_region(int nc, const T* __restrict__ in, int pi, int ry0,
+                                                 int rx0, T* out, int po, T* smem) {
+  using C = PreRegion<T, RH, RW>;
+  constexpr int kWaves = NT / 64;
+  __shared__ int rtab[C::HI], ctab[C::WI];
+  T* si = smem;
+  T* sm = si + C::HI * C::PI;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int k = t; k < C::HI + C::WI; k += NT) {
+    bool neg;
+    if (k < C::HI) {
+      const int r = ext_node_any<BC>(ry0 - C::K + k, nc, &neg);
+      rtab[k] = neg ? ~r : r;
+    } else {
+      const int c = ext_node_any<BC>(rx0 - C::K + (k - C::HI), nc, &neg);
+      ctab[k - C::HI] = neg ? ~c : c;
+    }
+  }
+  __syncthreads();
+  constexpr int kRows = (C::HI + kWaves - 1) / kWaves;
+  const int lx1 = lane + 64 < C::WI ? lane + 64 : C::WI - 1;
+  const int ce0 = ctab[lane < C::WI ? lane : C::WI - 1], ce1 = ctab[lx1];
+  const int c0 = ce0 < 0 ? ~ce0 : ce0, c1 = ce1 < 0 ? ~ce1 : ce1;
+  T v0[kRows], v1[kRows];
+  int re[kRows];
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const int ly = wave + i * kWaves;
+    re[i] = rtab[ly < C::HI ? ly : C::HI - 1];
+  }
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const T* row = in + (size_t)(re[i] < 0 ? ~re[i] : re[i]) * pi;
+    v0[i] = row[c0];
+    v1[i] = row[c1];
+  }
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const int ly = wave + i * kWaves;
+    if (ly < C::HI) {
+      if (lane < C::WI) si[ly * C::PI + lane] = ((re[i] ^ ce0) < 0) ? -v0[i] : v0[i];
+      if (lane + 64 < C::WI) si[ly * C::PI + lane + 64] = ((re[i] ^ ce1) < 0) ? -v1[i] : v1[i];
+    }
+  }
+  __syncthreads();
+  auto boundary = [&](int e) {  // table entry of a node: a Dirichlet boundary node?
+    const int j = e < 0 ? ~e : e;
+    return BC == kDirichlet && (j == 0 || j == nc - 1);
+  };
+  for (int w = t; w < C::HI * C::CX; w += NT) {
+    const int ly = w % C::HI, q = (w / C::HI) * C::S;
+    T y[C::S];
+    chunk_iir<T, C::S, C::K>(si + ly * C::PI + q, 1, y);
+#pragma unroll
+    for (int k = 0; k < C::S; ++k)
+      sm[ly * C::PM + q + k] = boundary(ctab[C::K + q + k]) ? T(0) : y[k];
+  }
+  __syncthreads();
+  for (int w = t; w < RW * C::CY; w += NT) {
+    const int x = w % RW, q = (w / RW) * C::S;
+    T y[C::S];
+    chunk_iir<T, C::S, C::K>(sm + q * C::PM + x, C::PM, y);
+#pragma unroll
+    for (int k = 0; k < C::S; ++k)
+      if (q + k < RH) out[(q + k) * po + x] = boundary(rtab[C::K + q + k]) ? T(0) : y[k];
+  }
+  __syncthreads();
+}
+
 // Prefilter of the tail grids by per-thread chunks.  A thread takes S
 // consecutive coefficients q0 .. q0 + S - 1 of one line: the causal
 // recursion starts K nodes before the chunk from a zero state and runs K

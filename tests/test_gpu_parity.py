@@ -548,6 +548,46 @@ def test_autotune_writes_and_reuses_cache(B, dev, tmp_path):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("bc", [D, P])
+def test_tile_up_with_own_prefilter(B, dev, tmp_path, precision, bc):
+    """Up-pass variant 2 (the LDS tiles prefilter their own coarse support,
+    no separate prefilter pass), forced from a cache file on every level
+    where it applies, gives the oracle's cycle."""
+    n = 1025
+    prec = "fp64" if precision == 0 else "fp32"
+    top = "fp32a" if precision == 1 else prec
+    path = tmp_path / "tune.txt"
+    # Level-0 lines for the mixed path stay streaming (it adds into FP64).
+    text = "".join(f"L {device_arch()} {top if m == n else prec} {bc} {m} 0 0 "
+                   f"{0 if (m == n and precision == 1) else 2} 0 0\n"
+                   for m in (1025, 513, 257, 129))
+    path.write_text(text)
+    o = B.mg_options_default()
+    o.precision = precision
+    o.tune_cache_path = str(path).encode()
+    f = make_rhs(n, bc, 91)
+    u0 = rand_grid(n, bc, np.random.default_rng(92)) * 1e-3
+    ctx = B.mg_setup([(n, bc, 0)], o, torch.cuda.current_stream().cuda_stream)
+    try:
+        ut, ft = gpu(u0, dev), gpu(f, dev)
+        B.mg_vcycle(ctx, [ut.data_ptr()], [ft.data_ptr()], 1)
+        got = host(ut)
+    finally:
+        B.mg_destroy(ctx)
+    assert path.read_text() == text  # nothing measured: all came from the file
+    if precision == 0:
+        ref = oracle.vcycle(u0, f, bc)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        bound = 1e-12
+    else:
+        ref = oracle.refine_step(u0, f, bc)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref - u0)
+        bound = 1e-5
+    say(f"tile up with own prefilter precision={precision} bc={bc}: {err:.2e}")
+    assert err <= bound
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_autotune_cache_forces_variants(B, dev, tmp_path, precision):
     """Choices read from a cache file are applied: the LDS-tiled down pass
     and fixed segment heights on the streamed levels give the oracle's
