@@ -34,6 +34,7 @@ constexpr int kTileChunks = (kTH + 2) * kHW * 8;  // 16-byte chunks of the input
 constexpr int kWChunks = 9 * kC * 8;              // 16-byte chunks of one 64x64 weight set
 constexpr int kConvThreads = 256;
 constexpr int kPartials = 256;    // blocks of the max-abs pass
+constexpr int kAheadK = 3;        // K-steps the operand reads run ahead of the products
 
 __device__ __forceinline__ unsigned short to_bf16(float x) {
   return __builtin_bit_cast(unsigned short, (__bf16)x);
@@ -246,8 +247,11 @@ __global__ void __launch_bounds__(kConvThreads)
       for (int i = 0; i < 2; ++i)
         for (int v = 0; v < 16; ++v) acc[j][i][v] = 0.f;
     // K loop of 36 steps (9 taps x 4 chunks of 16 input channels), fully
-    // unrolled, with the four operand fragments of step s + 2 read from LDS
-    // while the four products of step s run.
+    // unrolled, with the four operand fragments of step s + kAheadK read
+    // from LDS while the four products of step s run (LDS latency under
+    // this load is several steps of products; at most 15 LDS reads may be
+    // outstanding, so 3 steps of 4: measured 5 % faster than 2, and 4
+    // steps, which make the compiler wait on the counter, slower).
     const uint4* wb = wl + kh * kWRows + m;                 // chunk kh, row m
     const uint4* ibase = il + kh * kTPix + 2 * wave * kHW + m;  // chunk kh, pixel (2 wave, m)
     auto fetch = [&](int st, bf16x8 (&fr)[4]) {
@@ -258,20 +262,20 @@ __global__ void __launch_bounds__(kConvThreads)
       fr[2] = __builtin_bit_cast(bf16x8, ibase[poff]);
       fr[3] = __builtin_bit_cast(bf16x8, ibase[poff + kHW]);
     };
-    bf16x8 fr[3][4];
-    fetch(0, fr[0]);
-    fetch(1, fr[1]);
+    bf16x8 fr[kAheadK + 1][4];
+#pragma unroll
+    for (int st = 0; st < kAheadK; ++st) fetch(st, fr[st]);
 #pragma unroll
     for (int st = 0; st < 36; ++st) {
-      if (st + 2 < 36) fetch(st + 2, fr[(st + 2) % 3]);
-      const bf16x8(&f)[4] = fr[st % 3];
+      if (st + kAheadK < 36) fetch(st + kAheadK, fr[(st + kAheadK) % (kAheadK + 1)]);
+      const bf16x8(&f)[4] = fr[st % (kAheadK + 1)];
       acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f[0], f[2], acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f[0], f[3], acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f[1], f[2], acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f[1], f[3], acc[1][1], 0, 0, 0);
-      // Nothing moves across step boundaries: the reads of step st + 2 stay
-      // in step st, two steps of products ahead of their use, so the LDS
-      // latency hides behind the matrix pipe.
+      // Nothing moves across step boundaries: the reads of step
+      // st + kAheadK stay in step st, ahead of their use by that many steps
+      // of products, so the LDS latency hides behind the matrix pipe.
       __builtin_amdgcn_sched_barrier(0);
     }
 
