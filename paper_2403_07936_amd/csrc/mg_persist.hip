@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kPersistThreads)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int gwave = blockIdx.x * kWavesPerBlock + wave;
+  const int gwave = wave_uniform(blockIdx.x * kWavesPerBlock + wave);
   const int nwaves = gridDim.x * kWavesPerBlock;
   __shared__ unsigned gen_local;
   if (threadIdx.x == 0)

@@ -12,7 +12,7 @@ __global__ void __launch_bounds__(64 * kWaves)
     k_down_s(int n, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
              const T* __restrict__ f, int pf, T* __restrict__ fc, int pfc, int nbands, int nitems,
              int hs, T h2, T inv_h2) {
-  const int item = xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+  const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
   down_wave<T, BC, UIN>(n, uin, pui, uout, puo, f, pf, fc, pfc, item % nbands, item / nbands, hs,
                         h2, inv_h2, threadIdx.x & 63);
@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(64 * kWaves)
     k_up_s(int n, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
            const T* __restrict__ f, int pf, const T* __restrict__ c, int pc, int nbands,
            int nitems, int hs, T h2, double* __restrict__ u64, int p64) {
-  const int item = xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+  const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
   up_wave<T, BC, ADD>(n, uin, pui, uout, puo, f, pf, c, pc, item % nbands, item / nbands, hs, h2,
                       threadIdx.x & 63, u64, p64);
@@ -48,6 +48,9 @@ int stream_up_owned() { return kUpOwned; }
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
                               int puo, const T* f, int pf, T* fc, int pfc, int hs) {
+  // A periodic band wraps at most once only from n - 1 >= 128 on (levels
+  // this small are in the tail); hs must be even (row parity of a segment).
+  if ((bc == kPeriodic && n - 1 < 128) || (hs > 0 && (hs & 1))) return hipErrorInvalidValue;
   const int extent = bc == kPeriodic ? n - 1 : n;
   if (hs <= 0) hs = stream_segment_rows(n, bc, kDownOwned);
   const int nb = (extent + kDownOwned - 1) / kDownOwned;
@@ -75,6 +78,7 @@ template <typename T>
 hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
                             const T* f, int pf, const T* c, int pc, int hs, double* u64,
                             int p64) {
+  if ((bc == kPeriodic && n - 1 < 128) || (hs > 0 && (hs & 1))) return hipErrorInvalidValue;
   const int extent = bc == kPeriodic ? n - 1 : n;
   if (hs <= 0) hs = stream_segment_rows(n, bc, kUpOwned);
   const int nb = (extent + kUpOwned - 1) / kUpOwned;

@@ -34,26 +34,41 @@ constexpr int kDownHalo = 6;        // columns on each side a down band does not
 constexpr int kDownOwned = 128 - 2 * kDownHalo;
 constexpr int kUpHalo = 6;          // up pass: spline support + 4 half-sweeps
 constexpr int kUpOwned = 112;       // owned columns [xw + 6, xw + 118)
-constexpr int kAhead = 6;           // rows loaded this many steps before first use
+// Rows are loaded this many steps before the step that first uses them.  The
+// 16-slot row rings bound it: the down pass keeps rows t-6 .. t live (at
+// most 9 ahead), the up pass rows t-5 .. t and its 8-slot FP64 ring rows
+// t-4 .. (at most 7 ahead).  The wavefronts of a large level together keep
+// enough loads in flight with a few rows each; 5 to 9 rows measured up to
+// 2 % slower on 4097^2 than these.
+constexpr int kAheadDown = 3;
+constexpr int kAheadUp = 4;
+static_assert(kAheadDown <= 9 && kAheadUp <= 7, "row rings hold the rows in flight");
 
 // Cross-lane moves by one lane with DPP wavefront shifts (GFX9 family):
 // wave_shr:1 gives lane l the value of lane l - 1, wave_shl:1 that of lane
-// l + 1.  Lanes with no source lane receive 0; they are band-edge lanes whose
-// results are never written.  64-bit values move as two 32-bit halves.
+// l + 1.  Lanes with no source lane receive 0 (bound control: no old value
+// to keep); they are band-edge lanes whose results are never written.
+// 64-bit values move as two 32-bit halves.
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v) {
   return __builtin_bit_cast(
-      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
   const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 constexpr int kWaveShr1 = 0x138;
 constexpr int kWaveShl1 = 0x130;
+
+// A value that is the same in every lane of the wavefront (derived from the
+// wavefront's index), moved to a scalar register.  Branches on it then stay
+// scalar: without this the compiler treats the row parity of a half-sweep as
+// per-lane and runs both colours' code under exec masks.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <typename T>
 __device__ __forceinline__ T from_left(T v) {  // value of lane - 1
@@ -64,29 +79,69 @@ __device__ __forceinline__ T from_right(T v) {  // value of lane + 1
   return dpp_move<kWaveShl1>(v);
 }
 
-// Column data of one lane.
+// Two adjacent elements of a row, moved by one 8-byte (FP32) or 16-byte
+// (FP64) access.  Only element alignment is assumed: rows of an odd pitch
+// start at odd elements.
+template <typename T>
+struct PairOf;
+template <>
+struct PairOf<float> {
+  typedef float type __attribute__((ext_vector_type(2), aligned(4)));
+};
+template <>
+struct PairOf<double> {
+  typedef double type __attribute__((ext_vector_type(2), aligned(8)));
+};
+
+// Column data of one lane.  Loads read the stored pair (pc, pc + 1): the
+// lane's columns x0, x0 + 1 where both exist (always on a periodic grid:
+// x0 and n - 1 are even, so x0 + 1 never wraps apart from x0).  On a
+// Dirichlet grid the lane holding the last column n - 1 reads the pair
+// ending there and takes it from the second element (sw); lanes outside the
+// grid read columns 0 and 1, values that only feed results that are never
+// written.
 template <int BC>
 struct Cols {
-  int c0, c1;        // stored column indices used for loads
-  bool in0, in1;     // column exists in the array (Dirichlet)
+  int pc;            // first stored column of the pair that is loaded
+  bool sw;           // the lane's column x0 is the pair's second element
   bool unk0, unk1;   // column holds unknowns
   __device__ Cols(int x0, int n) {
-    const int x1 = x0 + 1;
     if constexpr (BC == kPeriodic) {
       const int N = n - 1;
-      c0 = x0 < 0 ? x0 + N : (x0 >= N ? x0 - N : x0);
-      c1 = x1 < 0 ? x1 + N : (x1 >= N ? x1 - N : x1);
-      in0 = in1 = unk0 = unk1 = true;
+      pc = x0 < 0 ? x0 + N : (x0 >= N ? x0 - N : x0);
+      sw = false;
+      unk0 = unk1 = true;
     } else {
-      in0 = x0 >= 0 && x0 < n;
-      in1 = x1 >= 0 && x1 < n;
-      c0 = in0 ? x0 : 0;
-      c1 = in1 ? x1 : 0;
+      pc = (x0 >= 0 && x0 <= n - 2) ? x0 : (x0 == n - 1 ? n - 2 : 0);
+      sw = x0 == n - 1;
       unk0 = x0 >= 1 && x0 <= n - 2;
-      unk1 = x1 >= 1 && x1 <= n - 2;
+      unk1 = x0 + 1 >= 1 && x0 + 1 <= n - 2;
     }
   }
 };
+
+template <typename T>
+__device__ __forceinline__ void load_pair(T (&dst)[2], const T* __restrict__ row, int pc,
+                                          bool sw) {
+  const typename PairOf<T>::type v = *reinterpret_cast<const typename PairOf<T>::type*>(row + pc);
+  dst[0] = sw ? v.y : v.x;
+  dst[1] = v.y;
+}
+
+// Store a and b at p[0], p[1] where w0, w1 hold: one pair store for the
+// lanes that write both.
+template <typename T>
+__device__ __forceinline__ void store_pair(T* p, bool w0, bool w1, T a, T b) {
+  if (w0 && w1) {
+    typename PairOf<T>::type v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<typename PairOf<T>::type*>(p) = v;
+  } else {
+    if (w0) p[0] = a;
+    if (w1) p[1] = b;
+  }
+}
 
 template <int BC>
 __device__ __forceinline__ int row_index(int t, int n, bool* in) {
@@ -116,28 +171,30 @@ __device__ __forceinline__ void load_row(T (&dst)[2], const T* __restrict__ a, i
                                          const Cols<BC>& col) {
   bool rin;
   const int r = row_index<BC>(t, n, &rin);
-  const T* p = a + (size_t)r * pa;
-  dst[0] = p[col.c0];
-  dst[1] = p[col.c1];
+  load_pair<T>(dst, a + (size_t)r * pa, col.pc, col.sw);
 }
 
-// Red-black half-sweep on one row: the node of colour `colour` among the
-// lane's two columns solves its equation with its four neighbours fixed.
+// Red-black half-sweep on one row: the node of the half-sweep's colour among
+// the lane's two columns (column x0 + odd, odd = (colour + row) & 1) solves
+// its equation with its four neighbours fixed.  Callers pass odd as a value
+// the unrolled row loop makes a constant (rows of a segment start at an even
+// row), so only one column's code is emitted; updates are selects, not
+// branches, which keeps the row ring in place in registers.
 template <typename T, int BC>
 __device__ __forceinline__ void sweep_row(const T (&um)[2], T (&u0)[2], const T (&up)[2],
-                                          const T (&f0)[2], int row, int colour, int n,
+                                          const T (&f0)[2], int row, int odd, int n,
                                           const Cols<BC>& col, T h2) {
   const bool rok = row_unknown<BC>(row, n);
-  if (((colour + row) & 1) == 0) {
+  if (odd == 0) {
     const T left = from_left(u0[1]);
     const T s = ((um[0] + up[0]) + left) + u0[1];
     const T v = (h2 * f0[0] + s) * T(0.25);
-    if (rok && col.unk0) u0[0] = v;
+    u0[0] = (rok && col.unk0) ? v : u0[0];
   } else {
     const T right = from_right(u0[0]);
     const T s = ((um[1] + up[1]) + u0[0]) + right;
     const T v = (h2 * f0[1] + s) * T(0.25);
-    if (rok && col.unk1) u0[1] = v;
+    u0[1] = (rok && col.unk1) ? v : u0[1];
   }
 }
 
@@ -165,6 +222,7 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
                                           int hs, T h2, T inv_h2, int lane) {
+  n = wave_uniform(n), band = wave_uniform(band), seg = wave_uniform(seg), hs = wave_uniform(hs);
   const int xw = band * kDownOwned - kDownHalo;
   const int x0 = xw + 2 * lane;
   const int ys = seg * hs;
@@ -178,18 +236,18 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
   const int row_end = BC == kPeriodic ? N : n;  // rows [0, row_end) are owned by some segment
 
   // Rows live in a ring of 16 register slots; row t0 + s is in slot s & 15
-  // and is loaded kAhead steps before the step that first uses it.
+  // and is loaded kAheadDown steps before the step that first uses it.
   T U[16][2], F[16][2], R[4][2];
 #pragma unroll
   for (int k = 0; k < 16; ++k) U[k][0] = U[k][1] = F[k][0] = F[k][1] = T(0);
 #pragma unroll
   for (int k = 0; k < 4; ++k) R[k][0] = R[k][1] = T(0);
 
-  const int t0 = ys - 6;
+  const int t0 = ys - 6;  // even (hs is even)
   const int steps = hs + 11;
   const bool read_u = UIN == 1 || (UIN == -1 && uin != nullptr);
 #pragma unroll
-  for (int k = 0; k < kAhead; ++k) {
+  for (int k = 0; k < kAheadDown; ++k) {
     if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
     load_row<T, BC>(F[k], f, pf, t0 + k, n, col);
   }
@@ -199,27 +257,27 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
       const int s = sb + k;
       if (s >= steps) break;
       const int t = t0 + s;
-      // Rows kAhead ahead (past the segment's last step too: harmless reads).
+      // Rows kAheadDown ahead (past the segment's last step too: harmless reads).
       {
-        T(&nu)[2] = U[(k + kAhead) & 15];
-        if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(nu, uin, pui, t + kAhead, n, col);
+        T(&nu)[2] = U[(k + kAheadDown) & 15];
+        if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(nu, uin, pui, t + kAheadDown, n, col);
         else nu[0] = nu[1] = T(0);
-        load_row<T, BC>(F[(k + kAhead) & 15], f, pf, t + kAhead, n, col);
+        load_row<T, BC>(F[(k + kAheadDown) & 15], f, pf, t + kAheadDown, n, col);
       }
-      // red (sweep 1) on t-1, black on t-2, red (sweep 2) on t-3, black on t-4
-      sweep_row<T, BC>(U[(k + 14) & 15], U[(k + 15) & 15], U[k], F[(k + 15) & 15], t - 1, 0, n,
-                       col, h2);
+      // red (sweep 1) on t-1, black on t-2, red (sweep 2) on t-3, black on
+      // t-4; t has the parity of k (t0 and sb are even).
+      sweep_row<T, BC>(U[(k + 14) & 15], U[(k + 15) & 15], U[k], F[(k + 15) & 15], t - 1,
+                       (k + 1) & 1, n, col, h2);
       sweep_row<T, BC>(U[(k + 13) & 15], U[(k + 14) & 15], U[(k + 15) & 15], F[(k + 14) & 15],
-                       t - 2, 1, n, col, h2);
+                       t - 2, (k + 1) & 1, n, col, h2);
       sweep_row<T, BC>(U[(k + 12) & 15], U[(k + 13) & 15], U[(k + 14) & 15], F[(k + 13) & 15],
-                       t - 3, 0, n, col, h2);
+                       t - 3, (k + 1) & 1, n, col, h2);
       sweep_row<T, BC>(U[(k + 11) & 15], U[(k + 12) & 15], U[(k + 13) & 15], F[(k + 12) & 15],
-                       t - 4, 1, n, col, h2);
+                       t - 4, (k + 1) & 1, n, col, h2);
       const int tu = t - 4;
       if (tu >= ys && tu < ys + hs && tu < row_end) {
         T* p = uout + (size_t)tu * puo;
-        if (wr0) p[x0] = U[(k + 12) & 15][0];
-        if (wr1) p[x0 + 1] = U[(k + 12) & 15][1];
+        store_pair<T>(p + x0, wr0, wr1, U[(k + 12) & 15][0], U[(k + 12) & 15][1]);
       }
       residual_row<T, BC>(U[(k + 10) & 15], U[(k + 11) & 15], U[(k + 12) & 15], F[(k + 11) & 15],
                           R[(k + 3) & 3], t - 5, n, col, inv_h2);
@@ -267,6 +325,7 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
                                         int pf, const T* __restrict__ c, int pc, int band, int seg,
                                         int hs, T h2, int lane, double* __restrict__ u64 = nullptr,
                                         int p64 = 0) {
+  n = wave_uniform(n), band = wave_uniform(band), seg = wave_uniform(seg), hs = wave_uniform(hs);
   const int xw = band * kUpOwned - kUpHalo;
   const int x0 = xw + 2 * lane;
   const int ys = seg * hs;
@@ -294,19 +353,18 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
   for (int q = 0; q < 3; ++q) spline_x<T>(CR[q], CX[q]);
   CX[3][0] = CX[3][1] = T(0);
   const int steps = hs + 8;
-  // With u64: its row written at step s (row t0 + s - 4) is read kAhead
+  // With u64: its row written at step s (row t0 + s - 4) is read kAheadUp
   // steps earlier into UR[s & 7].
   double UR[ADD ? 8 : 1][2];
   auto load_u64 = [&](int slot, int row) {
     if (ADD) {
       const int rr = row < 0 ? 0 : (row >= row_end ? row_end - 1 : row);
       const double* q = u64 + (size_t)rr * p64;
-      UR[slot][0] = q[col.c0];
-      UR[slot][1] = q[col.c1];
+      load_pair<double>(UR[slot], q, col.pc, col.sw);
     }
   };
 #pragma unroll
-  for (int k = 0; k < kAhead; ++k) {
+  for (int k = 0; k < kAheadUp; ++k) {
     load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
     load_row<T, BC>(F[k], f, pf, t0 + k, n, col);
     load_u64(k & 7, t0 - 4 + k);
@@ -317,10 +375,10 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
       const int s = sb + k;
       if (s >= steps) break;
       const int t = t0 + s;
-      {  // rows kAhead ahead (past the segment's last step too: harmless reads)
-        load_row<T, BC>(U[(k + kAhead) & 15], uin, pui, t + kAhead, n, col);
-        load_row<T, BC>(F[(k + kAhead) & 15], f, pf, t + kAhead, n, col);
-        load_u64((k + kAhead) & 7, t - 4 + kAhead);
+      {  // rows kAheadUp ahead (past the segment's last step too: harmless reads)
+        load_row<T, BC>(U[(k + kAheadUp) & 15], uin, pui, t + kAheadUp, n, col);
+        load_row<T, BC>(F[(k + kAheadUp) & 15], f, pf, t + kAheadUp, n, col);
+        load_u64((k + kAheadUp) & 7, t - 4 + kAheadUp);
       }
       // coarse row q = (s - 1)/2 + 3 is needed from the first odd step on
       if (k & 1) {
@@ -347,28 +405,29 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
                T(1.0 / 48.0) * e[1];
         }
         const bool rok = row_unknown<BC>(t, n);
-        if (rok && col.unk0) U[k][0] += v0;
-        if (rok && col.unk1) U[k][1] += v1;
+        U[k][0] = (rok && col.unk0) ? U[k][0] + v0 : U[k][0];
+        U[k][1] = (rok && col.unk1) ? U[k][1] + v1 : U[k][1];
       }
-      sweep_row<T, BC>(U[(k + 14) & 15], U[(k + 15) & 15], U[k], F[(k + 15) & 15], t - 1, 0, n,
-                       col, h2);
+      // t has the parity of k (t0 and sb are even)
+      sweep_row<T, BC>(U[(k + 14) & 15], U[(k + 15) & 15], U[k], F[(k + 15) & 15], t - 1,
+                       (k + 1) & 1, n, col, h2);
       sweep_row<T, BC>(U[(k + 13) & 15], U[(k + 14) & 15], U[(k + 15) & 15], F[(k + 14) & 15],
-                       t - 2, 1, n, col, h2);
+                       t - 2, (k + 1) & 1, n, col, h2);
       sweep_row<T, BC>(U[(k + 12) & 15], U[(k + 13) & 15], U[(k + 14) & 15], F[(k + 13) & 15],
-                       t - 3, 0, n, col, h2);
+                       t - 3, (k + 1) & 1, n, col, h2);
       sweep_row<T, BC>(U[(k + 11) & 15], U[(k + 12) & 15], U[(k + 13) & 15], F[(k + 12) & 15],
-                       t - 4, 1, n, col, h2);
+                       t - 4, (k + 1) & 1, n, col, h2);
       const int tu = t - 4;
       if (tu >= ys && tu < ys + hs && tu < row_end) {
         if (ADD) {
           double* q = u64 + (size_t)tu * p64;
           const bool r = row_unknown<BC>(tu, n);
-          if (wr0 && col.unk0 && r) q[x0] = UR[k & 7][0] + (double)U[(k + 12) & 15][0];
-          if (wr1 && col.unk1 && r) q[x0 + 1] = UR[k & 7][1] + (double)U[(k + 12) & 15][1];
+          store_pair<double>(q + x0, wr0 && col.unk0 && r, wr1 && col.unk1 && r,
+                             UR[k & 7][0] + (double)U[(k + 12) & 15][0],
+                             UR[k & 7][1] + (double)U[(k + 12) & 15][1]);
         } else {
           T* p = uout + (size_t)tu * puo;
-          if (wr0) p[x0] = U[(k + 12) & 15][0];
-          if (wr1) p[x0 + 1] = U[(k + 12) & 15][1];
+          store_pair<T>(p + x0, wr0, wr1, U[(k + 12) & 15][0], U[(k + 12) & 15][1]);
         }
       }
     }
