@@ -113,7 +113,7 @@ hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uou
                      const T* f, int pf, const T* c, int pc,
                      bool pre = false);
 // Register-streaming versions of the two passes (mg_stream.hip); same
-// contracts.  hs = rows per wavefront segment (even, 8..128; 0 = chosen per level).
+// contracts.  hs = rows per wavefront segment (even, 4..128; 0 = chosen per level).
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
                               int puo, const T* f, int pf, T* fc, int pfc, int hs);

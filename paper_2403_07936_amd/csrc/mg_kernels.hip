@@ -271,32 +271,6 @@ __global__ void k_coarse(const T* __restrict__ f, int pf, T* __restrict__ u, int
 
 template <int BC>
 __global__ void __launch_bounds__(TX* TY)
-    k_residual_mixed(int n, const double* __restrict__ u, int pu, const double* __restrict__ f,
-                     int pf, float* __restrict__ r32, int pr, double* __restrict__ partials,
-                     double inv_h2) {
-  __shared__ double sh[TX * TY];
-  const int j = blockIdx.x * TX + threadIdx.x;
-  const int i = blockIdx.y * TY + threadIdx.y;
-  double sq = 0.0;
-  if (i < n && j < n) {
-    double v;
-    bool unknown;
-    if constexpr (BC == kDirichlet) {
-      unknown = !(i == 0 || j == 0 || i == n - 1 || j == n - 1);
-      v = unknown ? residual_at<double, BC>(n, u, pu, f, pf, i, j, inv_h2) : 0.0;
-    } else {
-      unknown = i < n - 1 && j < n - 1;
-      v = residual_at<double, BC>(n, u, pu, f, pf, unwrap_seam(i, n), unwrap_seam(j, n), inv_h2);
-    }
-    r32[(size_t)i * pr + j] = (float)v;
-    if (unknown) sq = v * v;
-  }
-  const double s = block_sum(sq, sh);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = s;
-}
-
-template <int BC>
-__global__ void __launch_bounds__(TX* TY)
     k_update_mixed(int n, double* __restrict__ u, int pu, const float* __restrict__ e, int pe) {
   constexpr int lo = first_unknown<BC>();
   const int j = lo + blockIdx.x * TX + threadIdx.x;
@@ -499,21 +473,6 @@ hipError_t launch_coarse(hipStream_t s, int bc, const T* f, int pf, T* u, int pu
     hipLaunchKernelGGL((k_coarse<T, kDirichlet>), dim3(1), dim3(64), 0, s, f, pf, u, pu, inv);
   else
     hipLaunchKernelGGL((k_coarse<T, kPeriodic>), dim3(1), dim3(64), 0, s, f, pf, u, pu, inv);
-  return hipGetLastError();
-}
-
-hipError_t launch_residual_mixed(hipStream_t s, int bc, int n, const double* u, int pu,
-                                 const double* f, int pf, float* r32, int pr, double* partials,
-                                 int* nblocks) {
-  const double inv_h2 = (double)(n - 1) * (double)(n - 1);
-  const dim3 g = grid_nodes(n);
-  *nblocks = (int)(g.x * g.y);
-  if (bc == kDirichlet)
-    hipLaunchKernelGGL((k_residual_mixed<kDirichlet>), g, kBlock, 0, s, n, u, pu, f, pf, r32, pr,
-                       partials, inv_h2);
-  else
-    hipLaunchKernelGGL((k_residual_mixed<kPeriodic>), g, kBlock, 0, s, n, u, pu, f, pf, r32, pr,
-                       partials, inv_h2);
   return hipGetLastError();
 }
 

@@ -1008,7 +1008,7 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
     const int pu = l == 0 ? pitch0 : p.pitch[l];
     const T* uin = (l == 0 && !mixed) ? u : nullptr;
     const int reps = n >= 2049 ? 3 : 6;
-    const int hs_cands[] = {0, 8, 16, 32, 64, 96, 128};
+    const int hs_cands[] = {0, 4, 8, 16, 32, 64, 96, 128};
     if (add && !u64) {
       if (hipMalloc(&u64, sizeof(double) * (size_t)n * p.pitch[0]) != hipSuccess) {
         (void)hipGetLastError();

@@ -108,7 +108,8 @@ struct Cols {
   __device__ Cols(int x0, int n) {
     if constexpr (BC == kPeriodic) {
       const int N = n - 1;
-      pc = x0 < 0 ? x0 + N : (x0 >= N ? x0 - N : x0);
+      pc = x0 % N;
+      if (pc < 0) pc += N;
       sw = false;
       unk0 = unk1 = true;
     } else {

@@ -246,6 +246,28 @@ def test_mixed_step_parity(B, dev, bc, n, kernel_path):
         B.mg_destroy(ctx)
 
 
+@pytest.mark.parametrize("bc,n", [(D, 5), (P, 5), (P, 9), (D, 17), (P, 129), (D, 257),
+                                  (P, 1025)])
+def test_mixed_relres_matches_oracle_norm(B, dev, bc, n):
+    """The mixed path's norm check (FP64 residual by rows, per-wavefront
+    partial sums, fixed-order reduction) against the oracle's residual norm
+    of the iterate it returns, on grids from the coarsest up: a dropped row,
+    column or seam node shows as a relative difference far above 1e-12."""
+    say(f"mixed relres bc={bc} n={n}")
+    f = make_rhs(n, bc, 3)
+    ctx = ctx_for(B, n, bc, 1)
+    try:
+        ut = gpu(np.zeros_like(f), dev)
+        ft = gpu(f, dev)
+        for c in range(2):
+            rel = B.mg_vcycle(ctx, [ut.data_ptr()], [ft.data_ptr()], 1, want_relres=True)[0]
+            ref = oracle.relres(host(ut), f, bc)
+            say(f"  cycle {c + 1}: relres {rel:.6e} oracle {ref:.6e}")
+            assert abs(rel - ref) <= 1e-12 * ref + 1e-300
+    finally:
+        B.mg_destroy(ctx)
+
+
 @pytest.mark.parametrize("name", ["dirichlet4097", "periodic1025"])
 def test_full_size_cycle_parity(B, dev, name):
     """The benchmark configurations at full size, in the launch configuration
