@@ -204,16 +204,24 @@ template <typename T, int BC, int TR>
 __device__ __forceinline__ void tail_sweeps(T* u, const T* f, int n, int count) {
   const double hd = 1.0 / (double)(n - 1);
   const T h2 = T(hd * hd);
+  // The unknowns of a side n <= 65 lie in rows and columns 0 .. 63, so the
+  // 32 lanes of a row take the 32 nodes of the half-sweep's colour (every
+  // lane busy, where a lane per column would leave half of them idle).
+  static_assert(kTailMaxSide <= 65, "one node of a colour per lane and row");
+  const int ty = tail_tid() >> 5, tx = tail_tid() & 31;
   for (int s = 0; s < count; ++s) {
     const int colour = s & 1;
-    MG_TAIL_FOR(n, i, j, {
-      if (tail_unknown<BC>(i, j, n) && ((i + j) & 1) == colour) {
+#pragma unroll
+    for (int a = 0; a < (64 + TR - 1) / TR; ++a) {
+      const int i = ty + TR * a;
+      const int j = 2 * tx + ((i + colour) & 1);
+      if (i < n && j < n && tail_unknown<BC>(i, j, n)) {
         const T sum = ((u[wrap_prev<BC>(i, n) * n + j] + u[wrap_next<BC>(i, n) * n + j]) +
                        u[i * n + wrap_prev<BC>(j, n)]) +
                       u[i * n + wrap_next<BC>(j, n)];
         u[i * n + j] = (h2 * f[i * n + j] + sum) * T(0.25);
       }
-    });
+    }
     __syncthreads();
   }
 }
