@@ -254,7 +254,9 @@ template <typename T, int BC>
 __global__ void __launch_bounds__(256)
     k_pre_tile(int nc, const T* __restrict__ in, int pi, T* __restrict__ out, int po, int tiles_x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  pre_tile_block<T, BC, 256>(nc, in, pi, out, po, blockIdx.x, tiles_x,
+  // Consecutive tiles on one XCD, so that the halos neighbouring tiles share
+  // are read from that XCD's L2 rather than again from HBM.
+  pre_tile_block<T, BC, 256>(nc, in, pi, out, po, xcd_tile(blockIdx.x, gridDim.x), tiles_x,
                              reinterpret_cast<T*>(smem_raw));
 }
 
