@@ -170,6 +170,17 @@ __global__ void __launch_bounds__(kPersistThreads)
           case kItemUp: {
             const PLevel& C = p.lv[it.level + 1];
             const double hd = 1.0 / (double)(L.n - 1);
+            // Mixed path, level 0: the finished rows go straight into the
+            // FP64 iterate (the refinement update), as in the graph path.
+            if constexpr (sizeof(T) == sizeof(float)) {
+              if (it.level == 0 && p.zero_guess) {
+                up_wave<T, BC, true>(L.n, static_cast<const T*>(L.b), L.pitch, nullptr, 0,
+                                     static_cast<const T*>(L.f), L.pitch_f,
+                                     static_cast<const T*>(C.c), C.pitch, it.a, it.b, L.hs_up,
+                                     T(hd * hd), lane, p.u64, p.pitch64);
+                break;
+              }
+            }
             up_wave<T, BC>(L.n, static_cast<const T*>(L.b), L.pitch, static_cast<T*>(L.u),
                            L.pitch_u, static_cast<const T*>(L.f), L.pitch_f,
                            static_cast<const T*>(C.c), C.pitch, it.a, it.b, L.hs_up,

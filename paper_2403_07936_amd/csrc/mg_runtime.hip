@@ -686,7 +686,15 @@ int32_t build_persistent(mg_ctx_s* ctx) {
     }
     close_phase(kItemUp, first);
   }
-  if (mixed) rows_items(kItemUpd);
+  // Mixed path: the level-0 up pass adds into the FP64 iterate; only
+  // problems that lie wholly in the tail still need the update rows.
+  if (mixed) {
+    const size_t first = items.size();
+    for (int b = 0; b < B; ++b)
+      if (ctx->probs[b].tail == 0)
+        for (int r = 0; r < ctx->probs[b].n; r += kRowsPerItem) items.push_back({b, 0, r, 0});
+    close_phase(kItemUpd, first);
+  }
 
   P.lds = lds;
   MG_HIP(persistent_init(std::max(lds, (size_t)65536), std::max(lds, (size_t)65536)));
