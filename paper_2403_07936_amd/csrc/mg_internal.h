@@ -163,7 +163,8 @@ hipError_t launch_cnn_final(hipStream_t s, int N, const unsigned short* z, const
 // ---- persistent cycle kernel (mg_persist.hip) -------------------------------
 constexpr int kMaxLevels = 13;   // 16385 -> 5
 constexpr int kPersistThreads = 512;
-constexpr int kRowsPerItem = 8;  // rows of a residual / update item
+constexpr int kRowsPerItem = 8;  // rows of an update item
+constexpr int kResSegRows = 32;  // rows of a residual item (one band of columns)
 
 // One level of one problem as the persistent kernel sees it.  Arrays are of
 // the cycle's precision except where noted.
@@ -187,7 +188,7 @@ struct PProblem {
 };
 
 enum PKind : int {
-  kItemRes = 0,   // FP64 residual rows -> FP32 right-hand side (a = first row)
+  kItemRes = 0,   // FP64 residual -> FP32 right-hand side (a = band, b = segment)
   kItemDown = 1,  // a = band, b = segment
   kItemTail = 2,  // workgroup item
   kItemPre = 3,   // workgroup item: prefilter tile a of b tiles along x
@@ -225,5 +226,6 @@ hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob);
 int stream_segment_rows(int n, int bc, int owned_cols);
 int stream_down_owned();
 int stream_up_owned();
+int stream_res_owned();
 
 }  // namespace mg

@@ -56,41 +56,6 @@ __device__ bool grid_barrier(PBarrier* bar, unsigned* gen_local) {
   return ok != 0;
 }
 
-template <int BC>
-__device__ __forceinline__ int wrap_n(int i, int N) {
-  return i < 0 ? i + N : (i >= N ? i - N : i);
-}
-
-// FP64 residual of level 0 stored as the FP32 right-hand side, rows
-// [r0, r0 + kRowsPerItem); Dirichlet boundary 0, periodic seam = node 0.
-template <int BC>
-__device__ __forceinline__ void res_rows(const PProblem& p, int r0, int lane) {
-  const int n = p.lv[0].n, pu = p.pitch64, pr = p.lv[0].pitch_f;
-  const double* u = p.u64;
-  const double* f = p.f64;
-  float* r = static_cast<float*>(p.lv[0].f);
-  const double inv_h2 = (double)(n - 1) * (double)(n - 1);
-  for (int i = r0; i < r0 + kRowsPerItem && i < n; ++i) {
-    for (int j = lane; j < n; j += 64) {
-      double v = 0.0;
-      if (BC == kPeriodic) {
-        const int N = n - 1;
-        const int ii = i == N ? 0 : i, jj = j == N ? 0 : j;
-        const int im = ii == 0 ? N - 1 : ii - 1, ip = ii == N - 1 ? 0 : ii + 1;
-        const int jm = jj == 0 ? N - 1 : jj - 1, jp = jj == N - 1 ? 0 : jj + 1;
-        const double s = ((u[(size_t)im * pu + jj] + u[(size_t)ip * pu + jj]) +
-                          u[(size_t)ii * pu + jm]) + u[(size_t)ii * pu + jp];
-        v = f[(size_t)ii * pu + jj] - (4.0 * u[(size_t)ii * pu + jj] - s) * inv_h2;
-      } else if (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) {
-        const double s = ((u[(size_t)(i - 1) * pu + j] + u[(size_t)(i + 1) * pu + j]) +
-                          u[(size_t)i * pu + j - 1]) + u[(size_t)i * pu + j + 1];
-        v = f[(size_t)i * pu + j] - (4.0 * u[(size_t)i * pu + j] - s) * inv_h2;
-      }
-      r[(size_t)i * pr + j] = (float)v;
-    }
-  }
-}
-
 // u64 += e on the unknowns of rows [r0, r0 + kRowsPerItem).
 template <int BC>
 __device__ __forceinline__ void upd_rows(const PProblem& p, int r0, int lane) {
@@ -152,7 +117,9 @@ __global__ void __launch_bounds__(kPersistThreads)
         const PLevel& L = p.lv[it.level];
         switch (P.kind) {
           case kItemRes:
-            res_rows<BC>(p, it.a, lane);
+            (void)residual_wave<BC>(L.n, p.u64, p.pitch64, p.f64, p.pitch64,
+                                    static_cast<float*>(L.f), L.pitch_f, it.a, it.b, kResSegRows,
+                                    (double)(L.n - 1) * (double)(L.n - 1), lane);
             break;
           case kItemUpd:
             upd_rows<BC>(p, it.a, lane);

@@ -638,12 +638,6 @@ int32_t build_persistent(mg_ctx_s* ctx) {
   auto close_phase = [&](int kind, size_t first) {
     if (items.size() > first) phases.push_back({kind, (int)first, (int)(items.size() - first), 0});
   };
-  auto rows_items = [&](int kind) {
-    const size_t first = items.size();
-    for (int b = 0; b < B; ++b)
-      for (int r = 0; r < ctx->probs[b].n; r += kRowsPerItem) items.push_back({b, 0, r, 0});
-    close_phase(kind, first);
-  };
   auto band_items = [&](int b, int l, bool down) {
     const PLevel& L = P.h_probs[b].lv[l];
     const int extent = P.bc == kPeriodic ? L.n - 1 : L.n;
@@ -652,7 +646,16 @@ int32_t build_persistent(mg_ctx_s* ctx) {
     for (int sg = 0; sg < ns; ++sg)
       for (int bd = 0; bd < nb; ++bd) items.push_back({b, l, bd, sg});
   };
-  if (mixed) rows_items(kItemRes);
+  if (mixed) {
+    const size_t first = items.size();
+    const int ow = stream_res_owned();
+    for (int b = 0; b < B; ++b) {
+      const int n = ctx->probs[b].n;
+      for (int sg = 0; sg < (n + kResSegRows - 1) / kResSegRows; ++sg)
+        for (int bd = 0; bd < (n + ow - 1) / ow; ++bd) items.push_back({b, 0, bd, sg});
+    }
+    close_phase(kItemRes, first);
+  }
   for (int k = K - 1; k >= 0; --k) {
     const size_t first = items.size();
     for (int b = 0; b < B; ++b) {

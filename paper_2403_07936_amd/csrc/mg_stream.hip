@@ -29,18 +29,9 @@ __global__ void __launch_bounds__(64 * kWaves)
                       threadIdx.x & 63, u64, p64);
 }
 
-// Mixed path, level 0: r32 = fl32(f - A u) with f, u and the arithmetic in
-// FP64, at every node of rows [ys, ys + hs) (0 on the Dirichlet boundary;
-// periodic seam row and column = node 0).  One wavefront per (band, row
-// segment): lanes 1 .. 62 own the band's kResOwned columns, lanes 0 and 63
-// only supply neighbours.  Rows stream through 8-slot rings, u loaded
-// kAheadRes + 1 rows and f kAheadRes rows before use.  Each wavefront writes
-// the sum of r^2 over the unknowns it owns to partials[item], in a fixed
-// order.
-constexpr int kResOwned = 124;
-constexpr int kAheadRes = 4;
-static_assert(kAheadRes <= 5, "u ring holds rows t-1 .. t+1+kAheadRes");
-
+// Mixed path, level 0: the FP64 residual by rows (residual_wave); each
+// wavefront writes the sum of r^2 over the unknowns it owns to
+// partials[item], reduced across its lanes in a fixed order.
 template <int BC>
 __global__ void __launch_bounds__(64 * kWaves)
     k_residual_mixed_s(int n, const double* __restrict__ u, int pu, const double* __restrict__ f,
@@ -49,66 +40,8 @@ __global__ void __launch_bounds__(64 * kWaves)
   const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
   const int lane = threadIdx.x & 63;
-  const int band = item % nbands, seg = item / nbands;
-  const int x0 = band * kResOwned - 2 + 2 * lane;
-  const Cols<BC> col(x0, n);
-  const int N = n - 1;
-  const bool owns = lane >= 1 && lane <= 62;
-  const bool w0 = owns && x0 < n, w1 = owns && x0 + 1 < n;
-  // Unknowns counted in the norm (periodic: the unique nodes).
-  const bool k0 = owns && (BC == kPeriodic ? x0 < N : col.unk0);
-  const bool k1 = owns && (BC == kPeriodic ? x0 + 1 < N : col.unk1);
-  const int ys = seg * hs;
-  const int steps = (ys + hs < n ? ys + hs : n) - ys;
-
-  double U[8][2], F[8][2];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) U[k][0] = U[k][1] = F[k][0] = F[k][1] = 0.0;
-  // u row ys - 1 + q in U[q & 7], f row ys + q in F[q & 7].
-#pragma unroll
-  for (int q = 0; q < kAheadRes + 2; ++q) {
-    const int r = ys - 1 + q;
-    load_row<double, BC>(U[q], u, pu, r < n ? r : n, n, col);
-  }
-#pragma unroll
-  for (int q = 0; q < kAheadRes; ++q) {
-    const int r = ys + q;
-    load_row<double, BC>(F[q], f, pf, r < n ? r : n - 1, n, col);
-  }
-  double acc = 0.0;
-  for (int sb = 0; sb < steps; sb += 8) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int s = sb + k;
-      if (s >= steps) break;
-      const int t = ys + s;
-      // Rows past n feed no step of the segment: clamped, so that a periodic
-      // row index wraps at most once.
-      const int tu = t + kAheadRes + 1, tf = t + kAheadRes;
-      load_row<double, BC>(U[(k + kAheadRes + 2) & 7], u, pu, tu < n ? tu : n, n, col);
-      load_row<double, BC>(F[(k + kAheadRes) & 7], f, pf, tf < n ? tf : n - 1, n, col);
-      const double(&um)[2] = U[k & 7];
-      const double(&u0)[2] = U[(k + 1) & 7];
-      const double(&up)[2] = U[(k + 2) & 7];
-      const double(&f0)[2] = F[k & 7];
-      const double left = from_left(u0[1]);
-      const double right = from_right(u0[0]);
-      const double s0 = ((um[0] + up[0]) + left) + u0[1];
-      const double s1 = ((um[1] + up[1]) + u0[0]) + right;
-      double r0 = f0[0] - (4.0 * u0[0] - s0) * inv_h2;
-      double r1 = f0[1] - (4.0 * u0[1] - s1) * inv_h2;
-      if constexpr (BC == kDirichlet) {
-        const bool rok = row_unknown<BC>(t, n);
-        r0 = (rok && col.unk0) ? r0 : 0.0;
-        r1 = (rok && col.unk1) ? r1 : 0.0;
-      }
-      store_pair<float>(r32 + (size_t)t * pr + x0, w0, w1, (float)r0, (float)r1);
-      if (BC == kDirichlet || t < N) {
-        acc += k0 ? r0 * r0 : 0.0;
-        acc += k1 ? r1 * r1 : 0.0;
-      }
-    }
-  }
+  double acc = residual_wave<BC>(n, u, pu, f, pf, r32, pr, item % nbands, item / nbands, hs,
+                                 inv_h2, lane);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
   if (lane == 0) partials[item] = acc;
@@ -129,6 +62,7 @@ int stream_segment_rows(int n, int bc, int owned_cols) {
 
 int stream_down_owned() { return kDownOwned; }
 int stream_up_owned() { return kUpOwned; }
+int stream_res_owned() { return kResOwned; }
 
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
