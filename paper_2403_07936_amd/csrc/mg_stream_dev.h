@@ -258,12 +258,14 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
       const int s = sb + k;
       if (s >= steps) break;
       const int t = t0 + s;
-      // Rows kAheadDown ahead (past the segment's last step too: harmless reads).
+      // Rows kAheadDown ahead; past the last row a step uses, that row again
+      // (a cache hit instead of a row of HBM traffic; never used).
       {
+        const int ta = t + kAheadDown < t0 + steps - 1 ? t + kAheadDown : t0 + steps - 1;
         T(&nu)[2] = U[(k + kAheadDown) & 15];
-        if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(nu, uin, pui, t + kAheadDown, n, col);
+        if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(nu, uin, pui, ta, n, col);
         else nu[0] = nu[1] = T(0);
-        load_row<T, BC>(F[(k + kAheadDown) & 15], f, pf, t + kAheadDown, n, col);
+        load_row<T, BC>(F[(k + kAheadDown) & 15], f, pf, ta, n, col);
       }
       // red (sweep 1) on t-1, black on t-2, red (sweep 2) on t-3, black on
       // t-4; t has the parity of k (t0 and sb are even).
@@ -357,9 +359,12 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
   // With u64: its row written at step s (row t0 + s - 4) is read kAheadUp
   // steps earlier into UR[s & 7].
   double UR[ADD ? 8 : 1][2];
+  // Only rows the segment stores are read: others repeat its first or last
+  // row (cache hits; never used).
+  const int ylast = (ys + hs < row_end ? ys + hs : row_end) - 1;
   auto load_u64 = [&](int slot, int row) {
     if (ADD) {
-      const int rr = row < 0 ? 0 : (row >= row_end ? row_end - 1 : row);
+      const int rr = row < ys ? ys : (row > ylast ? ylast : row);
       const double* q = u64 + (size_t)rr * p64;
       load_pair<double>(UR[slot], q, col.pc, col.sw);
     }
@@ -376,9 +381,10 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
       const int s = sb + k;
       if (s >= steps) break;
       const int t = t0 + s;
-      {  // rows kAheadUp ahead (past the segment's last step too: harmless reads)
-        load_row<T, BC>(U[(k + kAheadUp) & 15], uin, pui, t + kAheadUp, n, col);
-        load_row<T, BC>(F[(k + kAheadUp) & 15], f, pf, t + kAheadUp, n, col);
+      {  // rows kAheadUp ahead; past the last row a step uses, that row again
+        const int ta = t + kAheadUp < t0 + steps - 1 ? t + kAheadUp : t0 + steps - 1;
+        load_row<T, BC>(U[(k + kAheadUp) & 15], uin, pui, ta, n, col);
+        load_row<T, BC>(F[(k + kAheadUp) & 15], f, pf, ta, n, col);
         load_u64((k + kAheadUp) & 7, t - 4 + kAheadUp);
       }
       // coarse row q = (s - 1)/2 + 3 is needed from the first odd step on
@@ -467,15 +473,19 @@ __device__ __forceinline__ double residual_wave(int n, const double* __restrict_
 #pragma unroll
   for (int k = 0; k < 8; ++k) U[k][0] = U[k][1] = F[k][0] = F[k][1] = 0.0;
   // u row ys - 1 + q in U[q & 7], f row ys + q in F[q & 7].
+  // Rows past the last ones the segment uses (u: ys + steps <= n, f: one
+  // less) repeat them: cache hits, never used, and a periodic row index
+  // wraps at most once.
+  const int ulast = ys + steps, flast = ys + steps - 1;
 #pragma unroll
   for (int q = 0; q < kAheadRes + 2; ++q) {
     const int r = ys - 1 + q;
-    load_row<double, BC>(U[q], u, pu, r < n ? r : n, n, col);
+    load_row<double, BC>(U[q], u, pu, r < ulast ? r : ulast, n, col);
   }
 #pragma unroll
   for (int q = 0; q < kAheadRes; ++q) {
     const int r = ys + q;
-    load_row<double, BC>(F[q], f, pf, r < n ? r : n - 1, n, col);
+    load_row<double, BC>(F[q], f, pf, r < flast ? r : flast, n, col);
   }
   double acc = 0.0;
   for (int sb = 0; sb < steps; sb += 8) {
@@ -484,11 +494,9 @@ __device__ __forceinline__ double residual_wave(int n, const double* __restrict_
       const int s = sb + k;
       if (s >= steps) break;
       const int t = ys + s;
-      // Rows past n feed no step of the segment: clamped, so that a periodic
-      // row index wraps at most once.
       const int tu = t + kAheadRes + 1, tf = t + kAheadRes;
-      load_row<double, BC>(U[(k + kAheadRes + 2) & 7], u, pu, tu < n ? tu : n, n, col);
-      load_row<double, BC>(F[(k + kAheadRes) & 7], f, pf, tf < n ? tf : n - 1, n, col);
+      load_row<double, BC>(U[(k + kAheadRes + 2) & 7], u, pu, tu < ulast ? tu : ulast, n, col);
+      load_row<double, BC>(F[(k + kAheadRes) & 7], f, pf, tf < flast ? tf : flast, n, col);
       const double(&um)[2] = U[k & 7];
       const double(&u0)[2] = U[(k + 1) & 7];
       const double(&up)[2] = U[(k + 2) & 7];
