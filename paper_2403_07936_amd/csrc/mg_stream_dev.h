@@ -359,14 +359,16 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
   // With u64: its row written at step s (row t0 + s - 4) is read kAheadUp
   // steps earlier into UR[s & 7].
   double UR[ADD ? 8 : 1][2];
-  // Only rows the segment stores are read: others repeat its first or last
-  // row (cache hits; never used).
+  // Only rows and columns the segment stores are read: other rows repeat its
+  // first or last row, and the halo lanes read the first owned lane's pair
+  // (cache hits; never used).
   const int ylast = (ys + hs < row_end ? ys + hs : row_end) - 1;
+  const Cols<BC> col64(lane_owns ? x0 : xw + kUpHalo, n);
   auto load_u64 = [&](int slot, int row) {
     if (ADD) {
       const int rr = row < ys ? ys : (row > ylast ? ylast : row);
       const double* q = u64 + (size_t)rr * p64;
-      load_pair<double>(UR[slot], q, col.pc, col.sw);
+      load_pair<double>(UR[slot], q, col64.pc, col64.sw);
     }
   };
 #pragma unroll
