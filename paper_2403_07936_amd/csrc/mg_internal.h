@@ -223,6 +223,12 @@ hipError_t launch_resnorm_batched(hipStream_t s, int bc, const PProblem* probs, 
                                   double* partials, int slots, double* sums);
 hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob);
 // Segment rows / band count of the streaming passes for a level.
+// Mixed path, level 0, from e = 0: the streaming down pass whose
+// right-hand side r32 = fl32(f64 - A u64) it computes itself (and stores on
+// the rows and columns it owns, for the up pass): no separate residual pass.
+hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u64, int p64,
+                                  const double* f64, int pf64, float* r32, int pr, float* uout,
+                                  int puo, float* fc, int pfc, int hs);
 int stream_segment_rows(int n, int bc, int owned_cols);
 int stream_down_owned();
 int stream_up_owned();

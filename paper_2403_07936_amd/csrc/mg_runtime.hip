@@ -368,7 +368,8 @@ template <typename T>
 int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
                             const PrefilterTaps* taps_dev, T* u0, int pu0, const T* f0, int pf0,
                             bool zero_guess, hipStream_t s, bool cnn, double* u64 = nullptr,
-                            int p64 = 0, bool* added = nullptr) {
+                            int p64 = 0, bool* added = nullptr, const double* res_u = nullptr,
+                            const double* res_f = nullptr, int res_p = 0, T* r_out = nullptr) {
   const int t = p.tail, bc = p.bc;
   const double sz = sizeof(T);
   auto F = [&](int l) { return l == 0 ? f0 : (const T*)h.f[l]; };
@@ -378,6 +379,17 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
     const double m = unknowns_side(n, bc), mc = unknowns_side(p.side[l + 1], bc);
     const T* uin = (l == 0 && !zero_guess) ? u0 : nullptr;
     const double bytes = ((uin ? 3 : 2) * m * m + mc * mc) * sz;
+    if constexpr (sizeof(T) == sizeof(float)) {
+      if (l == 0 && res_u) {
+        // Mixed level 0: the right-hand side is made from the FP64 iterate
+        // inside the down pass (and stored for the up pass).
+        MG_TRY(timed(ctx, s, MG_K_DOWN, 0, (16 + 4 + 4) * m * m + 4 * mc * mc, [&] {
+          return launch_down_res_stream(s, bc, n, res_u, res_p, res_f, res_p, r_out, pf0,
+                                        h.r[0], p.pitch[0], h.f[1], p.pitch[1], p.down_hs[0]);
+        }));
+        continue;
+      }
+    }
     MG_TRY(timed(ctx, s, MG_K_DOWN, l, bytes, [&] {
       if (ctx->opt.kernel_path == 2 || p.down_var[l] == 1)
         return launch_down<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l), h.f[l + 1],
@@ -459,7 +471,12 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
     int nb = 0;
     float* e0 = p.h32.u[0];
     float* r0 = p.h32.f[0];
-    if (!have_res)
+    // The first inner cycle's streaming down pass can make the residual
+    // itself when level 0 lies above the tail and both level-0 passes stream
+    // (the up pass reads only rows and columns that down pass stores).
+    const bool res_in_down = fused && !have_res && p.tail > 0 && ctx->opt.kernel_path != 2 &&
+                             p.down_var[0] == 0 && p.up_var[0] == 0;
+    if (!have_res && !res_in_down)
       MG_TRY(timed(ctx, s, MG_K_RESIDUAL_MIXED, 0, 20 * nn, [&] {
         return launch_residual_mixed(s, p.bc, p.n, u, p.pitch0, f, p.pitch0, r0, p.pitch[0],
                                      p.partials, &nb);
@@ -467,10 +484,13 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
     bool added = false;
     if (fused) {
       const int K = ctx->opt.inner_cycles;
-      for (int k = 0; k < K; ++k)
+      for (int k = 0; k < K; ++k) {
+        const bool rd = res_in_down && k == 0;
         MG_TRY(enqueue_cycle_fused<float>(ctx, p, p.h32, p.taps32_dev, e0, p.pitch[0], r0,
                                           p.pitch[0], k == 0, s, cnn, k == K - 1 ? u : nullptr,
-                                          p.pitch0, &added));
+                                          p.pitch0, &added, rd ? u : nullptr, rd ? f : nullptr,
+                                          p.pitch0, r0));
+      }
     } else {
       MG_TRY(timed(ctx, s, MG_K_ZERO, 0, 4 * nn,
                    [&] { return launch_zero<float>(s, p.n, e0, p.pitch[0]); }));
@@ -985,7 +1005,9 @@ int32_t time_launches(mg_ctx_s* ctx, int reps, Launch&& launch, float* ms) {
 // shape).  Values do not matter to the timing.  The mixed path's level-0 up
 // pass adds into the FP64 iterate (a different kernel variant, keyed
 // "fp32a"), so it is timed that way, against a scratch FP64 array, and
-// only among the streaming candidates.
+// only among the streaming candidates; its streaming down pass makes the
+// FP64 residual itself, so it is timed in that form, and the tiled down
+// pass is charged the separate residual pass it then needs.
 template <typename T>
 int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scratch_u, T* scratch_f,
                     int pitch0) {
@@ -1030,7 +1052,14 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
     LevelChoice c;
     // The separate prefilter of level l + 1, charged to the up-pass variants
     // that need it (variant 2 prefilters inside its tiles).
-    float mp = 0.f;
+    float mp = 0.f, mr = 0.f;
+    if (add) {
+      int nb = 0;
+      MG_TRY(time_launches(ctx, reps, [&] {
+        return launch_residual_mixed(ctx->stream, p.bc, n, u64, p.pitch[0], u64, p.pitch[0],
+                                     reinterpret_cast<float*>(scratch_f), pu, p.partials, &nb);
+      }, &mr));
+    }
     const bool can_pre = !add && l + 1 < p.tail;
     if (can_pre) {
       const int nc = p.side[l + 1], pc = p.pitch[l + 1];
@@ -1046,12 +1075,19 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
         float md = 1e30f, mu = 0.f;
         if (var < 2)  // variant 2 concerns the up pass only
           MG_TRY(time_launches(ctx, reps, [&] {
+            if constexpr (sizeof(T) == sizeof(float)) {
+              if (add && var == 0)
+                return launch_down_res_stream(ctx->stream, p.bc, n, u64, p.pitch[0], u64,
+                                              p.pitch[0], scratch_f, pu, h.r[l], p.pitch[l],
+                                              h.f[l + 1], p.pitch[l + 1], hs);
+            }
             return var == 1 ? launch_down<T>(ctx->stream, p.bc, n, uin, pu, h.r[l], p.pitch[l], f,
                                              pu, h.f[l + 1], p.pitch[l + 1])
                             : launch_down_stream<T>(ctx->stream, p.bc, n, uin, pu, h.r[l],
                                                     p.pitch[l], f, pu, h.f[l + 1], p.pitch[l + 1],
                                                     hs);
           }, &md));
+        if (add && var == 1) md += mr;
         if (add && var >= 1) {
           mu = 1e30f;  // the tiled up pass does not add into the FP64 iterate
         } else {

@@ -18,6 +18,21 @@ __global__ void __launch_bounds__(64 * kWaves)
                         h2, inv_h2, threadIdx.x & 63);
 }
 
+// Level-0 down pass of the mixed path with its right-hand side made from
+// the FP64 iterate (down_wave with RES).
+template <int BC>
+__global__ void __launch_bounds__(64 * kWaves)
+    k_down_res_s(int n, const double* __restrict__ u64, int p64, const double* __restrict__ f64,
+                 int pf64, float* __restrict__ r32, int pr, float* __restrict__ uout, int puo,
+                 float* __restrict__ fc, int pfc, int nbands, int nitems, int hs, float h2,
+                 float inv_h2, double inv_h2d) {
+  const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
+  if (item >= nitems) return;
+  down_wave<float, BC, 0, true>(n, nullptr, 0, uout, puo, nullptr, 0, fc, pfc, item % nbands,
+                                item / nbands, hs, h2, inv_h2, threadIdx.x & 63, u64, p64, f64,
+                                pf64, inv_h2d, r32, pr);
+}
+
 template <typename T, int BC, bool ADD>
 __global__ void __launch_bounds__(64 * kWaves)
     k_up_s(int n, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
@@ -90,6 +105,29 @@ hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pu
   else
     hipLaunchKernelGGL((k_down_s<T, kPeriodic, 0>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
                        pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2);
+  return hipGetLastError();
+}
+
+hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u64, int p64,
+                                  const double* f64, int pf64, float* r32, int pr, float* uout,
+                                  int puo, float* fc, int pfc, int hs) {
+  if ((bc == kPeriodic && n - 1 < 128) || (hs > 0 && (hs & 1))) return hipErrorInvalidValue;
+  const int extent = bc == kPeriodic ? n - 1 : n;
+  if (hs <= 0) hs = stream_segment_rows(n, bc, kDownOwned);
+  const int nb = (extent + kDownOwned - 1) / kDownOwned;
+  const int items = nb * ((extent + hs - 1) / hs);
+  const int blocks = (items + kWaves - 1) / kWaves;
+  const double hd = 1.0 / (double)(n - 1);
+  const double inv_h2d = (double)(n - 1) * (double)(n - 1);
+  const float h2 = (float)(hd * hd), inv_h2 = (float)inv_h2d;
+  if (bc == kDirichlet)
+    hipLaunchKernelGGL((k_down_res_s<kDirichlet>), dim3(blocks), dim3(64 * kWaves), 0, s, n, u64,
+                       p64, f64, pf64, r32, pr, uout, puo, fc, pfc, nb, items, hs, h2, inv_h2,
+                       inv_h2d);
+  else
+    hipLaunchKernelGGL((k_down_res_s<kPeriodic>), dim3(blocks), dim3(64 * kWaves), 0, s, n, u64,
+                       p64, f64, pf64, r32, pr, uout, puo, fc, pfc, nb, items, hs, h2, inv_h2,
+                       inv_h2d);
   return hipGetLastError();
 }
 

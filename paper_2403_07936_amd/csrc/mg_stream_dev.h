@@ -218,11 +218,23 @@ __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2],
 // `seg` (hs rows) of a level with n nodes per side.  lane = threadIdx & 63.
 // UIN: 1 reads the initial u from uin, 0 starts from u = 0 (uin unused),
 // -1 decides at run time (uin == nullptr: zero).
-template <typename T, int BC, int UIN = -1>
+// RES (mixed path, level 0, from u = 0): the right-hand side is not read
+// but made here, a row at a time just before the pipeline needs it, as the
+// FP64 residual r = f64 - A u64 of the FP64 iterate (u64, f64: pitch p64,
+// pf64), rounded to FP32; the rows and columns the wavefront owns are also
+// stored to rout (pitch pro; f is not used), where the up pass reads them.  The same
+// arithmetic as residual_wave, so r32 is bitwise what that writes on the
+// nodes the up pass reads.
+template <typename T, int BC, int UIN = -1, bool RES = false>
 __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
-                                          int hs, T h2, T inv_h2, int lane) {
+                                          int hs, T h2, T inv_h2, int lane,
+                                          const double* __restrict__ u64 = nullptr, int p64 = 0,
+                                          const double* __restrict__ f64 = nullptr, int pf64 = 0,
+                                          double inv_h2d = 0.0, T* __restrict__ rout = nullptr,
+                                          int pro = 0) {
+  static_assert(!RES || (UIN == 0 && sizeof(T) == sizeof(float)), "RES: FP32 cycle from u = 0");
   n = wave_uniform(n), band = wave_uniform(band), seg = wave_uniform(seg), hs = wave_uniform(hs);
   const int xw = band * kDownOwned - kDownHalo;
   const int x0 = xw + 2 * lane;
@@ -247,10 +259,29 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
   const int t0 = ys - 6;  // even (hs is even)
   const int steps = hs + 11;
   const bool read_u = UIN == 1 || (UIN == -1 && uin != nullptr);
+  // RES: u64 row t0 - 1 + q in RU[q & 7], f64 row t0 + q in RF[q & 3],
+  // loaded kAheadR + 1 and kAheadR rows before their residual row.
+  constexpr int kAheadR = 3;
+  double RU[RES ? 8 : 1][2], RF[RES ? 4 : 1][2];
+  const int tl = t0 + steps - 1;  // last row a step uses
+  const bool rw0 = lane_owns && x0 < n, rw1 = lane_owns && x0 + 1 < n;
+  if constexpr (RES) {
 #pragma unroll
-  for (int k = 0; k < kAheadDown; ++k) {
-    if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
-    load_row<T, BC>(F[k], f, pf, t0 + k, n, col);
+    for (int q = 0; q < kAheadR + 2; ++q) {
+      const int r = t0 - 1 + q;
+      load_row<double, BC>(RU[q], u64, p64, r < tl + 1 ? r : tl + 1, n, col);
+    }
+#pragma unroll
+    for (int q = 0; q < kAheadR; ++q) {
+      const int r = t0 + q;
+      load_row<double, BC>(RF[q], f64, pf64, r < tl ? r : tl, n, col);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kAheadDown; ++k) {
+      if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
+      load_row<T, BC>(F[k], f, pf, t0 + k, n, col);
+    }
   }
   for (int sb = 0; sb < steps; sb += 16) {
 #pragma unroll
@@ -260,7 +291,34 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
       const int t = t0 + s;
       // Rows kAheadDown ahead; past the last row a step uses, that row again
       // (a cache hit instead of a row of HBM traffic; never used).
-      {
+      if constexpr (RES) {
+        // Right-hand side row t (first used at the next step) from u64 rows
+        // t - 1 .. t + 1 and f64 row t.
+        const int tu = t + kAheadR + 1 < tl + 1 ? t + kAheadR + 1 : tl + 1;
+        const int tf = t + kAheadR < tl ? t + kAheadR : tl;
+        load_row<double, BC>(RU[(k + kAheadR + 2) & 7], u64, p64, tu, n, col);
+        load_row<double, BC>(RF[(k + kAheadR) & 3], f64, pf64, tf, n, col);
+        const double(&um)[2] = RU[k & 7];
+        const double(&u0)[2] = RU[(k + 1) & 7];
+        const double(&up)[2] = RU[(k + 2) & 7];
+        const double(&ff)[2] = RF[k & 3];
+        const double left = from_left(u0[1]);
+        const double right = from_right(u0[0]);
+        const double s0 = ((um[0] + up[0]) + left) + u0[1];
+        const double s1 = ((um[1] + up[1]) + u0[0]) + right;
+        double r0 = ff[0] - (4.0 * u0[0] - s0) * inv_h2d;
+        double r1 = ff[1] - (4.0 * u0[1] - s1) * inv_h2d;
+        if constexpr (BC == kDirichlet) {
+          const bool rok = row_unknown<BC>(t, n);
+          r0 = (rok && col.unk0) ? r0 : 0.0;
+          r1 = (rok && col.unk1) ? r1 : 0.0;
+        }
+        F[k & 15][0] = (T)r0;
+        F[k & 15][1] = (T)r1;
+        if (t >= ys && t < ys + hs && t < row_end)
+          store_pair<T>(rout + (size_t)t * pro + x0, rw0, rw1, (T)r0, (T)r1);
+        U[(k + kAheadDown) & 15][0] = U[(k + kAheadDown) & 15][1] = T(0);
+      } else {
         const int ta = t + kAheadDown < t0 + steps - 1 ? t + kAheadDown : t0 + steps - 1;
         T(&nu)[2] = U[(k + kAheadDown) & 15];
         if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(nu, uin, pui, ta, n, col);
