@@ -49,10 +49,15 @@ def measured_traffic(kind_name: str, precision: str, bc: int):
     if hh.hexdigest() != rec["sources_sha256"]:
         return None
     t = "float" if precision == "mixed" else "double"
-    # Template variants of the kernel (input/accumulation flags); the
-    # level-0 launch is the one with the most traffic.
-    head = f"{names[kind_name]}<{t}, {bc}"
-    ents = [v for k, v in rec["per_launch"].items() if k == head + ">" or k.startswith(head + ",")]
+    if kind_name == "down" and precision == "mixed":
+        # The mixed level-0 down pass that makes the FP64 residual itself.
+        ents = [v for k, v in rec["per_launch"].items() if k == f"k_down_res_s<{bc}>"]
+    else:
+        # Template variants of the kernel (input/accumulation flags); the
+        # level-0 launch is the one with the most traffic.
+        head = f"{names[kind_name]}<{t}, {bc}"
+        ents = [v for k, v in rec["per_launch"].items()
+                if k == head + ">" or k.startswith(head + ",")]
     return round(max(e["bytes"] for e in ents), 0) if ents else None
 
 

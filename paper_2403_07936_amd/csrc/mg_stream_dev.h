@@ -248,11 +248,14 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
   const bool wrc = lane_owns && (BC == kPeriodic ? J < nc - 1 : (J >= 1 && J <= nc - 2));
   const int row_end = BC == kPeriodic ? N : n;  // rows [0, row_end) are owned by some segment
 
-  // Rows live in a ring of 16 register slots; row t0 + s is in slot s & 15
-  // and is loaded kAheadDown steps before the step that first uses it.
-  T U[16][2], F[16][2], R[4][2];
+  // Rows live in a ring of register slots; row t0 + s is in slot s & RM and
+  // is loaded kAheadDown steps before the step that first uses it.  RES
+  // loads nothing ahead into these rings (rows t - 6 .. t are live), so 8
+  // slots hold them.
+  constexpr int RM = RES ? 7 : 15;
+  T U[RM + 1][2], F[RM + 1][2], R[4][2];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) U[k][0] = U[k][1] = F[k][0] = F[k][1] = T(0);
+  for (int k = 0; k <= RM; ++k) U[k][0] = U[k][1] = F[k][0] = F[k][1] = T(0);
 #pragma unroll
   for (int k = 0; k < 4; ++k) R[k][0] = R[k][1] = T(0);
 
@@ -313,34 +316,34 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
           r0 = (rok && col.unk0) ? r0 : 0.0;
           r1 = (rok && col.unk1) ? r1 : 0.0;
         }
-        F[k & 15][0] = (T)r0;
-        F[k & 15][1] = (T)r1;
+        F[k & RM][0] = (T)r0;
+        F[k & RM][1] = (T)r1;
         if (t >= ys && t < ys + hs && t < row_end)
           store_pair<T>(rout + (size_t)t * pro + x0, rw0, rw1, (T)r0, (T)r1);
-        U[(k + kAheadDown) & 15][0] = U[(k + kAheadDown) & 15][1] = T(0);
+        U[k & RM][0] = U[k & RM][1] = T(0);  // row t starts from 0
       } else {
         const int ta = t + kAheadDown < t0 + steps - 1 ? t + kAheadDown : t0 + steps - 1;
-        T(&nu)[2] = U[(k + kAheadDown) & 15];
+        T(&nu)[2] = U[(k + kAheadDown) & RM];
         if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(nu, uin, pui, ta, n, col);
         else nu[0] = nu[1] = T(0);
-        load_row<T, BC>(F[(k + kAheadDown) & 15], f, pf, ta, n, col);
+        load_row<T, BC>(F[(k + kAheadDown) & RM], f, pf, ta, n, col);
       }
       // red (sweep 1) on t-1, black on t-2, red (sweep 2) on t-3, black on
       // t-4; t has the parity of k (t0 and sb are even).
-      sweep_row<T, BC>(U[(k + 14) & 15], U[(k + 15) & 15], U[k], F[(k + 15) & 15], t - 1,
+      sweep_row<T, BC>(U[(k + 14) & RM], U[(k + 15) & RM], U[k & RM], F[(k + 15) & RM], t - 1,
                        (k + 1) & 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 13) & 15], U[(k + 14) & 15], U[(k + 15) & 15], F[(k + 14) & 15],
+      sweep_row<T, BC>(U[(k + 13) & RM], U[(k + 14) & RM], U[(k + 15) & RM], F[(k + 14) & RM],
                        t - 2, (k + 1) & 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 12) & 15], U[(k + 13) & 15], U[(k + 14) & 15], F[(k + 13) & 15],
+      sweep_row<T, BC>(U[(k + 12) & RM], U[(k + 13) & RM], U[(k + 14) & RM], F[(k + 13) & RM],
                        t - 3, (k + 1) & 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 11) & 15], U[(k + 12) & 15], U[(k + 13) & 15], F[(k + 12) & 15],
+      sweep_row<T, BC>(U[(k + 11) & RM], U[(k + 12) & RM], U[(k + 13) & RM], F[(k + 12) & RM],
                        t - 4, (k + 1) & 1, n, col, h2);
       const int tu = t - 4;
       if (tu >= ys && tu < ys + hs && tu < row_end) {
         T* p = uout + (size_t)tu * puo;
-        store_pair<T>(p + x0, wr0, wr1, U[(k + 12) & 15][0], U[(k + 12) & 15][1]);
+        store_pair<T>(p + x0, wr0, wr1, U[(k + 12) & RM][0], U[(k + 12) & RM][1]);
       }
-      residual_row<T, BC>(U[(k + 10) & 15], U[(k + 11) & 15], U[(k + 12) & 15], F[(k + 11) & 15],
+      residual_row<T, BC>(U[(k + 10) & RM], U[(k + 11) & RM], U[(k + 12) & RM], F[(k + 11) & RM],
                           R[(k + 3) & 3], t - 5, n, col, inv_h2);
       const int i = t - 6;
       if ((i & 1) == 0 && i >= ys && i < ys + hs) {
