@@ -167,11 +167,13 @@ __device__ __forceinline__ bool row_unknown(int t, int n) {
 // written.  Conditional loads would leave the compiler unable to count the
 // loads in flight, and every use of a row would then wait for all of them,
 // the prefetched rows included.
-template <typename T, int BC>
+// IN (interior segment): every row index a pass forms lies inside the grid,
+// so rows are neither clamped nor wrapped and every row holds unknowns.
+template <typename T, int BC, bool IN = false>
 __device__ __forceinline__ void load_row(T (&dst)[2], const T* __restrict__ a, int pa, int t, int n,
                                          const Cols<BC>& col) {
   bool rin;
-  const int r = row_index<BC>(t, n, &rin);
+  const int r = IN ? t : row_index<BC>(t, n, &rin);
   load_pair<T>(dst, a + (size_t)r * pa, col.pc, col.sw);
 }
 
@@ -181,11 +183,11 @@ __device__ __forceinline__ void load_row(T (&dst)[2], const T* __restrict__ a, i
 // the unrolled row loop makes a constant (rows of a segment start at an even
 // row), so only one column's code is emitted; updates are selects, not
 // branches, which keeps the row ring in place in registers.
-template <typename T, int BC>
+template <typename T, int BC, bool IN = false>
 __device__ __forceinline__ void sweep_row(const T (&um)[2], T (&u0)[2], const T (&up)[2],
                                           const T (&f0)[2], int row, int odd, int n,
                                           const Cols<BC>& col, T h2) {
-  const bool rok = row_unknown<BC>(row, n);
+  const bool rok = IN || row_unknown<BC>(row, n);
   if (odd == 0) {
     const T left = from_left(u0[1]);
     const T s = ((um[0] + up[0]) + left) + u0[1];
@@ -199,7 +201,7 @@ __device__ __forceinline__ void sweep_row(const T (&um)[2], T (&u0)[2], const T 
   }
 }
 
-template <typename T, int BC>
+template <typename T, int BC, bool IN = false>
 __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2], const T (&up)[2],
                                              const T (&f0)[2], T (&r)[2], int row, int n,
                                              const Cols<BC>& col, T inv_h2) {
@@ -209,7 +211,7 @@ __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2],
   const T s1 = ((um[1] + up[1]) + u0[0]) + right;
   const T r0 = f0[0] - (T(4) * u0[0] - s0) * inv_h2;
   const T r1 = f0[1] - (T(4) * u0[1] - s1) * inv_h2;
-  const bool rok = row_unknown<BC>(row, n);
+  const bool rok = IN || row_unknown<BC>(row, n);
   r[0] = (rok && col.unk0) ? r0 : T(0);
   r[1] = (rok && col.unk1) ? r1 : T(0);
 }
@@ -225,17 +227,15 @@ __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2],
 // stored to rout (pitch pro; f is not used), where the up pass reads them.  The same
 // arithmetic as residual_wave, so r32 is bitwise what that writes on the
 // nodes the up pass reads.
-template <typename T, int BC, int UIN = -1, bool RES = false>
-__device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int pui,
+template <typename T, int BC, int UIN, bool RES, bool IN>
+__device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
                                           int hs, T h2, T inv_h2, int lane,
-                                          const double* __restrict__ u64 = nullptr, int p64 = 0,
-                                          const double* __restrict__ f64 = nullptr, int pf64 = 0,
-                                          double inv_h2d = 0.0, T* __restrict__ rout = nullptr,
-                                          int pro = 0) {
+                                          const double* __restrict__ u64, int p64,
+                                          const double* __restrict__ f64, int pf64,
+                                          double inv_h2d, T* __restrict__ rout, int pro) {
   static_assert(!RES || (UIN == 0 && sizeof(T) == sizeof(float)), "RES: FP32 cycle from u = 0");
-  n = wave_uniform(n), band = wave_uniform(band), seg = wave_uniform(seg), hs = wave_uniform(hs);
   const int xw = band * kDownOwned - kDownHalo;
   const int x0 = xw + 2 * lane;
   const int ys = seg * hs;
@@ -272,18 +272,18 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
 #pragma unroll
     for (int q = 0; q < kAheadR + 2; ++q) {
       const int r = t0 - 1 + q;
-      load_row<double, BC>(RU[q], u64, p64, r < tl + 1 ? r : tl + 1, n, col);
+      load_row<double, BC, IN>(RU[q], u64, p64, r < tl + 1 ? r : tl + 1, n, col);
     }
 #pragma unroll
     for (int q = 0; q < kAheadR; ++q) {
       const int r = t0 + q;
-      load_row<double, BC>(RF[q], f64, pf64, r < tl ? r : tl, n, col);
+      load_row<double, BC, IN>(RF[q], f64, pf64, r < tl ? r : tl, n, col);
     }
   } else {
 #pragma unroll
     for (int k = 0; k < kAheadDown; ++k) {
-      if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
-      load_row<T, BC>(F[k], f, pf, t0 + k, n, col);
+      if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC, IN>(U[k], uin, pui, t0 + k, n, col);
+      load_row<T, BC, IN>(F[k], f, pf, t0 + k, n, col);
     }
   }
   for (int sb = 0; sb < steps; sb += 16) {
@@ -299,8 +299,8 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
         // t - 1 .. t + 1 and f64 row t.
         const int tu = t + kAheadR + 1 < tl + 1 ? t + kAheadR + 1 : tl + 1;
         const int tf = t + kAheadR < tl ? t + kAheadR : tl;
-        load_row<double, BC>(RU[(k + kAheadR + 2) & 7], u64, p64, tu, n, col);
-        load_row<double, BC>(RF[(k + kAheadR) & 3], f64, pf64, tf, n, col);
+        load_row<double, BC, IN>(RU[(k + kAheadR + 2) & 7], u64, p64, tu, n, col);
+        load_row<double, BC, IN>(RF[(k + kAheadR) & 3], f64, pf64, tf, n, col);
         const double(&um)[2] = RU[k & 7];
         const double(&u0)[2] = RU[(k + 1) & 7];
         const double(&up)[2] = RU[(k + 2) & 7];
@@ -312,43 +312,43 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
         double r0 = ff[0] - (4.0 * u0[0] - s0) * inv_h2d;
         double r1 = ff[1] - (4.0 * u0[1] - s1) * inv_h2d;
         if constexpr (BC == kDirichlet) {
-          const bool rok = row_unknown<BC>(t, n);
+          const bool rok = IN || row_unknown<BC>(t, n);
           r0 = (rok && col.unk0) ? r0 : 0.0;
           r1 = (rok && col.unk1) ? r1 : 0.0;
         }
         F[k & RM][0] = (T)r0;
         F[k & RM][1] = (T)r1;
-        if (t >= ys && t < ys + hs && t < row_end)
+        if (t >= ys && t < ys + hs && (IN || t < row_end))
           store_pair<T>(rout + (size_t)t * pro + x0, rw0, rw1, (T)r0, (T)r1);
         U[k & RM][0] = U[k & RM][1] = T(0);  // row t starts from 0
       } else {
         const int ta = t + kAheadDown < t0 + steps - 1 ? t + kAheadDown : t0 + steps - 1;
         T(&nu)[2] = U[(k + kAheadDown) & RM];
-        if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC>(nu, uin, pui, ta, n, col);
+        if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC, IN>(nu, uin, pui, ta, n, col);
         else nu[0] = nu[1] = T(0);
-        load_row<T, BC>(F[(k + kAheadDown) & RM], f, pf, ta, n, col);
+        load_row<T, BC, IN>(F[(k + kAheadDown) & RM], f, pf, ta, n, col);
       }
       // red (sweep 1) on t-1, black on t-2, red (sweep 2) on t-3, black on
       // t-4; t has the parity of k (t0 and sb are even).
-      sweep_row<T, BC>(U[(k + 14) & RM], U[(k + 15) & RM], U[k & RM], F[(k + 15) & RM], t - 1,
+      sweep_row<T, BC, IN>(U[(k + 14) & RM], U[(k + 15) & RM], U[k & RM], F[(k + 15) & RM], t - 1,
                        (k + 1) & 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 13) & RM], U[(k + 14) & RM], U[(k + 15) & RM], F[(k + 14) & RM],
+      sweep_row<T, BC, IN>(U[(k + 13) & RM], U[(k + 14) & RM], U[(k + 15) & RM], F[(k + 14) & RM],
                        t - 2, (k + 1) & 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 12) & RM], U[(k + 13) & RM], U[(k + 14) & RM], F[(k + 13) & RM],
+      sweep_row<T, BC, IN>(U[(k + 12) & RM], U[(k + 13) & RM], U[(k + 14) & RM], F[(k + 13) & RM],
                        t - 3, (k + 1) & 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 11) & RM], U[(k + 12) & RM], U[(k + 13) & RM], F[(k + 12) & RM],
+      sweep_row<T, BC, IN>(U[(k + 11) & RM], U[(k + 12) & RM], U[(k + 13) & RM], F[(k + 12) & RM],
                        t - 4, (k + 1) & 1, n, col, h2);
       const int tu = t - 4;
-      if (tu >= ys && tu < ys + hs && tu < row_end) {
+      if (tu >= ys && tu < ys + hs && (IN || tu < row_end)) {
         T* p = uout + (size_t)tu * puo;
         store_pair<T>(p + x0, wr0, wr1, U[(k + 12) & RM][0], U[(k + 12) & RM][1]);
       }
-      residual_row<T, BC>(U[(k + 10) & RM], U[(k + 11) & RM], U[(k + 12) & RM], F[(k + 11) & RM],
+      residual_row<T, BC, IN>(U[(k + 10) & RM], U[(k + 11) & RM], U[(k + 12) & RM], F[(k + 11) & RM],
                           R[(k + 3) & 3], t - 5, n, col, inv_h2);
       const int i = t - 6;
       if ((i & 1) == 0 && i >= ys && i < ys + hs) {
         const int I = i >> 1;
-        const bool rowc = BC == kPeriodic ? I < nc - 1 : (I >= 1 && I <= nc - 2);
+        const bool rowc = IN || (BC == kPeriodic ? I < nc - 1 : (I >= 1 && I <= nc - 2));
         const T(&rm)[2] = R[(k + 1) & 3];
         const T(&r0)[2] = R[(k + 2) & 3];
         const T(&rp)[2] = R[(k + 3) & 3];
@@ -362,6 +362,30 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
   }
 }
 
+template <typename T, int BC, int UIN = -1, bool RES = false>
+__device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int pui,
+                                          T* __restrict__ uout, int puo, const T* __restrict__ f,
+                                          int pf, T* __restrict__ fc, int pfc, int band, int seg,
+                                          int hs, T h2, T inv_h2, int lane,
+                                          const double* __restrict__ u64 = nullptr, int p64 = 0,
+                                          const double* __restrict__ f64 = nullptr, int pf64 = 0,
+                                          double inv_h2d = 0.0, T* __restrict__ rout = nullptr,
+                                          int pro = 0) {
+  n = wave_uniform(n), band = wave_uniform(band), seg = wave_uniform(seg), hs = wave_uniform(hs);
+  // Rows the segment touches: t0 - 1 .. t0 + hs + 11 (t0 = seg * hs - 6).
+  // Inside rows 1 .. n - 2 (periodic: 0 .. n - 2) the interior form runs.
+  const int lo = seg * hs - 7, hi = seg * hs + hs + 5;
+  const bool in = BC == kPeriodic ? (lo >= 0 && hi <= n - 2) : (lo >= 1 && hi <= n - 2);
+  if (in)
+    down_wave_rows<T, BC, UIN, RES, true>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
+                                          h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
+                                          pro);
+  else
+    down_wave_rows<T, BC, UIN, RES, false>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
+                                           h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
+                                           pro);
+}
+
 // Spline along x at the lane's two columns from coarse row values held one
 // coarse column per lane (lane L holds coefficient column x0/2).
 template <typename T>
@@ -371,10 +395,10 @@ __device__ __forceinline__ void spline_x(T cj, T (&out)[2]) {
   out[1] = ((T(1.0 / 48.0) * cl + T(23.0 / 48.0) * cj) + T(23.0 / 48.0) * cr) + T(1.0 / 48.0) * cr2;
 }
 
-template <typename T, int BC>
+template <typename T, int BC, bool IN = false>
 __device__ __forceinline__ T load_coef(const T* __restrict__ c, int pc, int I, int J, int nc) {
-  bool ni, nj;
-  const int ii = ext_node_any<BC>(I, nc, &ni);
+  bool ni = false, nj;
+  const int ii = IN ? I : ext_node_any<BC>(I, nc, &ni);
   const int jj = ext_node_any<BC>(J, nc, &nj);
   const T v = c[(size_t)ii * pc + jj];
   return (ni != nj) ? -v : v;
@@ -383,13 +407,13 @@ __device__ __forceinline__ T load_coef(const T* __restrict__ c, int pc, int I, i
 // Up pass of one wavefront item (see down_wave).  With ADD, the finished
 // rows are added to u64 (the FP64 iterate of the mixed path, pitch p64) over
 // the unknowns -- the refinement update -- instead of being written to uout.
-template <typename T, int BC, bool ADD = false>
-__device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pui,
-                                        T* __restrict__ uout, int puo, const T* __restrict__ f,
-                                        int pf, const T* __restrict__ c, int pc, int band, int seg,
-                                        int hs, T h2, int lane, double* __restrict__ u64 = nullptr,
-                                        int p64 = 0) {
-  n = wave_uniform(n), band = wave_uniform(band), seg = wave_uniform(seg), hs = wave_uniform(hs);
+template <typename T, int BC, bool ADD, bool IN>
+__device__ __forceinline__ void up_wave_rows(int n, const T* __restrict__ uin, int pui,
+                                             T* __restrict__ uout, int puo,
+                                             const T* __restrict__ f, int pf,
+                                             const T* __restrict__ c, int pc, int band, int seg,
+                                             int hs, T h2, int lane, double* __restrict__ u64,
+                                             int p64) {
   const int xw = band * kUpOwned - kUpHalo;
   const int x0 = xw + 2 * lane;
   const int ys = seg * hs;
@@ -411,7 +435,7 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
   // CR[q & 7], loaded 4 coarse rows ahead; CX[q & 3] holds their spline
   // along x at the lane's two columns.
 #pragma unroll
-  for (int q = 0; q < 7; ++q) CR[q] = load_coef<T, BC>(c, pc, cbase + q, Jc, nc);
+  for (int q = 0; q < 7; ++q) CR[q] = load_coef<T, BC, IN>(c, pc, cbase + q, Jc, nc);
   CR[7] = T(0);
 #pragma unroll
   for (int q = 0; q < 3; ++q) spline_x<T>(CR[q], CX[q]);
@@ -434,8 +458,8 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
   };
 #pragma unroll
   for (int k = 0; k < kAheadUp; ++k) {
-    load_row<T, BC>(U[k], uin, pui, t0 + k, n, col);
-    load_row<T, BC>(F[k], f, pf, t0 + k, n, col);
+    load_row<T, BC, IN>(U[k], uin, pui, t0 + k, n, col);
+    load_row<T, BC, IN>(F[k], f, pf, t0 + k, n, col);
     load_u64(k & 7, t0 - 4 + k);
   }
   for (int sb = 0; sb < steps; sb += 16) {
@@ -446,15 +470,15 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
       const int t = t0 + s;
       {  // rows kAheadUp ahead; past the last row a step uses, that row again
         const int ta = t + kAheadUp < t0 + steps - 1 ? t + kAheadUp : t0 + steps - 1;
-        load_row<T, BC>(U[(k + kAheadUp) & 15], uin, pui, ta, n, col);
-        load_row<T, BC>(F[(k + kAheadUp) & 15], f, pf, ta, n, col);
+        load_row<T, BC, IN>(U[(k + kAheadUp) & 15], uin, pui, ta, n, col);
+        load_row<T, BC, IN>(F[(k + kAheadUp) & 15], f, pf, ta, n, col);
         load_u64((k + kAheadUp) & 7, t - 4 + kAheadUp);
       }
       // coarse row q = (s - 1)/2 + 3 is needed from the first odd step on
       if (k & 1) {
         const int qk = ((k - 1) >> 1) + 3;  // q mod 8
         spline_x<T>(CR[qk & 7], CX[qk & 3]);
-        CR[(qk + 4) & 7] = load_coef<T, BC>(c, pc, cbase + ((s - 1) >> 1) + 7, Jc, nc);
+        CR[(qk + 4) & 7] = load_coef<T, BC, IN>(c, pc, cbase + ((s - 1) >> 1) + 7, Jc, nc);
       }
       {
         // u += P e_c on row t: coincident rows (1, 4, 1)/6 on coarse rows
@@ -474,24 +498,24 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
           v1 = ((T(1.0 / 48.0) * a[1] + T(23.0 / 48.0) * b[1]) + T(23.0 / 48.0) * d[1]) +
                T(1.0 / 48.0) * e[1];
         }
-        const bool rok = row_unknown<BC>(t, n);
+        const bool rok = IN || row_unknown<BC>(t, n);
         U[k][0] = (rok && col.unk0) ? U[k][0] + v0 : U[k][0];
         U[k][1] = (rok && col.unk1) ? U[k][1] + v1 : U[k][1];
       }
       // t has the parity of k (t0 and sb are even)
-      sweep_row<T, BC>(U[(k + 14) & 15], U[(k + 15) & 15], U[k], F[(k + 15) & 15], t - 1,
+      sweep_row<T, BC, IN>(U[(k + 14) & 15], U[(k + 15) & 15], U[k], F[(k + 15) & 15], t - 1,
                        (k + 1) & 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 13) & 15], U[(k + 14) & 15], U[(k + 15) & 15], F[(k + 14) & 15],
+      sweep_row<T, BC, IN>(U[(k + 13) & 15], U[(k + 14) & 15], U[(k + 15) & 15], F[(k + 14) & 15],
                        t - 2, (k + 1) & 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 12) & 15], U[(k + 13) & 15], U[(k + 14) & 15], F[(k + 13) & 15],
+      sweep_row<T, BC, IN>(U[(k + 12) & 15], U[(k + 13) & 15], U[(k + 14) & 15], F[(k + 13) & 15],
                        t - 3, (k + 1) & 1, n, col, h2);
-      sweep_row<T, BC>(U[(k + 11) & 15], U[(k + 12) & 15], U[(k + 13) & 15], F[(k + 12) & 15],
+      sweep_row<T, BC, IN>(U[(k + 11) & 15], U[(k + 12) & 15], U[(k + 13) & 15], F[(k + 12) & 15],
                        t - 4, (k + 1) & 1, n, col, h2);
       const int tu = t - 4;
-      if (tu >= ys && tu < ys + hs && tu < row_end) {
+      if (tu >= ys && tu < ys + hs && (IN || tu < row_end)) {
         if (ADD) {
           double* q = u64 + (size_t)tu * p64;
-          const bool r = row_unknown<BC>(tu, n);
+          const bool r = IN || row_unknown<BC>(tu, n);
           store_pair<double>(q + x0, wr0 && col.unk0 && r, wr1 && col.unk1 && r,
                              UR[k & 7][0] + (double)U[(k + 12) & 15][0],
                              UR[k & 7][1] + (double)U[(k + 12) & 15][1]);
@@ -502,6 +526,26 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
       }
     }
   }
+}
+
+template <typename T, int BC, bool ADD = false>
+__device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pui,
+                                        T* __restrict__ uout, int puo, const T* __restrict__ f,
+                                        int pf, const T* __restrict__ c, int pc, int band, int seg,
+                                        int hs, T h2, int lane, double* __restrict__ u64 = nullptr,
+                                        int p64 = 0) {
+  n = wave_uniform(n), band = wave_uniform(band), seg = wave_uniform(seg), hs = wave_uniform(hs);
+  // Fine rows touched: seg * hs - 4 .. seg * hs + hs + 3; coarse rows up to
+  // (seg * hs + hs) / 2 + 7.  Inside the grid (and coarse rows from 0) the
+  // interior form runs.
+  const int lo = seg * hs - 4, hi = seg * hs + hs + 15;
+  const bool in = lo >= 2 && hi <= n - 1;
+  if (in)
+    up_wave_rows<T, BC, ADD, true>(n, uin, pui, uout, puo, f, pf, c, pc, band, seg, hs, h2, lane,
+                                   u64, p64);
+  else
+    up_wave_rows<T, BC, ADD, false>(n, uin, pui, uout, puo, f, pf, c, pc, band, seg, hs, h2, lane,
+                                    u64, p64);
 }
 
 // Mixed path, level 0: r32 = fl32(f - A u) with f, u and the arithmetic in
