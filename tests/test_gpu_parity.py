@@ -268,6 +268,39 @@ def test_mixed_relres_matches_oracle_norm(B, dev, bc, n):
         B.mg_destroy(ctx)
 
 
+@pytest.mark.parametrize("bc,n", [(D, 257), (P, 257), (D, 1025), (P, 1025)])
+def test_mixed_step_residual_in_down_pass_is_bitwise(B, dev, bc, n):
+    """A mixed step whose level-0 down pass makes the FP64 residual itself
+    (mg_vcycle) against the same step started from the residual pass's
+    output (mg_solve's first step follows its norm check): the right-hand
+    side is the same arithmetic, so the iterates agree bit for bit (periodic:
+    up to the mean mg_solve removes)."""
+    from paper_2403_07936_amd.solver import Solver
+    say(f"residual in down pass bc={bc} n={n}")
+    f = make_rhs(n, bc, 4)
+    u0 = oracle.vcycle(np.zeros_like(f), f, bc)
+    ft = gpu(f, dev)
+    sa = Solver([(n, bc)], precision="mixed")
+    ua = gpu(u0, dev)
+    sa.vcycle([ua], [ft], 1)
+    sa.close()
+    sb = Solver([(n, bc)], precision="mixed", check_every=1)
+    ub = gpu(u0, dev)
+    st, cyc, rel = sb.solve([ub], [ft], rtol=1e-300, max_cycles=1)
+    sb.close()
+    assert cyc[0] == 1
+    a, b = host(ua), host(ub)
+    if bc == P:
+        # mg_solve removes the mean of a periodic u on exit: compare both
+        # with the mean removed here (the subtraction rounds differently).
+        a, b = zero_mean(a), zero_mean(b)
+        say(f"  max |diff| {np.abs(a - b).max():.3e}")
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+    else:
+        say(f"  max |diff| {np.abs(a - b).max():.3e}")
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("name", ["dirichlet4097", "periodic1025"])
 def test_full_size_cycle_parity(B, dev, name):
     """The benchmark configurations at full size, in the launch configuration
