@@ -1068,10 +1068,18 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
                                        h.c[l + 1], pc);
       }, &mp));
     }
+    // Short segments re-read more halo rows.  Timed alone, a pass finds those
+    // rows in the 256 MB last-level cache; inside a cycle over a level larger
+    // than that cache they come from HBM (4097^2 mixed down pass: 16-row
+    // segments time faster here but run 9 % slower in the cycle), so such
+    // levels do not try them.
+    const double level_bytes = (double)n * n * (add ? 24.0 : 3.0 * sizeof(T));
+    const bool big = level_bytes > 256e6;
     for (int var = 0; var < 3; ++var)
       for (int hs : hs_cands) {
         if (var >= 1 && hs != 0) continue;
         if (var == 2 && !can_pre) continue;
+        if (big && hs > 0 && hs < 32) continue;
         float md = 1e30f, mu = 0.f;
         if (var < 2)  // variant 2 concerns the up pass only
           MG_TRY(time_launches(ctx, reps, [&] {
