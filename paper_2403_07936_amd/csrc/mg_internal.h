@@ -41,6 +41,16 @@ void spline_taps(int nc, int bc, int half_taps, PrefilterTaps* out);
 // 5 x 5 level's operator, row-major, from its eigen-decomposition.
 void coarsest_inverse(int bc, double* out /* 256 */);
 
+// The prefilter of the tail sides 5, 9, 17 and 33 as dense nc x nc matrices
+// (c = M e along one axis, every extension folded onto the stored nodes),
+// stored after the coarsest inverse in the same device table.
+constexpr int kTailMatOffset = 256;                  // doubles before the first matrix
+constexpr int kTailMatElems = 25 + 81 + 289 + 1089;  // sides 5, 9, 17, 33
+__host__ __device__ constexpr int tail_mat_offset(int nc) {
+  return nc == 5 ? 0 : (nc == 9 ? 25 : (nc == 17 ? 106 : 395));
+}
+void prefilter_matrix(int nc, int bc, double* out /* nc * nc */);
+
 // ---- launchers (mg_kernels.hip); all asynchronous on `s` -------------------
 // Every array is a level array with `n` nodes per side and the given pitch.
 

@@ -57,6 +57,33 @@ void spline_taps(int nc, int bc, int half_taps, PrefilterTaps* out) {
   }
 }
 
+// The period is at most 64 nodes for nc <= 33, so the table of spline_taps
+// holds the whole period and M is the exact inverse: M[q][k] sums the taps
+// w[t] whose extended node q + t is stored node k (with the odd extension's
+// sign).  Dirichlet rows 0 and nc-1 (boundary coefficients) are 0; the
+// periodic seam row repeats row 0.
+void prefilter_matrix(int nc, int bc, double* out) {
+  PrefilterTaps tp;
+  spline_taps(nc, bc, kMaxPrefilterTaps / 2, &tp);
+  const int Q = tp.period;
+  for (int i = 0; i < nc * nc; ++i) out[i] = 0.0;
+  for (int q = 0; q < nc; ++q) {
+    if (bc == kDirichlet && (q == 0 || q == nc - 1)) continue;
+    for (int t = 0; t < tp.count; ++t) {
+      const int x = ((q + t - tp.offset) % Q + Q) % Q;
+      int node = x;
+      double sign = 1.0;
+      if (bc == kDirichlet && x > nc - 1) {
+        node = Q - x;
+        sign = -1.0;
+      }
+      out[q * nc + node] += sign * tp.w[t];
+    }
+  }
+  if (bc == kPeriodic)
+    for (int k = 0; k < nc; ++k) out[(nc - 1) * nc + k] = out[k];
+}
+
 // 5 x 5 level (h = 1/4) from the eigen-decomposition of the 5-point operator.
 // Dirichlet: orthonormal sine vectors phi_a(i) = sqrt(1/2) sin(a pi i / 4),
 // eigenvalues 64 (sin^2(a pi/8) + sin^2(b pi/8)).  Periodic: Fourier modes
@@ -1357,9 +1384,10 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
   }
 
   for (int bc = 0; bc < 2; ++bc) {
-    double tbl[256];
+    double tbl[kTailMatOffset + kTailMatElems];
     coarsest_inverse(bc, tbl);
-    int32_t st = alloc_level<double>(ctx, 1, 256, &ctx->inv[bc]);
+    for (int nc : {5, 9, 17, 33}) prefilter_matrix(nc, bc, tbl + kTailMatOffset + tail_mat_offset(nc));
+    int32_t st = alloc_level<double>(ctx, 1, kTailMatOffset + kTailMatElems, &ctx->inv[bc]);
     if (st != MG_OK) return bail(st);
     if (hipMemcpyAsync(ctx->inv[bc], tbl, sizeof tbl, hipMemcpyHostToDevice, ctx->stream) !=
         hipSuccess)

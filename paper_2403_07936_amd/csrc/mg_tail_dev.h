@@ -366,11 +366,6 @@ struct TailPre {
   static constexpr int K = PreCfg<T>::K;
   static constexpr int S = sizeof(T) == 8 ? 8 : 16;
   static constexpr int kTable = kTailMaxSide + S + 2 * K;
-  // Direct form: coefficients per thread, and the largest side it is used
-  // for (beyond, the 2K + 1 FP64 loads per coefficient cost more LDS time
-  // than the recursions' latency).
-  static constexpr int R = sizeof(T) == 8 ? 1 : 2;
-  static constexpr int kFirMax = sizeof(T) == 8 ? 17 : 33;
 };
 
 template <typename T, int BC>
@@ -411,56 +406,48 @@ __device__ __forceinline__ void tail_chunk(const T* src, int ss, T* dst, int ds,
   }
 }
 
-// Direct form of the same truncated prefilter, for small tail grids: c_q =
-// sum over |d| <= K of h_|d| e(q + d) on the extended line, h_d = g z^d /
-// (1 - z^2) the impulse response of g / ((1 - z q^-1)(1 - z q)).  A few
-// coefficients per thread and no serial chain, where the chunked recursions
-// of a small grid are all latency.  The lines are first copied out to
-// their extended form, so that every tap is a load at a fixed offset.
-template <int K>
-struct FirTaps {
-  double h[K + 1];
-  constexpr FirTaps() : h() {
-    double p = kPrefG / (1.0 - kPrefZ * kPrefZ);
-    for (int d = 0; d <= K; ++d) {
-      h[d] = p;
-      p *= kPrefZ;
-    }
+// Sides 5 to 33: the prefilter as a dense matrix M (side NC, in LDS; see
+// prefilter_matrix: the exact inverse, every extension folded onto the
+// stored nodes), rows then columns, two barrier phases in all.  On these
+// sides chunked recursions are all latency.
+template <typename T, int BC, int TR, int NC>
+__device__ __forceinline__ void tail_prefilter_mat(const T* src, T* tmp, T* dst, int pd,
+                                                   const T* M) {
+  const int t = tail_tid();
+  constexpr int rows = BC == kPeriodic ? NC - 1 : NC;  // the seam row is never read
+  for (int w = t; w < rows * NC; w += 32 * TR) {
+    const int line = w / NC, q = w - line * NC;
+    T acc = T(0);
+#pragma unroll 11
+    for (int k = 0; k < NC; ++k) acc += M[q * NC + k] * src[line * NC + k];
+    tmp[line * NC + q] = acc;
   }
-};
-// Pitch of an extended line of the direct form (nodes -K .. nc - 1 + K, R - 1
-// more read past the end for a ragged last group, odd against bank
-// conflicts) and its scratch elements: nc such lines and the row pass.
-__host__ __device__ constexpr int tail_fir_pitch(int nc, int K, int R) {
-  return (nc + 2 * K + R) | 1;
-}
-__host__ __device__ constexpr int tail_fir_elems(int nc, int K, int R) {
-  return nc * tail_fir_pitch(nc, K, R) + nc * nc;
-}
-
-// R consecutive coefficients y[r] from an extended line, x pointing at the
-// node of the first: each node is loaded once and added into every
-// coefficient within K of it.
-template <typename T, int R>
-__device__ __forceinline__ void tail_fir(const T* x, T (&y)[R]) {
-  constexpr int K = TailPre<T>::K;
-  constexpr FirTaps<K> H{};
-#pragma unroll
-  for (int r = 0; r < R; ++r) y[r] = T(0);
-#pragma unroll
-  for (int p = -K; p < R + K; ++p) {
-    const T v = x[p];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (p - r >= -K && p - r <= K) y[r] += T(H.h[p - r < 0 ? r - p : p - r]) * v;
+  __syncthreads();
+  for (int w = t; w < NC * NC; w += 32 * TR) {
+    const int q = w / NC, line = w - q * NC;
+    T acc = T(0);
+#pragma unroll 11
+    for (int k = 0; k < rows; ++k) acc += M[q * NC + k] * tmp[k * NC + line];
+    dst[q * pd + line] = acc;
   }
+  __syncthreads();
 }
 
 // Prefilter a tail grid src (side nc, pitch nc): rows into the scratch grid
-// tmp, then columns into dst (pitch pd; may be src).  FIR = false leaves the
-// direct form out of a call site that only sees the top side.
-template <typename T, int BC, int TR, bool FIR = true>
-__device__ __forceinline__ void tail_prefilter(const T* src, T* tmp, T* dst, int pd, int nc) {
+// tmp, then columns into dst (pitch pd; may be src).  MAT = false leaves the
+// matrix form out of a call site that only sees the top side.  mat: the
+// dense matrices of the sides 5, 9, 17, 33 (LDS, tail_mat_offset).
+template <typename T, int BC, int TR, bool MAT = true>
+__device__ __forceinline__ void tail_prefilter(const T* src, T* tmp, T* dst, int pd, int nc,
+                                               const T* mat) {
+  if (MAT) {
+    if (nc == 5) return tail_prefilter_mat<T, BC, TR, 5>(src, tmp, dst, pd, mat);
+    if (nc == 9) return tail_prefilter_mat<T, BC, TR, 9>(src, tmp, dst, pd, mat + tail_mat_offset(9));
+    if (nc == 17)
+      return tail_prefilter_mat<T, BC, TR, 17>(src, tmp, dst, pd, mat + tail_mat_offset(17));
+    if (nc == 33)
+      return tail_prefilter_mat<T, BC, TR, 33>(src, tmp, dst, pd, mat + tail_mat_offset(33));
+  }
   using C = TailPre<T>;
   __shared__ int tbl[C::kTable];
   const int t = tail_tid();
@@ -472,52 +459,6 @@ __device__ __forceinline__ void tail_prefilter(const T* src, T* tmp, T* dst, int
   __syncthreads();
   // Rows: the periodic seam row is never read by the column pass.
   const int rows = BC == kPeriodic ? nc - 1 : nc;
-  const int M = BC == kPeriodic ? nc - 1 : nc;  // coefficients of a line to compute
-  if (FIR && nc <= C::kFirMax) {
-    auto put = [&](T* d, int ds, int q, T v) {
-      if (BC == kDirichlet && (q == 0 || q == nc - 1)) v = T(0);
-      d[q * ds] = v;
-      if (BC == kPeriodic && q == 0) d[(nc - 1) * ds] = v;
-    };
-    constexpr int R = C::R;
-    const int E = nc + 2 * C::K;  // nodes -K .. nc - 1 + K of a line
-    const int EP = tail_fir_pitch(nc, C::K, R);
-    const int G = (M + R - 1) / R;  // groups of R coefficients per line
-    T* ext = tmp;                   // [line][EP]
-    T* row = tmp + nc * EP;         // row pass, [nc][nc]
-    for (int w = t; w < rows * E; w += 32 * TR) {
-      const int line = w / E, p = w - line * E, e = tbl[p];
-      const T x = src[line * nc + (e < 0 ? ~e : e)];
-      ext[line * EP + p] = e < 0 ? -x : x;
-    }
-    __syncthreads();
-    // Lanes take consecutive lines: reads at the odd pitch EP.
-    for (int w = t; w < rows * G; w += 32 * TR) {
-      const int line = w % rows, q0 = (w / rows) * R;
-      T y[R];
-      tail_fir<T, R>(ext + line * EP + q0 + C::K, y);
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (q0 + r < M) put(row + line * nc, 1, q0 + r, y[r]);
-    }
-    __syncthreads();
-    for (int w = t; w < nc * E; w += 32 * TR) {
-      const int col = w / E, p = w - col * E, e = tbl[p];
-      const T x = row[(e < 0 ? ~e : e) * nc + col];
-      ext[col * EP + p] = e < 0 ? -x : x;
-    }
-    __syncthreads();
-    for (int w = t; w < nc * G; w += 32 * TR) {
-      const int col = w % nc, q0 = (w / nc) * R;
-      T y[R];
-      tail_fir<T, R>(ext + col * EP + q0 + C::K, y);
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (q0 + r < M) put(dst + col, pd, q0 + r, y[r]);
-    }
-    __syncthreads();
-    return;
-  }
   const int chunks = (nc + C::S - 1) / C::S;
   for (int w = t; w < rows * chunks; w += 32 * TR) {
     const int line = w % rows, q0 = (w / rows) * C::S;
@@ -590,6 +531,9 @@ __device__ __forceinline__ int tail_offf(int nt, int l) {
   return tail_offu(nt, l) + n * n;
 }
 
+// Elements of the tail's scratch grid (defined with tail_bytes).
+__host__ __device__ inline int tail_scratch_elems(int nt, size_t elem);
+
 // The whole tail for one problem by one workgroup of 32 TR threads; sm =
 // LDS of tail_bytes(nt) bytes.
 template <typename T, int BC, int TR>
@@ -599,10 +543,12 @@ __device__ __forceinline__ void tail_block(int nt, const T* __restrict__ uin, in
                                            const double* __restrict__ inv, T* sm) {
   const int L = tail_levels(nt);
   T* tmp = sm + tail_offu(nt, L);
+  T* mat = tmp + tail_scratch_elems(nt, sizeof(T));
   MG_TAIL_FOR(nt, i, j, {
     sm[i * nt + j] = uin ? uin[(size_t)i * pui + j] : T(0);
     sm[nt * nt + i * nt + j] = f[(size_t)i * pf + j];
   });
+  for (int q = tail_tid(); q < kTailMatElems; q += 32 * TR) mat[q] = T(inv[kTailMatOffset + q]);
   __syncthreads();
   for (int l = 0; l + 1 < L; ++l) {
     const int n = tail_side(nt, l);
@@ -643,7 +589,7 @@ __device__ __forceinline__ void tail_block(int nt, const T* __restrict__ uin, in
   for (int l = L - 2; l >= 0; --l) {
     const int n = tail_side(nt, l), nc = tail_side(nt, l + 1);
     T* uc = sm + tail_offu(nt, l + 1);
-    tail_prefilter<T, BC, TR>(uc, tmp, uc, nc, nc);
+    tail_prefilter<T, BC, TR>(uc, tmp, uc, nc, nc, mat);
     tail_prolong_add<T, BC, TR>(sm + tail_offu(nt, l), uc, tmp, n);
     tail_sweeps<T, BC, TR>(sm + tail_offu(nt, l), sm + tail_offf(nt, l), n, 4);
   }
@@ -653,27 +599,25 @@ __device__ __forceinline__ void tail_block(int nt, const T* __restrict__ uin, in
     });
   if (cout) {
     __syncthreads();
-    tail_prefilter<T, BC, TR, false>(sm, tmp, cout, pco, nt);
+    tail_prefilter<T, BC, TR, false>(sm, tmp, cout, pco, nt, mat);
   }
 }
 
-// u and f of every tail level, then the scratch grid of at least nt x nt:
-// the residual of the top level, the x-interpolated rows of a prolongation
-// ((nt+1)/2 + 2 rows of nt), or the passes of the prefilter.
+// u and f of every tail level, then the scratch grid of at least nt x nt
+// (the residual of the top level, the x-interpolated rows of a prolongation
+// ((nt+1)/2 + 2 rows of nt), or the row pass of the prefilter), then the
+// dense prefilter matrices of the sides 5, 9, 17 and 33.
 __host__ __device__ inline size_t tail_bytes(int nt, size_t elem) {
   size_t tot = 0;
   for (int n = nt;; n = (n - 1) / 2 + 1) {
     tot += 2 * (size_t)n * n;
     if (n == 5) break;
   }
-  const bool f64 = elem == sizeof(double);
-  const int K = f64 ? TailPre<double>::K : TailPre<float>::K;
-  const int R = f64 ? TailPre<double>::R : TailPre<float>::R;
-  // The direct form runs on the sides below the top one.
-  const int fm = f64 ? TailPre<double>::kFirMax : TailPre<float>::kFirMax;
-  const int nf = (nt - 1) / 2 + 1 < fm ? (nt - 1) / 2 + 1 : fm;
-  const size_t fir = (size_t)tail_fir_elems(nf, K, R);
-  return (tot + ((size_t)nt * nt > fir ? (size_t)nt * nt : fir)) * elem;
+  return (tot + (size_t)tail_scratch_elems(nt, elem) + kTailMatElems) * elem;
+}
+__host__ __device__ inline int tail_scratch_elems(int nt, size_t elem) {
+  (void)elem;
+  return nt * nt;
 }
 
 }  // namespace dev
