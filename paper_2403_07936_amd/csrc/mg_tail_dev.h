@@ -479,34 +479,55 @@ __device__ __forceinline__ void tail_prefilter(const T* src, T* tmp, T* dst, int
 template <typename T, int BC, int TR>
 __device__ __forceinline__ void tail_prolong_add(T* u, const T* c, T* t, int n) {
   const int nc = (n - 1) / 2 + 1;
-  const int rows = nc + 2;  // coarse rows -1 .. nc
-  for (int q = tail_tid(); q < rows * n; q += 32 * TR) {
-    const int I = q / n - 1, j = q % n;
-    bool ni;
-    const int Ie = tail_ext<BC>(I, nc, &ni);
-    int bj;
-    T wj[4];
-    const int nj = bspline_taps<T>(j, &bj, wj);
-    T row = T(0);
-    for (int b = 0; b < nj; ++b) {
-      bool nb;
-      const int J = ext_node<BC>(bj + b, nc, &nb);
-      const T x = c[Ie * nc + J];
-      row += wj[b] * (nb ? -x : x);
+  const int ty = tail_tid() >> 5, tx = tail_tid() & 31;
+  // The unknowns of a side n <= 65 lie in rows and columns 0 .. 63: fine
+  // columns 2J, 2J + 1 for J < 32, read from coarse rows -1 .. nc (scratch
+  // rows 0 .. nc + 1).  Each thread makes both fine columns of its J from
+  // the four coarse values J - 1 .. J + 2.
+  static_assert(kTailMaxSide <= 65, "fine columns 2J, 2J + 1 with J < 32");
+  for (int a = 0; a < (kTailMaxSide / 2 + 3 + TR - 1) / TR; ++a) {
+    const int r = ty + TR * a;
+    if (r < nc + 2 && tx < nc) {
+      bool ni, n0, n1, n2, n3;
+      const int Ie = tail_ext<BC>(r - 1, nc, &ni);
+      const T* cr = c + Ie * nc;
+      const int j0 = ext_node<BC>(tx - 1, nc, &n0), j1 = ext_node<BC>(tx, nc, &n1);
+      const int j2 = ext_node<BC>(tx + 1, nc, &n2), j3 = ext_node<BC>(tx + 2, nc, &n3);
+      T x0 = cr[j0], x1 = cr[j1], x2 = cr[j2], x3 = cr[j3];
+      x0 = (n0 != ni) ? -x0 : x0;
+      x1 = (n1 != ni) ? -x1 : x1;
+      x2 = (n2 != ni) ? -x2 : x2;
+      x3 = (n3 != ni) ? -x3 : x3;
+      const int j = 2 * tx;
+      t[r * n + j] = (T(1.0 / 6.0) * x0 + T(4.0 / 6.0) * x1) + T(1.0 / 6.0) * x2;
+      if (j + 1 < n)
+        t[r * n + j + 1] =
+            ((T(1.0 / 48.0) * x0 + T(23.0 / 48.0) * x1) + T(23.0 / 48.0) * x2) + T(1.0 / 48.0) * x3;
     }
-    t[q] = ni ? -row : row;
   }
   __syncthreads();
-  MG_TAIL_FOR(n, i, j, {
-    if (tail_unknown<BC>(i, j, n)) {
-      int bi;
-      T wi[4];
-      const int ni = bspline_taps<T>(i, &bi, wi);
-      T v = T(0);
-      for (int a = 0; a < ni; ++a) v += wi[a] * t[(bi + a + 1) * n + j];
-      u[i * n + j] += v;
+  // Fine rows 2I, 2I + 1 for I < 32 from scratch rows I .. I + 3 (coarse
+  // rows I - 1 .. I + 2), columns 0 .. 63.
+  for (int a = 0; a < (kTailMaxSide / 2 + TR - 1) / TR; ++a) {
+    const int I = ty + TR * a;
+    if (I < nc - 1) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int j = tx + 32 * b;
+        if (j < n) {
+          const T* tr = t + I * n + j;
+          const T y0 = tr[0], y1 = tr[n], y2 = tr[2 * n], y3 = tr[3 * n];
+          const int i = 2 * I;
+          if (tail_unknown<BC>(i, j, n))
+            u[i * n + j] += (T(1.0 / 6.0) * y0 + T(4.0 / 6.0) * y1) + T(1.0 / 6.0) * y2;
+          if (tail_unknown<BC>(i + 1, j, n))
+            u[(i + 1) * n + j] +=
+                ((T(1.0 / 48.0) * y0 + T(23.0 / 48.0) * y1) + T(23.0 / 48.0) * y2) +
+                T(1.0 / 48.0) * y3;
+        }
+      }
     }
-  });
+  }
   __syncthreads();
 }
 
