@@ -227,33 +227,49 @@ __device__ __forceinline__ void tail_sweeps(T* u, const T* f, int n, int count) 
 }
 
 // r = f - A u into r (pitch n, unknown nodes only), then f_c = FW(r).
+// Only rows and columns 0 .. 63 of r are read (a coarse unknown I <= 31
+// reaches fine row 2I + 1 <= 63; periodic wraps reach n - 2 <= 63), so
+// each thread makes both columns 2tx, 2tx + 1 of a row; and only the coarse
+// unknowns I, J <= 31 are written (the rest of f_c is never read).
 template <typename T, int BC, int TR>
 __device__ __forceinline__ void tail_restrict(const T* u, const T* f, T* r, T* fc, int n) {
   const T inv_h2 = T((double)(n - 1) * (double)(n - 1));
-  MG_TAIL_FOR(n, i, j, {
-    T v = T(0);
-    if (tail_unknown<BC>(i, j, n)) {
-      const T s = ((u[wrap_prev<BC>(i, n) * n + j] + u[wrap_next<BC>(i, n) * n + j]) +
-                   u[i * n + wrap_prev<BC>(j, n)]) +
-                  u[i * n + wrap_next<BC>(j, n)];
-      v = f[i * n + j] - (T(4) * u[i * n + j] - s) * inv_h2;
+  const int ty = tail_tid() >> 5, tx = tail_tid() & 31;
+  static_assert(kTailMaxSide <= 65, "rows and columns 0 .. 63");
+#pragma unroll
+  for (int a = 0; a < (64 + TR - 1) / TR; ++a) {
+    const int i = ty + TR * a;
+    if (i < n - 1) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int j = 2 * tx + c;
+        if (j < n - 1) {
+          T v = T(0);
+          if (tail_unknown<BC>(i, j, n)) {
+            const T s = ((u[wrap_prev<BC>(i, n) * n + j] + u[wrap_next<BC>(i, n) * n + j]) +
+                         u[i * n + wrap_prev<BC>(j, n)]) +
+                        u[i * n + wrap_next<BC>(j, n)];
+            v = f[i * n + j] - (T(4) * u[i * n + j] - s) * inv_h2;
+          }
+          r[i * n + j] = v;
+        }
+      }
     }
-    r[i * n + j] = v;
-  });
+  }
   __syncthreads();
   const int nc = (n - 1) / 2 + 1;
-  MG_TAIL_FOR(nc, I, J, {
-    T v = T(0);
-    if (tail_unknown<BC>(I, J, nc)) {
+#pragma unroll
+  for (int a = 0; a < (32 + TR - 1) / TR; ++a) {
+    const int I = ty + TR * a, J = tx;
+    if (I < nc && J < nc && tail_unknown<BC>(I, J, nc)) {
       const int i = 2 * I, j = 2 * J;
       const int im = wrap_prev<BC>(i, n), ip = wrap_next<BC>(i, n);
       const int jm = wrap_prev<BC>(j, n), jp = wrap_next<BC>(j, n);
       const T edges = ((r[im * n + j] + r[ip * n + j]) + r[i * n + jm]) + r[i * n + jp];
       const T corners = ((r[im * n + jm] + r[im * n + jp]) + r[ip * n + jm]) + r[ip * n + jp];
-      v = ((T(4) * r[i * n + j] + T(2) * edges) + corners) * T(0.0625);
+      fc[I * nc + J] = ((T(4) * r[i * n + j] + T(2) * edges) + corners) * T(0.0625);
     }
-    fc[I * nc + J] = v;
-  });
+  }
   __syncthreads();
 }
 
