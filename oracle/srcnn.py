@@ -194,3 +194,59 @@ def refine_step(u: np.ndarray, f: np.ndarray, layers: list[np.ndarray], cnn_leve
     r = oracle.residual(u.astype(np.float64), f.astype(np.float64), oracle.PERIODIC)
     e = vcycle(np.zeros(r.shape, np.float32), r.astype(np.float32), layers, cnn_levels, nu1, nu2)
     return u + e.astype(np.float64)
+
+
+def prolongation_choice(i: int, n_gan: float, switched: bool) -> bool:
+    """Operator of iteration i = 1, 2, ... of the hybrid schedule (appendix
+    V-CYCLE with the N_GAN and S_thres parameters of Table 1): True for the
+    network, False for the spline.
+
+    N_GAN >= 1 makes the network the first operator and the spline the
+    second, N_GAN < 1 the reverse, with N = N_GAN or 1 / N_GAN.  Reading:
+    N_GAN counts network prolongations per spline prolongation, so that
+    N_GAN = 1 alternates (Section 3), i.e. the first operator runs N times
+    and then the second once: the second is taken when i is a multiple of
+    N + 1.  (The appendix's modulus is N, which for N_GAN = 1 would never
+    alternate.)  Once the switch is set the second operator is used."""
+    if n_gan >= 1.0:
+        N, first = int(round(n_gan)), True
+    else:
+        N, first = int(round(1.0 / n_gan)), False
+    if i % (N + 1) != 0 and not switched:
+        return first
+    return not first
+
+
+def solve_schedule(f: np.ndarray, layers: list[np.ndarray], cnn_levels: int, rtol: float,
+                   max_cycles: int, n_gan: float, s_thres: float, mixed: bool = False,
+                   nu1: int = 2, nu2: int = 2):
+    """Solve a periodic problem from u = 0 with the hybrid schedule: each
+    iteration prolongs with prolongation_choice()'s operator (the network on
+    the `cnn_levels` finest prolongations, else the spline everywhere); the
+    switch of iteration i + 1 is set when iteration i changed the iterate by
+    at most s_thres, ||p_i - p_(i-1)||_2 over the unique nodes (Section 4;
+    s_thres = 0 never switches).  Stops once ||f - A u|| / ||f|| <= rtol or
+    after max_cycles iterations.  mixed: each iteration is refine_step()
+    (FP64 residual, FP32 cycle), else vcycle() in FP64.
+
+    Returns (u, ops, diffs, relres): ops[k] True where iteration k + 1 used
+    the network, diffs[k] its ||p_(k+1) - p_k||_2."""
+    import oracle
+
+    u = np.zeros_like(f)
+    rel = oracle.relres(u, f, oracle.PERIODIC)
+    ops: list[bool] = []
+    diffs: list[float] = []
+    switched = False
+    while rel > rtol and len(ops) < max_cycles:
+        net = prolongation_choice(len(ops) + 1, n_gan, switched)
+        lv = cnn_levels if net else 0
+        new = (refine_step(u, f, layers, lv, nu1, nu2) if mixed
+               else vcycle(u, f, layers, lv, nu1, nu2))
+        d = float(np.linalg.norm(to_unique(new - u)))
+        switched = s_thres > 0.0 and d <= s_thres
+        ops.append(net)
+        diffs.append(d)
+        u = new
+        rel = oracle.relres(u, f, oracle.PERIODIC)
+    return u, ops, diffs, rel

@@ -150,3 +150,95 @@ def test_mixed_refine_step_with_zero_network_levels_is_plain():
     f = dm.to_grid(dm.to_vec(f - f[:-1, :-1].mean(), P), n, P)
     u = np.zeros_like(f)
     np.testing.assert_array_equal(srcnn.refine_step(u, f, None, 0), oracle.refine_step(u, f, P))
+
+
+# Hybrid prolongation schedule (Table 1's N_GAN and S_thres; appendix
+# V-CYCLE).  The pins restate what Sections 3 and 4 say the parameters do.
+
+N_ITER = 300  # the paper's iteration cap (Table 1)
+
+
+@pytest.mark.parametrize("n_gan", [1.0, 5.0, 10.0, 1 / 5, 1 / 10])
+def test_schedule_n_gan_counts_network_per_spline(n_gan):
+    """N_GAN network prolongations per spline one (N_GAN >= 1), or 1/N_GAN
+    spline ones per network one; the first iteration uses the first
+    operator."""
+    ops = [srcnn.prolongation_choice(i, n_gan, False) for i in range(1, 121)]
+    first = n_gan >= 1.0
+    N = round(n_gan if first else 1.0 / n_gan)
+    assert ops[0] == first
+    for k in range(0, 120 - N):
+        window = ops[k:k + N + 1]
+        assert window.count(first) == N and window.count(not first) == 1
+
+
+def test_schedule_n_gan_one_alternates():
+    ops = [srcnn.prolongation_choice(i, 1.0, False) for i in range(1, 11)]
+    assert ops == [True, False] * 5
+
+
+@pytest.mark.parametrize("n_gan,only", [(N_ITER, True), (1 / N_ITER, False)])
+def test_schedule_edge_values_use_one_operator(n_gan, only):
+    """N_GAN = N_iter is network-only and 1/N_iter spline-only over N_iter
+    iterations; a set switch always selects the second operator."""
+    assert all(srcnn.prolongation_choice(i, n_gan, False) == only for i in range(1, N_ITER + 1))
+    assert all(srcnn.prolongation_choice(i, n_gan, True) == (not only) for i in range(1, 50))
+
+
+def schedule_rhs(n, scale=1.0):
+    import workloads
+    return workloads.rhs_divu_periodic(n, 5) * scale
+
+
+def test_schedule_single_operator_solves_are_plain_cycles():
+    """Network-only and spline-only schedules reproduce repeated network and
+    spline cycles bit for bit."""
+    n, levels, cycles = 65, 1, 4
+    layers = linear_layers()
+    f = schedule_rhs(n)
+    u_net, ops, _, _ = srcnn.solve_schedule(f, layers, levels, 0.0, cycles, N_ITER, 0.0)
+    u_spl, ops_s, _, _ = srcnn.solve_schedule(f, layers, levels, 0.0, cycles, 1 / N_ITER, 0.0)
+    a = np.zeros_like(f)
+    b = np.zeros_like(f)
+    for _ in range(cycles):
+        a = srcnn.vcycle(a, f, layers, levels)
+        b = oracle.vcycle(b, f, P)
+    assert ops == [True] * cycles and ops_s == [False] * cycles
+    np.testing.assert_array_equal(u_net, a)
+    np.testing.assert_array_equal(u_spl, b)
+
+
+@pytest.mark.parametrize("n_gan", [N_ITER, 1 / N_ITER, 1.0])
+def test_schedule_threshold_one_switches_after_the_first_iteration(n_gan):
+    """S_thres = 1 switches to the second operator right after the first
+    iteration when the iterates change by less than 1 (pressure-sized
+    values, Section 4)."""
+    layers = linear_layers()
+    f = schedule_rhs(65, 1e-4)
+    _, ops, diffs, _ = srcnn.solve_schedule(f, layers, 1, 0.0, 6, n_gan, 1.0)
+    assert diffs[0] <= 1.0
+    first = n_gan >= 1.0
+    assert ops == [first] + [not first] * 5
+
+
+def test_schedule_switch_follows_the_previous_iteration_change():
+    """The switch is set by the change the previous iteration made: with
+    S_thres between the changes of iterations 3 and 4 the first four
+    iterations use the network and the rest the spline."""
+    layers = linear_layers()
+    f = schedule_rhs(65)
+    _, ops0, d0, _ = srcnn.solve_schedule(f, layers, 1, 0.0, 8, N_ITER, 0.0)
+    assert all(ops0) and d0[3] < d0[2]
+    s = float(np.sqrt(d0[2] * d0[3]))
+    _, ops, d, _ = srcnn.solve_schedule(f, layers, 1, 0.0, 8, N_ITER, s)
+    assert ops == [True] * 4 + [False] * 4
+    assert d[:4] == d0[:4]
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_schedule_alternating_solve_converges(mixed):
+    layers = linear_layers()
+    f = schedule_rhs(65)
+    _, ops, _, rel = srcnn.solve_schedule(f, layers, 1, 1e-9, 40, 1.0, 0.0, mixed=mixed)
+    assert rel <= 1e-9 and len(ops) < 40
+    assert ops == [True, False] * (len(ops) // 2) + [True] * (len(ops) % 2)
