@@ -112,6 +112,15 @@ typedef struct {
   double cnn_max_ratio;       /* mg_solve with SR-CNN: after a network-prolongated cycle whose
                                  residual ratio exceeds this (0.5), use the spline from then on */
   double cnn_min_relres;      /* ... and likewise once the relative residual is <= this (1e-7) */
+  double n_gan;               /* mg_solve with SR-CNN: the hybrid schedule of Table 1 and the
+                                 appendix's V-CYCLE in place of the rule above.  0 (default):
+                                 off.  >= 1: N = round(n_gan) network prolongations, then one
+                                 spline one; in (0, 1): N = round(1 / n_gan) spline ones, then
+                                 one network one (cycle i = 1, 2, ... of the call takes the
+                                 second operator when i is a multiple of N + 1). */
+  double s_thres;             /* with n_gan: once a cycle changes u by at most this,
+                                 ||u_i - u_(i-1)||_2 over the unknowns, the next cycle takes
+                                 the second operator (Section 4); 0 (default): never. */
 } mg_options;
 
 /* SR-CNN weights (Section 3.1, generator after Ledig et al.; no biases):
@@ -166,10 +175,22 @@ MG_API int32_t mg_vcycle(mg_ctx ctx, double* const* u, const double* const* f, i
  * MG_PROLONG_SRCNN each problem starts with network-prolongated cycles,
  * checked after every cycle, and falls back to the spline for the rest of
  * the solve after a cycle whose residual ratio exceeds cnn_max_ratio or
- * once the relative residual is <= cnn_min_relres (the paper's switching
- * threshold S_thres, Table 1 and the appendix's V-CYCLE). */
+ * once the relative residual is <= cnn_min_relres (a minimal form of the
+ * paper's switching threshold S_thres); with n_gan > 0 the choice per cycle
+ * follows the hybrid schedule instead (N_GAN and S_thres, Table 1 and the
+ * appendix's V-CYCLE), and with s_thres > 0 every cycle is checked. */
 MG_API int32_t mg_solve(mg_ctx ctx, double* const* u, const double* const* f, double rtol,
                  int32_t max_cycles, int32_t* cycles_out, double* relres_out);
+
+/* Per-cycle record of the last mg_solve for problem `problem`: prolong_out[k]
+ * (MG_PROLONG_SPLINE or MG_PROLONG_SRCNN) is the prolongation cycle k + 1
+ * used, diff_out[k] the change it made, ||u_(k+1) - u_k||_2 over the
+ * unknowns, when the hybrid schedule tracks it (n_gan > 0 and s_thres > 0),
+ * else NaN.  At most `cap` entries are written (either output may be NULL);
+ * *count_out receives the number of cycles.  Host only, no device work.
+ * Errors: INVALID_ARG (NULL ctx or count_out, bad problem, cap < 0). */
+MG_API int32_t mg_solve_history(mg_ctx ctx, int32_t problem, int32_t cap, int32_t* prolong_out,
+                         double* diff_out, int32_t* count_out);
 
 /* Prolongation operator on its own (the appendix's SR-Prolongation and the
  * spline prolongation of Section 2.2): fine = P coarse for problem

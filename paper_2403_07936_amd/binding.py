@@ -63,6 +63,8 @@ class mg_options(ctypes.Structure):
         ("schedule", i32),
         ("cnn_max_ratio", ctypes.c_double),
         ("cnn_min_relres", ctypes.c_double),
+        ("n_gan", ctypes.c_double),
+        ("s_thres", ctypes.c_double),
     ]
 
 
@@ -93,6 +95,7 @@ def lib() -> ctypes.CDLL:
                            ctypes.POINTER(vp)]),
         "mg_vcycle": (i32, [vp, pp, pp, i32, pd]),
         "mg_solve": (i32, [vp, pp, pp, ctypes.c_double, i32, pi, pd]),
+        "mg_solve_history": (i32, [vp, i32, i32, pi, pd, pi]),
         "mg_prolong": (i32, [vp, i32, i32, i32, vp, vp, i32]),
         "mg_relax": (i32, [vp, i32, i32, vp, vp, i32, i32, i32]),
         "mg_residual": (i32, [vp, i32, i32, vp, vp, vp, i32]),
@@ -165,6 +168,17 @@ def mg_solve(ctx: int, u, f, rtol: float, max_cycles: int):
     if st in (MG_ERR_INVALID_ARG, MG_ERR_UNSUPPORTED, MG_ERR_OOM, MG_ERR_HIP):
         raise MGError(st, mg_last_error())
     return st, list(cyc), list(rel)
+
+
+def mg_solve_history(ctx: int, problem: int):
+    """Per-cycle record of the last mg_solve: (prolongations, changes), the
+    change NaN where the schedule does not measure it."""
+    n = i32()
+    _check(lib().mg_solve_history(vp(ctx), problem, 0, None, None, ctypes.byref(n)))
+    ops = (i32 * max(n.value, 1))()
+    dif = (ctypes.c_double * max(n.value, 1))()
+    _check(lib().mg_solve_history(vp(ctx), problem, n.value, ops, dif, ctypes.byref(n)))
+    return list(ops)[:n.value], list(dif)[:n.value]
 
 
 def mg_prolong(ctx: int, problem: int, coarse_level: int, kind: int, coarse: int, fine: int,

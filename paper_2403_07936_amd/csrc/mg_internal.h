@@ -94,6 +94,10 @@ hipError_t launch_resnorm(hipStream_t s, int bc, int n, const double* u, int pu,
 // Per-block partial sums of f and f^2 for the RHS checks.
 hipError_t launch_rhs_moments(hipStream_t s, int bc, int n, const double* f, int pf,
                               double* partials, int* nblocks);
+// Per-block partial sums of (u - prev)^2 over the unknowns in
+// partials[0 .. nblocks), and prev = u there.
+hipError_t launch_diffnorm(hipStream_t s, int bc, int n, const double* u, int pu, double* prev,
+                           int pp, double* partials, int* nblocks);
 // out[k] = sum of partials[k * stride + 0 .. count) for k < groups, in a
 // fixed order (single workgroup per group).
 hipError_t launch_reduce(hipStream_t s, const double* partials, int count, int stride, int groups,

@@ -325,6 +325,28 @@ __global__ void __launch_bounds__(TX* TY)
   }
 }
 
+// Per-block partial sums of (u - prev)^2 over the unknowns, then prev = u
+// there (the change one iteration made to the iterate).
+template <int BC>
+__global__ void __launch_bounds__(TX* TY)
+    k_diffnorm(int n, const double* __restrict__ u, int pu, double* __restrict__ prev, int pp,
+               double* __restrict__ partials) {
+  __shared__ double sh[TX * TY];
+  constexpr int lo = first_unknown<BC>();
+  const int j = lo + blockIdx.x * TX + threadIdx.x;
+  const int i = lo + blockIdx.y * TY + threadIdx.y;
+  double d2 = 0.0;
+  if (i <= n - 2 && j <= n - 2) {
+    const double v = ld(u, pu, i, j);
+    const double d = v - prev[(size_t)i * pp + j];
+    d2 = d * d;
+    prev[(size_t)i * pp + j] = v;
+  }
+  const int b = blockIdx.y * gridDim.x + blockIdx.x;
+  const double s = block_sum(d2, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[b] = s;
+}
+
 // Sum of `count` partials per group (group g at partials + g * stride), one
 // workgroup per group.  Each thread keeps 16 accumulators over its strided
 // share so that 16 loads are in flight at once; the order of every addition
@@ -519,6 +541,17 @@ hipError_t launch_sum(hipStream_t s, int bc, int n, const double* a, int pa, dou
     hipLaunchKernelGGL((k_moments<kDirichlet>), g, kBlock, 0, s, n, a, pa, partials, 0);
   else
     hipLaunchKernelGGL((k_moments<kPeriodic>), g, kBlock, 0, s, n, a, pa, partials, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_diffnorm(hipStream_t s, int bc, int n, const double* u, int pu, double* prev,
+                           int pp, double* partials, int* nblocks) {
+  const dim3 g = grid_unknowns(n, bc);
+  *nblocks = (int)(g.x * g.y);
+  if (bc == kDirichlet)
+    hipLaunchKernelGGL((k_diffnorm<kDirichlet>), g, kBlock, 0, s, n, u, pu, prev, pp, partials);
+  else
+    hipLaunchKernelGGL((k_diffnorm<kPeriodic>), g, kBlock, 0, s, n, u, pu, prev, pp, partials);
   return hipGetLastError();
 }
 

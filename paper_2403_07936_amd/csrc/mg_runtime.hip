@@ -148,6 +148,11 @@ struct Problem {
   double* partials = nullptr;  // 2 * blocks_for(n) doubles
   double* sums = nullptr;      // 4 doubles of reduced results
   int nblocks = 0;
+  // Hybrid prolongation schedule with a switch threshold: the previous
+  // iterate (n x n, pitch n), and the last mg_solve's per-cycle record.
+  double* uprev = nullptr;
+  std::vector<int> hist_op;
+  std::vector<double> hist_diff;
   // Captured step per variant (bit 0: SR-CNN prolongation, bit 1: mixed
   // step whose FP64 residual is already in place) and the caller arrays it
   // was captured with.
@@ -1358,6 +1363,11 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
     if (!(opt->cnn_max_ratio >= 0.0) || !(opt->cnn_min_relres >= 0.0))
       return fail(MG_ERR_INVALID_ARG, "cnn_max_ratio and cnn_min_relres must be >= 0");
   }
+  if (!(opt->n_gan >= 0.0) || opt->n_gan > 1e9 || (opt->n_gan > 0.0 && opt->n_gan < 1e-9) ||
+      !(opt->s_thres >= 0.0))
+    return fail(MG_ERR_INVALID_ARG, "n_gan must be 0 or in [1e-9, 1e9], s_thres >= 0");
+  if (opt->n_gan > 0.0 && opt->prolong != MG_PROLONG_SRCNN)
+    return fail(MG_ERR_INVALID_ARG, "n_gan needs the SR-CNN prolongation");
 
   int ndev = 0;
   MG_HIP(hipGetDeviceCount(&ndev));
@@ -1469,6 +1479,8 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
     p.nblocks = std::max(blocks_for(p.n, p.bc), (int)((p.n + 63) / 64) * ((p.n + 3) / 4));
     int32_t st = alloc_level<double>(ctx, 2, p.nblocks, &p.partials);
     if (st == MG_OK) st = alloc_level<double>(ctx, 1, 4, &p.sums);
+    if (st == MG_OK && opt->n_gan > 0.0 && opt->s_thres > 0.0)
+      st = alloc_level<double>(ctx, p.n, p.n, &p.uprev);
     if (st != MG_OK) return bail(st);
   }
   if (opt->prolong == MG_PROLONG_SRCNN) {
@@ -1502,16 +1514,28 @@ int32_t check_ctx_arrays(mg_ctx ctx, double* const* u, const double* const* f) {
   return MG_OK;
 }
 
-// Reads p.sums[0..1] of every listed problem into relres[b] (host sync).
-int32_t read_relres(mg_ctx ctx, const std::vector<int>& which, double* relres) {
+// Reads p.sums[0..1] of every listed problem into relres[b] (host sync),
+// and with `diff` also sqrt(p.sums[2]) into diff[b].
+int32_t read_relres(mg_ctx ctx, const std::vector<int>& which, double* relres,
+                    double* diff = nullptr) {
+  const int w = diff ? 3 : 2;
   for (size_t k = 0; k < which.size(); ++k)
-    MG_HIP(hipMemcpyAsync(ctx->host + 2 * k, ctx->probs[which[k]].sums, 2 * sizeof(double),
+    MG_HIP(hipMemcpyAsync(ctx->host + w * k, ctx->probs[which[k]].sums, w * sizeof(double),
                           hipMemcpyDeviceToHost, ctx->stream));
   MG_HIP(hipStreamSynchronize(ctx->stream));
   for (size_t k = 0; k < which.size(); ++k) {
-    const double rr = ctx->host[2 * k], ff = ctx->host[2 * k + 1];
+    const double rr = ctx->host[w * k], ff = ctx->host[w * k + 1];
     relres[k] = ff > 0.0 ? std::sqrt(rr) / std::sqrt(ff) : std::sqrt(rr);
+    if (diff) diff[k] = std::sqrt(ctx->host[w * k + 2]);
   }
+  return MG_OK;
+}
+
+// ||u - uprev||^2 over the unknowns into p.sums[2], and uprev = u.
+int32_t enqueue_diffnorm(mg_ctx_s* ctx, Problem& p, const double* u) {
+  int nb = 0;
+  MG_HIP(launch_diffnorm(ctx->stream, p.bc, p.n, u, p.pitch0, p.uprev, p.n, p.partials, &nb));
+  MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 1, p.sums + 2));
   return MG_OK;
 }
 
@@ -1616,6 +1640,28 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
   // cnn_max_ratio or the residual reaches cnn_min_relres; checked after every
   // such cycle.
   std::vector<char> cnn_on(B, cnn_cycles(ctx) ? 1 : 0);
+  // Hybrid schedule (n_gan > 0) in place of that rule: cycle i of this call
+  // takes the second operator when i is a multiple of N + 1 or when the
+  // previous cycle changed u by at most s_thres, else the first; with
+  // s_thres > 0 that change is measured and every cycle is checked.
+  const bool sched = ctx->opt.n_gan > 0.0 && cnn_cycles(ctx);
+  const bool track = sched && ctx->opt.s_thres > 0.0;
+  const bool net_first = ctx->opt.n_gan >= 1.0;
+  const long long nper =
+      sched ? std::llround(net_first ? ctx->opt.n_gan : 1.0 / ctx->opt.n_gan) + 1 : 1;
+  std::vector<char> sw(B, 0);
+  if (sched) std::fill(cnn_on.begin(), cnn_on.end(), 0);
+  auto use_net = [&](int b) -> bool {
+    if (!sched) return cnn_on[b] != 0;
+    const long long i = (long long)cycles[b] + 1;
+    return (i % nper != 0 && !sw[b]) ? net_first : !net_first;
+  };
+  for (int b = 0; b < B; ++b) {
+    ctx->probs[b].hist_op.clear();
+    ctx->probs[b].hist_diff.clear();
+    if (track && state[b] == 1) MG_TRY(enqueue_diffnorm(ctx, ctx->probs[b], u[b]));
+  }
+  std::vector<double> dif(B, 0.0);
   for (;;) {
     std::vector<int> act;
     for (int b = 0; b < B; ++b)
@@ -1634,6 +1680,8 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
             on[b] = 1;
             any = true;
             ++cycles[b];
+            ctx->probs[b].hist_op.push_back(MG_PROLONG_SPLINE);
+            ctx->probs[b].hist_diff.push_back(NAN);
           }
         if (any) {
           MG_TRY(persistent_bind(ctx, u, f, on));
@@ -1643,7 +1691,12 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
       }
       for (int b : act)
         if (cycles[b] < max_cycles && cycles[b] < next_check[b]) {
-          MG_TRY(run_step(ctx, ctx->probs[b], u[b], f[b], cnn_on[b] != 0, have_res[b] != 0));
+          const bool net = use_net(b);
+          Problem& p = ctx->probs[b];
+          MG_TRY(run_step(ctx, p, u[b], f[b], net, have_res[b] != 0));
+          if (track) MG_TRY(enqueue_diffnorm(ctx, p, u[b]));
+          p.hist_op.push_back(net ? MG_PROLONG_SRCNN : MG_PROLONG_SPLINE);
+          p.hist_diff.push_back(NAN);
           have_res[b] = 0;
           ++cycles[b];
         }
@@ -1661,16 +1714,20 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
         MG_TRY(enqueue_check_mixed(ctx, ctx->probs[b], u[b], f[b]));
         have_res[b] = 1;
       }
-      MG_TRY(read_relres(ctx, chk, r.data()));
+      MG_TRY(read_relres(ctx, chk, r.data(), track ? dif.data() : nullptr));
     } else {
       for (int b : chk) MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
-      MG_TRY(read_relres(ctx, chk, r.data()));
+      MG_TRY(read_relres(ctx, chk, r.data(), track ? dif.data() : nullptr));
     }
     for (size_t k = 0; k < chk.size(); ++k) {
       const int b = chk[k];
       const double rr = r[k], last = prev[b];
       const int span = cycles[b] - prev_cycles[b];
       rel[b] = rr;
+      if (track && !ctx->probs[b].hist_diff.empty()) {  // one cycle per check
+        ctx->probs[b].hist_diff.back() = dif[k];
+        sw[b] = dif[k] <= ctx->opt.s_thres ? 1 : 0;
+      }
       if (!std::isfinite(rr)) {
         state[b] = MG_ERR_NONFINITE;
         continue;
@@ -1701,7 +1758,7 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
       // Next check: every `every` cycles, or (auto) at the cycle where the
       // observed rate predicts the tolerance is crossed, at most 8 ahead.
       int gap = 1;
-      if (cnn_on[b] || switched) {
+      if (track || cnn_on[b] || switched) {
         gap = 1;
       } else if (every > 0) {
         gap = every;
@@ -1848,6 +1905,8 @@ void mg_options_default(mg_options* opt) {
   opt->schedule = 0;
   opt->cnn_max_ratio = 0.5;
   opt->cnn_min_relres = 1e-7;
+  opt->n_gan = 0.0;
+  opt->s_thres = 0.0;
 }
 
 int32_t mg_setup(const mg_grid* grids, int32_t batch, const mg_options* opt, void* hip_stream,
@@ -1970,6 +2029,22 @@ int32_t mg_num_levels(mg_ctx ctx, int32_t problem) {
   if (problem < 0 || problem >= (int)ctx->probs.size())
     return fail(MG_ERR_INVALID_ARG, "problem index out of range");
   return ctx->probs[problem].levels;
+}
+
+int32_t mg_solve_history(mg_ctx ctx, int32_t problem, int32_t cap, int32_t* prolong_out,
+                         double* diff_out, int32_t* count_out) {
+  if (!ctx || !count_out) return fail(MG_ERR_INVALID_ARG, "ctx or count_out is NULL");
+  if (problem < 0 || problem >= (int)ctx->probs.size())
+    return fail(MG_ERR_INVALID_ARG, "problem index out of range");
+  if (cap < 0) return fail(MG_ERR_INVALID_ARG, "cap < 0");
+  const mg::Problem& p = ctx->probs[problem];
+  const int n = (int)p.hist_op.size();
+  for (int k = 0; k < std::min(n, (int)cap); ++k) {
+    if (prolong_out) prolong_out[k] = p.hist_op[k];
+    if (diff_out) diff_out[k] = p.hist_diff[k];
+  }
+  *count_out = n;
+  return MG_OK;
 }
 
 int32_t mg_destroy(mg_ctx ctx) {

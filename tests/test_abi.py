@@ -61,6 +61,9 @@ def test_options_default(B):
     ([(65, 0, 0)], "nu_pre", 9),
     ([(65, 0, 0)], "inner_cycles", 0),
     ([(65, 0, 0)], "precision", 7),
+    ([(65, 0, 0)], "n_gan", -1.0),      # negative schedule ratio
+    ([(65, 0, 0)], "s_thres", -1.0),    # negative switch threshold
+    ([(65, 1, 0)], "n_gan", 1.0),       # schedule without the network prolongation
 ])
 def test_setup_rejects_bad_arguments_before_device_use(B, grids, field, value):
     o = B.mg_options_default()
@@ -87,3 +90,11 @@ def test_null_context_calls(B):
     assert ei.value.status == B.MG_ERR_INVALID_ARG
     with pytest.raises(B.MGError):
         B.mg_num_levels(0, 0)
+    with pytest.raises(B.MGError) as ei:
+        B.mg_solve_history(0, 0)
+    assert ei.value.status == B.MG_ERR_INVALID_ARG
+
+
+def test_options_default_schedule_is_off(B):
+    o = B.mg_options_default()
+    assert (o.n_gan, o.s_thres, o.cnn_max_ratio, o.cnn_min_relres) == (0.0, 0.0, 0.5, 1e-7)

@@ -10,7 +10,12 @@ Tolerances:
     values are printed);
   * one cycle: ||u_gpu - u_oracle|| <= 2e-2 ||u_oracle - u_in||;
   * solve: cycles to tolerance within +-1 of the oracle's run with the same
-    weights and the same switching rule.
+    weights and the same switching rule;
+  * hybrid schedule (N_GAN, S_thres) with the linear-interpolation weights:
+    the same prolongation in every cycle both ran, the per-cycle change of
+    the iterate within 1e-6 (FP64) / 1e-3 (mixed) relative, plus 1e-12 of
+    the first change (the rounding floor of FP64 iterates), cycles to
+    tolerance within +-1.
 """
 
 import numpy as np
@@ -230,3 +235,70 @@ def test_setup_rejections(B, dev):
         assert ei.value.status == B.MG_ERR_UNSUPPORTED
     finally:
         B.mg_destroy(ctx)
+
+
+N_ITER = 300
+
+
+def gpu_schedule(B, dev, f, blob, levels, precision, n_gan, s_thres, rtol, cap):
+    ctx = setup(B, [f.shape[0]], blob, levels, precision, n_gan=n_gan, s_thres=s_thres,
+                check_every=1)
+    try:
+        ft = torch.from_numpy(f).to(dev)
+        ut = torch.zeros_like(ft)
+        st, cyc, rel = B.mg_solve(ctx, [ut.data_ptr()], [ft.data_ptr()], rtol, cap)
+        ops, dif = B.mg_solve_history(ctx, 0)
+    finally:
+        B.mg_destroy(ctx)
+    return st, cyc[0], rel[0], [o == B.MG_PROLONG_SRCNN for o in ops], dif
+
+
+@pytest.mark.parametrize("n_gan,levels", [(1.0, 1), (3.0, 1), (1 / 3, 1)])
+def test_solve_hybrid_schedule_matches_oracle(B, dev, n_gan, levels):
+    """N_GAN network prolongations per spline one (no switch): the GPU takes
+    the oracle's operator in every cycle and reaches the tolerance in its
+    number of cycles (+-1)."""
+    n, rtol, cap = 257, 1e-8, 40
+    blob = linear_blob()
+    layers = srcnn.unpack_weights(blob)
+    f = workloads.rhs_divu_periodic(n, 4)
+    _, ops_o, _, rel_o = srcnn.solve_schedule(f, layers, levels, rtol, cap, n_gan, 0.0)
+    st, cyc, rel, ops, dif = gpu_schedule(B, dev, f, blob, levels, F64, n_gan, 0.0, rtol, cap)
+    say(f"N_GAN={n_gan:.3g} levels={levels}: GPU {cyc} cycles {rel:.2e}; oracle {len(ops_o)} "
+        f"cycles {rel_o:.2e}; ops {''.join('N' if o else 's' for o in ops)}")
+    assert st == 0 and rel <= rtol and abs(cyc - len(ops_o)) <= 1
+    k = min(cyc, len(ops_o))
+    assert len(ops) == cyc and ops[:k] == ops_o[:k]
+    assert all(np.isnan(dif))
+
+
+@pytest.mark.parametrize("precision,n_gan", [(F64, N_ITER), (F64, 1 / N_ITER), (F64, 1.0),
+                                             (F32, 1.0)])
+def test_solve_switch_threshold_matches_oracle(B, dev, precision, n_gan):
+    """S_thres between the changes the 3rd and 4th cycles make: the GPU
+    switches after the same cycle as the oracle, and the changes it
+    measures agree with the oracle's."""
+    n, levels, rtol, cap = 257, 1, 1e-9, 40
+    mixed = precision == F32
+    blob = linear_blob()
+    layers = srcnn.unpack_weights(blob)
+    f = workloads.rhs_divu_periodic(n, 6)
+    _, _, d0, _ = srcnn.solve_schedule(f, layers, levels, rtol, cap, n_gan, 0.0, mixed=mixed)
+    assert d0[3] < 0.5 * d0[2]
+    s = float(np.sqrt(d0[2] * d0[3]))
+    _, ops_o, d_o, rel_o = srcnn.solve_schedule(f, layers, levels, rtol, cap, n_gan, s,
+                                                mixed=mixed)
+    st, cyc, rel, ops, dif = gpu_schedule(B, dev, f, blob, levels, precision, n_gan, s, rtol, cap)
+    say(f"S_thres={s:.3e} N_GAN={n_gan:.3g} mixed={mixed}: GPU {cyc} cycles {rel:.2e}; oracle "
+        f"{len(ops_o)} cycles {rel_o:.2e}; ops {''.join('N' if o else 's' for o in ops)}")
+    assert st == 0 and rel <= rtol and abs(cyc - len(ops_o)) <= 1
+    k = min(cyc, len(ops_o))
+    assert ops[:k] == ops_o[:k]
+    first = n_gan >= 1.0
+    if n_gan != 1.0:
+        assert ops_o[:5] == [first] * 4 + [not first]
+    # Relative, plus an absolute floor at the rounding noise of the FP64
+    # iterates (a few ulps of u summed over 256^2 nodes: ~1e-13 of the first
+    # change).
+    tol = 1e-3 if mixed else 1e-6
+    np.testing.assert_allclose(dif[:k], d_o[:k], rtol=tol, atol=1e-12 * d_o[0])
