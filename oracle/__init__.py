@@ -11,7 +11,9 @@ Every function takes and returns ``numpy`` arrays laid out as in
 Pins: each function is checked in ``tests/test_oracle_pins.py`` against
 something other than itself (closed forms, scipy/numpy library routines,
 dense linear algebra on tiny grids, invariants).  No function is "parity
-unpinned".
+unpinned".  The SR-CNN prolongation and the hybrid schedule live in
+``srcnn.py`` (pins in ``tests/test_srcnn_pins.py``), the pressure-projection
+steps around the solve in ``projection.py`` (``tests/test_projection_pins.py``).
 """
 
 from __future__ import annotations

@@ -26,5 +26,6 @@ from .rhs import (  # noqa: F401
     rhs_divu_dirichlet,
     rhs_divu_periodic,
     rhs_manufactured_dirichlet,
+    velocity_periodic,
     workload,
 )

@@ -121,6 +121,35 @@ def rhs_divu_periodic(n: int, seed: int, kmax: float | None = None) -> np.ndarra
     return _with_seam(f)
 
 
+def velocity_periodic(n: int, seed: int, kmax: float | None = None):
+    """Divergence-free periodic velocity (u_x, u_y) with E(k) ~ k^(-5/3).
+
+    The unique grid is N x N, N = n-1, on the unit torus; x runs along the
+    columns (axis 1), y along the rows (axis 0).  A stream function psi has
+    Fourier amplitudes sqrt(E(|k|)/(2 pi |k|)) / (2 pi |k|) on integer
+    wavenumbers 1 <= |k| <= kmax (default (n-1)/4) with uniform random phases
+    drawn from ``default_rng(seed)`` as one array of shape (N, N//2+1) from
+    ``uniform(0, 2 pi)``; u_x = d psi/dy, u_y = -d psi/dx (spectral), scaled
+    together to unit RMS speed over the unique nodes.  Returned with the
+    duplicated seam, float64.
+    """
+    _check_n(n)
+    N = n - 1
+    if kmax is None:
+        kmax = N / 4
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=(N, N // 2 + 1))
+    ky = np.fft.fftfreq(N, d=1.0 / N)[:, None]
+    kx = np.fft.rfftfreq(N, d=1.0 / N)[None, :]
+    kappa = np.sqrt(kx * kx + ky * ky)
+    amp = _spectral_amplitude(kappa, float(kmax))
+    psi_hat = np.where(kappa > 0, amp / (2.0 * np.pi * np.maximum(kappa, 1.0)), 0.0) * np.exp(1j * ph)
+    ux = np.fft.irfft2(2j * np.pi * ky * psi_hat, s=(N, N))
+    uy = np.fft.irfft2(-2j * np.pi * kx * psi_hat, s=(N, N))
+    speed = np.sqrt(np.mean(ux * ux + uy * uy))
+    return _with_seam(ux / speed), _with_seam(uy / speed)
+
+
 def rhs_divu_dirichlet(n: int, seed: int, kmax: float | None = None) -> np.ndarray:
     """Zero-Dirichlet analogue of ``rhs_divu_periodic`` in the sine basis.
 
