@@ -67,7 +67,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dirichlet4097",
-                    choices=["dirichlet4097", "periodic1025", "dirichlet65", "periodic1025_srcnn"])
+                    choices=["dirichlet4097", "periodic1025", "dirichlet65", "periodic1025_srcnn",
+                             "periodic4097_projection"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -85,7 +86,8 @@ def bench_srcnn(args) -> int:
     """1025 x 1025 periodic div-u source, V(2,2) cycles whose two finest
     prolongations use the SR-CNN (bf16 matrix cores), FP64 cycle.  A step is
     one such cycle.  Also reported: time to 1e-8 with the network-then-spline
-    schedule, and the spline cycle for comparison."""
+    schedule, with the hybrid schedule at N_GAN = 1 (network and spline
+    cycles alternating), and the spline cycle for comparison."""
     import numpy as np
     import torch
 
@@ -104,8 +106,10 @@ def bench_srcnn(args) -> int:
     ft = torch.from_numpy(f).to(dev)
     ut = torch.zeros_like(ft)
     res = {}
-    for mode in ("srcnn", "spline"):
-        kw = dict(cnn_weights=W, cnn_levels=2) if mode == "srcnn" else {}
+    for mode in ("srcnn", "spline", "hybrid"):
+        kw = dict(cnn_weights=W, cnn_levels=2) if mode != "spline" else {}
+        if mode == "hybrid":
+            kw.update(n_gan=1.0)
         s = Solver([(n, bc)], precision="fp64", use_graph=True, **kw)
         ut.zero_()
         s.vcycle([ut], [ft], args.warmup)
@@ -124,7 +128,8 @@ def bench_srcnn(args) -> int:
             dt = time.perf_counter() - t0
             if best is None or dt < best[0]:
                 best = (dt, st, cyc[0], rel[0])
-        res[mode] = {"solver": s, "sec": sec, "ttt": best}
+        ops = "".join("N" if o == B.MG_PROLONG_SRCNN else "s" for o in s.history()[0])
+        res[mode] = {"solver": s, "sec": sec, "ttt": best, "ops": ops}
         log(f"{mode}: {sec * 1e3:.3f} ms/cycle; to 1e-8: {best[0] * 1e3:.2f} ms, {best[2]} cycles, "
             f"relres {best[3]:.2e}")
     hs = res["srcnn"]["solver"]
@@ -181,10 +186,124 @@ def bench_srcnn(args) -> int:
         "spline": {"ms_per_cycle": round(res["spline"]["sec"] * 1e3, 4),
                    "time_to_1e-8_s": round(res["spline"]["ttt"][0], 6),
                    "cycles_to_1e-8": res["spline"]["ttt"][2]},
+        "hybrid_n_gan_1": {"time_to_1e-8_s": round(res["hybrid"]["ttt"][0], 6),
+                           "cycles_to_1e-8": res["hybrid"]["ttt"][2],
+                           "final_relres": res["hybrid"]["ttt"][3],
+                           "prolongations": res["hybrid"]["ops"]},
         "roofline": roofline, "kernels": per_kernel, "cpu_baseline": cpu,
     }
     for v in res.values():
         v["solver"].close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_projection(args) -> int:
+    """4097 x 4097 periodic pressure-projection time step: the source
+    f = -div((u . grad) u) (mg_ns_rhs), the pressure solve to 1e-10 (mixed
+    precision, from the previous step's pressure) and the explicit Euler
+    velocity step (mg_ns_update), ping-ponging two velocity buffers.  A step
+    is those three.  Each projection kernel is also timed on its own with HIP
+    events on the stream it runs on."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2403_07936_amd import binding as B
+    from paper_2403_07936_amd.solver import Solver
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    B.lib()
+    n, N, dt = 4097, 4096, 1e-4
+    log(f"generating velocity n={n} seed {args.seed}")
+    ux, uy = workloads.velocity_periodic(n, args.seed)
+    vel = [[torch.from_numpy(ux).to(dev), torch.from_numpy(uy).to(dev)]]
+    vel.append([torch.empty_like(vel[0][0]), torch.empty_like(vel[0][0])])
+    f = torch.zeros_like(vel[0][0])
+    p = torch.zeros_like(f)
+    stream = torch.cuda.current_stream().cuda_stream
+    s = Solver([(n, "periodic")], precision="mixed")
+    F64 = B.MG_DT_F64
+    cyc_log = []
+
+    def step(k):
+        a, b = vel[k % 2], vel[(k + 1) % 2]
+        B.mg_ns_rhs(n, a[0].data_ptr(), a[1].data_ptr(), f.data_ptr(), n, F64, stream)
+        st, cyc, rel = s.solve([p], [f], rtol=1e-10, max_cycles=30)
+        if st != 0:
+            raise RuntimeError(f"pressure solve failed: status {st}, relres {rel[0]:.2e}")
+        cyc_log.append(cyc[0])
+        B.mg_ns_update(n, a[0].data_ptr(), a[1].data_ptr(), p.data_ptr(), dt, b[0].data_ptr(),
+                       b[1].data_ptr(), n, F64, stream)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    cyc_log.clear()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    log(f"projection step: {sec * 1e3:.3f} ms, solve cycles {cyc_log}")
+
+    def kernel_avg(fn, reps=20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    a, b = vel[0], vel[1]
+    t_rhs = kernel_avg(lambda: B.mg_ns_rhs(n, a[0].data_ptr(), a[1].data_ptr(), f.data_ptr(), n,
+                                           F64, stream))
+    t_upd = kernel_avg(lambda: B.mg_ns_update(n, a[0].data_ptr(), a[1].data_ptr(), p.data_ptr(),
+                                              dt, b[0].data_ptr(), b[1].data_ptr(), n, F64,
+                                              stream))
+    by_rhs, by_upd = 3 * 8 * N * N, 5 * 8 * N * N
+    kernels = {"ns_rhs": {"avg_us": round(t_rhs * 1e6, 2), "bytes": by_rhs,
+                          "GBps": round(by_rhs / t_rhs / 1e9, 1)},
+               "ns_update": {"avg_us": round(t_upd * 1e6, 2), "bytes": by_upd,
+                             "GBps": round(by_upd / t_upd / 1e9, 1)}}
+    log(f"kernels: {kernels}")
+    ach = by_upd / t_upd / 1e9
+    roofline = {"bound": "hbm", "kernel": "ns_update", "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_us": round(t_upd * 1e6, 2), "bytes_per_launch": by_upd}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        from oracle import projection as pj
+
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        fo = pj.ns_rhs(ux, uy)
+        po = oracle.solve(fo, oracle.PERIODIC, rtol=1e-10, max_cycles=30)[0]
+        pj.ns_update(ux, uy, po, dt)
+        el = time.perf_counter() - t0
+        cpu = {"value": round(N * N / el, 1), "unit": "grid-points/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"one projection step of periodic4097 from p = 0 ({el:.1f} s: numpy "
+                         f"source and update, plain C FP64 V-cycles to 1e-10)"}
+    out = {
+        "metric": "grid-points/s per pressure-projection time step (source, solve to 1e-10, "
+                  "velocity step)",
+        "value": round(N * N / sec, 1), "unit": "grid-points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "periodic4097_projection", "n": n, "bc": "periodic",
+                   "unknowns": N * N, "dt": dt, "solve": "mixed, rtol 1e-10, warm start",
+                   "seed": args.seed},
+        "solve_cycles": cyc_log, "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
+    }
+    s.close()
     print(json.dumps(out), flush=True)
     return 0
 
@@ -197,6 +316,8 @@ def main() -> int:
         return 2
     if args.workload == "periodic1025_srcnn":
         return bench_srcnn(args)
+    if args.workload == "periodic4097_projection":
+        return bench_projection(args)
 
     import numpy as np
     import torch

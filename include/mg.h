@@ -205,6 +205,29 @@ MG_API int32_t mg_solve_history(mg_ctx ctx, int32_t problem, int32_t cap, int32_
 MG_API int32_t mg_prolong(mg_ctx ctx, int32_t problem, int32_t coarse_level, int32_t kind,
                    const void* coarse, void* fine, int32_t dtype);
 
+/* The steps either side of the pressure solve in a time step of the
+ * incompressible flow (Section 2.1's momentum system; Section 2.3's source
+ * with zero viscosity), on one periodic n x n grid with the duplicated seam
+ * (n - 1 = 4 * 2^k, 5 <= n <= 16385; spacing h = 1/(n-1); x along the
+ * columns, y along the rows).  Every derivative is the second-order central
+ * difference of the nodal values, (a[j+1] - a[j-1]) / (2h).
+ *   mg_ns_rhs:    f = -div((u . grad) u), the source of the pressure-Poisson
+ *                 equation (mean zero up to rounding); seam written.
+ *   mg_ns_update: (ux_out, uy_out) = u - dt ((u . grad) u + grad p), one
+ *                 explicit Euler step of the momentum equation; seams
+ *                 written.  The outputs must not alias the inputs or each
+ *                 other.
+ * All arrays are device arrays of dtype MG_DT_F64 or MG_DT_F32 with row
+ * pitch `pitch` (>= n) elements, owned by the caller; only the unique nodes
+ * of the inputs are read.  Asynchronous on hip_stream (NULL: the null
+ * stream); no context needed.  Errors: INVALID_ARG (bad n, pitch or dtype,
+ * NULL or aliased arrays, non-finite dt), HIP. */
+MG_API int32_t mg_ns_rhs(int32_t n, const void* ux, const void* uy, void* f, int32_t pitch,
+                  int32_t dtype, void* hip_stream);
+MG_API int32_t mg_ns_update(int32_t n, const void* ux, const void* uy, const void* p, double dt,
+                     void* ux_out, void* uy_out, int32_t pitch, int32_t dtype,
+                     void* hip_stream);
+
 /* Single steps of the cycle on caller arrays, for operator-level checks.
  * Arrays are device arrays of level `level` of problem `problem`, pitch =
  * side, in dtype MG_DT_F64 or MG_DT_F32.  All are asynchronous.

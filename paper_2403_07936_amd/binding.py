@@ -96,6 +96,8 @@ def lib() -> ctypes.CDLL:
         "mg_vcycle": (i32, [vp, pp, pp, i32, pd]),
         "mg_solve": (i32, [vp, pp, pp, ctypes.c_double, i32, pi, pd]),
         "mg_solve_history": (i32, [vp, i32, i32, pi, pd, pi]),
+        "mg_ns_rhs": (i32, [i32, vp, vp, vp, i32, i32, vp]),
+        "mg_ns_update": (i32, [i32, vp, vp, vp, ctypes.c_double, vp, vp, i32, i32, vp]),
         "mg_prolong": (i32, [vp, i32, i32, i32, vp, vp, i32]),
         "mg_relax": (i32, [vp, i32, i32, vp, vp, i32, i32, i32]),
         "mg_residual": (i32, [vp, i32, i32, vp, vp, vp, i32]),
@@ -179,6 +181,16 @@ def mg_solve_history(ctx: int, problem: int):
     dif = (ctypes.c_double * max(n.value, 1))()
     _check(lib().mg_solve_history(vp(ctx), problem, n.value, ops, dif, ctypes.byref(n)))
     return list(ops)[:n.value], list(dif)[:n.value]
+
+
+def mg_ns_rhs(n: int, ux: int, uy: int, f: int, pitch: int, dtype: int, stream: int = 0) -> None:
+    _check(lib().mg_ns_rhs(n, vp(ux), vp(uy), vp(f), pitch, dtype, vp(stream or None)))
+
+
+def mg_ns_update(n: int, ux: int, uy: int, p: int, dt: float, ux_out: int, uy_out: int,
+                 pitch: int, dtype: int, stream: int = 0) -> None:
+    _check(lib().mg_ns_update(n, vp(ux), vp(uy), vp(p), float(dt), vp(ux_out), vp(uy_out), pitch,
+                              dtype, vp(stream or None)))
 
 
 def mg_prolong(ctx: int, problem: int, coarse_level: int, kind: int, coarse: int, fine: int,

@@ -1,0 +1,149 @@
+// Pressure-projection steps around the Poisson solve on a periodic grid with
+// the duplicated seam (unique nodes 0 .. N-1, N = n - 1, spacing h = 1/N, x
+// along the columns):
+//   * the source of the pressure-Poisson equation with zero viscosity
+//     (Section 2.3, Eq. for f(x, y)): f = -div((u . grad) u);
+//   * the explicit Euler step of the momentum equation (Section 2.1, first
+//     line of the system): u <- u - dt ((u . grad) u + grad p).
+// Every derivative is the central difference (a[j+1] - a[j-1]) / (2h) of the
+// nodal values; 1 / (2h) = N / 2 is a power of two, so the products by it
+// are exact and, with contraction off, each result is rounded exactly as
+// the plain expression in the order written.
+//
+// One workgroup of 64 x 4 threads per tile of 64 columns x 16 rows: the
+// tile and a halo of 2 (source) or 1 (update) nodes of every input are
+// staged in LDS with periodic wrap, then each thread makes 4 rows of one
+// column.  Both passes are bound by HBM: algorithmic bytes per unique node
+// are 3 values (source: read u_x, u_y, write f) and 5 values (update: read
+// u_x, u_y, p, write both components).
+
+#include "mg_internal.h"
+
+namespace mg {
+namespace {
+
+constexpr int kNsTX = 64, kNsTY = 4, kNsRows = 16;
+
+template <typename T, int H>
+__device__ __forceinline__ void ns_load_tile(const T* __restrict__ a, int pa, int N, int i0,
+                                             int j0, T* __restrict__ sh) {
+  constexpr int C = kNsTX + 2 * H, R = kNsRows + 2 * H;
+  const int t = threadIdx.y * kNsTX + threadIdx.x;
+  for (int k = t; k < R * C; k += kNsTX * kNsTY) {
+    const int r = k / C, c = k - r * C;
+    int i = i0 - H + r, j = j0 - H + c;
+    while (i < 0) i += N;  // more than one period only on grids smaller than the tile
+    while (i >= N) i -= N;
+    while (j < 0) j += N;
+    while (j >= N) j -= N;
+    sh[k] = a[(size_t)i * pa + j];
+  }
+}
+
+// (u . grad) u at LDS position (r, c) of a tile with row length C.
+template <typename T, int C>
+__device__ __forceinline__ void ns_convection(const T* su, const T* sv, int r, int c, T inv2h,
+                                              T* cx, T* cy) {
+#pragma clang fp contract(off)
+  const int k = r * C + c;
+  const T u = su[k], v = sv[k];
+  const T ux_x = (su[k + 1] - su[k - 1]) * inv2h, ux_y = (su[k + C] - su[k - C]) * inv2h;
+  const T uy_x = (sv[k + 1] - sv[k - 1]) * inv2h, uy_y = (sv[k + C] - sv[k - C]) * inv2h;
+  *cx = u * ux_x + v * ux_y;
+  *cy = u * uy_x + v * uy_y;
+}
+
+// Writes node (i, j) and, on the first row / column, its seam copies.
+template <typename T>
+__device__ __forceinline__ void ns_store(T* a, int pa, int N, int i, int j, T val) {
+  a[(size_t)i * pa + j] = val;
+  if (i == 0) a[(size_t)N * pa + j] = val;
+  if (j == 0) a[(size_t)i * pa + N] = val;
+  if (i == 0 && j == 0) a[(size_t)N * pa + N] = val;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNsTX* kNsTY)
+    k_ns_rhs(int N, const T* __restrict__ ux, const T* __restrict__ uy, int pu, T* __restrict__ f,
+             T inv2h) {
+#pragma clang fp contract(off)
+  constexpr int H = 2, C = kNsTX + 2 * H, R = kNsRows + 2 * H;
+  __shared__ T su[R * C], sv[R * C];
+  const int i0 = blockIdx.y * kNsRows, j0 = blockIdx.x * kNsTX;
+  ns_load_tile<T, H>(ux, pu, N, i0, j0, su);
+  ns_load_tile<T, H>(uy, pu, N, i0, j0, sv);
+  __syncthreads();
+  const int j = j0 + threadIdx.x, c = threadIdx.x + H;
+  if (j >= N) return;
+#pragma unroll
+  for (int q = 0; q < kNsRows / kNsTY; ++q) {
+    const int rl = threadIdx.y + q * kNsTY, i = i0 + rl, r = rl + H;
+    if (i >= N) break;
+    T cxe, cye, cxw, cyw, cxn, cyn, cxs, cys;
+    ns_convection<T, C>(su, sv, r, c + 1, inv2h, &cxe, &cye);
+    ns_convection<T, C>(su, sv, r, c - 1, inv2h, &cxw, &cyw);
+    ns_convection<T, C>(su, sv, r + 1, c, inv2h, &cxn, &cyn);
+    ns_convection<T, C>(su, sv, r - 1, c, inv2h, &cxs, &cys);
+    const T val = -((cxe - cxw) * inv2h + (cyn - cys) * inv2h);
+    ns_store(f, pu, N, i, j, val);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNsTX* kNsTY)
+    k_ns_update(int N, const T* __restrict__ ux, const T* __restrict__ uy,
+                const T* __restrict__ p, int pu, T dt, T* __restrict__ ox, T* __restrict__ oy,
+                T inv2h) {
+#pragma clang fp contract(off)
+  constexpr int H = 1, C = kNsTX + 2 * H, R = kNsRows + 2 * H;
+  __shared__ T su[R * C], sv[R * C], sp[R * C];
+  const int i0 = blockIdx.y * kNsRows, j0 = blockIdx.x * kNsTX;
+  ns_load_tile<T, H>(ux, pu, N, i0, j0, su);
+  ns_load_tile<T, H>(uy, pu, N, i0, j0, sv);
+  ns_load_tile<T, H>(p, pu, N, i0, j0, sp);
+  __syncthreads();
+  const int j = j0 + threadIdx.x, c = threadIdx.x + H;
+  if (j >= N) return;
+#pragma unroll
+  for (int q = 0; q < kNsRows / kNsTY; ++q) {
+    const int rl = threadIdx.y + q * kNsTY, i = i0 + rl, r = rl + H;
+    if (i >= N) break;
+    T cx, cy;
+    ns_convection<T, C>(su, sv, r, c, inv2h, &cx, &cy);
+    const int k = r * C + c;
+    const T px = (sp[k + 1] - sp[k - 1]) * inv2h, py = (sp[k + C] - sp[k - C]) * inv2h;
+    ns_store(ox, pu, N, i, j, su[k] - dt * (cx + px));
+    ns_store(oy, pu, N, i, j, sv[k] - dt * (cy + py));
+  }
+}
+
+dim3 ns_grid(int N) { return dim3((N + kNsTX - 1) / kNsTX, (N + kNsRows - 1) / kNsRows); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_ns_rhs(hipStream_t s, int n, const T* ux, const T* uy, T* f, int pitch) {
+  const int N = n - 1;
+  hipLaunchKernelGGL(k_ns_rhs<T>, ns_grid(N), dim3(kNsTX, kNsTY), 0, s, N, ux, uy, pitch, f,
+                     (T)(0.5 * N));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ns_update(hipStream_t s, int n, const T* ux, const T* uy, const T* p, double dt,
+                            T* ox, T* oy, int pitch) {
+  const int N = n - 1;
+  hipLaunchKernelGGL(k_ns_update<T>, ns_grid(N), dim3(kNsTX, kNsTY), 0, s, N, ux, uy, p, pitch,
+                     (T)dt, ox, oy, (T)(0.5 * N));
+  return hipGetLastError();
+}
+
+template hipError_t launch_ns_rhs<double>(hipStream_t, int, const double*, const double*, double*,
+                                          int);
+template hipError_t launch_ns_rhs<float>(hipStream_t, int, const float*, const float*, float*, int);
+template hipError_t launch_ns_update<double>(hipStream_t, int, const double*, const double*,
+                                             const double*, double, double*, double*, int);
+template hipError_t launch_ns_update<float>(hipStream_t, int, const float*, const float*,
+                                            const float*, double, float*, float*, int);
+
+}  // namespace mg

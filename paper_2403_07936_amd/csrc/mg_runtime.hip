@@ -1970,6 +1970,57 @@ int32_t mg_coarse_solve(mg_ctx ctx, int32_t problem, const void* f, void* u, int
            return fail(MG_ERR_INVALID_ARG, "bad dtype");)
 }
 
+namespace mg {
+namespace {
+int32_t ns_check(int32_t n, int32_t pitch, int32_t dtype, std::initializer_list<const void*> in,
+                 std::initializer_list<const void*> out) {
+  if (!valid_side(n)) return fail(MG_ERR_INVALID_ARG, "n is not 4*2^k+1 in 5..16385");
+  if (pitch < n) return fail(MG_ERR_INVALID_ARG, "pitch < n");
+  if (dtype != MG_DT_F64 && dtype != MG_DT_F32) return fail(MG_ERR_INVALID_ARG, "bad dtype");
+  for (const void* a : in)
+    if (!a) return fail(MG_ERR_INVALID_ARG, "NULL array");
+  for (const void* a : out) {
+    if (!a) return fail(MG_ERR_INVALID_ARG, "NULL array");
+    for (const void* b : in)
+      if (a == b) return fail(MG_ERR_INVALID_ARG, "an output aliases an input");
+  }
+  return MG_OK;
+}
+}  // namespace
+}  // namespace mg
+
+int32_t mg_ns_rhs(int32_t n, const void* ux, const void* uy, void* f, int32_t pitch,
+                  int32_t dtype, void* hip_stream) {
+  g_last_error.clear();
+  MG_GUARD(MG_TRY(ns_check(n, pitch, dtype, {ux, uy}, {f}));
+           const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+           if (dtype == MG_DT_F64) MG_HIP(launch_ns_rhs<double>(
+               s, n, static_cast<const double*>(ux), static_cast<const double*>(uy),
+               static_cast<double*>(f), pitch));
+           else MG_HIP(launch_ns_rhs<float>(s, n, static_cast<const float*>(ux),
+                                            static_cast<const float*>(uy),
+                                            static_cast<float*>(f), pitch));
+           return MG_OK;)
+}
+
+int32_t mg_ns_update(int32_t n, const void* ux, const void* uy, const void* p, double dt,
+                     void* ux_out, void* uy_out, int32_t pitch, int32_t dtype, void* hip_stream) {
+  g_last_error.clear();
+  MG_GUARD(MG_TRY(ns_check(n, pitch, dtype, {ux, uy, p}, {ux_out, uy_out}));
+           if (ux_out == uy_out) return fail(MG_ERR_INVALID_ARG, "ux_out == uy_out");
+           if (!std::isfinite(dt)) return fail(MG_ERR_INVALID_ARG, "dt is not finite");
+           const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+           if (dtype == MG_DT_F64) MG_HIP(launch_ns_update<double>(
+               s, n, static_cast<const double*>(ux), static_cast<const double*>(uy),
+               static_cast<const double*>(p), dt, static_cast<double*>(ux_out),
+               static_cast<double*>(uy_out), pitch));
+           else MG_HIP(launch_ns_update<float>(
+               s, n, static_cast<const float*>(ux), static_cast<const float*>(uy),
+               static_cast<const float*>(p), dt, static_cast<float*>(ux_out),
+               static_cast<float*>(uy_out), pitch));
+           return MG_OK;)
+}
+
 int32_t mg_timing_enable(mg_ctx ctx, int32_t enable) {
   g_last_error.clear();
   if (!ctx) return fail(MG_ERR_INVALID_ARG, "ctx is NULL");

@@ -21,14 +21,17 @@ class Solver:
                  pitch=None, stream: torch.cuda.Stream | None = None, schedule: int = 0,
                  kernel_path: int = 0, tune_cache_path: str | None = None,
                  cnn_weights=None, cnn_levels: int = 2, cnn_max_ratio: float = 0.5,
-                 cnn_min_relres: float = 1e-7):
+                 cnn_min_relres: float = 1e-7, n_gan: float = 0.0, s_thres: float = 0.0):
         """grids: sequence of (n, bc) with bc 0/1 or "dirichlet"/"periodic".
         pitch: optional sequence of row pitches (elements) of the level-0 arrays.
         schedule: 0 autotuned, 1 per-problem graphs, 2 one persistent launch per step.
         tune_cache_path: optional text file the autotuner reads and appends to.
         cnn_weights: optional flat float32 array of SR-CNN weights (MG_SRCNN_WEIGHT_COUNT
         values, see include/mg.h); selects the network prolongation on the
-        cnn_levels finest levels."""
+        cnn_levels finest levels.
+        n_gan, s_thres: the hybrid prolongation schedule of mg_solve (N_GAN
+        network prolongations per spline one, switch once a cycle changes u by
+        at most s_thres); n_gan = 0 keeps the network-then-spline rule."""
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = B.mg_options_default()
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -51,6 +54,8 @@ class Solver:
             opt.cnn_weights_bytes = self._weights.nbytes
             opt.cnn_max_ratio = cnn_max_ratio
             opt.cnn_min_relres = cnn_min_relres
+            opt.n_gan = n_gan
+            opt.s_thres = s_thres
         self.grids = [(int(n), BCS[bc] if isinstance(bc, str) else int(bc)) for n, bc in grids]
         pitches = list(pitch) if pitch is not None else [0] * len(self.grids)
         self.pitch = [p if p else n for (n, _), p in zip(self.grids, pitches)]
@@ -74,6 +79,10 @@ class Solver:
 
     def solve(self, u, f, rtol: float = 1e-10, max_cycles: int = 50):
         return B.mg_solve(self.ctx, self._addr(u, True), self._addr(f, False), rtol, max_cycles)
+
+    def history(self, problem: int = 0):
+        """(prolongations, changes) per cycle of the last solve."""
+        return B.mg_solve_history(self.ctx, problem)
 
     def num_levels(self, problem: int = 0) -> int:
         return B.mg_num_levels(self.ctx, problem)
