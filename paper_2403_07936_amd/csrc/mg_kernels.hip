@@ -279,6 +279,11 @@ __global__ void __launch_bounds__(TX* TY)
   u[(size_t)i * pu + j] += (double)e[(size_t)i * pe + j];
 }
 
+// The norm kernels give each thread kNormRows rows of one column (rows
+// q * TY + threadIdx.y of the block's band), so that a workgroup's share
+// outweighs its tree reduction.
+constexpr int kNormRows = 8;
+
 template <int BC>
 __global__ void __launch_bounds__(TX* TY)
     k_resnorm(int n, const double* __restrict__ u, int pu, const double* __restrict__ f, int pf,
@@ -286,13 +291,16 @@ __global__ void __launch_bounds__(TX* TY)
   __shared__ double sh[TX * TY];
   constexpr int lo = first_unknown<BC>();
   const int j = lo + blockIdx.x * TX + threadIdx.x;
-  const int i = lo + blockIdx.y * TY + threadIdx.y;
   double rr = 0.0, ff = 0.0;
-  if (i <= n - 2 && j <= n - 2) {
-    const double v = residual_at<double, BC>(n, u, pu, f, pf, i, j, inv_h2);
-    rr = v * v;
-    const double fv = ld(f, pf, i, j);
-    ff = fv * fv;
+  if (j <= n - 2) {
+    for (int q = 0; q < kNormRows; ++q) {
+      const int i = lo + (blockIdx.y * kNormRows + q) * TY + threadIdx.y;
+      if (i > n - 2) break;
+      const double v = residual_at<double, BC>(n, u, pu, f, pf, i, j, inv_h2);
+      rr += v * v;
+      const double fv = ld(f, pf, i, j);
+      ff += fv * fv;
+    }
   }
   const int b = blockIdx.y * gridDim.x + blockIdx.x;
   const double s = block_sum(rr, sh);
@@ -312,15 +320,22 @@ __global__ void __launch_bounds__(TX* TY)
   __shared__ double sh[TX * TY];
   constexpr int lo = first_unknown<BC>();
   const int j = lo + blockIdx.x * TX + threadIdx.x;
-  const int i = lo + blockIdx.y * TY + threadIdx.y;
-  double x = 0.0;
-  if (i <= n - 2 && j <= n - 2) x = ld(a, pa, i, j);
+  double x = 0.0, x2 = 0.0;
+  if (j <= n - 2) {
+    for (int q = 0; q < kNormRows; ++q) {
+      const int i = lo + (blockIdx.y * kNormRows + q) * TY + threadIdx.y;
+      if (i > n - 2) break;
+      const double v = ld(a, pa, i, j);
+      x += v;
+      x2 += v * v;
+    }
+  }
   const int b = blockIdx.y * gridDim.x + blockIdx.x;
   const double s = block_sum(x, sh);
   if (threadIdx.x == 0 && threadIdx.y == 0) partials[b] = s;
   if (with_sq) {
     __syncthreads();
-    const double s2 = block_sum(x * x, sh);
+    const double s2 = block_sum(x2, sh);
     if (threadIdx.x == 0 && threadIdx.y == 0) partials[gridDim.x * gridDim.y + b] = s2;
   }
 }
@@ -398,6 +413,11 @@ inline dim3 grid_unknowns(int n, int bc) {
   return dim3((m + TX - 1) / TX, (m + TY - 1) / TY);
 }
 const dim3 kBlock(TX, TY);
+// Grid of the norm kernels: kNormRows rows per thread.
+inline dim3 grid_norm(int n, int bc) {
+  const dim3 g = grid_unknowns(n, bc);
+  return dim3(g.x, (g.y + kNormRows - 1) / kNormRows);
+}
 
 template <typename T>
 constexpr double h2_of(int n) {
@@ -511,7 +531,7 @@ hipError_t launch_update_mixed(hipStream_t s, int bc, int n, double* u, int pu, 
 hipError_t launch_resnorm(hipStream_t s, int bc, int n, const double* u, int pu, const double* f,
                           int pf, double* partials, bool with_f, int* nblocks) {
   const double inv_h2 = (double)(n - 1) * (double)(n - 1);
-  const dim3 g = grid_unknowns(n, bc);
+  const dim3 g = grid_norm(n, bc);
   *nblocks = (int)(g.x * g.y);
   if (bc == kDirichlet)
     hipLaunchKernelGGL((k_resnorm<kDirichlet>), g, kBlock, 0, s, n, u, pu, f, pf, partials,
@@ -524,7 +544,7 @@ hipError_t launch_resnorm(hipStream_t s, int bc, int n, const double* u, int pu,
 
 hipError_t launch_rhs_moments(hipStream_t s, int bc, int n, const double* f, int pf,
                               double* partials, int* nblocks) {
-  const dim3 g = grid_unknowns(n, bc);
+  const dim3 g = grid_norm(n, bc);
   *nblocks = (int)(g.x * g.y);
   if (bc == kDirichlet)
     hipLaunchKernelGGL((k_moments<kDirichlet>), g, kBlock, 0, s, n, f, pf, partials, 1);
@@ -535,7 +555,7 @@ hipError_t launch_rhs_moments(hipStream_t s, int bc, int n, const double* f, int
 
 hipError_t launch_sum(hipStream_t s, int bc, int n, const double* a, int pa, double* partials,
                       int* nblocks) {
-  const dim3 g = grid_unknowns(n, bc);
+  const dim3 g = grid_norm(n, bc);
   *nblocks = (int)(g.x * g.y);
   if (bc == kDirichlet)
     hipLaunchKernelGGL((k_moments<kDirichlet>), g, kBlock, 0, s, n, a, pa, partials, 0);

@@ -13,10 +13,16 @@
 // One workgroup of 64 x 4 threads per tile of 64 columns x 16 rows: the
 // tile and a halo of 2 (source) or 1 (update) nodes of every input are
 // staged in LDS with periodic wrap, then each thread makes 4 rows of one
-// column.  Both passes are bound by HBM: algorithmic bytes per unique node
+// column (the source evaluates (u . grad) u at the four neighbours of its
+// node from LDS; forming it once per node in LDS first, behind a second
+// barrier, measured slower, and so did loading the tile row by row with the
+// halo columns as extra masked loads).  Tiles are handed out so that
+// every XCD works through one contiguous run of them in row-major order:
+// the halos that neighbouring tiles share are then hits in that XCD's L2.  Both passes are bound by HBM: algorithmic bytes per unique node
 // are 3 values (source: read u_x, u_y, write f) and 5 values (update: read
 // u_x, u_y, p, write both components).
 
+#include "mg_device.h"
 #include "mg_internal.h"
 
 namespace mg {
@@ -24,6 +30,18 @@ namespace {
 
 constexpr int kNsTX = 64, kNsTY = 4, kNsRows = 16;
 
+// Periodic index: more than one period away only on grids smaller than a
+// tile.
+__device__ __forceinline__ int ns_wrap(int i, int N) {
+  while (i < 0) i += N;
+  while (i >= N) i -= N;
+  return i;
+}
+
+// Rows i0-H .. i0+kNsRows+H-1 and columns j0-H .. j0+kNsTX+H-1 of `a`
+// (wrapped) into sh (row length kNsTX + 2H), the threads running over the
+// flattened tile so that every load instruction is a full wavefront of
+// consecutive nodes.
 template <typename T, int H>
 __device__ __forceinline__ void ns_load_tile(const T* __restrict__ a, int pa, int N, int i0,
                                              int j0, T* __restrict__ sh) {
@@ -31,12 +49,7 @@ __device__ __forceinline__ void ns_load_tile(const T* __restrict__ a, int pa, in
   const int t = threadIdx.y * kNsTX + threadIdx.x;
   for (int k = t; k < R * C; k += kNsTX * kNsTY) {
     const int r = k / C, c = k - r * C;
-    int i = i0 - H + r, j = j0 - H + c;
-    while (i < 0) i += N;  // more than one period only on grids smaller than the tile
-    while (i >= N) i -= N;
-    while (j < 0) j += N;
-    while (j >= N) j -= N;
-    sh[k] = a[(size_t)i * pa + j];
+    sh[k] = a[(size_t)ns_wrap(i0 - H + r, N) * pa + ns_wrap(j0 - H + c, N)];
   }
 }
 
@@ -62,6 +75,14 @@ __device__ __forceinline__ void ns_store(T* a, int pa, int N, int i, int j, T va
   if (i == 0 && j == 0) a[(size_t)N * pa + N] = val;
 }
 
+// Tile origin of this workgroup (XCD-contiguous row-major tile order).
+__device__ __forceinline__ void ns_tile(int N, int* i0, int* j0) {
+  const int ntx = (N + kNsTX - 1) / kNsTX;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  *i0 = (t / ntx) * kNsRows;
+  *j0 = (t % ntx) * kNsTX;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kNsTX* kNsTY)
     k_ns_rhs(int N, const T* __restrict__ ux, const T* __restrict__ uy, int pu, T* __restrict__ f,
@@ -69,7 +90,8 @@ __global__ void __launch_bounds__(kNsTX* kNsTY)
 #pragma clang fp contract(off)
   constexpr int H = 2, C = kNsTX + 2 * H, R = kNsRows + 2 * H;
   __shared__ T su[R * C], sv[R * C];
-  const int i0 = blockIdx.y * kNsRows, j0 = blockIdx.x * kNsTX;
+  int i0, j0;
+  ns_tile(N, &i0, &j0);
   ns_load_tile<T, H>(ux, pu, N, i0, j0, su);
   ns_load_tile<T, H>(uy, pu, N, i0, j0, sv);
   __syncthreads();
@@ -97,7 +119,8 @@ __global__ void __launch_bounds__(kNsTX* kNsTY)
 #pragma clang fp contract(off)
   constexpr int H = 1, C = kNsTX + 2 * H, R = kNsRows + 2 * H;
   __shared__ T su[R * C], sv[R * C], sp[R * C];
-  const int i0 = blockIdx.y * kNsRows, j0 = blockIdx.x * kNsTX;
+  int i0, j0;
+  ns_tile(N, &i0, &j0);
   ns_load_tile<T, H>(ux, pu, N, i0, j0, su);
   ns_load_tile<T, H>(uy, pu, N, i0, j0, sv);
   ns_load_tile<T, H>(p, pu, N, i0, j0, sp);
@@ -117,7 +140,9 @@ __global__ void __launch_bounds__(kNsTX* kNsTY)
   }
 }
 
-dim3 ns_grid(int N) { return dim3((N + kNsTX - 1) / kNsTX, (N + kNsRows - 1) / kNsRows); }
+dim3 ns_grid(int N) {
+  return dim3(((N + kNsTX - 1) / kNsTX) * ((N + kNsRows - 1) / kNsRows));
+}
 
 }  // namespace
 

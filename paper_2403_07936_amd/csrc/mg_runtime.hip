@@ -1620,7 +1620,9 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
     MG_TRY(persistent_relres(ctx, rel.data()));
   } else if (mixed_chk) {
     for (int b = 0; b < B; ++b) {
-      MG_TRY(enqueue_fnorm(ctx, ctx->probs[b], f[b]));
+      // Periodic problems: the right-hand-side check above left ||f||^2 in
+      // p.sums[1] already (the same kernel and reduction).
+      if (ctx->probs[b].bc != kPeriodic) MG_TRY(enqueue_fnorm(ctx, ctx->probs[b], f[b]));
       MG_TRY(enqueue_check_mixed(ctx, ctx->probs[b], u[b], f[b]));
       have_res[b] = 1;
     }
