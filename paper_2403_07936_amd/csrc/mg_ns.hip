@@ -10,10 +10,10 @@
 // are exact and, with contraction off, each result is rounded exactly as
 // the plain expression in the order written.
 //
-// One workgroup of 64 x 4 threads per tile of 64 columns x 16 rows: the
-// tile and a halo of 2 (source) or 1 (update) nodes of every input are
-// staged in LDS with periodic wrap, then each thread makes 4 rows of one
-// column (the source evaluates (u . grad) u at the four neighbours of its
+// One workgroup of 64 x 4 threads per tile of 64 columns x 16 (source) or
+// 8 (update) rows: the tile and a halo of 2 (source) or 1 (update) nodes of
+// every input are staged in LDS with periodic wrap, then each thread makes
+// 4 (2) rows of one column (the source evaluates (u . grad) u at the four neighbours of its
 // node from LDS; forming it once per node in LDS first, behind a second
 // barrier, measured slower, and so did loading the tile row by row with the
 // halo columns as extra masked loads).  Tiles are handed out so that
@@ -28,7 +28,10 @@
 namespace mg {
 namespace {
 
-constexpr int kNsTX = 64, kNsTY = 4, kNsRows = 16;
+constexpr int kNsTX = 64, kNsTY = 4;
+// Tile rows: 16 for the source (halo 2), 8 for the update (halo 1, three
+// inputs), the faster of 8, 16 and 32 for each on 4097^2.
+constexpr int kRowsRhs = 16, kRowsUpd = 8;
 
 // Periodic index: more than one period away only on grids smaller than a
 // tile.
@@ -38,14 +41,14 @@ __device__ __forceinline__ int ns_wrap(int i, int N) {
   return i;
 }
 
-// Rows i0-H .. i0+kNsRows+H-1 and columns j0-H .. j0+kNsTX+H-1 of `a`
+// Rows i0-H .. i0+ROWS+H-1 and columns j0-H .. j0+kNsTX+H-1 of `a`
 // (wrapped) into sh (row length kNsTX + 2H), the threads running over the
 // flattened tile so that every load instruction is a full wavefront of
 // consecutive nodes.
-template <typename T, int H>
+template <typename T, int H, int ROWS>
 __device__ __forceinline__ void ns_load_tile(const T* __restrict__ a, int pa, int N, int i0,
                                              int j0, T* __restrict__ sh) {
-  constexpr int C = kNsTX + 2 * H, R = kNsRows + 2 * H;
+  constexpr int C = kNsTX + 2 * H, R = ROWS + 2 * H;
   const int t = threadIdx.y * kNsTX + threadIdx.x;
   for (int k = t; k < R * C; k += kNsTX * kNsTY) {
     const int r = k / C, c = k - r * C;
@@ -76,10 +79,11 @@ __device__ __forceinline__ void ns_store(T* a, int pa, int N, int i, int j, T va
 }
 
 // Tile origin of this workgroup (XCD-contiguous row-major tile order).
+template <int ROWS>
 __device__ __forceinline__ void ns_tile(int N, int* i0, int* j0) {
   const int ntx = (N + kNsTX - 1) / kNsTX;
   const int t = xcd_tile(blockIdx.x, gridDim.x);
-  *i0 = (t / ntx) * kNsRows;
+  *i0 = (t / ntx) * ROWS;
   *j0 = (t % ntx) * kNsTX;
 }
 
@@ -88,17 +92,17 @@ __global__ void __launch_bounds__(kNsTX* kNsTY)
     k_ns_rhs(int N, const T* __restrict__ ux, const T* __restrict__ uy, int pu, T* __restrict__ f,
              T inv2h) {
 #pragma clang fp contract(off)
-  constexpr int H = 2, C = kNsTX + 2 * H, R = kNsRows + 2 * H;
+  constexpr int H = 2, C = kNsTX + 2 * H, R = kRowsRhs + 2 * H;
   __shared__ T su[R * C], sv[R * C];
   int i0, j0;
-  ns_tile(N, &i0, &j0);
-  ns_load_tile<T, H>(ux, pu, N, i0, j0, su);
-  ns_load_tile<T, H>(uy, pu, N, i0, j0, sv);
+  ns_tile<kRowsRhs>(N, &i0, &j0);
+  ns_load_tile<T, H, kRowsRhs>(ux, pu, N, i0, j0, su);
+  ns_load_tile<T, H, kRowsRhs>(uy, pu, N, i0, j0, sv);
   __syncthreads();
   const int j = j0 + threadIdx.x, c = threadIdx.x + H;
   if (j >= N) return;
 #pragma unroll
-  for (int q = 0; q < kNsRows / kNsTY; ++q) {
+  for (int q = 0; q < kRowsRhs / kNsTY; ++q) {
     const int rl = threadIdx.y + q * kNsTY, i = i0 + rl, r = rl + H;
     if (i >= N) break;
     T cxe, cye, cxw, cyw, cxn, cyn, cxs, cys;
@@ -117,18 +121,18 @@ __global__ void __launch_bounds__(kNsTX* kNsTY)
                 const T* __restrict__ p, int pu, T dt, T* __restrict__ ox, T* __restrict__ oy,
                 T inv2h) {
 #pragma clang fp contract(off)
-  constexpr int H = 1, C = kNsTX + 2 * H, R = kNsRows + 2 * H;
+  constexpr int H = 1, C = kNsTX + 2 * H, R = kRowsUpd + 2 * H;
   __shared__ T su[R * C], sv[R * C], sp[R * C];
   int i0, j0;
-  ns_tile(N, &i0, &j0);
-  ns_load_tile<T, H>(ux, pu, N, i0, j0, su);
-  ns_load_tile<T, H>(uy, pu, N, i0, j0, sv);
-  ns_load_tile<T, H>(p, pu, N, i0, j0, sp);
+  ns_tile<kRowsUpd>(N, &i0, &j0);
+  ns_load_tile<T, H, kRowsUpd>(ux, pu, N, i0, j0, su);
+  ns_load_tile<T, H, kRowsUpd>(uy, pu, N, i0, j0, sv);
+  ns_load_tile<T, H, kRowsUpd>(p, pu, N, i0, j0, sp);
   __syncthreads();
   const int j = j0 + threadIdx.x, c = threadIdx.x + H;
   if (j >= N) return;
 #pragma unroll
-  for (int q = 0; q < kNsRows / kNsTY; ++q) {
+  for (int q = 0; q < kRowsUpd / kNsTY; ++q) {
     const int rl = threadIdx.y + q * kNsTY, i = i0 + rl, r = rl + H;
     if (i >= N) break;
     T cx, cy;
@@ -140,16 +144,14 @@ __global__ void __launch_bounds__(kNsTX* kNsTY)
   }
 }
 
-dim3 ns_grid(int N) {
-  return dim3(((N + kNsTX - 1) / kNsTX) * ((N + kNsRows - 1) / kNsRows));
-}
+dim3 ns_grid(int N, int rows) { return dim3(((N + kNsTX - 1) / kNsTX) * ((N + rows - 1) / rows)); }
 
 }  // namespace
 
 template <typename T>
 hipError_t launch_ns_rhs(hipStream_t s, int n, const T* ux, const T* uy, T* f, int pitch) {
   const int N = n - 1;
-  hipLaunchKernelGGL(k_ns_rhs<T>, ns_grid(N), dim3(kNsTX, kNsTY), 0, s, N, ux, uy, pitch, f,
+  hipLaunchKernelGGL(k_ns_rhs<T>, ns_grid(N, kRowsRhs), dim3(kNsTX, kNsTY), 0, s, N, ux, uy, pitch, f,
                      (T)(0.5 * N));
   return hipGetLastError();
 }
@@ -158,7 +160,7 @@ template <typename T>
 hipError_t launch_ns_update(hipStream_t s, int n, const T* ux, const T* uy, const T* p, double dt,
                             T* ox, T* oy, int pitch) {
   const int N = n - 1;
-  hipLaunchKernelGGL(k_ns_update<T>, ns_grid(N), dim3(kNsTX, kNsTY), 0, s, N, ux, uy, p, pitch,
+  hipLaunchKernelGGL(k_ns_update<T>, ns_grid(N, kRowsUpd), dim3(kNsTX, kNsTY), 0, s, N, ux, uy, p, pitch,
                      (T)dt, ox, oy, (T)(0.5 * N));
   return hipGetLastError();
 }
