@@ -10,17 +10,19 @@
 // are exact and, with contraction off, each result is rounded exactly as
 // the plain expression in the order written.
 //
-// One workgroup of 64 x 4 threads per tile of 64 columns x 16 (source) or
-// 8 (update) rows: the tile and a halo of 2 (source) or 1 (update) nodes of
-// every input are staged in LDS with periodic wrap, then each thread makes
-// 4 (2) rows of one column (the source evaluates (u . grad) u at the four neighbours of its
-// node from LDS; forming it once per node in LDS first, behind a second
-// barrier, measured slower, and so did loading the tile row by row with the
-// halo columns as extra masked loads).  Tiles are handed out so that
-// every XCD works through one contiguous run of them in row-major order:
-// the halos that neighbouring tiles share are then hits in that XCD's L2.  Both passes are bound by HBM: algorithmic bytes per unique node
-// are 3 values (source: read u_x, u_y, write f) and 5 values (update: read
-// u_x, u_y, p, write both components).
+// Workgroups of 64 x 4 threads work on tiles of 64 columns x 16 (source) or
+// 8 (update) rows.  The tile and a halo of 2 (source) or 1 (update) nodes of
+// every input are staged in LDS with periodic wrap; each thread then makes
+// 4 (2) rows of one column.  The source evaluates (u . grad) u at the four
+// neighbours of its node from LDS, and each of its workgroups walks a
+// contiguous run of tiles with the next tile's loads in flight; the update
+// takes one tile per workgroup.  Tried and slower: forming (u . grad) u once
+// per node in LDS behind a second barrier, and loading the tile row by row
+// with the halo columns as extra masked loads.  Every XCD works through one
+// contiguous run of tiles in row-major order, so the halos that neighbouring
+// tiles share are hits in that XCD's L2.  Both passes are bound by HBM:
+// algorithmic bytes per unique node are 3 values (source: read u_x, u_y,
+// write f) and 5 values (update: read u_x, u_y, p, write both components).
 
 #include "mg_device.h"
 #include "mg_internal.h"
@@ -32,6 +34,8 @@ constexpr int kNsTX = 64, kNsTY = 4;
 // Tile rows: 16 for the source (halo 2), 8 for the update (halo 1, three
 // inputs), the faster of 8, 16 and 32 for each on 4097^2.
 constexpr int kRowsRhs = 16, kRowsUpd = 8;
+// Workgroups of the source's tile walk (16 per CU).
+constexpr int kRhsGroups = 4096;
 
 // Periodic index: more than one period away only on grids smaller than a
 // tile.
@@ -87,34 +91,90 @@ __device__ __forceinline__ void ns_tile(int N, int* i0, int* j0) {
   *j0 = (t % ntx) * kNsTX;
 }
 
+// Registers holding one thread's share of a tile and halo (the flattened
+// tile order of ns_load_tile), so that the next tile's loads are in flight
+// while the current one is computed.
+template <typename T, int H, int ROWS>
+struct NsPrefetch {
+  static constexpr int C = kNsTX + 2 * H, R = ROWS + 2 * H, E = R * C;
+  static constexpr int NT = kNsTX * kNsTY, PER = (E + NT - 1) / NT;
+  T v[PER];
+  __device__ __forceinline__ void load(const T* __restrict__ a, int pa, int N, int i0, int j0) {
+    const int t = threadIdx.y * kNsTX + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = t + q * NT;
+      if (k < E) {
+        const int r = k / C, c = k - r * C;
+        v[q] = a[(size_t)ns_wrap(i0 - H + r, N) * pa + ns_wrap(j0 - H + c, N)];
+      }
+    }
+  }
+  __device__ __forceinline__ void store(T* __restrict__ sh) const {
+    const int t = threadIdx.y * kNsTX + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = t + q * NT;
+      if (k < E) sh[k] = v[q];
+    }
+  }
+};
+
+// Origin of tile t in row-major tile order.
+template <int ROWS>
+__device__ __forceinline__ void ns_origin(int t, int N, int* i0, int* j0) {
+  const int ntx = (N + kNsTX - 1) / kNsTX;
+  *i0 = (t / ntx) * ROWS;
+  *j0 = (t % ntx) * kNsTX;
+}
+
+// The source walks a contiguous run of tiles per workgroup (XCD-contiguous
+// runs), loading the next tile into registers while it computes the
+// current one.
 template <typename T>
 __global__ void __launch_bounds__(kNsTX* kNsTY)
     k_ns_rhs(int N, const T* __restrict__ ux, const T* __restrict__ uy, int pu, T* __restrict__ f,
-             T inv2h) {
+               T inv2h, int ntiles) {
 #pragma clang fp contract(off)
   constexpr int H = 2, C = kNsTX + 2 * H, R = kRowsRhs + 2 * H;
   __shared__ T su[R * C], sv[R * C];
-  int i0, j0;
-  ns_tile<kRowsRhs>(N, &i0, &j0);
-  ns_load_tile<T, H, kRowsRhs>(ux, pu, N, i0, j0, su);
-  ns_load_tile<T, H, kRowsRhs>(uy, pu, N, i0, j0, sv);
-  __syncthreads();
-  const int j = j0 + threadIdx.x, c = threadIdx.x + H;
-  if (j >= N) return;
+  const int w = xcd_tile(blockIdx.x, gridDim.x);
+  const int tb = (int)((long long)w * ntiles / gridDim.x);
+  const int te = (int)((long long)(w + 1) * ntiles / gridDim.x);
+  NsPrefetch<T, H, kRowsRhs> fu, fv;
+  int i0 = 0, j0 = 0;
+  if (tb < te) {
+    ns_origin<kRowsRhs>(tb, N, &i0, &j0);
+    fu.load(ux, pu, N, i0, j0);
+    fv.load(uy, pu, N, i0, j0);
+  }
+  for (int t = tb; t < te; ++t) {
+    __syncthreads();
+    fu.store(su); fv.store(sv);
+    __syncthreads();
+    const int ci0 = i0, cj0 = j0;
+    if (t + 1 < te) {
+      ns_origin<kRowsRhs>(t + 1, N, &i0, &j0);
+      fu.load(ux, pu, N, i0, j0);
+      fv.load(uy, pu, N, i0, j0);
+    }
+    const int j = cj0 + threadIdx.x, c = threadIdx.x + H;
+    if (j < N) {
 #pragma unroll
-  for (int q = 0; q < kRowsRhs / kNsTY; ++q) {
-    const int rl = threadIdx.y + q * kNsTY, i = i0 + rl, r = rl + H;
-    if (i >= N) break;
-    T cxe, cye, cxw, cyw, cxn, cyn, cxs, cys;
-    ns_convection<T, C>(su, sv, r, c + 1, inv2h, &cxe, &cye);
-    ns_convection<T, C>(su, sv, r, c - 1, inv2h, &cxw, &cyw);
-    ns_convection<T, C>(su, sv, r + 1, c, inv2h, &cxn, &cyn);
-    ns_convection<T, C>(su, sv, r - 1, c, inv2h, &cxs, &cys);
-    const T val = -((cxe - cxw) * inv2h + (cyn - cys) * inv2h);
-    ns_store(f, pu, N, i, j, val);
+      for (int q = 0; q < kRowsRhs / kNsTY; ++q) {
+        const int rl = threadIdx.y + q * kNsTY, i = ci0 + rl, r = rl + H;
+        if (i < N) {
+          T cxe, cye, cxw, cyw, cxn, cyn, cxs, cys;
+          ns_convection<T, C>(su, sv, r, c + 1, inv2h, &cxe, &cye);
+          ns_convection<T, C>(su, sv, r, c - 1, inv2h, &cxw, &cyw);
+          ns_convection<T, C>(su, sv, r + 1, c, inv2h, &cxn, &cyn);
+          ns_convection<T, C>(su, sv, r - 1, c, inv2h, &cxs, &cys);
+          ns_store(f, pu, N, i, j, -((cxe - cxw) * inv2h + (cyn - cys) * inv2h));
+        }
+      }
+    }
   }
 }
-
 template <typename T>
 __global__ void __launch_bounds__(kNsTX* kNsTY)
     k_ns_update(int N, const T* __restrict__ ux, const T* __restrict__ uy,
@@ -151,8 +211,9 @@ dim3 ns_grid(int N, int rows) { return dim3(((N + kNsTX - 1) / kNsTX) * ((N + ro
 template <typename T>
 hipError_t launch_ns_rhs(hipStream_t s, int n, const T* ux, const T* uy, T* f, int pitch) {
   const int N = n - 1;
-  hipLaunchKernelGGL(k_ns_rhs<T>, ns_grid(N, kRowsRhs), dim3(kNsTX, kNsTY), 0, s, N, ux, uy, pitch, f,
-                     (T)(0.5 * N));
+  const int ntiles = (int)ns_grid(N, kRowsRhs).x;
+  hipLaunchKernelGGL(k_ns_rhs<T>, dim3(std::min(ntiles, kRhsGroups)), dim3(kNsTX, kNsTY), 0, s, N,
+                     ux, uy, pitch, f, (T)(0.5 * N), ntiles);
   return hipGetLastError();
 }
 
