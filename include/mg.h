@@ -212,11 +212,17 @@ MG_API int32_t mg_prolong(mg_ctx ctx, int32_t problem, int32_t coarse_level, int
  * columns, y along the rows).  Every derivative is the second-order central
  * difference of the nodal values, (a[j+1] - a[j-1]) / (2h).
  *   mg_ns_rhs:    f = -div((u . grad) u), the source of the pressure-Poisson
- *                 equation (mean zero up to rounding); seam written.
+ *                 equation Laplacian p = f (mean zero up to rounding); seam
+ *                 written.
  *   mg_ns_update: (ux_out, uy_out) = u - dt ((u . grad) u + grad p), one
  *                 explicit Euler step of the momentum equation; seams
- *                 written.  The outputs must not alias the inputs or each
- *                 other.
+ *                 written.  The pressure is passed as q, the solution that
+ *                 mg_solve returns for the source f of mg_ns_rhs: mg_solve
+ *                 solves -Laplacian_h q = f, so q = -p, and the step is
+ *                 evaluated as u - dt ((u . grad) u - grad q).  A time step
+ *                 is therefore mg_ns_rhs -> mg_solve -> mg_ns_update with
+ *                 the solver's output handed over unchanged.  The outputs
+ *                 must not alias the inputs or each other.
  * All arrays are device arrays of dtype MG_DT_F64 or MG_DT_F32 with row
  * pitch `pitch` (>= n) elements, owned by the caller; only the unique nodes
  * of the inputs are read.  Asynchronous on hip_stream (NULL: the null
@@ -224,7 +230,7 @@ MG_API int32_t mg_prolong(mg_ctx ctx, int32_t problem, int32_t coarse_level, int
  * NULL or aliased arrays, non-finite dt), HIP. */
 MG_API int32_t mg_ns_rhs(int32_t n, const void* ux, const void* uy, void* f, int32_t pitch,
                   int32_t dtype, void* hip_stream);
-MG_API int32_t mg_ns_update(int32_t n, const void* ux, const void* uy, const void* p, double dt,
+MG_API int32_t mg_ns_update(int32_t n, const void* ux, const void* uy, const void* q, double dt,
                      void* ux_out, void* uy_out, int32_t pitch, int32_t dtype,
                      void* hip_stream);
 

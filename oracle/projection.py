@@ -10,7 +10,11 @@ nodes 0 .. n-2, spacing h = 1/(n-1), x along the columns, y along the rows):
     (Section 2.3, Eq. for f(x, y); the second line of the momentum system in
     Section 2.1): f = -div((u . grad) u);
   * the explicit Euler step of the momentum equation (first line of that
-    system): u <- u - dt ((u . grad) u + grad p).
+    system): u <- u - dt ((u . grad) u + grad p);
+  * the time step that chains them around the pressure solve: the source,
+    then p from Laplacian p = f, then the velocity step.  The Poisson solver
+    here (as in the library) solves A q = f with A = -Laplacian_h, so the
+    pressure of the momentum equation is p = -q.
 
 Readings (the paper gives neither discretisation): every derivative is the
 second-order central difference d/dx a[i, j] = (a[i, j+1] - a[i, j-1]) / (2h)
@@ -67,3 +71,14 @@ def ns_update(ux: np.ndarray, uy: np.ndarray, p: np.ndarray, dt: float):
     U, V, P = _unique(ux), _unique(uy), _unique(p)
     cx, cy = convection(U, V, h)
     return (_with_seam(U - dt * (cx + ddx(P, h))), _with_seam(V - dt * (cy + ddy(P, h))))
+
+
+def time_step(ux: np.ndarray, uy: np.ndarray, dt: float, solve):
+    """One projection time step (Section 2.1's system with Section 2.3's
+    source): f = -div((u . grad) u); q = solve(f), the solution of
+    -Laplacian_h q = f; p = -q, so that Laplacian_h p = f; then the
+    explicit Euler step with grad p.  Returns (u_x, u_y, p)."""
+    f = ns_rhs(ux, uy)
+    p = -np.asarray(solve(f), dtype=np.float64)
+    vx, vy = ns_update(ux, uy, p, dt)
+    return vx, vy, p

@@ -187,9 +187,10 @@ def mg_ns_rhs(n: int, ux: int, uy: int, f: int, pitch: int, dtype: int, stream: 
     _check(lib().mg_ns_rhs(n, vp(ux), vp(uy), vp(f), pitch, dtype, vp(stream or None)))
 
 
-def mg_ns_update(n: int, ux: int, uy: int, p: int, dt: float, ux_out: int, uy_out: int,
+def mg_ns_update(n: int, ux: int, uy: int, q: int, dt: float, ux_out: int, uy_out: int,
                  pitch: int, dtype: int, stream: int = 0) -> None:
-    _check(lib().mg_ns_update(n, vp(ux), vp(uy), vp(p), float(dt), vp(ux_out), vp(uy_out), pitch,
+    """q is mg_solve's solution for mg_ns_rhs's source (q = -p)."""
+    _check(lib().mg_ns_update(n, vp(ux), vp(uy), vp(q), float(dt), vp(ux_out), vp(uy_out), pitch,
                               dtype, vp(stream or None)))
 
 

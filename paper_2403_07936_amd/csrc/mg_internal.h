@@ -100,11 +100,12 @@ hipError_t launch_diffnorm(hipStream_t s, int bc, int n, const double* u, int pu
                            int pp, double* partials, int* nblocks);
 // Pressure-projection steps on a periodic n x n grid with seam, arrays of
 // row pitch `pitch`: f = -div((u . grad) u), and (ox, oy) = u - dt ((u .
-// grad) u + grad p) (outputs distinct from the inputs).
+// grad) u - grad q) with q = -p the Poisson solve's solution for f
+// (outputs distinct from the inputs).
 template <typename T>
 hipError_t launch_ns_rhs(hipStream_t s, int n, const T* ux, const T* uy, T* f, int pitch);
 template <typename T>
-hipError_t launch_ns_update(hipStream_t s, int n, const T* ux, const T* uy, const T* p, double dt,
+hipError_t launch_ns_update(hipStream_t s, int n, const T* ux, const T* uy, const T* q, double dt,
                             T* ox, T* oy, int pitch);
 // out[k] = sum of partials[k * stride + 0 .. count) for k < groups, in a
 // fixed order (single workgroup per group).

@@ -4,7 +4,10 @@
 //   * the source of the pressure-Poisson equation with zero viscosity
 //     (Section 2.3, Eq. for f(x, y)): f = -div((u . grad) u);
 //   * the explicit Euler step of the momentum equation (Section 2.1, first
-//     line of the system): u <- u - dt ((u . grad) u + grad p).
+//     line of the system): u <- u - dt ((u . grad) u + grad p).  The pressure
+//     arrives as the Poisson solve returns it for that source, q = -p (the
+//     solver's operator is the negative Laplacian), so the step evaluates
+//     u - dt ((u . grad) u - grad q), bitwise the same as with p = -q.
 // Every derivative is the central difference (a[j+1] - a[j-1]) / (2h) of the
 // nodal values; 1 / (2h) = N / 2 is a power of two, so the products by it
 // are exact and, with contraction off, each result is rounded exactly as
@@ -22,7 +25,7 @@
 // contiguous run of tiles in row-major order, so the halos that neighbouring
 // tiles share are hits in that XCD's L2.  Both passes are bound by HBM:
 // algorithmic bytes per unique node are 3 values (source: read u_x, u_y,
-// write f) and 5 values (update: read u_x, u_y, p, write both components).
+// write f) and 5 values (update: read u_x, u_y, q, write both components).
 
 #include "mg_device.h"
 #include "mg_internal.h"
@@ -178,16 +181,16 @@ __global__ void __launch_bounds__(kNsTX* kNsTY)
 template <typename T>
 __global__ void __launch_bounds__(kNsTX* kNsTY)
     k_ns_update(int N, const T* __restrict__ ux, const T* __restrict__ uy,
-                const T* __restrict__ p, int pu, T dt, T* __restrict__ ox, T* __restrict__ oy,
+                const T* __restrict__ q, int pu, T dt, T* __restrict__ ox, T* __restrict__ oy,
                 T inv2h) {
 #pragma clang fp contract(off)
   constexpr int H = 1, C = kNsTX + 2 * H, R = kRowsUpd + 2 * H;
-  __shared__ T su[R * C], sv[R * C], sp[R * C];
+  __shared__ T su[R * C], sv[R * C], sq[R * C];
   int i0, j0;
   ns_tile<kRowsUpd>(N, &i0, &j0);
   ns_load_tile<T, H, kRowsUpd>(ux, pu, N, i0, j0, su);
   ns_load_tile<T, H, kRowsUpd>(uy, pu, N, i0, j0, sv);
-  ns_load_tile<T, H, kRowsUpd>(p, pu, N, i0, j0, sp);
+  ns_load_tile<T, H, kRowsUpd>(q, pu, N, i0, j0, sq);
   __syncthreads();
   const int j = j0 + threadIdx.x, c = threadIdx.x + H;
   if (j >= N) return;
@@ -198,9 +201,10 @@ __global__ void __launch_bounds__(kNsTX* kNsTY)
     T cx, cy;
     ns_convection<T, C>(su, sv, r, c, inv2h, &cx, &cy);
     const int k = r * C + c;
-    const T px = (sp[k + 1] - sp[k - 1]) * inv2h, py = (sp[k + C] - sp[k - C]) * inv2h;
-    ns_store(ox, pu, N, i, j, su[k] - dt * (cx + px));
-    ns_store(oy, pu, N, i, j, sv[k] - dt * (cy + py));
+    // grad q = -grad p exactly, and c - g equals c + (-g) bit for bit.
+    const T qx = (sq[k + 1] - sq[k - 1]) * inv2h, qy = (sq[k + C] - sq[k - C]) * inv2h;
+    ns_store(ox, pu, N, i, j, su[k] - dt * (cx - qx));
+    ns_store(oy, pu, N, i, j, sv[k] - dt * (cy - qy));
   }
 }
 
@@ -218,10 +222,10 @@ hipError_t launch_ns_rhs(hipStream_t s, int n, const T* ux, const T* uy, T* f, i
 }
 
 template <typename T>
-hipError_t launch_ns_update(hipStream_t s, int n, const T* ux, const T* uy, const T* p, double dt,
+hipError_t launch_ns_update(hipStream_t s, int n, const T* ux, const T* uy, const T* q, double dt,
                             T* ox, T* oy, int pitch) {
   const int N = n - 1;
-  hipLaunchKernelGGL(k_ns_update<T>, ns_grid(N, kRowsUpd), dim3(kNsTX, kNsTY), 0, s, N, ux, uy, p, pitch,
+  hipLaunchKernelGGL(k_ns_update<T>, ns_grid(N, kRowsUpd), dim3(kNsTX, kNsTY), 0, s, N, ux, uy, q, pitch,
                      (T)dt, ox, oy, (T)(0.5 * N));
   return hipGetLastError();
 }

@@ -2005,20 +2005,20 @@ int32_t mg_ns_rhs(int32_t n, const void* ux, const void* uy, void* f, int32_t pi
            return MG_OK;)
 }
 
-int32_t mg_ns_update(int32_t n, const void* ux, const void* uy, const void* p, double dt,
+int32_t mg_ns_update(int32_t n, const void* ux, const void* uy, const void* q, double dt,
                      void* ux_out, void* uy_out, int32_t pitch, int32_t dtype, void* hip_stream) {
   g_last_error.clear();
-  MG_GUARD(MG_TRY(ns_check(n, pitch, dtype, {ux, uy, p}, {ux_out, uy_out}));
+  MG_GUARD(MG_TRY(ns_check(n, pitch, dtype, {ux, uy, q}, {ux_out, uy_out}));
            if (ux_out == uy_out) return fail(MG_ERR_INVALID_ARG, "ux_out == uy_out");
            if (!std::isfinite(dt)) return fail(MG_ERR_INVALID_ARG, "dt is not finite");
            const hipStream_t s = static_cast<hipStream_t>(hip_stream);
            if (dtype == MG_DT_F64) MG_HIP(launch_ns_update<double>(
                s, n, static_cast<const double*>(ux), static_cast<const double*>(uy),
-               static_cast<const double*>(p), dt, static_cast<double*>(ux_out),
+               static_cast<const double*>(q), dt, static_cast<double*>(ux_out),
                static_cast<double*>(uy_out), pitch));
            else MG_HIP(launch_ns_update<float>(
                s, n, static_cast<const float*>(ux), static_cast<const float*>(uy),
-               static_cast<const float*>(p), dt, static_cast<float*>(ux_out),
+               static_cast<const float*>(q), dt, static_cast<float*>(ux_out),
                static_cast<float*>(uy_out), pitch));
            return MG_OK;)
 }

@@ -1,6 +1,11 @@
 """GPU parity of the pressure-projection steps (mg_ns_rhs, mg_ns_update)
 against the oracle (oracle/projection.py), through the C ABI.
 
+mg_ns_update takes the Poisson solve's output q = -p (the library solves
+-Laplacian_h q = f); the oracle's update takes the paper's p, so every
+comparison hands the oracle p = -q (negation is exact, so FP64 stays
+bit-exact).
+
 Tolerances: FP64 bit-exact (the kernels evaluate the same expressions in the
 same order without contraction, and 1/(2h) is a power of two); FP32 against
 the FP64 oracle on the FP32-rounded inputs within 1e-5 of the largest
@@ -59,10 +64,11 @@ def gpu_rhs(B, dev, ux, uy, pitch, dt_):
     return out[:, :n]
 
 
-def gpu_update(B, dev, ux, uy, p, dt, pitch, dt_):
+def gpu_update(B, dev, ux, uy, q, dt, pitch, dt_):
+    """mg_ns_update with the solver-sign pressure q (= -p)."""
     tdt = torch.float64 if dt_ == F64 else torch.float32
     n = ux.shape[0]
-    a, b, q = (padded(x, pitch, dev, tdt) for x in (ux, uy, p))
+    a, b, q = (padded(x, pitch, dev, tdt) for x in (ux, uy, q))
     ox = torch.full((n, pitch), 7.0, dtype=tdt, device=dev)
     oy = torch.full((n, pitch), 7.0, dtype=tdt, device=dev)
     B.mg_ns_update(n, a.data_ptr(), b.data_ptr(), q.data_ptr(), dt, ox.data_ptr(), oy.data_ptr(),
@@ -86,9 +92,9 @@ def test_rhs_bit_exact_fp64(B, dev, n, pad):
 @pytest.mark.parametrize("n,pad", CASES)
 def test_update_bit_exact_fp64(B, dev, n, pad):
     ux, uy = workloads.velocity_periodic(n, 12)
-    p = workloads.rhs_divu_periodic(n, 13) * 1e-3
-    gx, gy = gpu_update(B, dev, ux, uy, p, 1e-3, n + pad, F64)
-    wx, wy = pj.ns_update(ux, uy, p, 1e-3)
+    q = workloads.rhs_divu_periodic(n, 13) * 1e-3
+    gx, gy = gpu_update(B, dev, ux, uy, q, 1e-3, n + pad, F64)
+    wx, wy = pj.ns_update(ux, uy, -q, 1e-3)
     say(f"ns_update n={n}: max |diff| {max(np.abs(gx - wx).max(), np.abs(gy - wy).max()):.3e}")
     np.testing.assert_array_equal(gx, wx)
     np.testing.assert_array_equal(gy, wy)
@@ -97,8 +103,8 @@ def test_update_bit_exact_fp64(B, dev, n, pad):
 @pytest.mark.parametrize("n", [17, 257])
 def test_fp32_within_rounding(B, dev, n):
     ux, uy = workloads.velocity_periodic(n, 14)
-    p = workloads.rhs_divu_periodic(n, 15) * 1e-3
-    r32 = [x.astype(np.float32).astype(np.float64) for x in (ux, uy, p)]
+    q = workloads.rhs_divu_periodic(n, 15) * 1e-3
+    r32 = [x.astype(np.float32).astype(np.float64) for x in (ux, uy, q)]
     h = 1.0 / (n - 1)
     cx, cy = pj.convection(r32[0][:-1, :-1], r32[1][:-1, :-1], h)
     scale = (np.abs(cx).max() + np.abs(cy).max()) / (2 * h)
@@ -108,9 +114,9 @@ def test_fp32_within_rounding(B, dev, n):
     say(f"ns_rhs fp32 n={n}: max err {err:.3e} of scale {scale:.3e}")
     assert err <= 1e-5 * scale
     dt = 1e-3
-    gx, gy = gpu_update(B, dev, ux, uy, p, dt, n, F32)
-    wx, wy = pj.ns_update(r32[0], r32[1], r32[2], dt)
-    sc = 1.0 + dt * (np.abs(cx).max() + np.abs(cy).max() + np.abs(p).max() / h)
+    gx, gy = gpu_update(B, dev, ux, uy, q, dt, n, F32)
+    wx, wy = pj.ns_update(r32[0], r32[1], -r32[2], dt)
+    sc = 1.0 + dt * (np.abs(cx).max() + np.abs(cy).max() + np.abs(q).max() / h)
     err = max(np.abs(gx - wx).max(), np.abs(gy - wy).max())
     say(f"ns_update fp32 n={n}: max err {err:.3e} of scale {sc:.3e}")
     assert err <= 1e-6 * sc
@@ -122,16 +128,18 @@ def test_full_size_fp64_bit_exact(B, dev):
     ux, uy = workloads.velocity_periodic(n, 16)
     got = gpu_rhs(B, dev, ux, uy, n, F64)
     np.testing.assert_array_equal(got, pj.ns_rhs(ux, uy))
-    p = workloads.rhs_divu_periodic(n, 17) * 1e-3
-    gx, gy = gpu_update(B, dev, ux, uy, p, 1e-4, n, F64)
-    wx, wy = pj.ns_update(ux, uy, p, 1e-4)
+    q = workloads.rhs_divu_periodic(n, 17) * 1e-3
+    gx, gy = gpu_update(B, dev, ux, uy, q, 1e-4, n, F64)
+    wx, wy = pj.ns_update(ux, uy, -q, 1e-4)
     np.testing.assert_array_equal(gx, wx)
     np.testing.assert_array_equal(gy, wy)
 
 
 def test_time_step_with_solve_matches_oracle(B, dev):
-    """Source, pressure solve to 1e-12 and velocity step on the GPU against
-    the same three steps with the oracle."""
+    """Source, pressure solve to 1e-12 and velocity step on the GPU (the
+    solver's output handed to mg_ns_update unchanged) against the oracle's
+    time step, which takes p = -q; plus the physics: on a steady
+    Taylor-Green flow the same GPU chain changes u only by O(h^2)."""
     n, dt = 257, 1e-3
     ux, uy = workloads.velocity_periodic(n, 18)
     a, b = padded(ux, n, dev, torch.float64), padded(uy, n, dev, torch.float64)
@@ -149,9 +157,8 @@ def test_time_step_with_solve_matches_oracle(B, dev):
         torch.cuda.synchronize()
     finally:
         B.mg_destroy(ctx)
-    fo = pj.ns_rhs(ux, uy)
-    po = oracle.solve(fo, oracle.PERIODIC, rtol=1e-12, max_cycles=60)[0]
-    wx, wy = pj.ns_update(ux, uy, po, dt)
+    wx, wy, _ = pj.time_step(
+        ux, uy, dt, lambda fo: oracle.solve(fo, oracle.PERIODIC, rtol=1e-12, max_cycles=60)[0])
     gx, gy = ox.cpu().numpy(), oy.cpu().numpy()
     err = max(np.abs(gx - wx).max(), np.abs(gy - wy).max()) / np.abs(wx - ux).max()
     say(f"time step n={n}: solve {cyc[0]} cycles relres {rel[0]:.2e}; step error {err:.3e}")
@@ -169,3 +176,30 @@ def test_rejections(B, dev):
     with pytest.raises(B.MGError):
         B.mg_ns_update(17, x.data_ptr(), y.data_ptr(), x.data_ptr(), 0.1, x.data_ptr(),
                        y.data_ptr(), 17, F64)
+
+
+def test_gpu_time_step_keeps_taylor_green_steady(B, dev):
+    """The GPU chain mg_ns_rhs -> mg_solve -> mg_ns_update on the steady
+    Taylor-Green flow: max |du| / dt = O(h^2) (<= 0.05 at 65^2), the same
+    bound the oracle's time step is pinned to."""
+    n, dt = 65, 1e-3
+    X = np.arange(n) / (n - 1)
+    x, y = np.meshgrid(2 * np.pi * X, 2 * np.pi * X, indexing="xy")
+    ux, uy = np.sin(x) * np.cos(y), -np.cos(x) * np.sin(y)
+    a, b = padded(ux, n, dev, torch.float64), padded(uy, n, dev, torch.float64)
+    f = torch.zeros((n, n), dtype=torch.float64, device=dev)
+    q = torch.zeros_like(f)
+    ox, oy = torch.zeros_like(f), torch.zeros_like(f)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = B.mg_setup([(n, oracle.PERIODIC, 0)], B.mg_options_default(), stream)
+    try:
+        B.mg_ns_rhs(n, a.data_ptr(), b.data_ptr(), f.data_ptr(), n, F64, stream)
+        st, cyc, rel = B.mg_solve(ctx, [q.data_ptr()], [f.data_ptr()], 1e-12, 60)
+        B.mg_ns_update(n, a.data_ptr(), b.data_ptr(), q.data_ptr(), dt, ox.data_ptr(),
+                       oy.data_ptr(), n, F64, stream)
+        torch.cuda.synchronize()
+    finally:
+        B.mg_destroy(ctx)
+    rate = max(np.abs(ox.cpu().numpy() - ux).max(), np.abs(oy.cpu().numpy() - uy).max()) / dt
+    say(f"Taylor-Green step n={n}: max |du|/dt {rate:.3e}")
+    assert st == 0 and rate <= 0.05
