@@ -156,7 +156,10 @@ MG_API int32_t mg_setup(const mg_grid* grids, int32_t batch, const mg_options* o
  * ||f - A u||_2 / ||f||_2 over the unknowns after the last cycle; otherwise
  * it returns after queueing.  Periodic seams of u are rewritten.  With
  * MG_PROLONG_SRCNN every cycle uses the network on the cnn_levels finest
- * prolongations.
+ * prolongations.  On the persistent schedule (option `schedule`) the call
+ * always synchronises before it returns, to read the device-wide barrier's
+ * status: a barrier that timed out makes the call return MG_ERR_HIP (u is
+ * then partly updated).
  * Errors: INVALID_ARG (NULL ctx/u/f or entries, ncycles < 0), HIP,
  * NONFINITE (only when relres_out is given). */
 MG_API int32_t mg_vcycle(mg_ctx ctx, double* const* u, const double* const* f, int32_t ncycles,
@@ -289,6 +292,15 @@ MG_API int32_t mg_timing_read(mg_ctx ctx, int32_t kind, int32_t level, int64_t* 
 
 /* Static name of a kernel class ("?" if unknown). */
 MG_API const char* mg_kernel_name(int32_t kind);
+
+/* Diagnostics for callers' error handling: marks the persistent schedule's
+ * device-wide barrier as timed out, exactly as a barrier that waited past
+ * its spin limit does.  The next persistent launch then exits at entry
+ * without touching any array, and the mg_vcycle or mg_solve call that
+ * queued it returns MG_ERR_HIP and clears the mark.  Synchronises the
+ * context's stream.  Errors: INVALID_ARG (NULL ctx), UNSUPPORTED (the
+ * context does not run the persistent schedule), HIP. */
+MG_API int32_t mg_persistent_mark_timeout(mg_ctx ctx);
 
 /* Number of levels of problem `problem` (>= 1), or a negative mg_status. */
 MG_API int32_t mg_num_levels(mg_ctx ctx, int32_t problem);

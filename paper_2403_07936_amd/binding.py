@@ -104,6 +104,7 @@ def lib() -> ctypes.CDLL:
         "mg_restrict": (i32, [vp, i32, i32, vp, vp, i32]),
         "mg_coarse_solve": (i32, [vp, i32, vp, vp, i32]),
         "mg_num_levels": (i32, [vp, i32]),
+        "mg_persistent_mark_timeout": (i32, [vp]),
         "mg_timing_enable": (i32, [vp, i32]),
         "mg_timing_read": (i32, [vp, i32, i32, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
@@ -214,6 +215,10 @@ def mg_restrict(ctx: int, problem: int, level: int, r: int, fc: int, dtype: int)
 
 def mg_coarse_solve(ctx: int, problem: int, f: int, u: int, dtype: int) -> None:
     _check(lib().mg_coarse_solve(vp(ctx), problem, vp(f), vp(u), dtype))
+
+
+def mg_persistent_mark_timeout(ctx: int) -> None:
+    _check(lib().mg_persistent_mark_timeout(vp(ctx)))
 
 
 def mg_num_levels(ctx: int, problem: int) -> int:

@@ -837,6 +837,23 @@ int32_t persistent_launch(mg_ctx_s* ctx) {
   return MG_OK;
 }
 
+// Reads the device-wide barrier's error word (synchronises).  A barrier that
+// timed out in an earlier launch leaves the word set, and every later launch
+// exits at entry while it is; so the word is cleared here and the call that
+// queued the failed launches reports MG_ERR_HIP.
+int32_t persistent_check(mg_ctx_s* ctx) {
+  Persist& P = ctx->ps;
+  PBarrier bar{};
+  MG_HIP(hipMemcpyAsync(&bar, P.d_bar, sizeof bar, hipMemcpyDeviceToHost, ctx->stream));
+  MG_HIP(hipStreamSynchronize(ctx->stream));
+  if (bar.error) {
+    MG_HIP(hipMemsetAsync(P.d_bar, 0, sizeof(PBarrier), ctx->stream));
+    MG_HIP(hipStreamSynchronize(ctx->stream));
+    return fail(MG_ERR_HIP, "persistent kernel: device-wide barrier timed out");
+  }
+  return MG_OK;
+}
+
 // Relative residuals of all problems from the batched kernels (synchronises);
 // also reports a timed-out device barrier.
 int32_t persistent_relres(mg_ctx_s* ctx, double* rel) {
@@ -847,14 +864,7 @@ int32_t persistent_relres(mg_ctx_s* ctx, double* rel) {
   std::vector<double> sums(2 * B);
   MG_HIP(hipMemcpyAsync(sums.data(), P.d_sums, sizeof(double) * 2 * B, hipMemcpyDeviceToHost,
                         ctx->stream));
-  PBarrier bar{};
-  MG_HIP(hipMemcpyAsync(&bar, P.d_bar, sizeof bar, hipMemcpyDeviceToHost, ctx->stream));
-  MG_HIP(hipStreamSynchronize(ctx->stream));
-  if (bar.error) {
-    MG_HIP(hipMemsetAsync(P.d_bar, 0, sizeof(PBarrier), ctx->stream));
-    MG_HIP(hipStreamSynchronize(ctx->stream));
-    return fail(MG_ERR_HIP, "persistent kernel: device-wide barrier timed out");
-  }
+  MG_TRY(persistent_check(ctx));
   for (int b = 0; b < B; ++b) {
     const double rr = sums[2 * b], ff = sums[2 * b + 1];
     rel[b] = ff > 0.0 ? std::sqrt(rr) / std::sqrt(ff) : std::sqrt(rr);
@@ -1550,7 +1560,7 @@ int32_t vcycle_impl(mg_ctx ctx, double* const* u, const double* const* f, int32_
     for (int c = 0; c < ncycles; ++c) MG_TRY(persistent_launch(ctx));
     if (ctx->ps.bc == kPeriodic && ncycles > 0)
       MG_HIP(launch_seam_batched(ctx->stream, ctx->ps.d_probs, B));
-    if (!relres_out) return MG_OK;
+    if (!relres_out) return ncycles > 0 ? persistent_check(ctx) : MG_OK;
     MG_TRY(persistent_relres(ctx, relres_out));
     for (int b = 0; b < B; ++b)
       if (!std::isfinite(relres_out[b])) return fail(MG_ERR_NONFINITE, "non-finite residual");
@@ -2075,6 +2085,18 @@ const char* mg_kernel_name(int32_t kind) {
     case MG_K_CNN_AUX: return "cnn_aux";
     default: return "?";
   }
+}
+
+int32_t mg_persistent_mark_timeout(mg_ctx ctx) {
+  g_last_error.clear();
+  if (!ctx) return fail(MG_ERR_INVALID_ARG, "ctx is NULL");
+  if (!ctx->ps.on) return fail(MG_ERR_UNSUPPORTED, "the context does not use the persistent schedule");
+  MG_GUARD(MG_HIP(hipSetDevice(ctx->device));
+           const unsigned one = 1u;
+           MG_HIP(hipMemcpyAsync(&ctx->ps.d_bar->error, &one, sizeof one, hipMemcpyHostToDevice,
+                                 ctx->stream));
+           MG_HIP(hipStreamSynchronize(ctx->stream));
+           return MG_OK;)
 }
 
 int32_t mg_num_levels(mg_ctx ctx, int32_t problem) {

@@ -305,7 +305,8 @@ def test_mixed_step_residual_in_down_pass_is_bitwise(B, dev, bc, n):
 def test_full_size_cycle_parity(B, dev, name):
     """The benchmark configurations at full size, in the launch configuration
     the benchmark times (fused kernels, graph): one FP64 cycle and one mixed
-    step from the same state, against the oracle, on every grid point."""
+    step from the same state, against the oracle, on every grid point (the
+    largest element-wise difference as well as the 2-norm)."""
     say(f"full size {name}")
     n, bc, f = workloads.workload(name, 0)
     ft = gpu(f, dev)
@@ -318,16 +319,21 @@ def test_full_size_cycle_parity(B, dev, name):
             got = host(ut)
         finally:
             B.mg_destroy(ctx)
+        # Both bars: the 2-norm, and element-wise against the largest value
+        # (an error confined to one band-edge column would be diluted ~64x
+        # in the 2-norm at 4097^2, but not in the max).
         if precision == 0:
             ref = oracle.vcycle(u1, f, bc)
             err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-            say(f"  fp64 cycle: {err:.2e}")
-            assert err <= 1e-12
+            mx = np.abs(got - ref).max() / np.abs(ref).max()
+            say(f"  fp64 cycle: l2 {err:.2e} max {mx:.2e}")
+            assert err <= 1e-12 and mx <= 1e-12
         else:
             ref = oracle.refine_step(u1, f, bc)
             err = np.linalg.norm(got - ref) / np.linalg.norm(ref - u1)
-            say(f"  mixed step: {err:.2e}")
-            assert err <= 1e-5
+            mx = np.abs(got - ref).max() / np.abs(ref - u1).max()
+            say(f"  mixed step: l2 {err:.2e} max {mx:.2e}")
+            assert err <= 1e-5 and mx <= 1e-5
 
 
 @pytest.mark.parametrize("precision", [0, 1])

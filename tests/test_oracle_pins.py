@@ -334,3 +334,34 @@ def test_refine_step_is_fp64_update_of_fp32_cycle():
     e = oracle.vcycle(np.zeros((n, n), np.float32), dm.to_grid(r, n, bc).astype(np.float32), bc)
     ref = u + e.astype(np.float64)
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-6 * np.abs(e).max())
+
+
+def test_oracle_is_bitwise_thread_count_independent():
+    """The oracle's OpenMP loops have disjoint outputs and its reductions run
+    in a fixed order, so its results are the same bits at 1 thread and at 8:
+    an FP64 cycle, a mixed refinement step and a solve, both boundary
+    conditions (each thread count in a process of its own)."""
+    import os
+    import subprocess
+    import sys
+
+    code = (
+        "import hashlib, numpy as np, oracle, workloads\n"
+        "h = hashlib.sha256()\n"
+        "for bc, f in ((0, workloads.rhs_divu_dirichlet(257, 5)),"
+        " (1, workloads.rhs_divu_periodic(257, 6))):\n"
+        "    u = oracle.vcycle(np.zeros_like(f), f, bc)\n"
+        "    h.update(u.tobytes())\n"
+        "    h.update(oracle.refine_step(u, f, bc).tobytes())\n"
+        "    us, c, hist = oracle.solve(f, bc, rtol=1e-10, max_cycles=30)\n"
+        "    h.update(us.tobytes()); h.update(hist.tobytes())\n"
+        "print(h.hexdigest())\n"
+    )
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    digests = []
+    for threads in ("1", "8"):
+        env = dict(os.environ, OMP_NUM_THREADS=threads, PYTHONPATH=root)
+        out = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, check=True,
+                             capture_output=True, text=True, timeout=300)
+        digests.append(out.stdout.strip())
+    assert len(digests[0]) == 64 and digests[0] == digests[1], digests
