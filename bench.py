@@ -67,11 +67,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dirichlet4097",
-                    choices=["dirichlet4097", "periodic1025", "dirichlet65", "periodic1025_srcnn",
-                             "periodic4097_projection"])
+                    choices=["dirichlet4097", "periodic1025", "dirichlet65", "batch256",
+                             "periodic1025_srcnn", "periodic4097_projection"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default workload only: skip the periodic1025 and batch256 sub-objects")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (read, and appended with new choices), so that "
                          "several runs (e.g. one per profiler counter) use the same launch shapes")
@@ -334,6 +336,218 @@ def bench_projection(args) -> int:
     return 0
 
 
+def measure_single(n, bc, f, steps, warmup, tune_cache, dev, reps=3):
+    """FP64 and mixed paths on one resident grid: seconds per step (K steps
+    after W warm-up steps, each one mg_vcycle call), and the best of `reps`
+    solves to 1e-10 from u = 0.  Returns {precision: {...}} with the solvers
+    left open."""
+    import torch
+
+    from paper_2403_07936_amd.solver import Solver
+
+    ft = torch.from_numpy(f).to(dev)
+    ut = torch.zeros_like(ft)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        s = Solver([(n, bc)], precision=prec, use_graph=True, tune_cache_path=tune_cache)
+        ut.zero_()
+        s.vcycle([ut], [ft], warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.vcycle([ut], [ft], 1)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        best = None
+        for _ in range(reps):
+            ut.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, cyc, rel = s.solve([ut], [ft], rtol=1e-10, max_cycles=50)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, st, cyc[0], rel[0])
+        res[prec] = {"solver": s, "sec_per_step": sec, "ttt": best, "u": ut.clone()}
+        log(f"n={n} {prec}: {sec * 1e3:.3f} ms/cycle; to 1e-10: {best[0] * 1e3:.2f} ms, "
+            f"{best[2]} cycles, relres {best[3]:.2e}, status {best[1]}")
+    return res, ft, ut
+
+
+def measure_batch(probs, steps, warmup, tune_cache, dev, reps=2):
+    """FP64 and mixed paths on the 256-problem batch (schedule autotuned:
+    the persistent launch or per-problem graphs): seconds per step (one
+    mg_vcycle call steps every problem), and the best of `reps` solves of
+    all problems to 1e-10 from u = 0 (problems stop independently)."""
+    import torch
+
+    from paper_2403_07936_amd.solver import Solver
+
+    fts = [torch.from_numpy(f).to(dev) for _, _, f in probs]
+    uts = [torch.zeros_like(t) for t in fts]
+    grids = [(n, bc) for n, bc, _ in probs]
+    res = {}
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        s = Solver(grids, precision=prec, use_graph=True, tune_cache_path=tune_cache)
+        t_setup = time.perf_counter() - t0
+        for t in uts:
+            t.zero_()
+        s.vcycle(uts, fts, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.vcycle(uts, fts, 1)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        best = None
+        for _ in range(reps):
+            for t in uts:
+                t.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, cyc, rel = s.solve(uts, fts, rtol=1e-10, max_cycles=50)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, st, max(cyc), max(rel), [u.clone() for u in uts])
+        res[prec] = {"solver": s, "sec_per_step": sec, "ttt": best, "setup_s": t_setup}
+        log(f"batch {prec}: {sec * 1e3:.3f} ms/step; all to 1e-10: {best[0] * 1e3:.2f} ms, "
+            f"max {best[2]} cycles, max relres {best[3]:.2e}, status {best[1]} "
+            f"(setup with tuning {t_setup:.1f} s)")
+    return res, fts
+
+
+def kernel_events(B, solver, run, level=0):
+    """Kernel classes of one context from HIP events around every launch
+    (on the context's stream) while `run()` queues steps: list of
+    (total_ms, kind, launches, algorithmic_bytes), largest time first."""
+    import torch
+
+    B.mg_timing_enable(solver.ctx, True)
+    torch.cuda.synchronize()
+    run()
+    torch.cuda.synchronize()
+    kern = []
+    for kind in range(B.MG_K_COUNT):
+        cnt, ms, by = B.mg_timing_read(solver.ctx, kind, level)
+        if cnt:
+            kern.append((ms, kind, cnt, by))
+    B.mg_timing_enable(solver.ctx, False)
+    kern.sort(reverse=True)
+    return kern
+
+
+def path_summary(res, unknowns):
+    return {p: {"ms_per_step": round(r["sec_per_step"] * 1e3, 4),
+                "grid_points_per_s": round(unknowns / r["sec_per_step"], 1),
+                "time_to_tol_s": round(r["ttt"][0], 6), "cycles_to_tol": r["ttt"][2],
+                "final_relres": r["ttt"][3], "status": r["ttt"][1]}
+            for p, r in res.items()}
+
+
+def batch_errors(probs, res, sample):
+    """Relative 2-norm error of the batch solves against the oracle's FP64
+    solutions on the problems in `sample` (mean removed: periodic)."""
+    import numpy as np
+
+    import oracle
+
+    err = {p: 0.0 for p in res}
+    for b in sample:
+        n, bc, f = probs[b]
+        uo = oracle.solve(f, bc, rtol=1e-10, max_cycles=50)[0]
+        uo = uo[:-1, :-1] - uo[:-1, :-1].mean()
+        for p, r in res.items():
+            g = r["ttt"][4][b].cpu().numpy()
+            g = g[:-1, :-1] - g[:-1, :-1].mean()
+            err[p] = max(err[p], float(np.linalg.norm(g - uo) / np.linalg.norm(uo)))
+    return err
+
+
+def bench_batch(args, B, dev, probs, full: bool):
+    """The 256-problem periodic batch (sides 129..1025, one persistent launch
+    per step when the tuner picks it).  full=False: the compact sub-object of
+    the default line; full=True: the workload's own JSON line."""
+    import numpy as np
+
+    import workloads
+
+    unknowns = sum(workloads.grid_unknowns(n, bc) for n, bc, _ in probs)
+    steps, warmup = (args.steps, args.warmup) if full else (min(args.steps, 10), 2)
+    res, fts = measure_batch(probs, steps, warmup, args.tune_cache, dev)
+    head = min(res, key=lambda p: res[p]["sec_per_step"])
+    hs = res[head]["solver"]
+    uts = res[head]["ttt"][4]
+
+    def run():
+        for _ in range(steps):
+            hs.vcycle(uts, fts, 1)
+
+    kern = kernel_events(B, hs, run)
+    ms, kind, cnt, by = kern[0]
+    avg = ms / cnt
+    ach = (by / cnt) / (avg * 1e-3) / 1e9 if by > 0 else None
+    roofline = {"bound": "hbm", "kernel": B.mg_kernel_name(kind),
+                "achieved": round(ach, 1) if ach else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None, "traffic": None,
+                "avg_launch_us": round(avg * 1e3, 2), "bytes_per_launch": by / cnt}
+    sample = list(range(0, len(probs), 16)) if not args.no_cpu else []
+    errs = batch_errors(probs, res, sample) if sample else {}
+    sub = {
+        "problems": len(probs), "unknowns": unknowns,
+        "sizes": {str(m): sum(1 for n, _, _ in probs if n == m) for m in workloads.SIZES_BATCHED},
+        "head": head, "paths": path_summary(res, unknowns),
+        "speedup_mixed_vs_fp64": round(res["fp64"]["sec_per_step"] / res["mixed"]["sec_per_step"], 3),
+        "schedule": "persistent" if B.MG_K_PERSISTENT == kind else "per-problem graphs",
+        "roofline": roofline,
+        "setup_s": {p: round(r["setup_s"], 2) for p, r in res.items()},
+    }
+    if errs:
+        sub["err_vs_oracle_fp64"] = {p: errs[p] for p in errs}
+        sub["err_sample"] = f"problems {sample[0]}, {sample[1]}, ... (every 16th), oracle FP64 " \
+                            f"solve to 1e-10"
+    cpu = None
+    if full and not args.no_cpu:
+        import oracle
+
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        log(f"CPU baseline: oracle {head} steps over the batch for ~{args.cpu_seconds:.0f} s")
+        done, t0, b = 0, time.perf_counter(), 0
+        while True:
+            n, bc, f = probs[b % len(probs)]
+            u = np.zeros_like(f)
+            u = oracle.vcycle(u, f, bc) if head == "fp64" else oracle.refine_step(u, f, bc)
+            done += workloads.grid_unknowns(n, bc)
+            b += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds:
+                break
+        cpu = {"value": round(done / el, 1), "unit": "grid-points/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"one {head} step of each of the first {b} problems of batch256 "
+                         f"({done} unknowns, {el:.1f} s, plain C oracle)"}
+    for r in res.values():
+        r["solver"].close()
+    if not full:
+        return sub
+    r = res[head]
+    out = {
+        "metric": "grid-points/s per V-cycle + time to 1e-10 rel. residual, 256-problem batch",
+        "value": round(unknowns / r["sec_per_step"], 1), "unit": "grid-points/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": round(r["sec_per_step"] * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "batch256", "bc": "periodic", "problems": len(probs),
+                   "unknowns": unknowns, "precision": head, "seed": args.seed},
+        "time_to_tol_s": round(r["ttt"][0], 6), "cycles_to_tol_max": r["ttt"][2],
+        "final_relres_max": r["ttt"][3],
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    out.update({k: v for k, v in sub.items() if k not in ("roofline",)})
+    return out
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
@@ -350,7 +564,6 @@ def main() -> int:
 
     import workloads
     from paper_2403_07936_amd import binding as B
-    from paper_2403_07936_amd.solver import Solver
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -368,63 +581,29 @@ def main() -> int:
     torch.cuda.synchronize()
     del calib, calib_dst
 
+    if args.workload == "batch256":
+        log(f"generating batch256 seed {args.seed}")
+        probs = workloads.workload("batch256", args.seed)
+        out = bench_batch(args, B, dev, probs, full=True)
+        print(json.dumps(out), flush=True)
+        return 0
+
     log(f"generating {args.workload} seed {args.seed}")
     n, bc, f = workloads.workload(args.workload, args.seed)
     unknowns = workloads.grid_unknowns(n, bc)
-    ft = torch.from_numpy(f).to(dev)
-    ut = torch.zeros_like(ft)
-
-    def timed_steps(s: Solver, K: int, W: int) -> float:
-        ut.zero_()
-        s.vcycle([ut], [ft], W)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(K):
-            s.vcycle([ut], [ft], 1)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / K
-
-    def time_to_tol(s: Solver, reps: int = 3):
-        best = None
-        for _ in range(reps):
-            ut.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st, cyc, rel = s.solve([ut], [ft], rtol=1e-10, max_cycles=50)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            if best is None or dt < best[0]:
-                best = (dt, st, cyc[0], rel[0])
-        return best
-
-    results = {}
-    for prec in ("fp64", "mixed"):
-        s = Solver([(n, bc)], precision=prec, use_graph=True, tune_cache_path=args.tune_cache)
-        sec = timed_steps(s, args.steps, args.warmup)
-        tt = time_to_tol(s)
-        u_final = ut.clone()
-        results[prec] = {"solver": s, "sec_per_step": sec, "ttt": tt, "u": u_final}
-        log(f"{prec}: {sec * 1e3:.3f} ms/cycle, {unknowns / sec:.3e} pts/s; "
-            f"to 1e-10: {tt[0] * 1e3:.2f} ms, {tt[2]} cycles, relres {tt[3]:.2e}, status {tt[1]}")
+    results, ft, ut = measure_single(n, bc, f, args.steps, args.warmup, args.tune_cache, dev)
 
     head = min(results, key=lambda p: results[p]["sec_per_step"])
     hs = results[head]["solver"]
 
     # Per-kernel timing: the same number of steps again with every launch
     # bracketed by HIP events on the solver's stream (no graph capture).
-    B.mg_timing_enable(hs.ctx, True)
-    ut.zero_()
-    torch.cuda.synchronize()
-    for _ in range(args.steps):
-        hs.vcycle([ut], [ft], 1)
-    torch.cuda.synchronize()
-    kern = []
-    for kind in range(B.MG_K_COUNT):
-        cnt, ms, by = B.mg_timing_read(hs.ctx, kind, 0)
-        if cnt:
-            kern.append((ms, kind, cnt, by))
-    B.mg_timing_enable(hs.ctx, False)
-    kern.sort(reverse=True)
+    def run():
+        ut.zero_()
+        for _ in range(args.steps):
+            hs.vcycle([ut], [ft], 1)
+
+    kern = kernel_events(B, hs, run)
     ms, kind, cnt, by = kern[0]
     avg_ms = ms / cnt
     achieved = (by / cnt) / (avg_ms * 1e-3) / 1e9
@@ -508,6 +687,26 @@ def main() -> int:
     out.update(extra)
     for r in results.values():
         r["solver"].close()
+    del ft, ut
+    torch.cuda.empty_cache()
+
+    if args.workload == "dirichlet4097" and not args.no_extra:
+        # The other configurations, measured by the same run: the periodic
+        # 1025^2 grid (FP64 against mixed) and the 256-problem batch.
+        subs = {}
+        n2, bc2, f2 = workloads.workload("periodic1025", args.seed)
+        r2, ft2, ut2 = measure_single(n2, bc2, f2, args.steps, args.warmup, args.tune_cache, dev)
+        u2 = workloads.grid_unknowns(n2, bc2)
+        subs["periodic1025"] = {"unknowns": u2, "paths": path_summary(r2, u2),
+                                "speedup_mixed_vs_fp64": round(
+                                    r2["fp64"]["sec_per_step"] / r2["mixed"]["sec_per_step"], 3)}
+        for r in r2.values():
+            r["solver"].close()
+        del ft2, ut2
+        log(f"generating batch256 seed {args.seed}")
+        probs = workloads.workload("batch256", args.seed)
+        subs["batch256"] = bench_batch(args, B, dev, probs, full=False)
+        out["other_workloads"] = subs
     print(json.dumps(out), flush=True)
     return 0
 

@@ -192,6 +192,10 @@ struct Persist {
   double* d_partials = nullptr;
   double* d_sums = nullptr;
   int slots = 32;
+  // Algorithmic bytes of one launch (every problem active): the bytes each
+  // pass of the step must read and write at its precision, as the
+  // per-problem schedule counts them.
+  double bytes = 0.0;
 };
 }  // namespace mg
 
@@ -751,6 +755,36 @@ int32_t build_persistent(mg_ctx_s* ctx) {
     close_phase(kItemUpd, first);
   }
 
+  // Algorithmic bytes of the step, per pass (m = unknowns per side):
+  // residual 20 m^2 (u, f FP64 read, r FP32 written); down pass
+  // (2 or 3) m^2 + mc^2 words (f read, pre-smoothed u written, u read
+  // unless the guess is zero, fc written); tail (2 or 3) nt^2 words;
+  // prefilter 2 nc^2 words; up pass 3 m^2 + nc^2 words, where the mixed
+  // level-0 pass adds into the FP64 iterate (16 m^2 instead of 4 m^2 for
+  // u); update 20 m^2.
+  {
+    const double sz = sizeof(T);
+    double by = 0.0;
+    for (int b = 0; b < B; ++b) {
+      const Problem& p = ctx->probs[b];
+      auto unk = [&](int l) {
+        const double m = unknowns_side(p.side[l], p.bc);
+        return m * m;
+      };
+      if (mixed) by += 20.0 * unk(0);
+      for (int l = 0; l < p.tail; ++l) {
+        const bool uin = l == 0 && !mixed;
+        by += ((uin ? 3.0 : 2.0) * unk(l) + unk(l + 1)) * sz;
+        const double nc2 = (double)p.side[l + 1] * p.side[l + 1];
+        if (l + 1 < p.tail) by += 2.0 * nc2 * sz;
+        by += (3.0 * unk(l) + nc2) * sz + ((l == 0 && mixed) ? 12.0 * unk(0) : 0.0);
+      }
+      const double nt2 = (double)p.side[p.tail] * p.side[p.tail];
+      by += ((p.tail == 0 && !mixed) ? 3.0 : 2.0) * nt2 * sz;
+      if (mixed && p.tail == 0) by += 20.0 * unk(0);
+    }
+    P.bytes = by;
+  }
   P.lds = lds;
   MG_HIP(persistent_init(std::max(lds, (size_t)65536), std::max(lds, (size_t)65536)));
   MG_HIP(persistent_blocks<T>(P.bc, lds, &P.blocks));
@@ -813,7 +847,7 @@ int32_t persistent_launch(mg_ctx_s* ctx) {
                                            P.d_bar, ctx->inv[P.bc], P.blocks, P.lds);
   };
   if (!ctx->opt.use_graph || ctx->timing) {
-    MG_TRY(timed(ctx, ctx->stream, MG_K_PERSISTENT, 0, 0.0, [&] { return launch(ctx->stream); }));
+    MG_TRY(timed(ctx, ctx->stream, MG_K_PERSISTENT, 0, P.bytes, [&] { return launch(ctx->stream); }));
     return MG_OK;
   }
   if (!P.graph) {
