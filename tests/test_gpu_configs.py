@@ -164,13 +164,17 @@ def test_inner_cycles_parity(B, dev, inner, kernel_path, bc, n):
 
     Bar.  From the second inner cycle on, the FP32 cycle restarts from the
     FP32 residual r - A e, whose smooth part is mostly rounding (A scales by
-    1/h^2 and the terms cancel), so two FP32 evaluations in different
-    rounding orders part by about as much as either parts from the same
-    step taken in FP64 (inner cycles in FP64 on the FP64 residual): at
-    1025^2 the oracle's own FP32 step lies 1e-5 .. 7e-5 of |e| from that
-    FP64 step.  The GPU step must therefore lie within twice that distance
-    of the oracle's FP32 step, plus 50 % margin (3x), and never further
-    than 1e-5 |e| when that distance is smaller; its FP64 residual must be
+    1/h^2 and the terms cancel), so the step depends on the rounding order at
+    the level of FP32 noise amplified by the cycle.  The natural spread D is
+    measured here on the oracle itself, as the larger of two distances: its
+    FP32 step from the same step with FP64 inner cycles, and its FP32 step
+    from the FP32 step of the transposed problem transposed back (the same
+    operations with x and y swapped, so only the rounding order differs).
+    At 257^2 and 1025^2 the second is 1-4x the first (e.g. 1.6e-5 against
+    1.25e-5 of |e|, periodic 1025^2, 3 inner cycles), and an FMA-contracted
+    build of the oracle lies as far.  The GPU step (contracted, its own
+    order) must lie within 3 D of the oracle's step, L2 and max norm, and
+    never further than 1e-5 |e| when D is smaller; its FP64 residual must be
     as small as the oracle's (within 5 %)."""
     from paper_2403_07936_amd.solver import Solver
     say(f"inner cycles {inner} path {kernel_path} bc={bc} n={n}")
@@ -188,14 +192,21 @@ def test_inner_cycles_parity(B, dev, inner, kernel_path, bc, n):
             e64 = np.zeros_like(f)
             for _ in range(inner):
                 e64 = oracle.vcycle(e64, r, bc)
+            tr = np.ascontiguousarray(oracle.refine_step(
+                np.ascontiguousarray(u.T), np.ascontiguousarray(f.T), bc, inner=inner).T)
             e = ref - u
-            d_l2 = np.linalg.norm(ref - (u + e64)) / np.linalg.norm(e)
-            d_mx = np.abs(ref - (u + e64)).max() / np.abs(e).max()
-            l2 = np.linalg.norm(got - ref) / np.linalg.norm(e)
-            mx = np.abs(got - ref).max() / np.abs(e).max()
+
+            def dist(a, b):
+                return (np.linalg.norm(a - b) / np.linalg.norm(e),
+                        np.abs(a - b).max() / np.abs(e).max())
+
+            d64, dtr = dist(ref, u + e64), dist(ref, tr)
+            d_l2, d_mx = max(d64[0], dtr[0]), max(d64[1], dtr[1])
+            l2, mx = dist(got, ref)
             rg, ro = oracle.relres(got, f, bc), oracle.relres(ref, f, bc)
-            say(f"  step {step + 1}: l2 {l2:.2e} max {mx:.2e} (oracle FP32 vs FP64 inner: l2 "
-                f"{d_l2:.2e} max {d_mx:.2e}); relres {rg:.3e} oracle {ro:.3e}")
+            say(f"  step {step + 1}: l2 {l2:.2e} max {mx:.2e} (oracle FP32 vs FP64 inner: "
+                f"{d64[0]:.2e} / {d64[1]:.2e}, vs transposed order: {dtr[0]:.2e} / "
+                f"{dtr[1]:.2e}); relres {rg:.3e} oracle {ro:.3e}")
             assert l2 <= max(1e-5, 3.0 * d_l2) and mx <= max(1e-5, 3.0 * d_mx)
             assert rg <= 1.05 * ro
             u = ref
