@@ -208,6 +208,26 @@ MG_API int32_t mg_solve_history(mg_ctx ctx, int32_t problem, int32_t cap, int32_
 MG_API int32_t mg_prolong(mg_ctx ctx, int32_t problem, int32_t coarse_level, int32_t kind,
                    const void* coarse, void* fine, int32_t dtype);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * spline prolongation of mg_prolong (kind MG_PROLONG_SPLINE), same kernels
+ * and bitwise the same result, with no context.  fine = P coarse from a grid
+ * of nc nodes per side (nc - 1 = 4 * 2^k, 5 <= nc <= 1025) to the grid of
+ * 2 nc - 1; coarse and fine are caller-owned device arrays of the current
+ * device, pitch = side, dtype MG_DT_F64 or MG_DT_F32; bc as in mg_grid.
+ * The result is written, not added; periodic seams are written.
+ * Asynchronous on hip_stream (NULL: the null stream), which must belong to
+ * the current device.  Its scratch (the prefilter's intermediate and the
+ * B-spline coefficients, 16.8 MB) is a static device array, one per GPU,
+ * held until the process ends; the call allocates nothing, and its first
+ * call on a device looks that array's address up once.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race.
+ * Errors: INVALID_ARG (bad nc, bc or dtype, NULL or aliased arrays),
+ * UNSUPPORTED (nc above 1025), HIP. */
+MG_API int32_t mg_prolong_noalloc(int32_t nc, int32_t bc, const void* coarse, void* fine,
+                                  int32_t dtype, void* hip_stream);
+
 /* The steps either side of the pressure solve in a time step of the
  * incompressible flow (Section 2.1's momentum system; Section 2.3's source
  * with zero viscosity), on one periodic n x n grid with the duplicated seam

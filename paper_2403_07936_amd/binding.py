@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
         "mg_ns_rhs": (i32, [i32, vp, vp, vp, i32, i32, vp]),
         "mg_ns_update": (i32, [i32, vp, vp, vp, ctypes.c_double, vp, vp, i32, i32, vp]),
         "mg_prolong": (i32, [vp, i32, i32, i32, vp, vp, i32]),
+        "mg_prolong_noalloc": (i32, [i32, i32, vp, vp, i32, vp]),
         "mg_relax": (i32, [vp, i32, i32, vp, vp, i32, i32, i32]),
         "mg_residual": (i32, [vp, i32, i32, vp, vp, vp, i32]),
         "mg_restrict": (i32, [vp, i32, i32, vp, vp, i32]),
@@ -198,6 +199,11 @@ def mg_ns_update(n: int, ux: int, uy: int, q: int, dt: float, ux_out: int, uy_ou
 def mg_prolong(ctx: int, problem: int, coarse_level: int, kind: int, coarse: int, fine: int,
                dtype: int) -> None:
     _check(lib().mg_prolong(vp(ctx), problem, coarse_level, kind, vp(coarse), vp(fine), dtype))
+
+
+def mg_prolong_noalloc(nc: int, bc: int, coarse: int, fine: int, dtype: int,
+                       stream: int = 0) -> None:
+    _check(lib().mg_prolong_noalloc(nc, bc, vp(coarse), vp(fine), dtype, vp(stream or None)))
 
 
 def mg_relax(ctx: int, problem: int, level: int, u: int, f: int, colour: int, count: int,

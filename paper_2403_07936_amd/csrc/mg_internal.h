@@ -34,6 +34,13 @@ struct PrefilterTaps {
   double w[kMaxPrefilterTaps];
 };
 
+// Records the detail string mg_last_error() returns on this thread, and
+// returns `status` (for entry points defined outside the runtime unit).
+int32_t set_last_error(int32_t status, const char* why);
+
+// True for a grid side of the form 4 * 2^k + 1 in 5 .. 16385.
+bool valid_side(int n);
+
 // Builds the prefilter table for a level with `nc` nodes per side.
 void spline_taps(int nc, int bc, int half_taps, PrefilterTaps* out);
 

@@ -242,6 +242,14 @@ int32_t fail(int32_t status, const std::string& why) {
   g_last_error = why;
   return status;
 }
+}  // namespace
+
+int32_t set_last_error(int32_t status, const char* why) {
+  g_last_error = why ? why : "";
+  return status;
+}
+
+namespace {
 
 #define MG_HIP(call)                                                                       \
   do {                                                                                     \
@@ -313,11 +321,15 @@ int32_t enqueue_cnn(mg_ctx_s* ctx, hipStream_t s, int level, int N, const T* ec,
   return MG_OK;
 }
 
+}  // namespace
+
 bool valid_side(int n) {
   if (n < 5 || n > 16385) return false;
   const int m = (n - 1) / 4;
   return (n - 1) % 4 == 0 && (m & (m - 1)) == 0;
 }
+
+namespace {
 
 int pitch_for(int n) { return (n + 63) / 64 * 64; }
 

@@ -98,3 +98,22 @@ def test_null_context_calls(B):
 def test_options_default_schedule_is_off(B):
     o = B.mg_options_default()
     assert (o.n_gan, o.s_thres, o.cnn_max_ratio, o.cnn_min_relres) == (0.0, 0.0, 0.5, 1e-7)
+
+
+@pytest.mark.parametrize("nc,bc,dtype,status", [
+    (2049, 0, 0, -2),   # above the static scratch's 1025
+    (6, 0, 0, -1),      # not 4 * 2^k + 1
+    (129, 2, 0, -1),    # bad boundary condition
+    (129, 0, 5, -1),    # bad dtype
+])
+def test_prolong_noalloc_rejects_before_any_device_call(B, nc, bc, dtype, status):
+    """Argument checks of mg_prolong_noalloc run on the host, before any HIP
+    call (the device pointers below are never touched)."""
+    st = B.lib().mg_prolong_noalloc(nc, bc, 0x1000, 0x2000, dtype, None)
+    assert st == status
+    assert B.mg_last_error()
+
+
+def test_prolong_noalloc_rejects_null_arrays(B):
+    assert B.lib().mg_prolong_noalloc(129, 0, None, 0x2000, 0, None) == -1
+    assert B.lib().mg_prolong_noalloc(129, 0, 0x1000, 0x1000, 0, None) == -1
