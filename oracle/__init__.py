@@ -80,7 +80,11 @@ def lib() -> ctypes.CDLL:
             getattr(L, f"orc_prolong_{sfx}").argtypes = [i, i, p, p]
             getattr(L, f"orc_coarse_{sfx}").argtypes = [i, p, p]
             getattr(L, f"orc_vcycle_{sfx}").argtypes = [i, i, i, i, p, p]
-            for name in ("relax", "residual", "restrict", "prolong", "coarse", "vcycle"):
+            getattr(L, f"orc_restrict_factor_{sfx}").argtypes = [i, i, p, p]
+            getattr(L, f"orc_prolong_factor_{sfx}").argtypes = [i, i, p, p]
+            getattr(L, f"orc_twolevel_{sfx}").argtypes = [i, i, i, i, p, p]
+            for name in ("relax", "residual", "restrict", "prolong", "coarse", "vcycle",
+                         "restrict_factor", "prolong_factor", "twolevel"):
                 getattr(L, f"orc_{name}_{sfx}").restype = None
         L.orc_coarse_direct.argtypes = [i, pd, pd]
         L.orc_coarse_direct.restype = None
@@ -94,6 +98,8 @@ def lib() -> ctypes.CDLL:
         L.orc_refine_step.restype = None
         L.orc_solve_mixed.argtypes = [i, i, i, i, i, pd, pd, ctypes.c_double, i, pd]
         L.orc_solve_mixed.restype = i
+        L.orc_twolevel_solve.argtypes = [i, i, i, i, i, pd, pd, ctypes.c_double, i, pd]
+        L.orc_twolevel_solve.restype = i
         _lib = L
     return _lib
 
@@ -227,3 +233,66 @@ def solve_mixed(f: np.ndarray, bc: int, rtol: float = 1e-10, max_steps: int = 50
                               _ptr(f, ctypes.c_double), rtol, max_steps,
                               _ptr(hist, ctypes.c_double))
     return u, c, hist[: c + 1]
+
+
+# ---- the paper's controlled two-level experiment (periodic grids only) -----
+
+def _check_factor(n: int, F: int) -> None:
+    """The two-level grids: N = n - 1 unique nodes, N / F of them on the
+    coarse grid, both even (red-black colouring must agree across the wrap)."""
+    N = n - 1
+    if F < 2 or N % F or N % 2 or (N // F) % 2 or N // F < 2:
+        raise ValueError(f"unique side {N} and factor {F}: need N and N/F even, N/F >= 2")
+
+
+def restrict_factor(r: np.ndarray, F: int) -> np.ndarray:
+    """Restriction of a periodic grid function by the factor F (full weighting
+    widened to the step: 1-D weights (F - |a|)/F^2, x then y)."""
+    r = _sq(r)
+    sfx, ct = _dt(r.dtype)
+    n = r.shape[0]
+    _check_factor(n, F)
+    nc = (n - 1) // F + 1
+    fc = np.empty((nc, nc), dtype=r.dtype)
+    getattr(lib(), f"orc_restrict_factor_{sfx}")(n, F, _ptr(r, ct), _ptr(fc, ct))
+    return fc
+
+
+def prolong_factor(ec: np.ndarray, F: int) -> np.ndarray:
+    """Periodic tensor cubic-spline interpolation by the factor F."""
+    ec = _sq(ec)
+    sfx, ct = _dt(ec.dtype)
+    nc = ec.shape[0]
+    n = F * (nc - 1) + 1
+    _check_factor(n, F)
+    ef = np.empty((n, n), dtype=ec.dtype)
+    getattr(lib(), f"orc_prolong_factor_{sfx}")(nc, F, _ptr(ec, ct), _ptr(ef, ct))
+    return ef
+
+
+def twolevel(p: np.ndarray, f: np.ndarray, F: int, n_smooth: int = 20,
+             coarse_sweeps: int = 10) -> np.ndarray:
+    """One iteration of the two-level method; returns the new p."""
+    p = _sq(p).copy()
+    _check_factor(p.shape[0], F)
+    sfx, ct = _dt(p.dtype)
+    f = _sq(f, p.dtype)
+    getattr(lib(), f"orc_twolevel_{sfx}")(p.shape[0], F, n_smooth, coarse_sweeps, _ptr(p, ct),
+                                          _ptr(f, ct))
+    return p
+
+
+def twolevel_solve(f: np.ndarray, p0: np.ndarray, F: int, n_smooth: int = 20,
+                   coarse_sweeps: int = 10, n_pre: int = 10, tol: float = 1e-10,
+                   max_iter: int = 300):
+    """n_pre sweeps on p0, then two-level iterations until the change between
+    iterates is <= tol.  Returns (p, iterations, changes)."""
+    f = _sq(f, np.float64)
+    p = _sq(p0, np.float64).copy()
+    _check_factor(p.shape[0], F)
+    hist = np.full(max_iter, np.nan)
+    it = lib().orc_twolevel_solve(f.shape[0], F, n_smooth, coarse_sweeps, n_pre,
+                                  _ptr(p, ctypes.c_double), _ptr(f, ctypes.c_double), tol,
+                                  max_iter, _ptr(hist, ctypes.c_double))
+    return p, it, hist[:it]
+

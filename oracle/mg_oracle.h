@@ -28,7 +28,11 @@
   void orc_restrict_##SFX(int n, int bc, const REAL* r, REAL* fc);                 \
   void orc_prolong_##SFX(int nc, int bc, const REAL* ec, REAL* ef);                \
   void orc_coarse_##SFX(int bc, const REAL* f, REAL* u);                           \
-  void orc_vcycle_##SFX(int n, int bc, int nu1, int nu2, REAL* u, const REAL* f);
+  void orc_vcycle_##SFX(int n, int bc, int nu1, int nu2, REAL* u, const REAL* f);    \
+  void orc_restrict_factor_##SFX(int n, int F, const REAL* r, REAL* fc);             \
+  void orc_prolong_factor_##SFX(int nc, int F, const REAL* ec, REAL* ef);            \
+  void orc_twolevel_##SFX(int n, int F, int n_smooth, int coarse_sweeps, REAL* p,    \
+                          const REAL* f);
 
 ORC_DECLARE(f64, double)
 ORC_DECLARE(f32, float)
@@ -41,6 +45,13 @@ double orc_relres(int n, int bc, const double* u, const double* f);
 int orc_solve_f64(int n, int bc, int nu1, int nu2, double* u, const double* f,
                   double rtol, int max_cycles, double* hist);
 void orc_refine_step(int n, int bc, int nu1, int nu2, int inner, double* u, const double* f);
+/* Two-level solve of the paper's controlled experiment: n_pre sweeps on the
+ * initial grid p, then iterations of orc_twolevel_f64 until the change
+ * ||p_i - p_(i-1)||_2 over the unique nodes is <= tol (Section 4.2's
+ * criterion) or max_iter iterations; hist[k] = the change of iteration k+1
+ * (max_iter entries).  Returns the iteration count. */
+int orc_twolevel_solve(int n, int F, int n_smooth, int coarse_sweeps, int n_pre, double* p,
+                       const double* f, double tol, int max_iter, double* hist);
 int orc_solve_mixed(int n, int bc, int nu1, int nu2, int inner, double* u,
                     const double* f, double rtol, int max_steps, double* hist);
 

@@ -282,3 +282,137 @@ void FN(orc_vcycle)(int n, int bc, int nu1, int nu2, real* u, const real* f) {
   free(fc);
   free(r);
 }
+
+/* ---------------------------------------------------------------------------
+ * The paper's controlled two-level experiment (Section 4.1; Table 1: N_grid,
+ * r_min, N_step, N_smooth, N_smooth,pre; appendix V-CYCLE with the coarse
+ * level relaxed rather than solved).  Periodic grids only (the paper's
+ * fields are biperiodic), n = N + 1 stored nodes per side with the seam, N
+ * divisible by the coarsening factor F = 2^N_step and N/F even (red-black
+ * colouring agrees across the wrap only on even sides).
+ * ------------------------------------------------------------------------- */
+
+/* Restriction by the factor F: the tensor product of the 1-D weights
+ * w_a = (F - |a|) / F^2 for |a| < F, centred on the fine node F*I under coarse
+ * node I.  For F = 2 these are (1/4, 1/2, 1/4), i.e. full weighting; for any F
+ * the 1-D operator is the transpose of linear interpolation by F divided by
+ * F, so constants are kept and sums are kept up to the factor F per axis.
+ * The paper coarsens 192 -> 12 in one step (Section 4.1) and names no
+ * weights; this is full weighting widened to the step.  Applied along x for
+ * every fine row, then along y; each sum runs over a = -(F-1) .. F-1 in
+ * increasing order. */
+void FN(orc_restrict_factor)(int n, int F, const real* r, real* fc) {
+  const int N = n - 1, Nc = N / F, nc = Nc + 1;
+  real* s = (real*)malloc(sizeof(real) * (size_t)N * Nc);
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < N; ++i)
+    for (int J = 0; J < Nc; ++J) {
+      real acc = 0;
+      for (int a = -(F - 1); a <= F - 1; ++a) {
+        const real w = (real)(F - abs(a)) / (real)(F * F);
+        acc += w * r[(size_t)i * n + wrap_index(F * J + a, N)];
+      }
+      s[(size_t)i * Nc + J] = acc;
+    }
+#pragma omp parallel for schedule(static)
+  for (int I = 0; I < Nc; ++I)
+    for (int J = 0; J < Nc; ++J) {
+      real acc = 0;
+      for (int a = -(F - 1); a <= F - 1; ++a) {
+        const real w = (real)(F - abs(a)) / (real)(F * F);
+        acc += w * s[(size_t)wrap_index(F * I + a, N) * Nc + J];
+      }
+      fc[(size_t)I * nc + J] = acc;
+    }
+  refresh_seam(fc, nc, ORC_PERIODIC);
+  free(s);
+}
+
+/* Periodic interpolating cubic spline through y_0..y_{m-1} (y_{m-1} = y_0)
+ * at unit spacing, evaluated at the F points t = q/F, q = 0..F-1, of every
+ * interval: out[F k + q], k = 0..m-2, and out[F (m-1)] = y_0.  Moments M from
+ * the cyclic system of spline_line; on [k, k+1] the spline is the textbook
+ *   S(t) = (1-t) y_k + t y_{k+1} + (((1-t)^3 - (1-t)) M_k + (t^3 - t) M_{k+1}) / 6. */
+static void spline_line_factor(int m, int F, const real* y, real* out, real* work) {
+  real* M = work;          /* m */
+  real* d = work + m;      /* m */
+  real* w = work + 2 * m;  /* 5m */
+  const int p = m - 1;
+  for (int k = 0; k < p; ++k) {
+    const real ym = y[(k - 1 + p) % p], y0 = y[k], yp = y[(k + 1) % p];
+    d[k] = (real)6 * (yp - (real)2 * y0 + ym);
+  }
+  solve_141_cyclic(p, d, w, M);
+  M[m - 1] = M[0];
+  for (int k = 0; k < p; ++k)
+    for (int q = 0; q < F; ++q) {
+      const real t = (real)q / (real)F, u = (real)1 - t;
+      out[F * k + q] = u * y[k] + t * y[k + 1] +
+                       ((u * u * u - u) * M[k] + (t * t * t - t) * M[k + 1]) / (real)6;
+    }
+  out[F * p] = y[0];
+}
+
+/* Prolongation by the factor F of a periodic coarse grid function (nc per
+ * side, seam included) to the fine grid n = F (nc - 1) + 1: the tensor cubic
+ * spline (Section 2.2's bivariate spline, periodic), along x for every coarse
+ * row, then along y for every fine column.  Returns P e_c (not added). */
+void FN(orc_prolong_factor)(int nc, int F, const real* ec, real* ef) {
+  const int n = F * (nc - 1) + 1;
+  real* tmp = (real*)malloc(sizeof(real) * (size_t)nc * n);
+#pragma omp parallel
+  {
+    real* work = (real*)malloc(sizeof(real) * (size_t)7 * (nc + 2));
+    real* col = (real*)malloc(sizeof(real) * (size_t)nc);
+    real* fcol = (real*)malloc(sizeof(real) * (size_t)n);
+#pragma omp for schedule(static)
+    for (int I = 0; I < nc; ++I)
+      spline_line_factor(nc, F, ec + (size_t)I * nc, tmp + (size_t)I * n, work);
+#pragma omp for schedule(static)
+    for (int j = 0; j < n; ++j) {
+      for (int I = 0; I < nc; ++I) col[I] = tmp[(size_t)I * n + j];
+      spline_line_factor(nc, F, col, fcol, work);
+      for (int i = 0; i < n; ++i) ef[(size_t)i * n + j] = fcol[i];
+    }
+    free(fcol);
+    free(col);
+    free(work);
+  }
+  free(tmp);
+}
+
+/* One iteration of the two-level method (appendix V-CYCLE with a single
+ * coarse level, Section 4.1's set-up): relax n_smooth times on the fine grid
+ * (red then black half-sweep each), r = f - A p, r_c = R_F r, delta_c = 0,
+ * relax coarse_sweeps times on A_c delta_c = r_c (the coarse operator is the
+ * 5-point one rediscretised at spacing F h; the coarsest level is relaxed,
+ * not solved), then p += P_F delta_c.  The paper relaxes only at the start
+ * of an iteration (N_smooth is the smoothing between iterations), so there
+ * is no post-smoothing.  p is updated in place (seam rewritten). */
+void FN(orc_twolevel)(int n, int F, int n_smooth, int coarse_sweeps, real* p, const real* f) {
+  const int nc = (n - 1) / F + 1;
+  for (int s = 0; s < n_smooth; ++s) {
+    FN(orc_relax)(n, ORC_PERIODIC, p, f, ORC_RED);
+    FN(orc_relax)(n, ORC_PERIODIC, p, f, ORC_BLACK);
+  }
+  real* r = (real*)malloc(sizeof(real) * (size_t)n * n);
+  real* rc = (real*)malloc(sizeof(real) * (size_t)nc * nc);
+  real* dc = (real*)calloc((size_t)nc * nc, sizeof(real));
+  FN(orc_residual)(n, ORC_PERIODIC, p, f, r);
+  FN(orc_restrict_factor)(n, F, r, rc);
+  for (int s = 0; s < coarse_sweeps; ++s) {
+    FN(orc_relax)(nc, ORC_PERIODIC, dc, rc, ORC_RED);
+    FN(orc_relax)(nc, ORC_PERIODIC, dc, rc, ORC_BLACK);
+  }
+  real* ef = r; /* reuse */
+  FN(orc_prolong_factor)(nc, F, dc, ef);
+  const int N = n - 1;
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) p[(size_t)i * n + j] += ef[(size_t)i * n + j];
+  refresh_seam(p, n, ORC_PERIODIC);
+  free(dc);
+  free(rc);
+  free(r);
+}
+

@@ -165,3 +165,30 @@ int orc_solve_mixed(int n, int bc, int nu1, int nu2, int inner, double* u,
   }
   return c;
 }
+
+/* Two-level solve of the paper's controlled experiment (Section 4.1): the
+ * initial grid is relaxed n_pre times (N_smooth,pre on an initially random
+ * grid, Table 1), then two-level iterations run until the change between
+ * successive iterates, ||p_i - p_(i-1)||_2 over the unique nodes, is at most
+ * tol (the paper's stopping rule, Section 4.2; it names no norm). */
+int orc_twolevel_solve(int n, int F, int n_smooth, int coarse_sweeps, int n_pre, double* p,
+                       const double* f, double tol, int max_iter, double* hist) {
+  const size_t nn = (size_t)n * n;
+  double* prev = (double*)malloc(sizeof(double) * nn);
+  for (int s = 0; s < n_pre; ++s) {
+    orc_relax_f64(n, ORC_PERIODIC, p, f, ORC_RED);
+    orc_relax_f64(n, ORC_PERIODIC, p, f, ORC_BLACK);
+  }
+  int it = 0;
+  while (it < max_iter) {
+    memcpy(prev, p, sizeof(double) * nn);
+    orc_twolevel_f64(n, F, n_smooth, coarse_sweeps, p, f);
+    for (size_t k = 0; k < nn; ++k) prev[k] = p[k] - prev[k];
+    const double change = orc_norm2(n, ORC_PERIODIC, prev);
+    if (hist) hist[it] = change;
+    ++it;
+    if (change <= tol) break;
+  }
+  free(prev);
+  return it;
+}

@@ -207,3 +207,63 @@ def exact_discrete_solution(f: np.ndarray, bc: int) -> np.ndarray:
     uh[0, 0] = 0.0
     core = np.fft.irfft2(uh, s=(N, N))
     return to_grid(core.reshape(-1), n, bc)
+
+
+# ---- factor-F transfers of the two-level experiment (periodic grids) --------
+
+@functools.lru_cache(maxsize=None)
+def linear_interp_factor_1d(mc: int, F: int) -> np.ndarray:
+    """Periodic piecewise-linear interpolation from mc coarse nodes (spacing F
+    fine cells) to the mc * F fine nodes: fine node F k + q lies q/F of the way
+    from coarse node k to k + 1."""
+    P = np.zeros((mc * F, mc))
+    for k in range(mc):
+        for q in range(F):
+            P[F * k + q, k] += 1.0 - q / F
+            P[F * k + q, (k + 1) % mc] += q / F
+    return P
+
+
+@functools.lru_cache(maxsize=None)
+def restrict_factor(N: int, F: int) -> np.ndarray:
+    """Full weighting widened to the factor F, as the transpose of bilinear
+    interpolation divided by F^2 (constants map to constants)."""
+    P1 = linear_interp_factor_1d(N // F, F)
+    return np.kron(P1.T, P1.T) / float(F * F)
+
+
+@functools.lru_cache(maxsize=None)
+def spline_1d_factor(mc: int, F: int) -> np.ndarray:
+    """Periodic cubic-spline interpolation matrix by the factor F (scipy's
+    CubicSpline on unit vectors, evaluated at the fine nodes)."""
+    nc = mc + 1
+    xc = np.arange(nc, dtype=np.float64)
+    xf = np.arange(mc * F, dtype=np.float64) / F
+    cols = []
+    for k in range(mc):
+        y = np.zeros(nc)
+        y[k] = 1.0
+        if k == 0:
+            y[-1] = 1.0
+        cols.append(CubicSpline(xc, y, bc_type="periodic")(xf))
+    return np.array(cols).T
+
+
+def twolevel(p: np.ndarray, f: np.ndarray, N: int, F: int, n_smooth: int,
+             coarse_sweeps: int) -> np.ndarray:
+    """One two-level iteration from the dense pieces: n_smooth red/black
+    sweeps, residual, factor-F restriction, coarse_sweeps red/black sweeps
+    from zero on the coarse 5-point operator, spline prolongation by F, no
+    post-smoothing."""
+    n, nc = N + 1, N // F + 1
+    for _ in range(n_smooth):
+        p = half_sweep(p, f, n, PERIODIC, 0)
+        p = half_sweep(p, f, n, PERIODIC, 1)
+    r = f - operator(n, PERIODIC) @ p
+    rc = restrict_factor(N, F) @ r
+    d = np.zeros_like(rc)
+    for _ in range(coarse_sweeps):
+        d = half_sweep(d, rc, nc, PERIODIC, 0)
+        d = half_sweep(d, rc, nc, PERIODIC, 1)
+    P1 = spline_1d_factor(N // F, F)
+    return p + np.kron(P1, P1) @ d

@@ -20,12 +20,17 @@ the divergence of a random velocity field with a Kolmogorov-like spectrum.
 
 from .rhs import (  # noqa: F401
     SIZES_BATCHED,
+    TWOLEVEL_BATCH,
+    TWOLEVEL_N,
     batch_sizes,
     grid_unknowns,
+    initial_grid_periodic,
     manufactured_solution,
     rhs_divu_dirichlet,
     rhs_divu_periodic,
     rhs_manufactured_dirichlet,
+    rhs_twolevel_periodic,
+    twolevel_batch,
     velocity_periodic,
     workload,
 )

@@ -100,7 +100,11 @@ def rhs_divu_periodic(n: int, seed: int, kmax: float | None = None) -> np.ndarra
     RMS over the unique nodes.  Returned with the duplicated seam.
     """
     _check_n(n)
-    N = n - 1
+    return _divu_periodic(n - 1, seed, kmax)
+
+
+def _divu_periodic(N: int, seed: int, kmax: float | None) -> np.ndarray:
+    """rhs_divu_periodic on N unique nodes per side (any even N)."""
     if kmax is None:
         kmax = N / 4
     rng = np.random.default_rng(seed)
@@ -179,6 +183,42 @@ def rhs_divu_dirichlet(n: int, seed: int, kmax: float | None = None) -> np.ndarr
     f = np.zeros((n, n), dtype=np.float64)
     f[1:-1, 1:-1] = interior
     return f
+
+
+# The paper's controlled two-level experiment (Section 4.1, Table 1): 192 x 192
+# periodic grids, a test set of 100 sources.
+TWOLEVEL_N = 192
+TWOLEVEL_BATCH = 100
+
+
+def rhs_twolevel_periodic(N: int, seed: int, kmax: float | None = None) -> np.ndarray:
+    """Periodic source on N unique nodes per side (N even, not necessarily
+    4 * 2^k; stored with the seam as (N+1, N+1)): the rhs_divu_periodic recipe
+    (divergence of a k^(-5/3) velocity field, kmax = N/4 by default, mean
+    removed, unit RMS)."""
+    if N < 8 or N % 2:
+        raise ValueError(f"unique side N={N} must be even and >= 8")
+    return _divu_periodic(N, seed, kmax)
+
+
+def initial_grid_periodic(N: int, seed: int, scale: float = 1e-3) -> np.ndarray:
+    """The initially random pressure grid of the two-level experiment
+    (Table 1's N_smooth,pre sweeps then smooth it): ``scale *
+    default_rng(seed).standard_normal((N, N))``, stored with the seam.  The
+    default scale is the order of the pressure a unit-RMS source of this
+    kind produces on the unit torus."""
+    rng = np.random.default_rng(seed)
+    return _with_seam(scale * rng.standard_normal((N, N)))
+
+
+def twolevel_batch(seed: int = 0, count: int = TWOLEVEL_BATCH, N: int = TWOLEVEL_N):
+    """The two-level test set: problem b has source rhs_twolevel_periodic(N,
+    2000 + b) and initial grid initial_grid_periodic(N, 3000 + b); ``seed``
+    shifts both seed bases by 10000 * seed.  Returns (f, p0) arrays of shape
+    (count, N+1, N+1)."""
+    f = np.stack([rhs_twolevel_periodic(N, 10000 * seed + 2000 + b) for b in range(count)])
+    p0 = np.stack([initial_grid_periodic(N, 10000 * seed + 3000 + b) for b in range(count)])
+    return f, p0
 
 
 def batch_sizes(seed: int, count: int = 256) -> list[int]:
