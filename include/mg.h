@@ -275,6 +275,55 @@ MG_API int32_t mg_restrict(mg_ctx ctx, int32_t problem, int32_t level, const voi
                     int32_t dtype);
 MG_API int32_t mg_coarse_solve(mg_ctx ctx, int32_t problem, const void* f, void* u, int32_t dtype);
 
+/* The paper's controlled two-level experiment (Section 4.1: a 192 x 192
+ * periodic grid coarsened directly to 12 x 12, N_step = 4 and r_min = 12 in
+ * Table 1; the appendix's V-CYCLE with one coarse level, which is relaxed 10
+ * times rather than solved), for a batch of problems.  One iteration:
+ * n_smooth red-black Gauss-Seidel sweeps (red = (i+j) even first) on
+ * A p = f, r = f - A p, r_c = R r with R the tensor product of the 1-D
+ * weights (F - |a|) / F^2, |a| < F (full weighting widened to the factor F;
+ * the paper names no weights), coarse_sweeps red-black sweeps from d_c = 0 on
+ * the 5-point system of spacing F h, then p += P d_c with P the periodic
+ * tensor cubic spline (Section 2.2) by the factor F.  There is no
+ * post-smoothing: the paper relaxes at the start of each iteration.
+ * Grids: N = n_unique nodes per side on the unit torus (h = 1/N), stored
+ * with the seam as (N+1) x (N+1); p and f are device arrays of `batch`
+ * such grids back to back ([batch][N+1][N+1], FP64), owned by the caller;
+ * p is updated in place (seams rewritten), f must have zero mean.  One
+ * workgroup runs each problem, the whole solve in one launch.
+ *   mg_twolevel_setup: N in {64, 128, 192}; factor F = 2^N_step in
+ *     {4, 8, 16, 32} with N/F even (the coarse side r_min = N/F); n_smooth
+ *     and coarse_sweeps in 0..1000 (the paper: 20 and 10).  Allocates the
+ *     workspaces (packed h^2 f, the smoothed iterate and the residual: 3
+ *     arrays of batch N^2 doubles).  Errors: INVALID_ARG, UNSUPPORTED (N),
+ *     OOM, HIP.
+ *   mg_twolevel_smooth: `sweeps` red-black sweeps on every problem (the
+ *     paper's N_smooth,pre sweeps on the initial random grid).  Asynchronous.
+ *   mg_twolevel_cycle: `ncycles` iterations on every problem; with
+ *     change_out (host [batch]) the call synchronises and writes the last
+ *     iteration's ||p_i - p_(i-1)||_2 over the unique nodes, else it is
+ *     asynchronous.  NONFINITE if a change is NaN or infinite.
+ *   mg_twolevel_solve: n_pre sweeps, then iterations until a problem's change
+ *     is <= tol (the paper's stopping rule, Section 4.2) or max_iter; each
+ *     problem stops on its own, on the device.  Synchronises once at the
+ *     end; iters_out / change_out (host [batch], may be NULL) receive the
+ *     iteration count and the last change.  Returns OK when every problem
+ *     converged, else NOT_CONVERGED or NONFINITE (outputs filled).
+ *   mg_twolevel_destroy: frees the context (NULL accepted).
+ * A context is not thread-safe.  Errors of the run calls: INVALID_ARG (NULL
+ * context or arrays, p == f, negative counts, tol not >= 0), HIP. */
+typedef struct mg_twolevel_s* mg_twolevel;
+MG_API int32_t mg_twolevel_setup(int32_t n_unique, int32_t factor, int32_t batch,
+                                 int32_t n_smooth, int32_t coarse_sweeps, void* hip_stream,
+                                 mg_twolevel* out);
+MG_API int32_t mg_twolevel_smooth(mg_twolevel ctx, double* p, const double* f, int32_t sweeps);
+MG_API int32_t mg_twolevel_cycle(mg_twolevel ctx, double* p, const double* f, int32_t ncycles,
+                                 double* change_out);
+MG_API int32_t mg_twolevel_solve(mg_twolevel ctx, double* p, const double* f, int32_t n_pre,
+                                 double tol, int32_t max_iter, int32_t* iters_out,
+                                 double* change_out);
+MG_API int32_t mg_twolevel_destroy(mg_twolevel ctx);
+
 /* Kernel classes for the timing diagnostics below. */
 enum {
   MG_K_RELAX = 0,          /* one red-black half-sweep */

@@ -100,6 +100,11 @@ def lib() -> ctypes.CDLL:
         "mg_ns_update": (i32, [i32, vp, vp, vp, ctypes.c_double, vp, vp, i32, i32, vp]),
         "mg_prolong": (i32, [vp, i32, i32, i32, vp, vp, i32]),
         "mg_prolong_noalloc": (i32, [i32, i32, vp, vp, i32, vp]),
+        "mg_twolevel_setup": (i32, [i32, i32, i32, i32, i32, vp, ctypes.POINTER(vp)]),
+        "mg_twolevel_smooth": (i32, [vp, vp, vp, i32]),
+        "mg_twolevel_cycle": (i32, [vp, vp, vp, i32, pd]),
+        "mg_twolevel_solve": (i32, [vp, vp, vp, i32, ctypes.c_double, i32, pi, pd]),
+        "mg_twolevel_destroy": (i32, [vp]),
         "mg_relax": (i32, [vp, i32, i32, vp, vp, i32, i32, i32]),
         "mg_residual": (i32, [vp, i32, i32, vp, vp, vp, i32]),
         "mg_restrict": (i32, [vp, i32, i32, vp, vp, i32]),
@@ -204,6 +209,40 @@ def mg_prolong(ctx: int, problem: int, coarse_level: int, kind: int, coarse: int
 def mg_prolong_noalloc(nc: int, bc: int, coarse: int, fine: int, dtype: int,
                        stream: int = 0) -> None:
     _check(lib().mg_prolong_noalloc(nc, bc, vp(coarse), vp(fine), dtype, vp(stream or None)))
+
+
+def mg_twolevel_setup(n_unique: int, factor: int, batch: int, n_smooth: int = 20,
+                      coarse_sweeps: int = 10, stream: int = 0) -> int:
+    out = vp()
+    _check(lib().mg_twolevel_setup(n_unique, factor, batch, n_smooth, coarse_sweeps,
+                                   vp(stream or None), ctypes.byref(out)))
+    return out.value
+
+
+def mg_twolevel_smooth(ctx: int, p: int, f: int, sweeps: int) -> None:
+    _check(lib().mg_twolevel_smooth(vp(ctx), vp(p), vp(f), sweeps))
+
+
+def mg_twolevel_cycle(ctx: int, p: int, f: int, ncycles: int, batch: int | None = None):
+    """Returns the last iteration's change per problem when batch is given."""
+    ch = (ctypes.c_double * batch)() if batch else None
+    _check(lib().mg_twolevel_cycle(vp(ctx), vp(p), vp(f), ncycles, ch))
+    return list(ch) if batch else None
+
+
+def mg_twolevel_solve(ctx: int, p: int, f: int, batch: int, n_pre: int, tol: float,
+                      max_iter: int):
+    """Returns (status, iterations, changes); raises only on argument/HIP errors."""
+    it = (i32 * batch)()
+    ch = (ctypes.c_double * batch)()
+    st = lib().mg_twolevel_solve(vp(ctx), vp(p), vp(f), n_pre, float(tol), max_iter, it, ch)
+    if st in (MG_ERR_INVALID_ARG, MG_ERR_UNSUPPORTED, MG_ERR_OOM, MG_ERR_HIP):
+        raise MGError(st, mg_last_error())
+    return st, list(it), list(ch)
+
+
+def mg_twolevel_destroy(ctx: int) -> None:
+    _check(lib().mg_twolevel_destroy(vp(ctx)))
 
 
 def mg_relax(ctx: int, problem: int, level: int, u: int, f: int, colour: int, count: int,

@@ -117,3 +117,24 @@ def test_prolong_noalloc_rejects_before_any_device_call(B, nc, bc, dtype, status
 def test_prolong_noalloc_rejects_null_arrays(B):
     assert B.lib().mg_prolong_noalloc(129, 0, None, 0x2000, 0, None) == -1
     assert B.lib().mg_prolong_noalloc(129, 0, 0x1000, 0x1000, 0, None) == -1
+
+
+@pytest.mark.parametrize("N,F,batch,ns,cs,status", [
+    (96, 8, 1, 20, 10, -2),     # unique side not 64, 128 or 192
+    (192, 3, 1, 20, 10, -1),    # factor not a power of two
+    (192, 64, 1, 20, 10, -1),   # factor above 32
+    (192, 16, 0, 20, 10, -1),   # empty batch
+    (192, 16, 1, -1, 10, -1),   # negative sweep count
+])
+def test_twolevel_setup_rejects_before_any_device_call(B, N, F, batch, ns, cs, status):
+    import ctypes
+    out = ctypes.c_void_p()
+    st = B.lib().mg_twolevel_setup(N, F, batch, ns, cs, None, ctypes.byref(out))
+    assert st == status and not out.value
+    assert B.mg_last_error()
+
+
+def test_twolevel_calls_reject_a_null_context(B):
+    assert B.lib().mg_twolevel_smooth(None, 0x1000, 0x2000, 1) == -1
+    assert B.lib().mg_twolevel_cycle(None, 0x1000, 0x2000, 1, None) == -1
+    assert B.lib().mg_twolevel_destroy(None) == 0
