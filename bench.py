@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dirichlet4097",
                     choices=["dirichlet4097", "periodic1025", "dirichlet65", "batch256",
-                             "periodic1025_srcnn", "periodic4097_projection"])
+                             "periodic1025_srcnn", "periodic4097_projection", "twolevel192"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -336,6 +336,135 @@ def bench_projection(args) -> int:
     return 0
 
 
+# FP64 vector arithmetic of MI355X for single adds and multiplies (the
+# two-level kernel has no fused multiply-adds): 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz = 39.3 T operations/s (the published 78.6 TFLOP/s counts an FMA
+# as two).
+FP64_ADDMUL_PEAK_TFLOPS = 39.3
+
+
+def twolevel_flops(N, F, n_smooth, coarse_sweeps):
+    """Algorithmic FP64 operations of one two-level iteration of one problem:
+    5 per node and sweep (three adds for the neighbour sum, one add, one
+    multiply), 7 per node for the residual, 2 per weight for the two
+    restriction passes, 5 per coarse node and sweep, 2 Nc per coefficient for
+    the two prefilter products, 8 per x-interpolated value, 10 per node for
+    the evaluation along y, the correction and the change."""
+    Nc = N // F
+    return (5 * n_smooth * N * N + 7 * N * N + 2 * (2 * F - 1) * (N * Nc + Nc * Nc)
+            + 5 * coarse_sweeps * Nc * Nc + 2 * 2 * Nc * Nc * Nc + 8 * Nc * N + 10 * N * N)
+
+
+def bench_twolevel(args) -> int:
+    """The paper's controlled two-level experiment (Section 4.1, Table 1):
+    the 100-problem test set of 192 x 192 periodic grids coarsened directly to
+    12 x 12 (N_step = 4), 20 sweeps per iteration, the coarse level relaxed 10
+    times, N_smooth,pre = 10 on the random initial grid, stop once the change
+    between iterates is <= 1e-10.  A step is one iteration of the whole test
+    set (every problem active).  Also reported: time to tolerance of the
+    whole set (device-side stopping per problem)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2403_07936_amd import binding as B
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    B.lib()
+    N, F, ns, cs, npre, tol = workloads.TWOLEVEL_N, 16, 20, 10, 10, 1e-10
+    count = workloads.TWOLEVEL_BATCH
+    log(f"generating the two-level test set ({count} problems of {N}^2) seed {args.seed}")
+    f, p0 = workloads.twolevel_batch(args.seed)
+    ft = torch.from_numpy(f).to(dev)
+    pt = torch.from_numpy(p0).to(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = B.mg_twolevel_setup(N, F, count, ns, cs, stream)
+    try:
+        B.mg_twolevel_cycle(ctx, pt.data_ptr(), ft.data_ptr(), args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.mg_twolevel_cycle(ctx, pt.data_ptr(), ft.data_ptr(), args.steps)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+
+        # The iteration kernel alone, with HIP events on the stream it runs on:
+        # a call of K iterations packs h^2 f once, so the difference between
+        # K and 1 iterations over K - 1 is one launch of the iteration kernel.
+        def timed(k, reps=3):
+            best = None
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                B.mg_twolevel_cycle(ctx, pt.data_ptr(), ft.data_ptr(), k)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                best = ms if best is None else min(best, ms)
+            return best * 1e-3
+
+        k = max(args.steps, 2)
+        t_launch = (timed(k) - timed(1)) / (k - 1)
+        best = None
+        for _ in range(3):
+            pt.copy_(torch.from_numpy(p0))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, it, ch = B.mg_twolevel_solve(ctx, pt.data_ptr(), ft.data_ptr(), count, npre, tol,
+                                             300)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, st, it, ch)
+        log(f"two-level: {sec * 1e3:.3f} ms per iteration of the test set "
+            f"(kernel {t_launch * 1e6:.1f} us); all to change <= {tol:g}: "
+            f"{best[0] * 1e3:.2f} ms, iterations {min(best[2])}..{max(best[2])}, status {best[1]}")
+    finally:
+        B.mg_twolevel_destroy(ctx)
+    flops = count * twolevel_flops(N, F, ns, cs)
+    ach = flops / t_launch / 1e12
+    roofline = {"bound": "alu", "kernel": "k_twolevel", "achieved": round(ach, 3),
+                "peak": FP64_ADDMUL_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP64_ADDMUL_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_us": round(t_launch * 1e6, 2), "flops_per_launch": flops,
+                "note": f"{count} workgroups (one per problem) on 256 compute units"}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            b = done % count
+            oracle.twolevel(p0[b], f[b], F, ns, cs)
+            done += 1
+        el = time.perf_counter() - t0
+        cpu = {"value": round(done * N * N / el, 1), "unit": "grid-points/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{done} two-level iterations of test-set problems ({el:.1f} s, plain "
+                         f"C oracle, OpenMP over independent grid lines)"}
+    out = {
+        "metric": "grid-points/s per two-level iteration of the 100-problem 192^2 test set, "
+                  "and time to a change <= 1e-10",
+        "value": round(count * N * N / sec, 1), "unit": "grid-points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "twolevel192", "problems": count, "n_unique": N, "factor": F,
+                   "coarse": N // F, "n_smooth": ns, "coarse_sweeps": cs, "n_smooth_pre": npre,
+                   "tol_change": tol, "bc": "periodic", "seed": args.seed},
+        "time_to_tol_s": round(best[0], 6), "status": best[1],
+        "iterations": {"min": min(best[2]), "max": max(best[2]),
+                       "mean": round(float(np.mean(best[2])), 2)},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def measure_single(n, bc, f, steps, warmup, tune_cache, dev, reps=3):
     """FP64 and mixed paths on one resident grid: seconds per step (K steps
     after W warm-up steps, each one mg_vcycle call), and the best of `reps`
@@ -558,6 +687,8 @@ def main() -> int:
         return bench_srcnn(args)
     if args.workload == "periodic4097_projection":
         return bench_projection(args)
+    if args.workload == "twolevel192":
+        return bench_twolevel(args)
 
     import numpy as np
     import torch

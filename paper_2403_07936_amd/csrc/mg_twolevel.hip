@@ -76,8 +76,10 @@ __device__ __forceinline__ int fresh(int i) {
   return i;
 }
 
-// h^2 f packed per (problem, colour, thread): entry i * PX/2 + k of colour c
-// is the node (y0 + i, x0 + ((i + c) & 1) + 2k) of the thread's patch.
+// h^2 f packed per (problem, colour, entry, thread), the thread index
+// fastest (a wave's loads of one entry are one contiguous run): entry
+// i * PX/2 + k of colour c is the node (y0 + i, x0 + ((i + c) & 1) + 2k) of
+// the thread's patch.
 template <int PY, int PX>
 __global__ __launch_bounds__(256) void k_tl_pack(int batch, const double* __restrict__ f,
                                                  double h2, double* __restrict__ g) {
@@ -86,11 +88,11 @@ __global__ __launch_bounds__(256) void k_tl_pack(int batch, const double* __rest
   const long total = (long)batch * 2 * kTlThreads * L;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
        e += (long)gridDim.x * blockDim.x) {
-    const int k = (int)(e % L);
-    const long rest = e / L;
-    const int tid = (int)(rest % kTlThreads);
-    const int c = (int)((rest / kTlThreads) % 2);
-    const long b = rest / (2 * kTlThreads);
+    const int tid = (int)(e % kTlThreads);
+    const long rest = e / kTlThreads;
+    const int k = (int)(rest % L);
+    const int c = (int)((rest / L) % 2);
+    const long b = rest / (2 * L);
     const int i = k / HX, m = k % HX;
     const int y = (tid / kTlCols) * PY + i, x = (tid % kTlCols) * PX + ((i + c) & 1) + 2 * m;
     g[e] = h2 * f[b * n * n + (long)y * n + x];
@@ -119,64 +121,98 @@ __device__ __forceinline__ void tl_publish(const double (&u)[PY][PX], double* B,
   }
 }
 
-// One half-sweep of colour C: reads the other colour's edge values of the
-// neighbouring patches from their buffer, updates this colour, publishes
-// this colour's edges, then one barrier (the buffer written here was last
-// read in the half-sweep before the previous barrier).
-template <int PY, int PX, int C>
-__device__ __forceinline__ void tl_half_sweep(double (&u)[PY][PX], double* E,
-                                              const double* __restrict__ gk, int tid, int tx,
-                                              int ty) {
+// Rows of h^2 f in flight: the row of step t (t = colour * PY + row, 2 PY
+// steps per sweep) sits in slot t % S, S = tl_slots<PY>() dividing 2 PY, so
+// a step's slot is the same in every sweep and known at compile time.  Each
+// step loads the row S - 1 steps ahead (into the next sweep for the last
+// steps: h^2 f does not change between sweeps).
+// Three slots for the 6 x 12 patch (its 144 registers leave room for no
+// more), four otherwise.
+template <int PY>
+constexpr int tl_slots() { return PY == 6 ? 3 : 4; }
+
+// One row of one half-sweep (step T of the sweep) on the patch u: reads the
+// other colour's edge values of the neighbouring patches from that colour's
+// exchange buffer.
+template <int PY, int PX, int T>
+__device__ __forceinline__ void tl_row(double (&u)[PY][PX], double (&ring)[tl_slots<PY>()][PX / 2],
+                                       const double* E, const double* g0, const double* g1,
+                                       int up, int dn, int lf, int rt) {
 #pragma clang fp contract(off)
-  constexpr int HX = PX / 2, HY = PY / 2, O = 1 - C;
+  constexpr int HX = PX / 2, HY = PY / 2;
+  constexpr int C = T / PY, i = T % PY, O = 1 - C;
   constexpr int BUF = kTlThreads * (PX + PY);
+  constexpr int kTlSlots = tl_slots<PY>();
+  // Prefetch the row kTlSlots - 1 steps ahead.
+  constexpr int TA = (T + kTlSlots - 1) % (2 * PY);
+  {
+    // The row's offset is formed afresh at every step: otherwise the compiler
+    // keeps the addresses of all 2 PY rows live across the sweep loop.
+    const double* ga = (TA / PY ? g1 : g0) + fresh((TA % PY) * HX * kTlThreads);
+#pragma unroll
+    for (int k = 0; k < HX; ++k) ring[TA % kTlSlots][k] = ga[k * kTlThreads];
+  }
   const double* B = E + O * BUF;
   const double* Bt = B;
   const double* Bb = B + kTlThreads * HX;
   const double* Bl = B + 2 * kTlThreads * HX;
   const double* Br = B + 2 * kTlThreads * HX + kTlThreads * HY;
-  const int up = ((ty + kTlRows - 1) % kTlRows) * kTlCols + tx;
-  const int dn = ((ty + 1) % kTlRows) * kTlCols + tx;
-  const int lf = ty * kTlCols + (tx + kTlCols - 1) % kTlCols;
-  const int rt = ty * kTlCols + (tx + 1) % kTlCols;
-  // Row by row, each row's loads issued just before its updates (the
-  // scheduling barrier keeps the compiler from hoisting every row's loads
-  // beside the patch).
 #pragma unroll
-  for (int i = 0; i < PY; ++i) {
-    double gv[HX];
-#pragma unroll
-    for (int k = 0; k < HX; ++k) gv[k] = gk[i * HX + k];
-#pragma unroll
-    for (int k = 0; k < HX; ++k) {
-      const int j = ((i + C) & 1) + 2 * k;
-      const double vu = i == 0 ? Bb[up * HX + (j >> 1)] : u[i > 0 ? i - 1 : 0][j];
-      const double vd = i == PY - 1 ? Bt[dn * HX + (j >> 1)] : u[i < PY - 1 ? i + 1 : 0][j];
-      const double vl = j == 0 ? Br[lf * HY + (i >> 1)] : u[i][j > 0 ? j - 1 : 0];
-      const double vr = j == PX - 1 ? Bl[rt * HY + (i >> 1)] : u[i][j < PX - 1 ? j + 1 : 0];
-      const double s = ((vu + vd) + vl) + vr;
-      u[i][j] = (gv[k] + s) * 0.25;
-    }
-    __builtin_amdgcn_sched_barrier(0);
+  for (int k = 0; k < HX; ++k) {
+    const int j = ((i + C) & 1) + 2 * k;
+    const double vu = i == 0 ? Bb[up * HX + (j >> 1)] : u[i > 0 ? i - 1 : 0][j];
+    const double vd = i == PY - 1 ? Bt[dn * HX + (j >> 1)] : u[i < PY - 1 ? i + 1 : 0][j];
+    const double vl = j == 0 ? Br[lf * HY + (i >> 1)] : u[i][j > 0 ? j - 1 : 0];
+    const double vr = j == PX - 1 ? Bl[rt * HY + (i >> 1)] : u[i][j < PX - 1 ? j + 1 : 0];
+    const double s = ((vu + vd) + vl) + vr;
+    u[i][j] = (ring[T % kTlSlots][k] + s) * 0.25;
   }
-  tl_publish<PY, PX, C>(u, E + C * BUF, tid);
-  __syncthreads();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int PY, int PX, int T>
+__device__ __forceinline__ void tl_steps(double (&u)[PY][PX],
+                                         double (&ring)[tl_slots<PY>()][PX / 2],
+                                         double* E, const double* g0, const double* g1, int tid,
+                                         int up, int dn, int lf, int rt) {
+  if constexpr (T < 2 * PY) {
+    tl_row<PY, PX, T>(u, ring, E, g0, g1, up, dn, lf, rt);
+    if constexpr (T % PY == PY - 1) {
+      // End of a half-sweep: publish this colour's edges (its buffer was last
+      // read before the previous barrier), then one barrier.
+      constexpr int C = T / PY;
+      tl_publish<PY, PX, C>(u, E + C * kTlThreads * (PX + PY), tid);
+      __syncthreads();
+    }
+    tl_steps<PY, PX, T + 1>(u, ring, E, g0, g1, tid, up, dn, lf, rt);
+  }
 }
 
 template <int PY, int PX>
 __device__ __forceinline__ void tl_smooth(double (&u)[PY][PX], double* E, const double* gb,
                                           int sweeps, int tid, int tx, int ty) {
-  constexpr int L = PY * (PX / 2);
-  const double* g0 = gb + (size_t)tid * L;
-  const double* g1 = gb + ((size_t)kTlThreads + tid) * L;
-  // The red half-sweep reads black edges: publish them first.
+  constexpr int HX = PX / 2, L = PY * HX, kTlSlots = tl_slots<PY>();
+  static_assert((2 * PY) % kTlSlots == 0, "the ring must divide the steps of a sweep");
+  const double* g0 = gb + tid;
+  const double* g1 = gb + (size_t)L * kTlThreads + tid;
+  const int up = ((ty + kTlRows - 1) % kTlRows) * kTlCols + tx;
+  const int dn = ((ty + 1) % kTlRows) * kTlCols + tx;
+  const int lf = ty * kTlCols + (tx + kTlCols - 1) % kTlCols;
+  const int rt = ty * kTlCols + (tx + 1) % kTlCols;
+  double ring[kTlSlots][HX];
+#pragma unroll
+  for (int t = 0; t < kTlSlots - 1; ++t)
+#pragma unroll
+    for (int k = 0; k < HX; ++k)
+      ring[t][k] = (t / PY ? g1 : g0)[((t % PY) * HX + k) * kTlThreads];
+  // The red half-sweep reads black edges: publish them first; the red ones
+  // too, so that both buffers hold the patch's edges even after no sweep
+  // (the residual reads them).
+  tl_publish<PY, PX, 0>(u, E, tid);
   tl_publish<PY, PX, 1>(u, E + kTlThreads * (PX + PY), tid);
   __syncthreads();
 #pragma unroll 1
-  for (int s = 0; s < sweeps; ++s) {
-    tl_half_sweep<PY, PX, 0>(u, E, g0, tid, tx, ty);
-    tl_half_sweep<PY, PX, 1>(u, E, g1, tid, tx, ty);
-  }
+  for (int s = 0; s < sweeps; ++s) tl_steps<PY, PX, 0>(u, ring, E, g0, g1, tid, up, dn, lf, rt);
 }
 
 // Patch store to the caller's grid, seam included (row and column N repeat
@@ -201,16 +237,15 @@ __device__ __forceinline__ void tl_store(const double (&u)[PY][PX], double* p, i
 
 // One launch = one iteration of every active problem (or, with
 // a.sweeps > 0, that many smoothing sweeps and nothing else).
-template <int PY, int PX>
+template <int PY, int PX, int F>
 __global__ __launch_bounds__(kTlThreads) void k_twolevel(TlArgs a) {
 #pragma clang fp contract(off)
   extern __shared__ double lds[];
-  constexpr int N = 32 * PY, n = N + 1, L = PY * (PX / 2);
+  constexpr int N = 32 * PY, n = N + 1, L = PY * (PX / 2), Nc = N / F;
   const int b = blockIdx.x;
   if (a.sweeps == 0 && !a.active[b]) return;  // the same value for the whole workgroup
   const int tid = threadIdx.x, tx = tid % kTlCols, ty = tid / kTlCols;
   const int y0 = ty * PY, x0 = tx * PX;
-  const int F = a.F, Nc = a.Nc;
   double* p = a.p + (size_t)b * n * n;
   const double* f = a.f + (size_t)b * n * n;
   const double* gb = a.g + (size_t)b * 2 * kTlThreads * L;
@@ -225,6 +260,10 @@ __global__ __launch_bounds__(kTlThreads) void k_twolevel(TlArgs a) {
   double* XR = S;                  // Nc x N: the coefficients interpolated along x
   double* red = lds + (2 * kTlThreads * (PX + PY) > N * Nc + Nc * Nc
                            ? 2 * kTlThreads * (PX + PY) : N * Nc + Nc * Nc);
+  double* W = red + kTlThreads;    // 4F B-spline weights
+  double* M = S + 2 * Nc * Nc;     // Nc x Nc prefilter matrix (loaded in phase 5)
+  static_assert(3 * Nc * Nc <= N * Nc, "d_c, t and the matrix must fit over the x-sums");
+  for (int t = threadIdx.x; t < 4 * F; t += kTlThreads) W[t] = a.w[t];
 
   {
     // Smoothing: the patch lives in registers only here.
@@ -241,33 +280,41 @@ __global__ __launch_bounds__(kTlThreads) void k_twolevel(TlArgs a) {
     }
     // 1. pre-smoothing (the appendix relaxes at the start of an iteration)
     tl_smooth<PY, PX>(u, E, gb, a.n_smooth, tid, tx, ty);
-    const int os = fresh(y0 * N + x0);
+    // The smoothed patch, thread index fastest (for the correction in 7).
+    double* pt = ps + tid;
 #pragma unroll
     for (int i = 0; i < PY; ++i)
 #pragma unroll
-      for (int j = 0; j < PX; ++j) ps[os + i * N + j] = u[i][j];
-  }
-  __syncthreads();
-  // 2. r = f - A p with A p = (4 p - (up + down + left + right)) N^2, from
-  //    the smoothed iterate (this thread's own values as it stored them)
-  const double inv_h2 = (double)N * (double)N;
-#pragma unroll 1
-  for (int i = 0; i < PY; ++i) {
-    const int y = y0 + i;
-    const double* srow = ps + (size_t)y * N;
-    const double* sup = ps + (size_t)wrapi(y - 1, N) * N;
-    const double* sdn = ps + (size_t)wrapi(y + 1, N) * N;
-    const double* frow = f + (size_t)y * n;
-    double* rrow = rr + (size_t)y * N;
-    double c[PX + 2];
+      for (int j = 0; j < PX; ++j) pt[(i * PX + j) * kTlThreads] = u[i][j];
+    // 2. r = f - A p with A p = (4 p - (up + down + left + right)) N^2.
+    //    Neighbours across the patch's edges come from the exchange buffers,
+    //    which hold both colours' edge values after the last sweep.
+    constexpr int HX = PX / 2, HY = PY / 2, BUF = kTlThreads * (PX + PY);
+    const int up = ((ty + kTlRows - 1) % kTlRows) * kTlCols + tx;
+    const int dn = ((ty + 1) % kTlRows) * kTlCols + tx;
+    const int lf = ty * kTlCols + (tx + kTlCols - 1) % kTlCols;
+    const int rt = ty * kTlCols + (tx + 1) % kTlCols;
+    const double inv_h2 = (double)N * (double)N;
 #pragma unroll
-    for (int j = 0; j < PX + 2; ++j) c[j] = srow[wrapi(x0 - 1 + j, N)];
+    for (int i = 0; i < PY; ++i) {
+      const int y = y0 + i;
+      const double* frow = f + fresh(y * n + x0);
+      double* rrow = rr + fresh(y * N + x0);
 #pragma unroll
-    for (int j = 0; j < PX; ++j) {
-      const int x = x0 + j;
-      const double s = ((sup[x] + sdn[x]) + c[j]) + c[j + 2];
-      const double au = (4.0 * c[j + 1] - s) * inv_h2;
-      rrow[x] = frow[x] - au;
+      for (int j = 0; j < PX; ++j) {
+        const double* Bu = E + ((1 + j) & 1) * BUF + kTlThreads * HX;          // bottom rows
+        const double* Bd = E + (j & 1) * BUF;                                  // top rows
+        const double* Bl = E + ((1 + i) & 1) * BUF + 2 * kTlThreads * HX + kTlThreads * HY;
+        const double* Br = E + (i & 1) * BUF + 2 * kTlThreads * HX;            // left columns
+        const double vu = i > 0 ? u[i > 0 ? i - 1 : 0][j] : Bu[up * HX + (j >> 1)];
+        const double vd = i < PY - 1 ? u[i < PY - 1 ? i + 1 : 0][j] : Bd[dn * HX + (j >> 1)];
+        const double vl = j > 0 ? u[i][j > 0 ? j - 1 : 0] : Bl[lf * HY + (i >> 1)];
+        const double vr = j < PX - 1 ? u[i][j < PX - 1 ? j + 1 : 0] : Br[rt * HY + (i >> 1)];
+        const double s = ((vu + vd) + vl) + vr;
+        const double au = (4.0 * u[i][j] - s) * inv_h2;
+        rrow[j] = frow[j] - au;
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   __syncthreads();
@@ -278,7 +325,7 @@ __global__ __launch_bounds__(kTlThreads) void k_twolevel(TlArgs a) {
     const int i = t / Nc, J = t % Nc;
     const double* row = rr + (size_t)i * N;
     double acc = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int q = -(F - 1); q <= F - 1; ++q) {
       const double wq = (double)(F - (q < 0 ? -q : q)) / wden;
       acc += wq * row[wrapi(F * J + q, N)];
@@ -290,7 +337,7 @@ __global__ __launch_bounds__(kTlThreads) void k_twolevel(TlArgs a) {
   for (int t = tid; t < Nc * Nc; t += kTlThreads) {
     const int I = t / Nc, J = t % Nc;
     double acc = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int q = -(F - 1); q <= F - 1; ++q) {
       const double wq = (double)(F - (q < 0 ? -q : q)) / wden;
       acc += wq * S[wrapi(F * I + q, N) * Nc + J];
@@ -316,12 +363,14 @@ __global__ __launch_bounds__(kTlThreads) void k_twolevel(TlArgs a) {
     __syncthreads();
   }
   // 5. B-spline coefficients of d_c (rows, then columns)
+  for (int t = tid; t < Nc * Nc; t += kTlThreads) M[t] = a.m[t];
+  __syncthreads();
 #pragma unroll 1
   for (int t = tid; t < Nc * Nc; t += kTlThreads) {
     const int I = t / Nc, J = t % Nc;
     double acc = 0.0;
 #pragma unroll 1
-    for (int k = 0; k < Nc; ++k) acc += a.m[J * Nc + k] * DC[I * Nc + k];
+    for (int k = 0; k < Nc; ++k) acc += M[J * Nc + k] * DC[I * Nc + k];
     T[t] = acc;
   }
   __syncthreads();
@@ -330,7 +379,7 @@ __global__ __launch_bounds__(kTlThreads) void k_twolevel(TlArgs a) {
     const int I = t / Nc, J = t % Nc;
     double acc = 0.0;
 #pragma unroll 1
-    for (int k = 0; k < Nc; ++k) acc += a.m[I * Nc + k] * T[k * Nc + J];
+    for (int k = 0; k < Nc; ++k) acc += M[I * Nc + k] * T[k * Nc + J];
     CC[t] = acc;
   }
   __syncthreads();
@@ -338,7 +387,7 @@ __global__ __launch_bounds__(kTlThreads) void k_twolevel(TlArgs a) {
 #pragma unroll 1
   for (int t = tid; t < Nc * N; t += kTlThreads) {
     const int I = t / N, x = t % N, J0 = x / F;
-    const double* wx = a.w + 4 * (x % F);
+    const double* wx = W + 4 * (x % F);
     const double* row = CC + I * Nc;
     double h = 0.0;
 #pragma unroll
@@ -349,22 +398,22 @@ __global__ __launch_bounds__(kTlThreads) void k_twolevel(TlArgs a) {
   // 7. then along y per node: p += P_F d_c from the smoothed iterate; the
   //    iteration's change against the previous iterate (still in p); store
   double ch = 0.0;
-#pragma unroll 1
+#pragma unroll 2
   for (int i = 0; i < PY; ++i) {
     const int y = y0 + i, I0 = y / F;
-    const double* wy = a.w + 4 * (y % F);
+    const double* wy = W + 4 * (y % F);
     const double w0 = wy[0], w1 = wy[1], w2 = wy[2], w3 = wy[3];
     const double* r0 = XR + wrapi(I0 - 1, Nc) * N + x0;
     const double* r1 = XR + I0 * N + x0;
     const double* r2 = XR + wrapi(I0 + 1, Nc) * N + x0;
     const double* r3 = XR + wrapi(I0 + 2, Nc) * N + x0;
-    const double* srow = ps + (size_t)y * N + x0;
+    const double* srow = ps + tid + i * PX * kTlThreads;
     double* prow = p + (size_t)y * n + x0;
     double nv[PX];
 #pragma unroll
     for (int j = 0; j < PX; ++j) {
       const double v = ((w0 * r0[j] + w1 * r1[j]) + w2 * r2[j]) + w3 * r3[j];
-      nv[j] = srow[j] + v;
+      nv[j] = srow[j * kTlThreads] + v;
       const double d = nv[j] - prow[j];
       ch += d * d;
     }
@@ -398,14 +447,14 @@ size_t tl_lds_bytes(int N, int Nc) {
   const int PY = N / 32, PX = N / 16;
   const size_t e = (size_t)2 * kTlThreads * (PX + PY);
   const size_t t = (size_t)N * Nc + (size_t)Nc * Nc;
-  return (std::max(e, t) + kTlThreads) * sizeof(double);
+  return (std::max(e, t) + kTlThreads + 4 * 32) * sizeof(double);
 }
 
-template <int PY, int PX>
+template <int PY, int PX, int F>
 hipError_t tl_prepare(size_t lds) {
   static bool done = false;
   if (done) return hipSuccess;
-  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_twolevel<PY, PX>),
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_twolevel<PY, PX, F>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
   if (e == hipSuccess) done = true;
@@ -475,7 +524,7 @@ TlArgs tl_args(const mg_twolevel_s* c, double* p, const double* f) {
   return a;
 }
 
-template <int PY, int PX>
+template <int PY, int PX, int F>
 int32_t tl_launch(mg_twolevel_s* c, const TlArgs& a, bool pack) {
   if (pack) {
     const long total = (long)c->batch * 2 * kTlThreads * PY * (PX / 2);
@@ -485,18 +534,29 @@ int32_t tl_launch(mg_twolevel_s* c, const TlArgs& a, bool pack) {
     TL_HIP(hipGetLastError());
   }
   const size_t lds = tl_lds_bytes(c->N, c->Nc);
-  TL_HIP((tl_prepare<PY, PX>(lds)));
-  hipLaunchKernelGGL((k_twolevel<PY, PX>), dim3(c->batch), dim3(kTlThreads), lds, c->stream, a);
+  TL_HIP((tl_prepare<PY, PX, F>(lds)));
+  hipLaunchKernelGGL((k_twolevel<PY, PX, F>), dim3(c->batch), dim3(kTlThreads), lds, c->stream,
+                     a);
   TL_HIP(hipGetLastError());
   return MG_OK;
+}
+
+template <int PY, int PX>
+int32_t tl_launch_f(mg_twolevel_s* c, const TlArgs& a, bool pack) {
+  switch (c->F) {
+    case 4: return tl_launch<PY, PX, 4>(c, a, pack);
+    case 8: return tl_launch<PY, PX, 8>(c, a, pack);
+    case 16: return tl_launch<PY, PX, 16>(c, a, pack);
+    default: return tl_launch<PY, PX, 32>(c, a, pack);
+  }
 }
 
 // One launch: smoothing only (a.sweeps > 0) or one iteration.
 int32_t tl_run(mg_twolevel_s* c, const TlArgs& a, bool pack) {
   switch (c->N) {
-    case 64: return tl_launch<2, 4>(c, a, pack);
-    case 128: return tl_launch<4, 8>(c, a, pack);
-    default: return tl_launch<6, 12>(c, a, pack);
+    case 64: return tl_launch_f<2, 4>(c, a, pack);
+    case 128: return tl_launch_f<4, 8>(c, a, pack);
+    default: return tl_launch_f<6, 12>(c, a, pack);
   }
 }
 
