@@ -259,6 +259,13 @@ hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob);
 hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u64, int p64,
                                   const double* f64, int pf64, float* r32, int pr, float* uout,
                                   int puo, float* fc, int pfc, int hs);
+// uout == nullptr: the pre-smoothed iterate is not stored; the level's up
+// pass must then be launch_up_pre_stream, which makes it again from r32.
+// Mixed path, level 0, after launch_down_res_stream without uout: the up
+// pass that re-makes the pre-smoothed iterate from r32 (same values) and
+// adds the result into u64.
+hipError_t launch_up_pre_stream(hipStream_t s, int bc, int n, const float* f, int pf,
+                                const float* c, int pc, int hs, double* u64, int p64);
 int stream_segment_rows(int n, int bc, int owned_cols);
 int stream_down_owned();
 int stream_up_owned();

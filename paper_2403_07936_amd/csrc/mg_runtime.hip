@@ -422,6 +422,15 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
   const double sz = sizeof(T);
   auto F = [&](int l) { return l == 0 ? f0 : (const T*)h.f[l]; };
   auto PF = [&](int l) { return l == 0 ? pf0 : p.pitch[l]; };
+  // Level l's up pass is a tiled kernel (variant 1, LDS tiles; variant 2,
+  // tiles that prefilter their own coarse support) rather than a stream.
+  auto up_tiled = [&](int l) {
+    return ctx->opt.kernel_path == 2 || p.up_var[l] == 1 || (p.up_var[l] == 2 && l + 1 < t);
+  };
+  // Mixed level 0 whose down pass makes the residual from e = 0 and whose
+  // up pass streams into the FP64 iterate: the up pass makes the
+  // pre-smoothed iterate again from r32, so the down pass does not store it.
+  const bool remake0 = res_u && u64 && t > 0 && !up_tiled(0) && !(cnn && ctx->cnn.levels > 0);
   for (int l = 0; l < t; ++l) {
     const int n = p.side[l];
     const double m = unknowns_side(n, bc), mc = unknowns_side(p.side[l + 1], bc);
@@ -431,9 +440,10 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
       if (l == 0 && res_u) {
         // Mixed level 0: the right-hand side is made from the FP64 iterate
         // inside the down pass (and stored for the up pass).
-        MG_TRY(timed(ctx, s, MG_K_DOWN, 0, (16 + 4 + 4) * m * m + 4 * mc * mc, [&] {
+        MG_TRY(timed(ctx, s, MG_K_DOWN, 0, (16 + 4 + (remake0 ? 0 : 4)) * m * m + 4 * mc * mc, [&] {
           return launch_down_res_stream(s, bc, n, res_u, res_p, res_f, res_p, r_out, pf0,
-                                        h.r[0], p.pitch[0], h.f[1], p.pitch[1], p.down_hs[0]);
+                                        remake0 ? nullptr : h.r[0], p.pitch[0], h.f[1],
+                                        p.pitch[1], p.down_hs[0]);
         }));
         continue;
       }
@@ -484,6 +494,13 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
     const bool tile = ctx->opt.kernel_path == 2 || p.up_var[l] == 1 || pre;
     const bool add = l == 0 && u64 && !tile;
     if (add && added) *added = true;
+    if (l == 0 && remake0) {
+      MG_TRY(timed(ctx, s, MG_K_UP, 0, (4 + 8 + 8) * m * m + ncc * sz, [&] {
+        return launch_up_pre_stream(s, bc, n, (const float*)F(0), PF(0), (const float*)h.c[1], pc,
+                                    p.up_hs[0], u64, p64);
+      }));
+      continue;
+    }
     MG_TRY(timed(ctx, s, MG_K_UP, l, (3 * m * m + ncc) * sz + (add ? 16 * m * m - 4 * m * m : 0), [&] {
       if (tile)
         return launch_up<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l),
@@ -1091,11 +1108,12 @@ int32_t time_launches(mg_ctx_s* ctx, int reps, Launch&& launch, float* ms) {
 // against the LDS-tiled passes, each timed on the level's own arrays (the
 // level-0 caller arrays are stood in for by library arrays of the same
 // shape).  Values do not matter to the timing.  The mixed path's level-0 up
-// pass adds into the FP64 iterate (a different kernel variant, keyed
-// "fp32a"), so it is timed that way, against a scratch FP64 array, and
-// only among the streaming candidates; its streaming down pass makes the
-// FP64 residual itself, so it is timed in that form, and the tiled down
-// pass is charged the separate residual pass it then needs.
+// pass adds into the FP64 iterate and makes the pre-smoothed iterate again
+// (a different kernel, keyed "fp32a"), so it is timed that way, against a
+// scratch FP64 array, and only among the streaming candidates; its
+// streaming down pass makes the FP64 residual itself and stores no
+// pre-smoothed iterate, so it is timed in that form, and the tiled down pass
+// is charged the separate residual pass it then needs.
 template <typename T>
 int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scratch_u, T* scratch_f,
                     int pitch0) {
@@ -1172,9 +1190,11 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
         if (var < 2)  // variant 2 concerns the up pass only
           MG_TRY(time_launches(ctx, reps, [&] {
             if constexpr (sizeof(T) == sizeof(float)) {
+              // As it runs in the cycle: the pre-smoothed iterate is not
+              // stored (the up pass makes it again).
               if (add && var == 0)
                 return launch_down_res_stream(ctx->stream, p.bc, n, u64, p.pitch[0], u64,
-                                              p.pitch[0], scratch_f, pu, h.r[l], p.pitch[l],
+                                              p.pitch[0], scratch_f, pu, nullptr, p.pitch[l],
                                               h.f[l + 1], p.pitch[l + 1], hs);
             }
             return var == 1 ? launch_down<T>(ctx->stream, p.bc, n, uin, pu, h.r[l], p.pitch[l], f,
@@ -1188,6 +1208,11 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
           mu = 1e30f;  // the tiled up pass does not add into the FP64 iterate
         } else {
           MG_TRY(time_launches(ctx, reps, [&] {
+            if constexpr (sizeof(T) == sizeof(float)) {
+              if (add)
+                return launch_up_pre_stream(ctx->stream, p.bc, n, f, pu, h.c[l + 1],
+                                            p.pitch[l + 1], hs, u64, p.pitch[0]);
+            }
             if (var >= 1)
               return launch_up<T>(ctx->stream, p.bc, n, h.r[l], p.pitch[l], u, pu, f, pu,
                                   var == 2 ? h.u[l + 1] : h.c[l + 1], p.pitch[l + 1], var == 2);

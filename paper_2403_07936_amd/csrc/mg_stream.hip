@@ -20,7 +20,9 @@ __global__ void __launch_bounds__(64 * kWaves)
 
 // Level-0 down pass of the mixed path with its right-hand side made from
 // the FP64 iterate (down_wave with RES).
-template <int BC>
+// SB = false: the pre-smoothed iterate is not stored (k_up_pre_s makes it
+// again).
+template <int BC, bool SB>
 __global__ void __launch_bounds__(64 * kWaves)
     k_down_res_s(int n, const double* __restrict__ u64, int p64, const double* __restrict__ f64,
                  int pf64, float* __restrict__ r32, int pr, float* __restrict__ uout, int puo,
@@ -28,9 +30,22 @@ __global__ void __launch_bounds__(64 * kWaves)
                  float inv_h2, double inv_h2d) {
   const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
-  down_wave<float, BC, 0, true>(n, nullptr, 0, uout, puo, nullptr, 0, fc, pfc, item % nbands,
-                                item / nbands, hs, h2, inv_h2, threadIdx.x & 63, u64, p64, f64,
-                                pf64, inv_h2d, r32, pr);
+  down_wave<float, BC, 0, true, SB>(n, nullptr, 0, uout, puo, nullptr, 0, fc, pfc, item % nbands,
+                                    item / nbands, hs, h2, inv_h2, threadIdx.x & 63, u64, p64,
+                                    f64, pf64, inv_h2d, r32, pr);
+}
+
+// Level-0 up pass of the mixed path after k_down_res_s<BC, false>: the
+// pre-smoothed iterate made again from the right-hand side (up_pre_wave),
+// the result added into the FP64 iterate.
+template <int BC>
+__global__ void __launch_bounds__(64 * kWaves)
+    k_up_pre_s(int n, const float* __restrict__ f, int pf, const float* __restrict__ c, int pc,
+               int nbands, int nitems, int hs, float h2, double* __restrict__ u64, int p64) {
+  const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
+  if (item >= nitems) return;
+  up_pre_wave<BC>(n, f, pf, c, pc, item % nbands, item / nbands, hs, h2, threadIdx.x & 63, u64,
+                  p64);
 }
 
 template <typename T, int BC, bool ADD>
@@ -120,14 +135,34 @@ hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u6
   const double hd = 1.0 / (double)(n - 1);
   const double inv_h2d = (double)(n - 1) * (double)(n - 1);
   const float h2 = (float)(hd * hd), inv_h2 = (float)inv_h2d;
+#define MG_DOWN_RES(B, SB)                                                                     \
+  hipLaunchKernelGGL((k_down_res_s<B, SB>), dim3(blocks), dim3(64 * kWaves), 0, s, n, u64, p64, \
+                     f64, pf64, r32, pr, uout, puo, fc, pfc, nb, items, hs, h2, inv_h2, inv_h2d)
+  if (bc == kDirichlet && uout) MG_DOWN_RES(kDirichlet, true);
+  else if (bc == kDirichlet) MG_DOWN_RES(kDirichlet, false);
+  else if (uout) MG_DOWN_RES(kPeriodic, true);
+  else MG_DOWN_RES(kPeriodic, false);
+#undef MG_DOWN_RES
+  return hipGetLastError();
+}
+
+hipError_t launch_up_pre_stream(hipStream_t s, int bc, int n, const float* f, int pf,
+                                const float* c, int pc, int hs, double* u64, int p64) {
+  if ((bc == kPeriodic && n - 1 < 128) || (hs > 0 && (hs & 1)) || !u64)
+    return hipErrorInvalidValue;
+  const int extent = bc == kPeriodic ? n - 1 : n;
+  if (hs <= 0) hs = stream_segment_rows(n, bc, kUpPreOwned);
+  const int nb = (extent + kUpPreOwned - 1) / kUpPreOwned;
+  const int items = nb * ((extent + hs - 1) / hs);
+  const int blocks = (items + kWaves - 1) / kWaves;
+  const double hd = 1.0 / (double)(n - 1);
+  const float h2 = (float)(hd * hd);
   if (bc == kDirichlet)
-    hipLaunchKernelGGL((k_down_res_s<kDirichlet>), dim3(blocks), dim3(64 * kWaves), 0, s, n, u64,
-                       p64, f64, pf64, r32, pr, uout, puo, fc, pfc, nb, items, hs, h2, inv_h2,
-                       inv_h2d);
+    hipLaunchKernelGGL((k_up_pre_s<kDirichlet>), dim3(blocks), dim3(64 * kWaves), 0, s, n, f, pf,
+                       c, pc, nb, items, hs, h2, u64, p64);
   else
-    hipLaunchKernelGGL((k_down_res_s<kPeriodic>), dim3(blocks), dim3(64 * kWaves), 0, s, n, u64,
-                       p64, f64, pf64, r32, pr, uout, puo, fc, pfc, nb, items, hs, h2, inv_h2,
-                       inv_h2d);
+    hipLaunchKernelGGL((k_up_pre_s<kPeriodic>), dim3(blocks), dim3(64 * kWaves), 0, s, n, f, pf,
+                       c, pc, nb, items, hs, h2, u64, p64);
   return hipGetLastError();
 }
 

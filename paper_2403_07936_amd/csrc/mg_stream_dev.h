@@ -177,6 +177,14 @@ __device__ __forceinline__ void load_row(T (&dst)[2], const T* __restrict__ a, i
   load_pair<T>(dst, a + (size_t)r * pa, col.pc, col.sw);
 }
 
+template <typename T>
+__device__ __forceinline__ T fused_mul_add(T a, T b, T c) {
+  if constexpr (sizeof(T) == sizeof(float))
+    return __builtin_fmaf(a, b, c);
+  else
+    return __builtin_fma(a, b, c);
+}
+
 // Red-black half-sweep on one row: the node of the half-sweep's colour among
 // the lane's two columns (column x0 + odd, odd = (colour + row) & 1) solves
 // its equation with its four neighbours fixed.  Callers pass odd as a value
@@ -187,16 +195,19 @@ template <typename T, int BC, bool IN = false>
 __device__ __forceinline__ void sweep_row(const T (&um)[2], T (&u0)[2], const T (&up)[2],
                                           const T (&f0)[2], int row, int odd, int n,
                                           const Cols<BC>& col, T h2) {
+  // h2 f + s as one fused multiply-add, written out: left to the compiler,
+  // whether it fuses depends on how often the unrolled code reuses h2 f,
+  // and the same sweep in two kernels could round differently.
   const bool rok = IN || row_unknown<BC>(row, n);
   if (odd == 0) {
     const T left = from_left(u0[1]);
     const T s = ((um[0] + up[0]) + left) + u0[1];
-    const T v = (h2 * f0[0] + s) * T(0.25);
+    const T v = fused_mul_add(h2, f0[0], s) * T(0.25);
     u0[0] = (rok && col.unk0) ? v : u0[0];
   } else {
     const T right = from_right(u0[0]);
     const T s = ((um[1] + up[1]) + u0[0]) + right;
-    const T v = (h2 * f0[1] + s) * T(0.25);
+    const T v = fused_mul_add(h2, f0[1], s) * T(0.25);
     u0[1] = (rok && col.unk1) ? v : u0[1];
   }
 }
@@ -227,7 +238,7 @@ __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2],
 // stored to rout (pitch pro; f is not used), where the up pass reads them.  The same
 // arithmetic as residual_wave, so r32 is bitwise what that writes on the
 // nodes the up pass reads.
-template <typename T, int BC, int UIN, bool RES, bool IN>
+template <typename T, int BC, int UIN, bool RES, bool IN, bool SB = true>
 __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
@@ -339,7 +350,7 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
       sweep_row<T, BC, IN>(U[(k + 11) & RM], U[(k + 12) & RM], U[(k + 13) & RM], F[(k + 12) & RM],
                        t - 4, (k + 1) & 1, n, col, h2);
       const int tu = t - 4;
-      if (tu >= ys && tu < ys + hs && (IN || tu < row_end)) {
+      if (SB && tu >= ys && tu < ys + hs && (IN || tu < row_end)) {
         T* p = uout + (size_t)tu * puo;
         store_pair<T>(p + x0, wr0, wr1, U[(k + 12) & RM][0], U[(k + 12) & RM][1]);
       }
@@ -362,7 +373,9 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
   }
 }
 
-template <typename T, int BC, int UIN = -1, bool RES = false>
+// SB = false (RES only): the pre-smoothed iterate is not stored (the up pass
+// makes it again from the stored right-hand side, up_pre_wave).
+template <typename T, int BC, int UIN = -1, bool RES = false, bool SB = true>
 __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
@@ -376,23 +389,36 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
   // Inside rows 1 .. n - 2 (periodic: 0 .. n - 2) the interior form runs.
   const int lo = seg * hs - 7, hi = seg * hs + hs + 5;
   const bool in = BC == kPeriodic ? (lo >= 0 && hi <= n - 2) : (lo >= 1 && hi <= n - 2);
+  static_assert(SB || RES, "only the residual-making down pass may skip its iterate");
   if (in)
-    down_wave_rows<T, BC, UIN, RES, true>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
-                                          h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
-                                          pro);
+    down_wave_rows<T, BC, UIN, RES, true, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg,
+                                              hs, h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d,
+                                              rout, pro);
   else
-    down_wave_rows<T, BC, UIN, RES, false>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
-                                           h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
-                                           pro);
+    down_wave_rows<T, BC, UIN, RES, false, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg,
+                                               hs, h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d,
+                                               rout, pro);
 }
 
 // Spline along x at the lane's two columns from coarse row values held one
 // coarse column per lane (lane L holds coefficient column x0/2).
+// The weighted sums of the spline are written as explicit fused multiply-
+// adds (w0 a, then + w1 b, + w2 c, ... each fused), so that every kernel
+// evaluating them rounds the same way.
+template <typename T>
+__device__ __forceinline__ T wsum3(T w0, T a, T w1, T b, T w2, T c) {
+  return fused_mul_add(w2, c, fused_mul_add(w1, b, w0 * a));
+}
+template <typename T>
+__device__ __forceinline__ T wsum4(T w0, T a, T w1, T b, T w2, T c, T w3, T d) {
+  return fused_mul_add(w3, d, fused_mul_add(w2, c, fused_mul_add(w1, b, w0 * a)));
+}
+
 template <typename T>
 __device__ __forceinline__ void spline_x(T cj, T (&out)[2]) {
   const T cl = from_left(cj), cr = from_right(cj), cr2 = from_right(cr);
-  out[0] = (T(1.0 / 6.0) * cl + T(4.0 / 6.0) * cj) + T(1.0 / 6.0) * cr;
-  out[1] = ((T(1.0 / 48.0) * cl + T(23.0 / 48.0) * cj) + T(23.0 / 48.0) * cr) + T(1.0 / 48.0) * cr2;
+  out[0] = wsum3(T(1.0 / 6.0), cl, T(4.0 / 6.0), cj, T(1.0 / 6.0), cr);
+  out[1] = wsum4(T(1.0 / 48.0), cl, T(23.0 / 48.0), cj, T(23.0 / 48.0), cr, T(1.0 / 48.0), cr2);
 }
 
 template <typename T, int BC, bool IN = false>
@@ -489,14 +515,14 @@ __device__ __forceinline__ void up_wave_rows(int n, const T* __restrict__ uin, i
         const T(&b)[2] = CX[(qb + 1) & 3];
         const T(&d)[2] = CX[(qb + 2) & 3];
         if ((k & 1) == 0) {
-          v0 = (T(1.0 / 6.0) * a[0] + T(4.0 / 6.0) * b[0]) + T(1.0 / 6.0) * d[0];
-          v1 = (T(1.0 / 6.0) * a[1] + T(4.0 / 6.0) * b[1]) + T(1.0 / 6.0) * d[1];
+          v0 = wsum3(T(1.0 / 6.0), a[0], T(4.0 / 6.0), b[0], T(1.0 / 6.0), d[0]);
+          v1 = wsum3(T(1.0 / 6.0), a[1], T(4.0 / 6.0), b[1], T(1.0 / 6.0), d[1]);
         } else {
           const T(&e)[2] = CX[(qb + 3) & 3];
-          v0 = ((T(1.0 / 48.0) * a[0] + T(23.0 / 48.0) * b[0]) + T(23.0 / 48.0) * d[0]) +
-               T(1.0 / 48.0) * e[0];
-          v1 = ((T(1.0 / 48.0) * a[1] + T(23.0 / 48.0) * b[1]) + T(23.0 / 48.0) * d[1]) +
-               T(1.0 / 48.0) * e[1];
+          v0 = wsum4(T(1.0 / 48.0), a[0], T(23.0 / 48.0), b[0], T(23.0 / 48.0), d[0],
+                     T(1.0 / 48.0), e[0]);
+          v1 = wsum4(T(1.0 / 48.0), a[1], T(23.0 / 48.0), b[1], T(23.0 / 48.0), d[1],
+                     T(1.0 / 48.0), e[1]);
         }
         const bool rok = IN || row_unknown<BC>(t, n);
         U[k][0] = (rok && col.unk0) ? U[k][0] + v0 : U[k][0];
@@ -546,6 +572,160 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
   else
     up_wave_rows<T, BC, ADD, false>(n, uin, pui, uout, puo, f, pf, c, pc, band, seg, hs, h2, lane,
                                     u64, p64);
+}
+
+// Up pass of the mixed path's level 0 when its down pass started from e = 0
+// and did not store its pre-smoothed iterate: the iterate is made again here
+// from the stored right-hand side f (the same two sweeps from zero, so
+// bitwise the same values), and neither pass moves it through memory.  At
+// the step that loads row t: red sweep on t-1, black t-2, red t-3, black
+// t-4 (the pre-smoothed row t-4); then the up pass proper on row tv = t-5:
+// u += P e_c on tv, red tv-1, black tv-2, red tv-3, black tv-4, added into
+// the FP64 iterate u64.  The lag of five keeps the correction of a row after
+// the last pre-smoothing sweep that reads it (the black sweep of row tv + 1,
+// made at the same step just before).  Rows above the segment start from
+// zero with f = 0 there; that error reaches at most 6 rows below the first
+// loaded one, which is 8 above the segment.  A band owns columns
+// [xw + 8, xw + 120): the edge lanes' missing neighbours spoil one column
+// per half-sweep (eight) and the spline's right support two lanes.
+constexpr int kUpPreLeft = 8;
+constexpr int kUpPreOwned = 112;
+
+template <int BC, bool IN>
+__device__ __forceinline__ void up_pre_wave_rows(int n, const float* __restrict__ f, int pf,
+                                                 const float* __restrict__ c, int pc, int band,
+                                                 int seg, int hs, float h2, int lane,
+                                                 double* __restrict__ u64, int p64) {
+  using T = float;
+  const int xw = band * kUpPreOwned - kUpPreLeft;
+  const int x0 = xw + 2 * lane;
+  const int ys = seg * hs;
+  const Cols<BC> col(x0, n);
+  const int N = n - 1, nc = (n - 1) / 2 + 1;
+  const bool lane_owns = lane >= kUpPreLeft / 2 && lane < kUpPreLeft / 2 + kUpPreOwned / 2;
+  const bool wr0 = lane_owns && (BC == kPeriodic ? x0 < N : col.unk0);
+  const bool wr1 = lane_owns && (BC == kPeriodic ? x0 + 1 < N : col.unk1);
+  const int Jc = x0 >> 1;
+  const int row_end = BC == kPeriodic ? N : n;
+
+  T U[16][2], F[16][2], CX[4][2], CR[8];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) U[k][0] = U[k][1] = F[k][0] = F[k][1] = T(0);
+
+  // Row r sits in ring slot (r - t0) & 15.  The correction starts at row
+  // tv0 = ys - 4 (as in up_wave_rows), at step 9; its own step index
+  // sv = s - 9 drives the coarse-row ring exactly as there.
+  const int t0 = ys - 8;             // first row of the pre-smoothing stage (even)
+  const int tv0 = ys - 4;
+  const int cbase = (tv0 >> 1) - 1;  // coarse row q = 0 of the ring
+#pragma unroll
+  for (int q = 0; q < 7; ++q) CR[q] = load_coef<T, BC, IN>(c, pc, cbase + q, Jc, nc);
+  CR[7] = T(0);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) spline_x<T>(CR[q], CX[q]);
+  CX[3][0] = CX[3][1] = T(0);
+  const int steps = hs + 17;
+  const int tlast = t0 + steps - 1;
+  // u64 row written at step s (row t0 + s - 9) is read kAheadUp steps
+  // earlier into UR[s & 7]; only rows and columns the segment stores.
+  double UR[8][2];
+  const int ylast = (ys + hs < row_end ? ys + hs : row_end) - 1;
+  const Cols<BC> col64(lane_owns ? x0 : xw + kUpPreLeft, n);
+  auto load_u64 = [&](int slot, int row) {
+    const int rr = row < ys ? ys : (row > ylast ? ylast : row);
+    load_pair<double>(UR[slot], u64 + (size_t)rr * p64, col64.pc, col64.sw);
+  };
+#pragma unroll
+  for (int k = 0; k < kAheadUp; ++k) {
+    load_row<T, BC, IN>(F[k], f, pf, t0 + k, n, col);
+    load_u64(k & 7, t0 - 9 + k);
+  }
+  for (int sb = 0; sb < steps; sb += 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int s = sb + k;
+      if (s >= steps) break;
+      const int t = t0 + s;
+      {  // rows kAheadUp ahead; past the last row a step uses, that row again
+        const int ta = t + kAheadUp < tlast ? t + kAheadUp : tlast;
+        load_row<T, BC, IN>(F[(k + kAheadUp) & 15], f, pf, ta, n, col);
+        load_u64((k + kAheadUp) & 7, t - 9 + kAheadUp);
+      }
+      U[k][0] = U[k][1] = T(0);  // row t starts from zero
+      // pre-smoothing from zero (t has the parity of k: t0 and sb are even)
+      sweep_row<T, BC, IN>(U[(k + 14) & 15], U[(k + 15) & 15], U[k], F[(k + 15) & 15], t - 1,
+                           (k + 1) & 1, n, col, h2);
+      sweep_row<T, BC, IN>(U[(k + 13) & 15], U[(k + 14) & 15], U[(k + 15) & 15],
+                           F[(k + 14) & 15], t - 2, (k + 1) & 1, n, col, h2);
+      sweep_row<T, BC, IN>(U[(k + 12) & 15], U[(k + 13) & 15], U[(k + 14) & 15],
+                           F[(k + 13) & 15], t - 3, (k + 1) & 1, n, col, h2);
+      sweep_row<T, BC, IN>(U[(k + 11) & 15], U[(k + 12) & 15], U[(k + 13) & 15],
+                           F[(k + 12) & 15], t - 4, (k + 1) & 1, n, col, h2);
+      if (s < 9) continue;
+      // The up pass on row tv = t - 5: ring slot kv of row tv; kq = sv mod 16
+      // for the coarse ring (sv = s - 9, t has the parity of k, so tv and sv
+      // have the parity of k + 1).
+      const int kv = (k + 11) & 15, kq = (k + 7) & 15;
+      const int sv = s - 9, tv = t - 5;
+      if (kq & 1) {
+        const int qk = ((kq - 1) >> 1) + 3;
+        spline_x<T>(CR[qk & 7], CX[qk & 3]);
+        CR[(qk + 4) & 7] = load_coef<T, BC, IN>(c, pc, cbase + ((sv - 1) >> 1) + 7, Jc, nc);
+      }
+      {
+        const int qb = (kq >> 1);
+        T v0, v1;
+        const T(&a)[2] = CX[qb & 3];
+        const T(&b)[2] = CX[(qb + 1) & 3];
+        const T(&d)[2] = CX[(qb + 2) & 3];
+        if ((kq & 1) == 0) {
+          v0 = wsum3(T(1.0 / 6.0), a[0], T(4.0 / 6.0), b[0], T(1.0 / 6.0), d[0]);
+          v1 = wsum3(T(1.0 / 6.0), a[1], T(4.0 / 6.0), b[1], T(1.0 / 6.0), d[1]);
+        } else {
+          const T(&e)[2] = CX[(qb + 3) & 3];
+          v0 = wsum4(T(1.0 / 48.0), a[0], T(23.0 / 48.0), b[0], T(23.0 / 48.0), d[0],
+                     T(1.0 / 48.0), e[0]);
+          v1 = wsum4(T(1.0 / 48.0), a[1], T(23.0 / 48.0), b[1], T(23.0 / 48.0), d[1],
+                     T(1.0 / 48.0), e[1]);
+        }
+        const bool rok = IN || row_unknown<BC>(tv, n);
+        U[kv][0] = (rok && col.unk0) ? U[kv][0] + v0 : U[kv][0];
+        U[kv][1] = (rok && col.unk1) ? U[kv][1] + v1 : U[kv][1];
+      }
+      sweep_row<T, BC, IN>(U[(kv + 14) & 15], U[(kv + 15) & 15], U[kv], F[(kv + 15) & 15], tv - 1,
+                           (kv + 1) & 1, n, col, h2);
+      sweep_row<T, BC, IN>(U[(kv + 13) & 15], U[(kv + 14) & 15], U[(kv + 15) & 15],
+                           F[(kv + 14) & 15], tv - 2, (kv + 1) & 1, n, col, h2);
+      sweep_row<T, BC, IN>(U[(kv + 12) & 15], U[(kv + 13) & 15], U[(kv + 14) & 15],
+                           F[(kv + 13) & 15], tv - 3, (kv + 1) & 1, n, col, h2);
+      sweep_row<T, BC, IN>(U[(kv + 11) & 15], U[(kv + 12) & 15], U[(kv + 13) & 15],
+                           F[(kv + 12) & 15], tv - 4, (kv + 1) & 1, n, col, h2);
+      const int tu = tv - 4;
+      if (tu >= ys && tu < ys + hs && (IN || tu < row_end)) {
+        double* q = u64 + (size_t)tu * p64;
+        const bool r = IN || row_unknown<BC>(tu, n);
+        store_pair<double>(q + x0, wr0 && col.unk0 && r, wr1 && col.unk1 && r,
+                           UR[k & 7][0] + (double)U[(kv + 12) & 15][0],
+                           UR[k & 7][1] + (double)U[(kv + 12) & 15][1]);
+      }
+    }
+  }
+}
+
+template <int BC>
+__device__ __forceinline__ void up_pre_wave(int n, const float* __restrict__ f, int pf,
+                                            const float* __restrict__ c, int pc, int band, int seg,
+                                            int hs, float h2, int lane, double* __restrict__ u64,
+                                            int p64) {
+  n = wave_uniform(n), band = wave_uniform(band), seg = wave_uniform(seg), hs = wave_uniform(hs);
+  // Fine rows touched: seg * hs - 10 .. seg * hs + hs + 8; coarse rows up to
+  // (seg * hs + hs) / 2 + 7.
+  const int lo = seg * hs - 10, hi = seg * hs + hs + 19;
+  const bool in = lo >= 2 && hi <= n - 1;
+  if (in)
+    up_pre_wave_rows<BC, true>(n, f, pf, c, pc, band, seg, hs, h2, lane, u64, p64);
+  else
+    up_pre_wave_rows<BC, false>(n, f, pf, c, pc, band, seg, hs, h2, lane, u64, p64);
 }
 
 // Mixed path, level 0: r32 = fl32(f - A u) with f, u and the arithmetic in
