@@ -49,9 +49,12 @@ def measured_traffic(kind_name: str, precision: str, bc: int):
     if hh.hexdigest() != rec["sources_sha256"]:
         return None
     t = "float" if precision == "mixed" else "double"
-    if kind_name == "down" and precision == "mixed":
-        # The mixed level-0 down pass that makes the FP64 residual itself.
-        ents = [v for k, v in rec["per_launch"].items() if k == f"k_down_res_s<{bc}>"]
+    if precision == "mixed":
+        # The mixed level-0 passes: the down pass that makes the FP64
+        # residual itself (and stores no pre-smoothed iterate), the up pass
+        # that re-makes that iterate and adds into the FP64 one.
+        head = {"down": f"k_down_res_s<{bc}, false>", "up": f"k_up_pre_s<{bc}>"}[kind_name]
+        ents = [v for k, v in rec["per_launch"].items() if k == head]
     else:
         # Template variants of the kernel (input/accumulation flags); the
         # level-0 launch is the one with the most traffic.
@@ -74,6 +77,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extra", action="store_true",
                     help="default workload only: skip the periodic1025 and batch256 sub-objects")
+    ap.add_argument("--weights", default=None,
+                    help="periodic1025_srcnn: SR-CNN weight blob (.npy) instead of the committed "
+                         "supervised one")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (read, and appended with new choices), so that "
                          "several runs (e.g. one per profiler counter) use the same launch shapes")
@@ -104,7 +110,8 @@ def bench_srcnn(args) -> int:
     B.lib()
     n, bc, f = workloads.workload("periodic1025", args.seed)
     unknowns = workloads.grid_unknowns(n, bc)
-    W = np.load(WEIGHTS)
+    wpath = args.weights or WEIGHTS
+    W = np.load(wpath)
     ft = torch.from_numpy(f).to(dev)
     ut = torch.zeros_like(ft)
     res = {}
@@ -182,7 +189,7 @@ def bench_srcnn(args) -> int:
         "dtype": "bf16 network, f64 cycle", "data": "synthetic",
         "config": {"workload": "periodic1025_srcnn", "n": n, "bc": "periodic",
                    "unknowns": unknowns, "cnn_levels": 2, "seed": args.seed,
-                   "weights": "paper_2403_07936_amd/weights/srcnn_divu_periodic.npy"},
+                   "weights": os.path.relpath(wpath, ROOT)},
         "time_to_1e-8_s": round(r["ttt"][0], 6), "cycles_to_1e-8": r["ttt"][2],
         "final_relres": r["ttt"][3],
         "spline": {"ms_per_cycle": round(res["spline"]["sec"] * 1e3, 4),

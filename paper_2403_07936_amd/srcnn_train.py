@@ -1,6 +1,9 @@
 """Offline training of the SR-CNN prolongation weights (Section 3.2 of the
-paper: supervised super-resolution with the MSE loss, here without the
-adversarial term).
+paper).  Two modes: supervised training with one content loss (below), and
+with --adversarial the paper's GAN training (Section 2.3): a discriminator
+after Ledig et al. trained with l_Dis (binary cross-entropy, real windows of
+the target against generated ones) alternating with the generator trained
+with l^SR = l_MSE + 1e-3 l_Gen, l_Gen = sum of -log D(G(I^LR)).
 
 Training pairs come from the solver itself: for each seeded periodic
 divergence-of-velocity source (workloads.rhs_divu_periodic), the iterate
@@ -21,6 +24,7 @@ shuffle) is trained in FP32 PyTorch and written as the flat float32 blob
 that mg_setup takes (include/mg.h, MG_SRCNN_WEIGHT_COUNT).
 
 Usage (on a GPU):  python -m paper_2403_07936_amd.srcnn_train --out W.npy
+                   [--adversarial --init W0.npy --content mse|cycle]
 """
 
 from __future__ import annotations
@@ -70,6 +74,20 @@ def build_model(torch):
             z = q(torch.relu(F.pixel_shuffle(apply(self.up, h), 2)))
             return apply(self.fin, z)
 
+        def load_blob(self, blob) -> None:
+            ws = [self.stem.weight]
+            for c1, c2 in zip(self.c1, self.c2):
+                ws += [c1.weight, c2.weight]
+            ws += [self.up.weight, self.fin.weight]
+            flat = np.asarray(blob, dtype=np.float32).reshape(-1)
+            k = 0
+            with torch.no_grad():
+                for w in ws:
+                    m = w.numel()
+                    w.copy_(torch.from_numpy(flat[k:k + m].reshape(tuple(w.shape))))
+                    k += m
+            assert k == flat.size, "weight blob of the wrong size"
+
         def blob(self) -> np.ndarray:
             ws = [self.stem.weight]
             for c1, c2 in zip(self.c1, self.c2):
@@ -78,6 +96,125 @@ def build_model(torch):
             return np.concatenate([w.detach().float().cpu().numpy().reshape(-1) for w in ws])
 
     return Net()
+
+
+# ---- adversarial training (Section 2.3: l_Dis and l^SR = l_MSE + 1e-3 l_Gen;
+# Fig. 2b: the discriminator after Ledig et al.) -----------------------------
+
+DISC_STRIDES = (1, 2, 1, 2, 1, 2, 1, 2)
+DISC_WIDTHS = (64, 64, 128, 128, 256, 256, 512, 512)
+DISC_LEAK = 0.2
+ADV_WEIGHT = 1e-3
+
+
+def build_discriminator(torch, widths=DISC_WIDTHS, window: int = 24, dense: int = 1024):
+    """Ledig et al.'s discriminator on one-channel windows of side `window`:
+    a 3x3 conv and LeakyReLU(0.2), seven 3x3 convs with strides 2,1,2,1,2,1,2
+    (zero padding 1, biases), each with LeakyReLU(0.2), a dense layer of
+    `dense` units with LeakyReLU(0.2), and a one-unit dense layer.  No batch
+    normalisation.  `logits(x)` is the last layer's output, `forward(x)` its
+    sigmoid (the probability that a window is a real sample)."""
+    nn = torch.nn
+    F = torch.nn.functional
+
+    class Disc(nn.Module):
+        def __init__(self):
+            super().__init__()
+            self.window = window
+            convs, cin, side = [], 1, window
+            for cout, st in zip(widths, DISC_STRIDES):
+                convs.append(nn.Conv2d(cin, cout, 3, stride=st, padding=1, bias=True))
+                cin = cout
+                side = (side + 2 - 3) // st + 1
+            self.convs = nn.ModuleList(convs)
+            self.d1 = nn.Linear(cin * side * side, dense)
+            self.d2 = nn.Linear(dense, 1)
+
+        def logits(self, x):
+            h = x
+            for c in self.convs:
+                h = F.leaky_relu(c(h), DISC_LEAK)
+            h = F.leaky_relu(self.d1(h.flatten(1)), DISC_LEAK)
+            return self.d2(h)[:, 0]
+
+        def forward(self, x):
+            return torch.sigmoid(self.logits(x))
+
+    return Disc()
+
+
+def set_discriminator_params(torch, disc, params) -> None:
+    """Load parameters given in order (conv weight, bias per conv, then the
+    two dense layers' weight and bias) as numpy arrays."""
+    mods = list(disc.convs) + [disc.d1, disc.d2]
+    with torch.no_grad():
+        for k, m in enumerate(mods):
+            m.weight.copy_(torch.from_numpy(np.asarray(params[2 * k])))
+            m.bias.copy_(torch.from_numpy(np.asarray(params[2 * k + 1])))
+
+
+def dis_loss(torch, d_real, d_fake):
+    """l_Dis: mean binary cross-entropy of D's probabilities, real windows
+    labelled 1 plus generated windows labelled 0."""
+    return torch.mean(-torch.log(d_real)) + torch.mean(-torch.log(1.0 - d_fake))
+
+
+def mse_loss(torch, hr, sr):
+    """l^SR_MSE: mean over the fine pixels of (I^HR - G(I^LR))^2."""
+    return torch.mean((hr - sr) ** 2)
+
+
+def gen_loss(torch, d_fake):
+    """l^SR_Gen: sum over the samples of -log D(G(I^LR))."""
+    return torch.sum(-torch.log(d_fake))
+
+
+def sr_loss(torch, hr, sr, d_fake):
+    """l^SR = l^SR_MSE + 1e-3 l^SR_Gen."""
+    return mse_loss(torch, hr, sr) + ADV_WEIGHT * gen_loss(torch, d_fake)
+
+
+def crop_windows(torch, side: int, window: int, count: int, rng):
+    """`count` window origins (y, x) inside a fine grid of the given side."""
+    return [(int(rng.integers(0, side - window + 1)), int(rng.integers(0, side - window + 1)))
+            for _ in range(count)]
+
+
+def _windows(torch, a, crops, window):
+    return torch.cat([a[:, :, y:y + window, x:x + window] for y, x in crops], 0)
+
+
+def adversarial_step(torch, gen, disc, og, od, x, y, crops, content: str = "mse"):
+    """One step of the paper's alternating training: (i) the generator,
+    fixed, makes synthetic fine corrections; (ii) the discriminator is
+    trained on real (target) and synthetic windows with l_Dis; (iii) with the
+    discriminator fixed, the generator is trained with l^SR = content +
+    1e-3 l_Gen, content the paper's l_MSE ("mse") or the post-smoothed
+    residual loss of the MSE-only trainer ("cycle").  The cross-entropies are
+    taken from D's logits (softplus form, the same values without log(0)).
+    Returns (l_Dis, l^SR, and mean D(real) - mean D(fake) on the step's
+    windows before and after the D step)."""
+    F = torch.nn.functional
+    window = disc.window
+    with torch.no_grad():
+        fake = gen(x)
+    real_w, fake_w = _windows(torch, y, crops, window), _windows(torch, fake, crops, window)
+    zr, zf = disc.logits(real_w), disc.logits(fake_w)
+    gap0 = float(torch.mean(torch.sigmoid(zr)) - torch.mean(torch.sigmoid(zf)))
+    ld = torch.mean(F.softplus(-zr)) + torch.mean(F.softplus(zf))
+    od.zero_grad(set_to_none=True)
+    ld.backward()
+    od.step()
+    with torch.no_grad():
+        gap = float(torch.mean(disc(real_w)) - torch.mean(disc(fake_w)))
+    sr = gen(x)
+    zg = disc.logits(_windows(torch, sr, crops, window))
+    base = mse_loss(torch, y, sr) if content == "mse" else cycle_loss(torch, y, sr)
+    lg = base + ADV_WEIGHT * torch.sum(F.softplus(-zg))
+    og.zero_grad(set_to_none=True)
+    lg.backward()
+    og.step()
+    return float(ld.detach()), float(lg.detach()), gap0, gap
 
 
 def exact_error(torch, r: "torch.Tensor") -> "torch.Tensor":
@@ -199,6 +336,14 @@ def main(argv=None) -> int:
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--adversarial", action="store_true",
+                    help="train with the paper's GAN losses (l_Dis; l^SR = content + 1e-3 l_Gen)")
+    ap.add_argument("--content", choices=["mse", "cycle"], default="mse",
+                    help="content term of l^SR: the paper's l_MSE, or the post-smoothed residual")
+    ap.add_argument("--init", default=None, help="generator weights to start from (.npy blob)")
+    ap.add_argument("--window", type=int, default=24, help="discriminator window side (n_l)")
+    ap.add_argument("--crops", type=int, default=8, help="windows per sample and step")
+    ap.add_argument("--d-lr", type=float, default=1e-4)
     args = ap.parse_args(argv)
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -222,10 +367,28 @@ def main(argv=None) -> int:
     groups = {N: (torch.stack([p[0] for p in v])[:, None], torch.stack([p[1] for p in v])[:, None])
               for N, v in by_size.items()}
     net = build_model(torch).to(dev)
+    if args.init:
+        net.load_blob(np.load(args.init))
+        log(f"generator initialised from {args.init}")
     opt = torch.optim.Adam(net.parameters(), lr=args.lr)
     sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, args.steps)
     rng = np.random.default_rng(args.seed)
     sizes = sorted(groups)
+    if args.adversarial:
+        disc = build_discriminator(torch, DISC_WIDTHS, args.window).to(dev)
+        od = torch.optim.Adam(disc.parameters(), lr=args.d_lr)
+        for step in range(args.steps):
+            N = sizes[step % len(sizes)]
+            X, Y = groups[N]
+            idx = torch.from_numpy(rng.integers(0, X.shape[0], args.batch)).to(dev)
+            crops = crop_windows(torch, 2 * N, args.window, args.crops, rng)
+            ld, lg, g0, g1 = adversarial_step(torch, net, disc, opt, od, X[idx], Y[idx], crops,
+                                              args.content)
+            sched.step()
+            if step % 100 == 0 or step == args.steps - 1:
+                log(f"step {step}: l_Dis {ld:.4e}, l^SR {lg:.4e}, D(real) - D(fake) {g0:+.3f} -> "
+                    f"{g1:+.3f} ({time.time() - t0:.1f} s)")
+        args.steps = 0
     for step in range(args.steps):
         N = sizes[step % len(sizes)]
         X, Y = groups[N]
@@ -239,7 +402,8 @@ def main(argv=None) -> int:
             log(f"step {step}: loss {float(loss.detach()):.4e} ({time.time() - t0:.1f} s)")
     with torch.no_grad():
         v = float(np.mean([float(cycle_loss(torch, y[None, None], net(x[None, None]))) for x, y in val]))
-    log(f"validation loss of the network: {v:.4e} (spline {base:.4e})")
+        m = float(np.mean([float(mse_loss(torch, y[None, None], net(x[None, None]))) for x, y in val]))
+    log(f"validation loss of the network: {v:.4e} (spline {base:.4e}); its l_MSE {m:.4e}")
     blob = net.blob().astype(np.float32)
     np.save(args.out, blob)
     log(f"wrote {blob.size} weights to {args.out}")
