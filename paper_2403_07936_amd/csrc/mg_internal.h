@@ -252,7 +252,6 @@ hipError_t persistent_init(size_t lds64, size_t lds32);
 hipError_t launch_resnorm_batched(hipStream_t s, int bc, const PProblem* probs, int nprob,
                                   double* partials, int slots, double* sums);
 hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob);
-// Segment rows / band count of the streaming passes for a level.
 // Mixed path, level 0, from e = 0: the streaming down pass whose
 // right-hand side r32 = fl32(f64 - A u64) it computes itself (and stores on
 // the rows and columns it owns, for the up pass): no separate residual pass.
@@ -266,7 +265,15 @@ hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u6
 // adds the result into u64.
 hipError_t launch_up_pre_stream(hipStream_t s, int bc, int n, const float* f, int pf,
                                 const float* c, int pc, int hs, double* u64, int p64);
+// Segment rows / band count of the streaming passes for a level.
 int stream_segment_rows(int n, int bc, int owned_cols);
+// Rows per segment at which every item of a streaming pass over a level is
+// resident on the current device at once: the smallest even height whose
+// item count fits the wave slots the kernel's occupancy allows (0: none up
+// to the grid's extent).  A candidate for the autotuner.
+enum StreamPass { kFitDown, kFitDownIn, kFitDownRes, kFitUp, kFitUpPre };
+template <typename T>
+int stream_fit_rows(StreamPass pass, int bc, int n);
 int stream_down_owned();
 int stream_up_owned();
 int stream_res_owned();

@@ -1147,7 +1147,17 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
     const int pu = l == 0 ? pitch0 : p.pitch[l];
     const T* uin = (l == 0 && !mixed) ? u : nullptr;
     const int reps = n >= 2049 ? 3 : 6;
-    const int hs_cands[] = {0, 4, 8, 16, 32, 64, 96, 128};
+    // Fixed heights, plus for each pass the height at which all its items
+    // are resident at once (at 4097^2 the mixed up pass runs 85 us at 64
+    // rows, 70 us at 38, and 97 us at 32, where the items no longer fit).
+    std::vector<int> hs_cands = {0, 4, 8, 16, 32, 64, 96, 128};
+    {
+      const int fd = stream_fit_rows<T>(add ? kFitDownRes : (uin ? kFitDownIn : kFitDown), p.bc, n);
+      const int fu = stream_fit_rows<T>(add ? kFitUpPre : kFitUp, p.bc, n);
+      for (int hs : {fd, fu})
+        if (hs > 0 && std::find(hs_cands.begin(), hs_cands.end(), hs) == hs_cands.end())
+          hs_cands.push_back(hs);
+    }
     if (add && !u64) {
       if (hipMalloc(&u64, sizeof(double) * (size_t)n * p.pitch[0]) != hipSuccess) {
         (void)hipGetLastError();

@@ -90,6 +90,54 @@ int stream_segment_rows(int n, int bc, int owned_cols) {
   return hs;
 }
 
+namespace {
+int fit_rows(const void* fn, int extent, int owned) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kWaves, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const long slots = (long)per_cu * kWaves * cus;
+  const int nb = (extent + owned - 1) / owned;
+  for (int hs = 2; hs < extent; hs += 2)
+    if ((long)nb * ((extent + hs - 1) / hs) <= slots) return hs;
+  return 0;
+}
+}  // namespace
+
+template <typename T>
+int stream_fit_rows(StreamPass pass, int bc, int n) {
+  const int extent = bc == kPeriodic ? n - 1 : n;
+  const bool d = bc == kDirichlet;
+  const void* fn = nullptr;
+  int owned = kDownOwned;
+  switch (pass) {
+    case kFitDown:
+      fn = d ? (const void*)&k_down_s<T, kDirichlet, 0> : (const void*)&k_down_s<T, kPeriodic, 0>;
+      break;
+    case kFitDownIn:
+      fn = d ? (const void*)&k_down_s<T, kDirichlet, 1> : (const void*)&k_down_s<T, kPeriodic, 1>;
+      break;
+    case kFitDownRes:
+      fn = d ? (const void*)&k_down_res_s<kDirichlet, false>
+             : (const void*)&k_down_res_s<kPeriodic, false>;
+      break;
+    case kFitUp:
+      fn = d ? (const void*)&k_up_s<T, kDirichlet, false> : (const void*)&k_up_s<T, kPeriodic, false>;
+      owned = kUpOwned;
+      break;
+    case kFitUpPre:
+      fn = d ? (const void*)&k_up_pre_s<kDirichlet> : (const void*)&k_up_pre_s<kPeriodic>;
+      owned = kUpPreOwned;
+      break;
+  }
+  return fit_rows(fn, extent, owned);
+}
+template int stream_fit_rows<float>(StreamPass, int, int);
+template int stream_fit_rows<double>(StreamPass, int, int);
+
 int stream_down_owned() { return kDownOwned; }
 int stream_up_owned() { return kUpOwned; }
 int stream_res_owned() { return kResOwned; }

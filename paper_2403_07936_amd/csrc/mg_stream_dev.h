@@ -121,6 +121,29 @@ struct Cols {
   }
 };
 
+// Interior forms of a pass (template argument IN): 0 general; 1 every row
+// index the wavefront item forms lies inside the grid (no row clamps or
+// wraps, every row holds unknowns); 2 the same for its columns as well, so
+// that the column masks, pair selection and coefficient-column extension
+// are compile-time constants and drop out of the code.
+template <int BC, int IN>
+__device__ __forceinline__ Cols<BC> make_cols(int x0, int n) {
+  Cols<BC> c(x0, n);
+  if constexpr (IN == 2) {
+    c.pc = x0;
+    c.sw = false;
+    c.unk0 = c.unk1 = true;
+  }
+  return c;
+}
+
+// Columns xw .. xw + 127 of a band all hold unknowns (periodic: none is the
+// seam copy), so the band may run with IN = 2.
+template <int BC>
+__device__ __forceinline__ bool band_inside(int xw, int n) {
+  return (BC == kPeriodic ? xw >= 0 : xw >= 1) && xw + 127 <= n - 2;
+}
+
 template <typename T>
 __device__ __forceinline__ void load_pair(T (&dst)[2], const T* __restrict__ row, int pc,
                                           bool sw) {
@@ -169,7 +192,7 @@ __device__ __forceinline__ bool row_unknown(int t, int n) {
 // the prefetched rows included.
 // IN (interior segment): every row index a pass forms lies inside the grid,
 // so rows are neither clamped nor wrapped and every row holds unknowns.
-template <typename T, int BC, bool IN = false>
+template <typename T, int BC, int IN = 0>
 __device__ __forceinline__ void load_row(T (&dst)[2], const T* __restrict__ a, int pa, int t, int n,
                                          const Cols<BC>& col) {
   bool rin;
@@ -191,7 +214,7 @@ __device__ __forceinline__ T fused_mul_add(T a, T b, T c) {
 // the unrolled row loop makes a constant (rows of a segment start at an even
 // row), so only one column's code is emitted; updates are selects, not
 // branches, which keeps the row ring in place in registers.
-template <typename T, int BC, bool IN = false>
+template <typename T, int BC, int IN = 0>
 __device__ __forceinline__ void sweep_row(const T (&um)[2], T (&u0)[2], const T (&up)[2],
                                           const T (&f0)[2], int row, int odd, int n,
                                           const Cols<BC>& col, T h2) {
@@ -212,7 +235,7 @@ __device__ __forceinline__ void sweep_row(const T (&um)[2], T (&u0)[2], const T 
   }
 }
 
-template <typename T, int BC, bool IN = false>
+template <typename T, int BC, int IN = 0>
 __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2], const T (&up)[2],
                                              const T (&f0)[2], T (&r)[2], int row, int n,
                                              const Cols<BC>& col, T inv_h2) {
@@ -238,7 +261,7 @@ __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2],
 // stored to rout (pitch pro; f is not used), where the up pass reads them.  The same
 // arithmetic as residual_wave, so r32 is bitwise what that writes on the
 // nodes the up pass reads.
-template <typename T, int BC, int UIN, bool RES, bool IN, bool SB = true>
+template <typename T, int BC, int UIN, bool RES, int IN, bool SB = true>
 __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
@@ -250,7 +273,7 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
   const int xw = band * kDownOwned - kDownHalo;
   const int x0 = xw + 2 * lane;
   const int ys = seg * hs;
-  const Cols<BC> col(x0, n);
+  const Cols<BC> col = make_cols<BC, IN>(x0, n);
   const int N = n - 1, nc = (n - 1) / 2 + 1;
   const bool lane_owns = lane >= kDownHalo / 2 && lane < 64 - kDownHalo / 2;
   const bool wr0 = lane_owns && (BC == kPeriodic ? x0 < N : col.unk0);
@@ -390,14 +413,21 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
   const int lo = seg * hs - 7, hi = seg * hs + hs + 5;
   const bool in = BC == kPeriodic ? (lo >= 0 && hi <= n - 2) : (lo >= 1 && hi <= n - 2);
   static_assert(SB || RES, "only the residual-making down pass may skip its iterate");
-  if (in)
-    down_wave_rows<T, BC, UIN, RES, true, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg,
-                                              hs, h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d,
-                                              rout, pro);
+  // The residual-making form stays at IN = 1 across columns: its IN = 2 code
+  // (fewer instructions, loads kept in flight differently) measured 78 -> 87
+  // us at 4097^2.
+  if (!RES && in && band_inside<BC>(band * kDownOwned - kDownHalo, n))
+    down_wave_rows<T, BC, UIN, RES, 2, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
+                                           h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
+                                           pro);
+  else if (in)
+    down_wave_rows<T, BC, UIN, RES, 1, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
+                                           h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
+                                           pro);
   else
-    down_wave_rows<T, BC, UIN, RES, false, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg,
-                                               hs, h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d,
-                                               rout, pro);
+    down_wave_rows<T, BC, UIN, RES, 0, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
+                                           h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
+                                           pro);
 }
 
 // Spline along x at the lane's two columns from coarse row values held one
@@ -421,11 +451,11 @@ __device__ __forceinline__ void spline_x(T cj, T (&out)[2]) {
   out[1] = wsum4(T(1.0 / 48.0), cl, T(23.0 / 48.0), cj, T(23.0 / 48.0), cr, T(1.0 / 48.0), cr2);
 }
 
-template <typename T, int BC, bool IN = false>
+template <typename T, int BC, int IN = 0>
 __device__ __forceinline__ T load_coef(const T* __restrict__ c, int pc, int I, int J, int nc) {
-  bool ni = false, nj;
+  bool ni = false, nj = false;
   const int ii = IN ? I : ext_node_any<BC>(I, nc, &ni);
-  const int jj = ext_node_any<BC>(J, nc, &nj);
+  const int jj = IN == 2 ? J : ext_node_any<BC>(J, nc, &nj);
   const T v = c[(size_t)ii * pc + jj];
   return (ni != nj) ? -v : v;
 }
@@ -433,7 +463,7 @@ __device__ __forceinline__ T load_coef(const T* __restrict__ c, int pc, int I, i
 // Up pass of one wavefront item (see down_wave).  With ADD, the finished
 // rows are added to u64 (the FP64 iterate of the mixed path, pitch p64) over
 // the unknowns -- the refinement update -- instead of being written to uout.
-template <typename T, int BC, bool ADD, bool IN>
+template <typename T, int BC, bool ADD, int IN>
 __device__ __forceinline__ void up_wave_rows(int n, const T* __restrict__ uin, int pui,
                                              T* __restrict__ uout, int puo,
                                              const T* __restrict__ f, int pf,
@@ -443,7 +473,7 @@ __device__ __forceinline__ void up_wave_rows(int n, const T* __restrict__ uin, i
   const int xw = band * kUpOwned - kUpHalo;
   const int x0 = xw + 2 * lane;
   const int ys = seg * hs;
-  const Cols<BC> col(x0, n);
+  const Cols<BC> col = make_cols<BC, IN>(x0, n);
   const int N = n - 1, nc = (n - 1) / 2 + 1;
   const bool lane_owns = lane >= kUpHalo / 2 && lane < kUpHalo / 2 + kUpOwned / 2;
   const bool wr0 = lane_owns && (BC == kPeriodic ? x0 < N : col.unk0);
@@ -474,7 +504,7 @@ __device__ __forceinline__ void up_wave_rows(int n, const T* __restrict__ uin, i
   // first or last row, and the halo lanes read the first owned lane's pair
   // (cache hits; never used).
   const int ylast = (ys + hs < row_end ? ys + hs : row_end) - 1;
-  const Cols<BC> col64(lane_owns ? x0 : xw + kUpHalo, n);
+  const Cols<BC> col64 = make_cols<BC, IN>(lane_owns ? x0 : xw + kUpHalo, n);
   auto load_u64 = [&](int slot, int row) {
     if (ADD) {
       const int rr = row < ys ? ys : (row > ylast ? ylast : row);
@@ -566,12 +596,15 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
   // interior form runs.
   const int lo = seg * hs - 4, hi = seg * hs + hs + 15;
   const bool in = lo >= 2 && hi <= n - 1;
-  if (in)
-    up_wave_rows<T, BC, ADD, true>(n, uin, pui, uout, puo, f, pf, c, pc, band, seg, hs, h2, lane,
-                                   u64, p64);
+  if (in && band_inside<BC>(band * kUpOwned - kUpHalo, n))
+    up_wave_rows<T, BC, ADD, 2>(n, uin, pui, uout, puo, f, pf, c, pc, band, seg, hs, h2, lane, u64,
+                                p64);
+  else if (in)
+    up_wave_rows<T, BC, ADD, 1>(n, uin, pui, uout, puo, f, pf, c, pc, band, seg, hs, h2, lane, u64,
+                                p64);
   else
-    up_wave_rows<T, BC, ADD, false>(n, uin, pui, uout, puo, f, pf, c, pc, band, seg, hs, h2, lane,
-                                    u64, p64);
+    up_wave_rows<T, BC, ADD, 0>(n, uin, pui, uout, puo, f, pf, c, pc, band, seg, hs, h2, lane, u64,
+                                p64);
 }
 
 // Up pass of the mixed path's level 0 when its down pass started from e = 0
@@ -591,7 +624,7 @@ __device__ __forceinline__ void up_wave(int n, const T* __restrict__ uin, int pu
 constexpr int kUpPreLeft = 8;
 constexpr int kUpPreOwned = 112;
 
-template <int BC, bool IN>
+template <int BC, int IN>
 __device__ __forceinline__ void up_pre_wave_rows(int n, const float* __restrict__ f, int pf,
                                                  const float* __restrict__ c, int pc, int band,
                                                  int seg, int hs, float h2, int lane,
@@ -600,7 +633,7 @@ __device__ __forceinline__ void up_pre_wave_rows(int n, const float* __restrict_
   const int xw = band * kUpPreOwned - kUpPreLeft;
   const int x0 = xw + 2 * lane;
   const int ys = seg * hs;
-  const Cols<BC> col(x0, n);
+  const Cols<BC> col = make_cols<BC, IN>(x0, n);
   const int N = n - 1, nc = (n - 1) / 2 + 1;
   const bool lane_owns = lane >= kUpPreLeft / 2 && lane < kUpPreLeft / 2 + kUpPreOwned / 2;
   const bool wr0 = lane_owns && (BC == kPeriodic ? x0 < N : col.unk0);
@@ -626,20 +659,20 @@ __device__ __forceinline__ void up_pre_wave_rows(int n, const float* __restrict_
   CX[3][0] = CX[3][1] = T(0);
   const int steps = hs + 17;
   const int tlast = t0 + steps - 1;
-  // u64 row written at step s (row t0 + s - 9) is read kAheadUp steps
-  // earlier into UR[s & 7]; only rows and columns the segment stores.
-  double UR[8][2];
+  // u64 row written at step s (row t0 + s - 9) is read kAheadU64 steps
+  // earlier into UR[s & 3]; only rows and columns the segment stores.
+  constexpr int kAheadU64 = 3;
+  double UR[4][2];
   const int ylast = (ys + hs < row_end ? ys + hs : row_end) - 1;
-  const Cols<BC> col64(lane_owns ? x0 : xw + kUpPreLeft, n);
+  const Cols<BC> col64 = make_cols<BC, IN>(lane_owns ? x0 : xw + kUpPreLeft, n);
   auto load_u64 = [&](int slot, int row) {
     const int rr = row < ys ? ys : (row > ylast ? ylast : row);
     load_pair<double>(UR[slot], u64 + (size_t)rr * p64, col64.pc, col64.sw);
   };
 #pragma unroll
-  for (int k = 0; k < kAheadUp; ++k) {
-    load_row<T, BC, IN>(F[k], f, pf, t0 + k, n, col);
-    load_u64(k & 7, t0 - 9 + k);
-  }
+  for (int k = 0; k < kAheadUp; ++k) load_row<T, BC, IN>(F[k], f, pf, t0 + k, n, col);
+#pragma unroll
+  for (int k = 0; k < kAheadU64; ++k) load_u64(k, t0 - 9 + k);
   for (int sb = 0; sb < steps; sb += 16) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -649,7 +682,7 @@ __device__ __forceinline__ void up_pre_wave_rows(int n, const float* __restrict_
       {  // rows kAheadUp ahead; past the last row a step uses, that row again
         const int ta = t + kAheadUp < tlast ? t + kAheadUp : tlast;
         load_row<T, BC, IN>(F[(k + kAheadUp) & 15], f, pf, ta, n, col);
-        load_u64((k + kAheadUp) & 7, t - 9 + kAheadUp);
+        load_u64((k + kAheadU64) & 3, t - 9 + kAheadU64);
       }
       U[k][0] = U[k][1] = T(0);  // row t starts from zero
       // pre-smoothing from zero (t has the parity of k: t0 and sb are even)
@@ -705,8 +738,8 @@ __device__ __forceinline__ void up_pre_wave_rows(int n, const float* __restrict_
         double* q = u64 + (size_t)tu * p64;
         const bool r = IN || row_unknown<BC>(tu, n);
         store_pair<double>(q + x0, wr0 && col.unk0 && r, wr1 && col.unk1 && r,
-                           UR[k & 7][0] + (double)U[(kv + 12) & 15][0],
-                           UR[k & 7][1] + (double)U[(kv + 12) & 15][1]);
+                           UR[k & 3][0] + (double)U[(kv + 12) & 15][0],
+                           UR[k & 3][1] + (double)U[(kv + 12) & 15][1]);
       }
     }
   }
@@ -722,10 +755,12 @@ __device__ __forceinline__ void up_pre_wave(int n, const float* __restrict__ f, 
   // (seg * hs + hs) / 2 + 7.
   const int lo = seg * hs - 10, hi = seg * hs + hs + 19;
   const bool in = lo >= 2 && hi <= n - 1;
-  if (in)
-    up_pre_wave_rows<BC, true>(n, f, pf, c, pc, band, seg, hs, h2, lane, u64, p64);
+  if (in && band_inside<BC>(band * kUpPreOwned - kUpPreLeft, n))
+    up_pre_wave_rows<BC, 2>(n, f, pf, c, pc, band, seg, hs, h2, lane, u64, p64);
+  else if (in)
+    up_pre_wave_rows<BC, 1>(n, f, pf, c, pc, band, seg, hs, h2, lane, u64, p64);
   else
-    up_pre_wave_rows<BC, false>(n, f, pf, c, pc, band, seg, hs, h2, lane, u64, p64);
+    up_pre_wave_rows<BC, 0>(n, f, pf, c, pc, band, seg, hs, h2, lane, u64, p64);
 }
 
 // Mixed path, level 0: r32 = fl32(f - A u) with f, u and the arithmetic in
