@@ -135,6 +135,11 @@ typedef struct {
 MG_API void mg_options_default(mg_options* opt);
 
 /* Create a context for `batch` problems grids[0..batch-1] (host array).
+ * The multigrid parameters of Table 1 map to it as follows: the grid side
+ * N_grid is grids[b].n; the hierarchy halves the side per level (N_step =
+ * 1) down to the coarsest side r_min = 5, solved directly; the sweeps per
+ * level are nu_pre and nu_post (N_smooth); N_GAN and S_thres are n_gan
+ * and s_thres of the options.
  * Allocates every device workspace (per problem: the coarse levels of the
  * hierarchy, and for MG_MIXED the FP32 hierarchy including level 0) and the
  * 5 x 5 inverses, computed in FP64 on the host.  hip_stream is a
@@ -361,6 +366,16 @@ MG_API int32_t mg_timing_read(mg_ctx ctx, int32_t kind, int32_t level, int64_t* 
 
 /* Static name of a kernel class ("?" if unknown). */
 MG_API const char* mg_kernel_name(int32_t kind);
+
+/* Diagnostics: how many times the context has captured a step into a
+ * hipGraph and instantiated one (all problems, since setup).  With the
+ * default kernels (nu_pre = nu_post = 2, kernel_path not per-operation, no
+ * SR-CNN prolongation) a step's graph reads u[b] and f[b] from a device
+ * slot of the problem that each call rewrites when the arrays differ from
+ * the last call's, so calls on new arrays reuse the graph; the other
+ * configurations capture the step again when its arrays change.  Either
+ * output may be NULL.  Errors: INVALID_ARG (NULL ctx). */
+MG_API int32_t mg_graph_stats(mg_ctx ctx, int64_t* captures, int64_t* instantiations);
 
 /* Diagnostics for callers' error handling: marks the persistent schedule's
  * device-wide barrier as timed out, exactly as a barrier that waited past

@@ -115,6 +115,8 @@ def lib() -> ctypes.CDLL:
         "mg_timing_read": (i32, [vp, i32, i32, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "mg_kernel_name": (ctypes.c_char_p, [i32]),
+        "mg_graph_stats": (i32, [vp, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int64)]),
         "mg_destroy": (i32, [vp]),
         "mg_status_string": (ctypes.c_char_p, [i32]),
         "mg_last_error": (ctypes.c_char_p, []),
@@ -295,6 +297,14 @@ def mg_timing_read(ctx: int, kind: int, level: int = -1):
     _check(lib().mg_timing_read(vp(ctx), kind, level, ctypes.byref(n), ctypes.byref(ms),
                                 ctypes.byref(by)))
     return n.value, ms.value, by.value
+
+
+def mg_graph_stats(ctx: int):
+    """Returns (captures, instantiations) of step graphs since setup."""
+    c = ctypes.c_int64()
+    i = ctypes.c_int64()
+    _check(lib().mg_graph_stats(vp(ctx), ctypes.byref(c), ctypes.byref(i)))
+    return c.value, i.value
 
 
 def mg_kernel_name(kind: int) -> str:

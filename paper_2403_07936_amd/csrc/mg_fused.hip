@@ -115,7 +115,12 @@ template <typename T, int BC, int TX, int TY>
 __global__ void __launch_bounds__(kThreads)
     k_down(int n, const T* __restrict__ uin, T* __restrict__ uout, int pui, int puo,
            const T* __restrict__ f, int pf, T* __restrict__ fc, int pfc, int tiles_x, int ntiles,
-           T h2, T inv_h2) {
+           T h2, T inv_h2, const CallerArgs* ca) {
+  if constexpr (sizeof(T) == sizeof(double))
+    if (ca) {
+      if (uin) uin = ca->u;
+      f = ca->f;
+    }
   constexpr int H = 6, W = TX + 2 * H, HH = TY + 2 * H;
   __shared__ T su[W * HH];
   __shared__ T sf[W * HH];
@@ -171,7 +176,9 @@ template <typename T, int BC, int TX, int TY, bool PRE>
 __global__ void __launch_bounds__(kThreads)
     k_up(int n, const T* __restrict__ uin, T* __restrict__ uout, int pui, int puo,
          const T* __restrict__ f, int pf, const T* __restrict__ c, int pc, int tiles_x, int ntiles,
-         T h2) {
+         T h2, const CallerArgs* ca) {
+  if constexpr (sizeof(T) == sizeof(double))
+    if (ca) uout = ca->u, f = ca->f;
   constexpr int H = kUpH, W = TX + 2 * H, HH = TY + 2 * H;
   constexpr int CW = TX / 2 + H + 3, CH = TY / 2 + H + 3;
   static_assert(!PRE || (CW == kUpCW && CH == kUpCH), "launch_up sizes the prefilter LDS");
@@ -273,7 +280,13 @@ template <typename T, int BC>
 __global__ void __launch_bounds__(kTailThreads)
     k_tail(int nt, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
            const T* __restrict__ f, int pf, T* __restrict__ cout, int pco,
-           const double* __restrict__ inv) {
+           const double* __restrict__ inv, const CallerArgs* ca) {
+  if constexpr (sizeof(T) == sizeof(double))
+    if (ca) {
+      if (uin) uin = ca->u;
+      if (uout) uout = ca->u;
+      f = ca->f;
+    }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   tail_block<T, BC, kTailThreads / 32>(nt, uin, pui, uout, puo, f, pf, cout, pco, inv,
                                        reinterpret_cast<T*>(smem_raw));
@@ -342,7 +355,7 @@ static inline int tiles_along(int n, int bc, int T) {
 
 template <typename T>
 hipError_t launch_down(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
-                       const T* f, int pf, T* fc, int pfc) {
+                       const T* f, int pf, T* fc, int pfc, const CallerArgs* ca) {
   constexpr int TX = 64, TY = 32;
   const int tx = tiles_along(n, bc, TX), ty = tiles_along(n, bc, TY);
   const int nt = tx * ty;
@@ -350,16 +363,16 @@ hipError_t launch_down(hipStream_t s, int bc, int n, const T* uin, int pui, T* u
   const T h2 = T(hd * hd), inv_h2 = T((double)(n - 1) * (double)(n - 1));
   if (bc == kDirichlet)
     hipLaunchKernelGGL((k_down<T, kDirichlet, TX, TY>), dim3(nt), dim3(kThreads), 0, s, n, uin,
-                       uout, pui, puo, f, pf, fc, pfc, tx, nt, h2, inv_h2);
+                       uout, pui, puo, f, pf, fc, pfc, tx, nt, h2, inv_h2, ca);
   else
     hipLaunchKernelGGL((k_down<T, kPeriodic, TX, TY>), dim3(nt), dim3(kThreads), 0, s, n, uin, uout,
-                       pui, puo, f, pf, fc, pfc, tx, nt, h2, inv_h2);
+                       pui, puo, f, pf, fc, pfc, tx, nt, h2, inv_h2, ca);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
-                     const T* f, int pf, const T* c, int pc, bool pre) {
+                     const T* f, int pf, const T* c, int pc, bool pre, const CallerArgs* ca) {
   constexpr int TX = kUpTX, TY = kUpTY;
   const int tx = tiles_along(n, bc, TX), ty = tiles_along(n, bc, TY);
   const int nt = tx * ty;
@@ -368,7 +381,7 @@ hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uou
   const size_t lds = pre ? dev::PreRegion<T, kUpCH, kUpCW>::kLds : 0;
 #define MG_TILE_UP(BCV, PREV)                                                                    \
   hipLaunchKernelGGL((k_up<T, BCV, TX, TY, PREV>), dim3(nt), dim3(kThreads), lds, s, n, uin, uout, \
-                     pui, puo, f, pf, c, pc, tx, nt, h2)
+                     pui, puo, f, pf, c, pc, tx, nt, h2, ca)
   if (bc == kDirichlet && pre)
     MG_TILE_UP(kDirichlet, true);
   else if (bc == kDirichlet)
@@ -401,27 +414,28 @@ hipError_t launch_prefilter_iir(hipStream_t s, int bc, int nc, const T* e, int p
 template <typename T>
 hipError_t launch_tail(hipStream_t s, int bc, int nt, const T* uin, int pui, T* uout, int puo,
                        const T* f, int pf, T* cout, int pco, const double* inv,
-                       const PrefilterTaps* taps) {
+                       const PrefilterTaps* taps, const CallerArgs* ca) {
   const size_t bytes = tail_bytes(nt, sizeof(T));
   (void)taps;
   if (bc == kDirichlet)
     hipLaunchKernelGGL((k_tail<T, kDirichlet>), dim3(1), dim3(32, 32), bytes, s, nt, uin, pui, uout,
-                       puo, f, pf, cout, pco, inv);
+                       puo, f, pf, cout, pco, inv, ca);
   else
     hipLaunchKernelGGL((k_tail<T, kPeriodic>), dim3(1), dim3(32, 32), bytes, s, nt, uin, pui, uout,
-                       puo, f, pf, cout, pco, inv);
+                       puo, f, pf, cout, pco, inv, ca);
   return hipGetLastError();
 }
 
 #define MG_FUSED_INSTANTIATE(T)                                                                  \
   template hipError_t launch_down<T>(hipStream_t, int, int, const T*, int, T*, int, const T*,    \
-                                     int, T*, int);                                              \
+                                     int, T*, int, const CallerArgs*);                           \
   template hipError_t launch_up<T>(hipStream_t, int, int, const T*, int, T*, int, const T*, int, \
-                                   const T*, int, bool);                                         \
+                                   const T*, int, bool, const CallerArgs*);                      \
   template hipError_t launch_prefilter_iir<T>(hipStream_t, int, int, const T*, int, T*, int, T*, \
                                               int);                                              \
   template hipError_t launch_tail<T>(hipStream_t, int, int, const T*, int, T*, int, const T*,    \
-                                     int, T*, int, const double*, const PrefilterTaps*);
+                                     int, T*, int, const double*, const PrefilterTaps*,          \
+                                     const CallerArgs*);
 
 MG_FUSED_INSTANTIATE(double)
 MG_FUSED_INSTANTIATE(float)

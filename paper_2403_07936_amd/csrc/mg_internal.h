@@ -58,13 +58,24 @@ __host__ __device__ constexpr int tail_mat_offset(int nc) {
 }
 void prefilter_matrix(int nc, int bc, double* out /* nc * nc */);
 
+// The caller's level-0 arrays of one problem, in device memory.  A
+// captured step reads them from here (`ca` of the launchers below, when not
+// null), so that one graph serves any u and f: the table is rewritten in
+// stream order before a launch whose arrays differ from the last ones.
+struct CallerArgs {
+  double* u;
+  const double* f;
+};
+hipError_t launch_bind_caller(hipStream_t s, CallerArgs* slot, double* u, const double* f);
+
 // ---- launchers (mg_kernels.hip); all asynchronous on `s` -------------------
 // Every array is a level array with `n` nodes per side and the given pitch.
 
 template <typename T>
 hipError_t launch_zero(hipStream_t s, int n, T* a, int pa);
+// ca (FP64 only): a = ca->u.
 template <typename T>
-hipError_t launch_seam(hipStream_t s, int n, T* a, int pa);
+hipError_t launch_seam(hipStream_t s, int n, T* a, int pa, const CallerArgs* ca = nullptr);
 template <typename T>
 hipError_t launch_relax(hipStream_t s, int bc, int n, T* u, int pu, const T* f, int pf,
                         int colour, int count);
@@ -88,12 +99,13 @@ hipError_t launch_coarse(hipStream_t s, int bc, const T* f, int pf, T* u, int pu
 
 // Mixed path, level 0: r32 = fl32(f - A u) computed in FP64, with per-block
 // partial sums of r^2 (FP64) in partials[0 .. blocks).
+// ca: u = ca->u, f = ca->f.
 hipError_t launch_residual_mixed(hipStream_t s, int bc, int n, const double* u, int pu,
                                  const double* f, int pf, float* r32, int pr, double* partials,
-                                 int* nblocks);
-// u += e (FP64 += FP32) over the unknowns.
+                                 int* nblocks, const CallerArgs* ca = nullptr);
+// u += e (FP64 += FP32) over the unknowns; ca: u = ca->u.
 hipError_t launch_update_mixed(hipStream_t s, int bc, int n, double* u, int pu, const float* e,
-                               int pe);
+                               int pe, const CallerArgs* ca = nullptr);
 // Per-block partial sums of (f - A u)^2 and, if with_f, of f^2 (stored at
 // partials[nblocks + b]).
 hipError_t launch_resnorm(hipStream_t s, int bc, int n, const double* u, int pu, const double* f,
@@ -132,27 +144,31 @@ hipError_t fused_init();
 // Down pass of one level (n > kTailMaxSide): 2 red-black sweeps from uin
 // (nullptr = zero guess) written to uout (must differ from uin), then
 // fc = full weighting of f - A u on the next level.
+// ca (FP64 level 0): uin = ca->u (when uin is not null), f = ca->f.
 template <typename T>
 hipError_t launch_down(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
-                       const T* f, int pf, T* fc, int pfc);
+                       const T* f, int pf, T* fc, int pfc, const CallerArgs* ca = nullptr);
 // Up pass: uout = uin + P c (c = prefiltered coarse correction), then 2
 // red-black sweeps.  uout must differ from uin.  pre: c is the coarse
 // correction itself, prefiltered by each tile on its own support.
+// ca (FP64 level 0): uout = ca->u, f = ca->f.
 template <typename T>
 hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
                      const T* f, int pf, const T* c, int pc,
-                     bool pre = false);
+                     bool pre = false, const CallerArgs* ca = nullptr);
 // Register-streaming versions of the two passes (mg_stream.hip); same
 // contracts.  hs = rows per wavefront segment (even, 4..128; 0 = chosen per level).
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
-                              int puo, const T* f, int pf, T* fc, int pfc, int hs);
+                              int puo, const T* f, int pf, T* fc, int pfc, int hs,
+                              const CallerArgs* ca = nullptr);
 // u64 (nullable): instead of writing uout, add the result to this FP64
-// array (pitch p64) over the unknowns (the mixed path's refinement update).
+// array (pitch p64) over the unknowns (the mixed path's refinement update);
+// ca: u64 = ca->u (FP32 with u64), or uout = ca->u and f = ca->f (FP64).
 template <typename T>
 hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
                             const T* f, int pf, const T* c, int pc, int hs,
-                            double* u64 = nullptr, int p64 = 0);
+                            double* u64 = nullptr, int p64 = 0, const CallerArgs* ca = nullptr);
 // c = spline coefficients of e (level with nc nodes), via tmp.
 template <typename T>
 hipError_t launch_prefilter_iir(hipStream_t s, int bc, int nc, const T* e, int pe, T* tmp, int pt,
@@ -160,10 +176,11 @@ hipError_t launch_prefilter_iir(hipStream_t s, int bc, int nc, const T* e, int p
 // Whole cycle from side nt (<= kTailMaxSide) down to 5 in one workgroup.
 // uin: initial guess (nullptr = zero); uout (nullable): result; cout
 // (nullable): prefiltered result; taps: device table for levels nt, .., 5.
+// ca (FP64 level 0): uin and uout = ca->u where not null, f = ca->f.
 template <typename T>
 hipError_t launch_tail(hipStream_t s, int bc, int nt, const T* uin, int pui, T* uout, int puo,
                        const T* f, int pf, T* cout, int pco, const double* inv,
-                       const PrefilterTaps* taps);
+                       const PrefilterTaps* taps, const CallerArgs* ca = nullptr);
 
 // ---- SR-CNN prolongation (mg_srcnn.hip) ------------------------------------
 // Activations are bf16 (stored as unsigned short) in NHWC order with 64
@@ -255,16 +272,20 @@ hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob);
 // Mixed path, level 0, from e = 0: the streaming down pass whose
 // right-hand side r32 = fl32(f64 - A u64) it computes itself (and stores on
 // the rows and columns it owns, for the up pass): no separate residual pass.
+// ca: u64 = ca->u, f64 = ca->f.
 hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u64, int p64,
                                   const double* f64, int pf64, float* r32, int pr, float* uout,
-                                  int puo, float* fc, int pfc, int hs);
+                                  int puo, float* fc, int pfc, int hs,
+                                  const CallerArgs* ca = nullptr);
 // uout == nullptr: the pre-smoothed iterate is not stored; the level's up
 // pass must then be launch_up_pre_stream, which makes it again from r32.
 // Mixed path, level 0, after launch_down_res_stream without uout: the up
 // pass that re-makes the pre-smoothed iterate from r32 (same values) and
 // adds the result into u64.
+// ca: u64 = ca->u.
 hipError_t launch_up_pre_stream(hipStream_t s, int bc, int n, const float* f, int pf,
-                                const float* c, int pc, int hs, double* u64, int p64);
+                                const float* c, int pc, int hs, double* u64, int p64,
+                                const CallerArgs* ca = nullptr);
 // Segment rows / band count of the streaming passes for a level.
 int stream_segment_rows(int n, int bc, int owned_cols);
 // Rows per segment at which every item of a streaming pass over a level is

@@ -63,7 +63,9 @@ __global__ void __launch_bounds__(TX* TY) k_zero(int n, T* a, int pa) {
 }
 
 template <typename T>
-__global__ void k_seam(int n, T* a, int pa) {
+__global__ void k_seam(int n, T* a, int pa, const CallerArgs* ca) {
+  if constexpr (sizeof(T) == sizeof(double))
+    if (ca) a = ca->u;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n - 1) {
     a[(size_t)t * pa + (n - 1)] = a[(size_t)t * pa];
@@ -271,7 +273,9 @@ __global__ void k_coarse(const T* __restrict__ f, int pf, T* __restrict__ u, int
 
 template <int BC>
 __global__ void __launch_bounds__(TX* TY)
-    k_update_mixed(int n, double* __restrict__ u, int pu, const float* __restrict__ e, int pe) {
+    k_update_mixed(int n, double* __restrict__ u, int pu, const float* __restrict__ e, int pe,
+                   const CallerArgs* ca) {
+  if (ca) u = ca->u;
   constexpr int lo = first_unknown<BC>();
   const int j = lo + blockIdx.x * TX + threadIdx.x;
   const int i = lo + blockIdx.y * TY + threadIdx.y;
@@ -438,8 +442,20 @@ hipError_t launch_zero(hipStream_t s, int n, T* a, int pa) {
 }
 
 template <typename T>
-hipError_t launch_seam(hipStream_t s, int n, T* a, int pa) {
-  hipLaunchKernelGGL(k_seam<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, a, pa);
+hipError_t launch_seam(hipStream_t s, int n, T* a, int pa, const CallerArgs* ca) {
+  hipLaunchKernelGGL(k_seam<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, a, pa, ca);
+  return hipGetLastError();
+}
+
+namespace {
+__global__ void k_bind_caller(CallerArgs* slot, double* u, const double* f) {
+  slot->u = u;
+  slot->f = f;
+}
+}  // namespace
+
+hipError_t launch_bind_caller(hipStream_t s, CallerArgs* slot, double* u, const double* f) {
+  hipLaunchKernelGGL(k_bind_caller, dim3(1), dim3(1), 0, s, slot, u, f);
   return hipGetLastError();
 }
 
@@ -519,12 +535,12 @@ hipError_t launch_coarse(hipStream_t s, int bc, const T* f, int pf, T* u, int pu
 }
 
 hipError_t launch_update_mixed(hipStream_t s, int bc, int n, double* u, int pu, const float* e,
-                               int pe) {
+                               int pe, const CallerArgs* ca) {
   const dim3 g = grid_unknowns(n, bc);
   if (bc == kDirichlet)
-    hipLaunchKernelGGL((k_update_mixed<kDirichlet>), g, kBlock, 0, s, n, u, pu, e, pe);
+    hipLaunchKernelGGL((k_update_mixed<kDirichlet>), g, kBlock, 0, s, n, u, pu, e, pe, ca);
   else
-    hipLaunchKernelGGL((k_update_mixed<kPeriodic>), g, kBlock, 0, s, n, u, pu, e, pe);
+    hipLaunchKernelGGL((k_update_mixed<kPeriodic>), g, kBlock, 0, s, n, u, pu, e, pe, ca);
   return hipGetLastError();
 }
 
@@ -591,7 +607,7 @@ hipError_t launch_remove_mean(hipStream_t s, int n, double* u, int pu, const dou
 
 #define MG_INSTANTIATE(T)                                                                        \
   template hipError_t launch_zero<T>(hipStream_t, int, T*, int);                                 \
-  template hipError_t launch_seam<T>(hipStream_t, int, T*, int);                                 \
+  template hipError_t launch_seam<T>(hipStream_t, int, T*, int, const CallerArgs*);              \
   template hipError_t launch_relax<T>(hipStream_t, int, int, T*, int, const T*, int, int, int);  \
   template hipError_t launch_residual<T>(hipStream_t, int, int, const T*, int, const T*, int, T*, \
                                          int);                                                   \

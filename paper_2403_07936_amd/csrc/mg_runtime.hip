@@ -159,6 +159,11 @@ struct Problem {
   hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
   const double* graph_u[4] = {nullptr, nullptr, nullptr, nullptr};
   const double* graph_f[4] = {nullptr, nullptr, nullptr, nullptr};
+  // Device slot of the caller's arrays read by captured steps that take
+  // them from there, and the arrays last written to it.
+  CallerArgs* caller = nullptr;
+  double* bound_u = nullptr;
+  const double* bound_f = nullptr;
   // Kernel choice per level (autotuned): variant 0 = register streaming with
   // `hs` rows per segment (0 = default), 1 = LDS tiles.
   std::vector<int> down_var, down_hs, up_var, up_hs;
@@ -231,6 +236,7 @@ struct mg_ctx_s {
   double* inv[2] = {nullptr, nullptr};
   std::vector<void*> owned;
   double* host = nullptr;  // pinned host slots for norm readback
+  int64_t graph_captures = 0, graph_instantiations = 0;
 };
 
 namespace mg {
@@ -417,8 +423,14 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
                             const PrefilterTaps* taps_dev, T* u0, int pu0, const T* f0, int pf0,
                             bool zero_guess, hipStream_t s, bool cnn, double* u64 = nullptr,
                             int p64 = 0, bool* added = nullptr, const double* res_u = nullptr,
-                            const double* res_f = nullptr, int res_p = 0, T* r_out = nullptr) {
+                            const double* res_f = nullptr, int res_p = 0, T* r_out = nullptr,
+                            const CallerArgs* ca = nullptr) {
   const int t = p.tail, bc = p.bc;
+  // ca: the caller's FP64 arrays are read from the device table.  They are
+  // level 0's u0 and f0 on the FP64 path, u64 / res_u / res_f on the mixed
+  // path's.
+  constexpr bool f64 = sizeof(T) == sizeof(double);
+  auto ca_at = [&](int l) { return (f64 && l == 0) ? ca : nullptr; };
   const double sz = sizeof(T);
   auto F = [&](int l) { return l == 0 ? f0 : (const T*)h.f[l]; };
   auto PF = [&](int l) { return l == 0 ? pf0 : p.pitch[l]; };
@@ -443,7 +455,7 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
         MG_TRY(timed(ctx, s, MG_K_DOWN, 0, (16 + 4 + (remake0 ? 0 : 4)) * m * m + 4 * mc * mc, [&] {
           return launch_down_res_stream(s, bc, n, res_u, res_p, res_f, res_p, r_out, pf0,
                                         remake0 ? nullptr : h.r[0], p.pitch[0], h.f[1],
-                                        p.pitch[1], p.down_hs[0]);
+                                        p.pitch[1], p.down_hs[0], ca);
         }));
         continue;
       }
@@ -451,9 +463,9 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
     MG_TRY(timed(ctx, s, MG_K_DOWN, l, bytes, [&] {
       if (ctx->opt.kernel_path == 2 || p.down_var[l] == 1)
         return launch_down<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l), h.f[l + 1],
-                              p.pitch[l + 1]);
+                              p.pitch[l + 1], ca_at(l));
       return launch_down_stream<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l),
-                                   h.f[l + 1], p.pitch[l + 1], p.down_hs[l]);
+                                   h.f[l + 1], p.pitch[l + 1], p.down_hs[l], ca_at(l));
     }));
   }
   {
@@ -464,7 +476,7 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
     const double nn = (double)nt * nt;
     MG_TRY(timed(ctx, s, MG_K_TAIL, t, (uin ? 3 : 2) * nn * sz, [&] {
       return launch_tail<T>(s, bc, nt, uin, pu0, uout, pu0, F(t), PF(t), cout, p.pitch[t],
-                            ctx->inv[bc], taps_dev + t);
+                            ctx->inv[bc], taps_dev + t, ca_at(t));
     }));
   }
   for (int l = t - 1; l >= 0; --l) {
@@ -497,16 +509,17 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
     if (l == 0 && remake0) {
       MG_TRY(timed(ctx, s, MG_K_UP, 0, (4 + 8 + 8) * m * m + ncc * sz, [&] {
         return launch_up_pre_stream(s, bc, n, (const float*)F(0), PF(0), (const float*)h.c[1], pc,
-                                    p.up_hs[0], u64, p64);
+                                    p.up_hs[0], u64, p64, ca);
       }));
       continue;
     }
     MG_TRY(timed(ctx, s, MG_K_UP, l, (3 * m * m + ncc) * sz + (add ? 16 * m * m - 4 * m * m : 0), [&] {
       if (tile)
         return launch_up<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l),
-                            pre ? h.u[l + 1] : h.c[l + 1], pc, pre);
+                            pre ? h.u[l + 1] : h.c[l + 1], pc, pre, ca_at(l));
       return launch_up_stream<T>(s, bc, n, h.r[l], p.pitch[l], uout, puo, F(l), PF(l),
-                                 h.c[l + 1], pc, p.up_hs[l], add ? u64 : nullptr, p64);
+                                 h.c[l + 1], pc, p.up_hs[l], add ? u64 : nullptr, p64,
+                                 add ? ca : ca_at(l));
     }));
   }
   return MG_OK;
@@ -523,13 +536,15 @@ bool use_fused(const mg_ctx_s* ctx) {
 // step's residual of this u is already in the level-0 right-hand side (left
 // there by enqueue_check_mixed), so the step starts with the inner cycles.
 int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f,
-                     hipStream_t s, bool cnn, bool have_res = false) {
+                     hipStream_t s, bool cnn, bool have_res = false,
+                     const CallerArgs* ca = nullptr) {
   const double m = unknowns_side(p.n, p.bc), nn = (double)p.n * p.n;
   const bool fused = use_fused(ctx);
   if (ctx->opt.precision == MG_FP64) {
     if (fused)
       MG_TRY(enqueue_cycle_fused<double>(ctx, p, p.h64, p.taps64_dev, u, p.pitch0, f, p.pitch0,
-                                         false, s, cnn));
+                                         false, s, cnn, nullptr, 0, nullptr, nullptr, nullptr, 0,
+                                         nullptr, ca));
     else
       MG_TRY(enqueue_cycle<double>(ctx, p, p.h64, p.taps64, u, p.pitch0, f, p.pitch0, s, cnn));
   } else {
@@ -544,7 +559,7 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
     if (!have_res && !res_in_down)
       MG_TRY(timed(ctx, s, MG_K_RESIDUAL_MIXED, 0, 20 * nn, [&] {
         return launch_residual_mixed(s, p.bc, p.n, u, p.pitch0, f, p.pitch0, r0, p.pitch[0],
-                                     p.partials, &nb);
+                                     p.partials, &nb, ca);
       }));
     bool added = false;
     if (fused) {
@@ -554,7 +569,7 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
         MG_TRY(enqueue_cycle_fused<float>(ctx, p, p.h32, p.taps32_dev, e0, p.pitch[0], r0,
                                           p.pitch[0], k == 0, s, cnn, k == K - 1 ? u : nullptr,
                                           p.pitch0, &added, rd ? u : nullptr, rd ? f : nullptr,
-                                          p.pitch0, r0));
+                                          p.pitch0, r0, ca));
       }
     } else {
       MG_TRY(timed(ctx, s, MG_K_ZERO, 0, 4 * nn,
@@ -565,10 +580,10 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
     }
     if (!added)
       MG_TRY(timed(ctx, s, MG_K_UPDATE_MIXED, 0, 20 * m * m, [&] {
-        return launch_update_mixed(s, p.bc, p.n, u, p.pitch0, e0, p.pitch[0]);
+        return launch_update_mixed(s, p.bc, p.n, u, p.pitch0, e0, p.pitch[0], ca);
       }));
   }
-  if (p.bc == kPeriodic) MG_HIP(launch_seam<double>(s, p.n, u, p.pitch0));
+  if (p.bc == kPeriodic) MG_HIP(launch_seam<double>(s, p.n, u, p.pitch0, ca));
   return MG_OK;
 }
 
@@ -577,15 +592,29 @@ int32_t run_step(mg_ctx_s* ctx, Problem& p, double* u, const double* f, bool cnn
   if (!ctx->opt.use_graph || ctx->timing)
     return enqueue_step(ctx, p, u, f, ctx->stream, cnn, have_res);
   const int k = (cnn ? 1 : 0) + (have_res ? 2 : 0);
-  if (p.graph[k] && (p.graph_u[k] != u || p.graph_f[k] != f)) {
+  // The fused schedule's kernels read the caller's arrays from the
+  // problem's device slot: one captured graph serves every u and f, and a
+  // change of arrays only rewrites the slot (in stream order, before the
+  // launch).  The per-operation and SR-CNN schedules take them as kernel
+  // arguments, so their graphs are captured again when the arrays change.
+  const bool table = use_fused(ctx) && !cnn;
+  if (table) {
+    if (p.bound_u != u || p.bound_f != f) {
+      MG_HIP(launch_bind_caller(ctx->stream, p.caller, u, f));
+      p.bound_u = u;
+      p.bound_f = f;
+    }
+  } else if (p.graph[k] && (p.graph_u[k] != u || p.graph_f[k] != f)) {
     MG_HIP(hipGraphExecDestroy(p.graph[k]));
     p.graph[k] = nullptr;
   }
   if (!p.graph[k]) {
     hipGraph_t g = nullptr;
     MG_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
-    const int32_t st = enqueue_step(ctx, p, u, f, ctx->capture, cnn, have_res);
+    const int32_t st =
+        enqueue_step(ctx, p, u, f, ctx->capture, cnn, have_res, table ? p.caller : nullptr);
     hipError_t e = hipStreamEndCapture(ctx->capture, &g);
+    ++ctx->graph_captures;
     if (st != MG_OK) {
       if (g) (void)hipGraphDestroy(g);
       return st;
@@ -597,6 +626,7 @@ int32_t run_step(mg_ctx_s* ctx, Problem& p, double* u, const double* f, bool cnn
       p.graph[k] = nullptr;
       return fail(MG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
+    ++ctx->graph_instantiations;
     p.graph_u[k] = u;
     p.graph_f[k] = f;
   }
@@ -1498,8 +1528,14 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
   }
 
   ctx->probs.resize(batch);
+  CallerArgs* slots = nullptr;
+  {
+    int32_t st = alloc_level<CallerArgs>(ctx, 1, batch, &slots);
+    if (st != MG_OK) return bail(st);
+  }
   for (int b = 0; b < batch; ++b) {
     Problem& p = ctx->probs[b];
+    p.caller = slots + b;
     p.n = grids[b].n;
     p.bc = grids[b].bc;
     p.pitch0 = grids[b].pitch ? grids[b].pitch : grids[b].n;
@@ -2121,6 +2157,14 @@ int32_t mg_timing_enable(mg_ctx ctx, int32_t enable) {
   ctx->recs.clear();
   ctx->pool_used = 0;
   ctx->timing = enable != 0;
+  return MG_OK;
+}
+
+int32_t mg_graph_stats(mg_ctx ctx, int64_t* captures, int64_t* instantiations) {
+  g_last_error.clear();
+  if (!ctx) return fail(MG_ERR_INVALID_ARG, "ctx is NULL");
+  if (captures) *captures = ctx->graph_captures;
+  if (instantiations) *instantiations = ctx->graph_instantiations;
   return MG_OK;
 }
 

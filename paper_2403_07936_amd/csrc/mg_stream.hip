@@ -11,9 +11,11 @@ template <typename T, int BC, int UIN>
 __global__ void __launch_bounds__(64 * kWaves)
     k_down_s(int n, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
              const T* __restrict__ f, int pf, T* __restrict__ fc, int pfc, int nbands, int nitems,
-             int hs, T h2, T inv_h2) {
+             int hs, T h2, T inv_h2, const CallerArgs* ca) {
   const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
+  if constexpr (sizeof(T) == sizeof(double))
+    if (ca) uin = ca->u, f = ca->f;
   down_wave<T, BC, UIN>(n, uin, pui, uout, puo, f, pf, fc, pfc, item % nbands, item / nbands, hs,
                         h2, inv_h2, threadIdx.x & 63);
 }
@@ -27,9 +29,10 @@ __global__ void __launch_bounds__(64 * kWaves)
     k_down_res_s(int n, const double* __restrict__ u64, int p64, const double* __restrict__ f64,
                  int pf64, float* __restrict__ r32, int pr, float* __restrict__ uout, int puo,
                  float* __restrict__ fc, int pfc, int nbands, int nitems, int hs, float h2,
-                 float inv_h2, double inv_h2d) {
+                 float inv_h2, double inv_h2d, const CallerArgs* ca) {
   const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
+  if (ca) u64 = ca->u, f64 = ca->f;
   down_wave<float, BC, 0, true, SB>(n, nullptr, 0, uout, puo, nullptr, 0, fc, pfc, item % nbands,
                                     item / nbands, hs, h2, inv_h2, threadIdx.x & 63, u64, p64,
                                     f64, pf64, inv_h2d, r32, pr);
@@ -41,9 +44,11 @@ __global__ void __launch_bounds__(64 * kWaves)
 template <int BC>
 __global__ void __launch_bounds__(64 * kWaves)
     k_up_pre_s(int n, const float* __restrict__ f, int pf, const float* __restrict__ c, int pc,
-               int nbands, int nitems, int hs, float h2, double* __restrict__ u64, int p64) {
+               int nbands, int nitems, int hs, float h2, double* __restrict__ u64, int p64,
+               const CallerArgs* ca) {
   const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
+  if (ca) u64 = ca->u;
   up_pre_wave<BC>(n, f, pf, c, pc, item % nbands, item / nbands, hs, h2, threadIdx.x & 63, u64,
                   p64);
 }
@@ -52,9 +57,15 @@ template <typename T, int BC, bool ADD>
 __global__ void __launch_bounds__(64 * kWaves)
     k_up_s(int n, const T* __restrict__ uin, int pui, T* __restrict__ uout, int puo,
            const T* __restrict__ f, int pf, const T* __restrict__ c, int pc, int nbands,
-           int nitems, int hs, T h2, double* __restrict__ u64, int p64) {
+           int nitems, int hs, T h2, double* __restrict__ u64, int p64, const CallerArgs* ca) {
   const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
+  if (ca) {
+    if constexpr (sizeof(T) == sizeof(double))
+      uout = ca->u, f = ca->f;
+    else
+      u64 = ca->u;
+  }
   up_wave<T, BC, ADD>(n, uin, pui, uout, puo, f, pf, c, pc, item % nbands, item / nbands, hs, h2,
                       threadIdx.x & 63, u64, p64);
 }
@@ -66,9 +77,10 @@ template <int BC>
 __global__ void __launch_bounds__(64 * kWaves)
     k_residual_mixed_s(int n, const double* __restrict__ u, int pu, const double* __restrict__ f,
                        int pf, float* __restrict__ r32, int pr, double* __restrict__ partials,
-                       int nbands, int nitems, int hs, double inv_h2) {
+                       int nbands, int nitems, int hs, double inv_h2, const CallerArgs* ca) {
   const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
+  if (ca) u = ca->u, f = ca->f;
   const int lane = threadIdx.x & 63;
   double acc = residual_wave<BC>(n, u, pu, f, pf, r32, pr, item % nbands, item / nbands, hs,
                                  inv_h2, lane);
@@ -144,7 +156,8 @@ int stream_res_owned() { return kResOwned; }
 
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
-                              int puo, const T* f, int pf, T* fc, int pfc, int hs) {
+                              int puo, const T* f, int pf, T* fc, int pfc, int hs,
+                              const CallerArgs* ca) {
   // A periodic band wraps at most once only from n - 1 >= 128 on (levels
   // this small are in the tail); hs must be even (row parity of a segment).
   if ((bc == kPeriodic && n - 1 < 128) || (hs > 0 && (hs & 1))) return hipErrorInvalidValue;
@@ -158,22 +171,22 @@ hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pu
   const T h2 = T(hd * hd), inv_h2 = T((double)(n - 1) * (double)(n - 1));
   if (bc == kDirichlet && uin)
     hipLaunchKernelGGL((k_down_s<T, kDirichlet, 1>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
-                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2);
+                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2, ca);
   else if (bc == kDirichlet)
     hipLaunchKernelGGL((k_down_s<T, kDirichlet, 0>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
-                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2);
+                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2, ca);
   else if (uin)
     hipLaunchKernelGGL((k_down_s<T, kPeriodic, 1>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
-                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2);
+                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2, ca);
   else
     hipLaunchKernelGGL((k_down_s<T, kPeriodic, 0>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
-                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2);
+                       pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2, ca);
   return hipGetLastError();
 }
 
 hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u64, int p64,
                                   const double* f64, int pf64, float* r32, int pr, float* uout,
-                                  int puo, float* fc, int pfc, int hs) {
+                                  int puo, float* fc, int pfc, int hs, const CallerArgs* ca) {
   if ((bc == kPeriodic && n - 1 < 128) || (hs > 0 && (hs & 1))) return hipErrorInvalidValue;
   const int extent = bc == kPeriodic ? n - 1 : n;
   if (hs <= 0) hs = stream_segment_rows(n, bc, kDownOwned);
@@ -185,7 +198,7 @@ hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u6
   const float h2 = (float)(hd * hd), inv_h2 = (float)inv_h2d;
 #define MG_DOWN_RES(B, SB)                                                                     \
   hipLaunchKernelGGL((k_down_res_s<B, SB>), dim3(blocks), dim3(64 * kWaves), 0, s, n, u64, p64, \
-                     f64, pf64, r32, pr, uout, puo, fc, pfc, nb, items, hs, h2, inv_h2, inv_h2d)
+                     f64, pf64, r32, pr, uout, puo, fc, pfc, nb, items, hs, h2, inv_h2, inv_h2d, ca)
   if (bc == kDirichlet && uout) MG_DOWN_RES(kDirichlet, true);
   else if (bc == kDirichlet) MG_DOWN_RES(kDirichlet, false);
   else if (uout) MG_DOWN_RES(kPeriodic, true);
@@ -195,7 +208,8 @@ hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u6
 }
 
 hipError_t launch_up_pre_stream(hipStream_t s, int bc, int n, const float* f, int pf,
-                                const float* c, int pc, int hs, double* u64, int p64) {
+                                const float* c, int pc, int hs, double* u64, int p64,
+                                const CallerArgs* ca) {
   if ((bc == kPeriodic && n - 1 < 128) || (hs > 0 && (hs & 1)) || !u64)
     return hipErrorInvalidValue;
   const int extent = bc == kPeriodic ? n - 1 : n;
@@ -207,17 +221,17 @@ hipError_t launch_up_pre_stream(hipStream_t s, int bc, int n, const float* f, in
   const float h2 = (float)(hd * hd);
   if (bc == kDirichlet)
     hipLaunchKernelGGL((k_up_pre_s<kDirichlet>), dim3(blocks), dim3(64 * kWaves), 0, s, n, f, pf,
-                       c, pc, nb, items, hs, h2, u64, p64);
+                       c, pc, nb, items, hs, h2, u64, p64, ca);
   else
     hipLaunchKernelGGL((k_up_pre_s<kPeriodic>), dim3(blocks), dim3(64 * kWaves), 0, s, n, f, pf,
-                       c, pc, nb, items, hs, h2, u64, p64);
+                       c, pc, nb, items, hs, h2, u64, p64, ca);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout, int puo,
                             const T* f, int pf, const T* c, int pc, int hs, double* u64,
-                            int p64) {
+                            int p64, const CallerArgs* ca) {
   if ((bc == kPeriodic && n - 1 < 128) || (hs > 0 && (hs & 1))) return hipErrorInvalidValue;
   const int extent = bc == kPeriodic ? n - 1 : n;
   if (hs <= 0) hs = stream_segment_rows(n, bc, kUpOwned);
@@ -229,31 +243,32 @@ hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui,
   const T h2 = T(hd * hd);
   if (bc == kDirichlet && u64)
     hipLaunchKernelGGL((k_up_s<T, kDirichlet, true>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
-                       pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64);
+                       pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64, ca);
   else if (bc == kDirichlet)
     hipLaunchKernelGGL((k_up_s<T, kDirichlet, false>), dim3(blocks), dim3(64 * kWaves), 0, s, n,
-                       uin, pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64);
+                       uin, pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64, ca);
   else if (u64)
     hipLaunchKernelGGL((k_up_s<T, kPeriodic, true>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
-                       pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64);
+                       pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64, ca);
   else
     hipLaunchKernelGGL((k_up_s<T, kPeriodic, false>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
-                       pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64);
+                       pui, uout, puo, f, pf, c, pc, nb, items, hs, h2, u64, p64, ca);
   return hipGetLastError();
 }
 
 #define MG_STREAM_INSTANTIATE(T)                                                                \
   template hipError_t launch_down_stream<T>(hipStream_t, int, int, const T*, int, T*, int,      \
-                                            const T*, int, T*, int, int);                        \
+                                            const T*, int, T*, int, int, const CallerArgs*);     \
   template hipError_t launch_up_stream<T>(hipStream_t, int, int, const T*, int, T*, int,        \
-                                          const T*, int, const T*, int, int, double*, int);
+                                          const T*, int, const T*, int, int, double*, int,      \
+                                          const CallerArgs*);
 
 MG_STREAM_INSTANTIATE(double)
 MG_STREAM_INSTANTIATE(float)
 
 hipError_t launch_residual_mixed(hipStream_t s, int bc, int n, const double* u, int pu,
                                  const double* f, int pf, float* r32, int pr, double* partials,
-                                 int* nblocks) {
+                                 int* nblocks, const CallerArgs* ca) {
   const double inv_h2 = (double)(n - 1) * (double)(n - 1);
   const int nb = (n + kResOwned - 1) / kResOwned;
   int hs = 64;
@@ -263,10 +278,10 @@ hipError_t launch_residual_mixed(hipStream_t s, int bc, int n, const double* u, 
   *nblocks = items;
   if (bc == kDirichlet)
     hipLaunchKernelGGL((k_residual_mixed_s<kDirichlet>), dim3(blocks), dim3(64 * kWaves), 0, s, n,
-                       u, pu, f, pf, r32, pr, partials, nb, items, hs, inv_h2);
+                       u, pu, f, pf, r32, pr, partials, nb, items, hs, inv_h2, ca);
   else
     hipLaunchKernelGGL((k_residual_mixed_s<kPeriodic>), dim3(blocks), dim3(64 * kWaves), 0, s, n,
-                       u, pu, f, pf, r32, pr, partials, nb, items, hs, inv_h2);
+                       u, pu, f, pf, r32, pr, partials, nb, items, hs, inv_h2, ca);
   return hipGetLastError();
 }
 

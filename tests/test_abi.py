@@ -93,6 +93,9 @@ def test_null_context_calls(B):
     with pytest.raises(B.MGError) as ei:
         B.mg_solve_history(0, 0)
     assert ei.value.status == B.MG_ERR_INVALID_ARG
+    with pytest.raises(B.MGError) as ei:
+        B.mg_graph_stats(0)
+    assert ei.value.status == B.MG_ERR_INVALID_ARG
 
 
 def test_options_default_schedule_is_off(B):
