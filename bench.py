@@ -635,7 +635,8 @@ def bench_batch(args, B, dev, probs, full: bool):
         "sizes": {str(m): sum(1 for n, _, _ in probs if n == m) for m in workloads.SIZES_BATCHED},
         "head": head, "paths": path_summary(res, unknowns),
         "speedup_mixed_vs_fp64": round(res["fp64"]["sec_per_step"] / res["mixed"]["sec_per_step"], 3),
-        "schedule": "persistent" if B.MG_K_PERSISTENT == kind else "per-problem graphs",
+        "schedule": {B.MG_K_PERSISTENT: "persistent", B.MG_K_PHASED: "one launch per phase"}.get(
+            kind, "per-problem graphs"),
         "roofline": roofline,
         "setup_s": {p: round(r["setup_s"], 2) for p, r in res.items()},
     }

@@ -108,7 +108,10 @@ typedef struct {
                                  1: per problem, one graph of per-level kernels per cycle;
                                  2: one persistent launch per cycle for the whole batch
                                  (all problems must share the boundary condition; needs
-                                 kernel_path 0, nu_pre = nu_post = 2, inner_cycles = 1). */
+                                 kernel_path 0, nu_pre = nu_post = 2, inner_cycles = 1);
+                                 3: as 2, but one launch per phase of the cycle (per level
+                                 and pass, over every problem), each kernel holding only
+                                 its phase's code; no device-wide barrier. */
   double cnn_max_ratio;       /* mg_solve with SR-CNN: after a network-prolongated cycle whose
                                  residual ratio exceeds this (0.5), use the spline from then on */
   double cnn_min_relres;      /* ... and likewise once the relative residual is <= this (1e-7) */
@@ -347,7 +350,8 @@ enum {
   MG_K_PERSISTENT = 13,    /* persistent schedule: one whole step of the batch */
   MG_K_CNN = 14,           /* SR-CNN 64-channel convolutions (matrix cores) */
   MG_K_CNN_AUX = 15,       /* SR-CNN scale, stem and final convolution */
-  MG_K_COUNT = 16
+  MG_K_PHASED = 16,        /* phased schedule: one whole step of the batch, a launch per phase */
+  MG_K_COUNT = 17
 };
 
 /* Diagnostics: while enabled, cycles run without graph capture and every
@@ -383,7 +387,8 @@ MG_API int32_t mg_graph_stats(mg_ctx ctx, int64_t* captures, int64_t* instantiat
  * without touching any array, and the mg_vcycle or mg_solve call that
  * queued it returns MG_ERR_HIP and clears the mark.  Synchronises the
  * context's stream.  Errors: INVALID_ARG (NULL ctx), UNSUPPORTED (the
- * context does not run the persistent schedule), HIP. */
+ * context does not run the persistent schedule, or runs it as one launch
+ * per phase: schedule 3 has no device-wide barrier), HIP. */
 MG_API int32_t mg_persistent_mark_timeout(mg_ctx ctx);
 
 /* Number of levels of problem `problem` (>= 1), or a negative mg_status. */

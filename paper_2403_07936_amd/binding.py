@@ -281,7 +281,8 @@ MG_K_TAIL = 12
 MG_K_PERSISTENT = 13
 MG_K_CNN = 14
 MG_K_CNN_AUX = 15
-MG_K_COUNT = 16
+MG_K_PHASED = 16
+MG_K_COUNT = 17
 MG_SRCNN_WEIGHT_COUNT = 738432
 
 

@@ -260,6 +260,13 @@ template <typename T>
 hipError_t launch_persistent(hipStream_t s, int bc, const PProblem* probs, const PPhase* phases,
                              int nphases, const PItem* items, PBarrier* bar, const double* inv,
                              int blocks, size_t lds);
+// Phase `ph` of the table alone, by a kernel that holds only the code of
+// its kind (`kind` must be phases[ph].kind); blocks of kPersistThreads
+// threads, `lds` bytes of dynamic LDS (tail and prefilter phases).
+template <typename T>
+hipError_t launch_phase(hipStream_t s, int bc, int kind, const PProblem* probs,
+                        const PPhase* phases, int ph, const PItem* items, const double* inv,
+                        int blocks, size_t lds);
 // Largest number of co-resident workgroups of the persistent kernel.
 template <typename T>
 hipError_t persistent_blocks(int bc, size_t lds, int* blocks);

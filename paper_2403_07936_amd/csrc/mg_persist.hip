@@ -67,6 +67,99 @@ __device__ __forceinline__ void upd_rows(const PProblem& p, int r0, int lane) {
       p.u64[(size_t)i * pu + j] += (double)e[(size_t)i * pe + j];
 }
 
+// The items of one phase of kind KIND: workgroup items (tails, prefilter
+// tiles) by workgroup index, wavefront items by global wavefront index,
+// both striding by the grid.  sm: dynamic LDS (workgroup items only).
+template <typename T, int BC, int KIND>
+__device__ __forceinline__ void run_phase(const PProblem* __restrict__ probs, const PPhase& P,
+                                          const PItem* __restrict__ items,
+                                          const double* __restrict__ inv, T* sm) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gwave = wave_uniform(blockIdx.x * kWavesPerBlock + wave);
+  const int nwaves = gridDim.x * kWavesPerBlock;
+  if constexpr (KIND == kItemTail) {
+    for (int i = blockIdx.x; i < P.count; i += gridDim.x) {
+      const PItem it = items[P.first + i];
+      const PProblem& p = probs[it.prob];
+      if (!p.active) continue;
+      const int t = it.level;
+      const PLevel& L = p.lv[t];
+      const bool top = t == 0;
+      const T* uin = (top && !p.zero_guess) ? static_cast<const T*>(L.u) : nullptr;
+      tail_block<T, BC, kPersistThreads / 32>(
+          L.n, uin, L.pitch_u, top ? static_cast<T*>(L.u) : nullptr, L.pitch_u,
+          static_cast<const T*>(L.f), L.pitch_f, top ? nullptr : static_cast<T*>(L.c), L.pitch,
+          inv, sm);
+      __syncthreads();
+    }
+  } else if constexpr (KIND == kItemPre) {
+    for (int i = blockIdx.x; i < P.count; i += gridDim.x) {
+      const PItem it = items[P.first + i];
+      const PProblem& p = probs[it.prob];
+      if (!p.active) continue;
+      const PLevel& L = p.lv[it.level];
+      pre_tile_block<T, BC, kPersistThreads>(L.n, static_cast<const T*>(L.u), L.pitch_u,
+                                             static_cast<T*>(L.c), L.pitch, it.a, it.b, sm);
+      __syncthreads();
+    }
+  } else {
+    for (int i = gwave; i < P.count; i += nwaves) {
+      const PItem it = items[P.first + i];
+      const PProblem& p = probs[it.prob];
+      if (!p.active) continue;
+      const PLevel& L = p.lv[it.level];
+      if constexpr (KIND == kItemRes) {
+        (void)residual_wave<BC>(L.n, p.u64, p.pitch64, p.f64, p.pitch64,
+                                static_cast<float*>(L.f), L.pitch_f, it.a, it.b, kResSegRows,
+                                (double)(L.n - 1) * (double)(L.n - 1), lane);
+      } else if constexpr (KIND == kItemUpd) {
+        upd_rows<BC>(p, it.a, lane);
+      } else if constexpr (KIND == kItemDown) {
+        const PLevel& C = p.lv[it.level + 1];
+        const double hd = 1.0 / (double)(L.n - 1);
+        // Mixed path, level 0 (from e = 0): the pass makes its FP32
+        // right-hand side from the FP64 iterate itself and stores it for the
+        // up pass, and stores no pre-smoothed iterate (the up pass makes it
+        // again), as in the per-problem schedule.
+        if constexpr (sizeof(T) == sizeof(float)) {
+          if (it.level == 0 && p.zero_guess) {
+            const double inv_h2d = (double)(L.n - 1) * (double)(L.n - 1);
+            down_wave<float, BC, 0, true, false>(
+                L.n, nullptr, 0, nullptr, 0, nullptr, 0, static_cast<float*>(C.f), C.pitch_f,
+                it.a, it.b, L.hs_down, float(hd * hd), float(inv_h2d), lane, p.u64, p.pitch64,
+                p.f64, p.pitch64, inv_h2d, static_cast<float*>(L.f), L.pitch_f);
+            continue;
+          }
+        }
+        const T* uin = (it.level == 0 && !p.zero_guess) ? static_cast<const T*>(L.u) : nullptr;
+        down_wave<T, BC>(L.n, uin, L.pitch_u, static_cast<T*>(L.b), L.pitch,
+                         static_cast<const T*>(L.f), L.pitch_f, static_cast<T*>(C.f), C.pitch_f,
+                         it.a, it.b, L.hs_down, T(hd * hd),
+                         T((double)(L.n - 1) * (double)(L.n - 1)), lane);
+      } else if constexpr (KIND == kItemUp) {
+        const PLevel& C = p.lv[it.level + 1];
+        const double hd = 1.0 / (double)(L.n - 1);
+        // Mixed path, level 0: the pre-smoothed iterate is made again from
+        // the stored right-hand side and the finished rows go straight into
+        // the FP64 iterate (the refinement update), as in the per-problem
+        // schedule.
+        if constexpr (sizeof(T) == sizeof(float)) {
+          if (it.level == 0 && p.zero_guess) {
+            up_pre_wave<BC>(L.n, static_cast<const float*>(L.f), L.pitch_f,
+                            static_cast<const float*>(C.c), C.pitch, it.a, it.b, L.hs_up,
+                            float(hd * hd), lane, p.u64, p.pitch64);
+            continue;
+          }
+        }
+        up_wave<T, BC>(L.n, static_cast<const T*>(L.b), L.pitch, static_cast<T*>(L.u),
+                       L.pitch_u, static_cast<const T*>(L.f), L.pitch_f,
+                       static_cast<const T*>(C.c), C.pitch, it.a, it.b, L.hs_up, T(hd * hd),
+                       lane);
+      }
+    }
+  }
+}
+
 template <typename T, int BC>
 __global__ void __launch_bounds__(kPersistThreads)
     k_persistent(const PProblem* __restrict__ probs, const PPhase* __restrict__ phases,
@@ -74,9 +167,6 @@ __global__ void __launch_bounds__(kPersistThreads)
                  const double* __restrict__ inv) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int gwave = wave_uniform(blockIdx.x * kWavesPerBlock + wave);
-  const int nwaves = gridDim.x * kWavesPerBlock;
   __shared__ unsigned gen_local;
   if (threadIdx.x == 0)
     gen_local = __hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -84,83 +174,29 @@ __global__ void __launch_bounds__(kPersistThreads)
   if (__hip_atomic_load(&bar->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   for (int ph = 0; ph < nphases; ++ph) {
     const PPhase P = phases[ph];
-    if (P.kind == kItemTail) {
-      for (int i = blockIdx.x; i < P.count; i += gridDim.x) {
-        const PItem it = items[P.first + i];
-        const PProblem& p = probs[it.prob];
-        if (!p.active) continue;
-        const int t = it.level;
-        const PLevel& L = p.lv[t];
-        const bool top = t == 0;
-        const T* uin = (top && !p.zero_guess) ? static_cast<const T*>(L.u) : nullptr;
-        tail_block<T, BC, kPersistThreads / 32>(
-            L.n, uin, L.pitch_u, top ? static_cast<T*>(L.u) : nullptr, L.pitch_u,
-            static_cast<const T*>(L.f), L.pitch_f, top ? nullptr : static_cast<T*>(L.c), L.pitch,
-            inv, sm);
-        __syncthreads();
-      }
-    } else if (P.kind == kItemPre) {
-      for (int i = blockIdx.x; i < P.count; i += gridDim.x) {
-        const PItem it = items[P.first + i];
-        const PProblem& p = probs[it.prob];
-        if (!p.active) continue;
-        const PLevel& L = p.lv[it.level];
-        pre_tile_block<T, BC, kPersistThreads>(L.n, static_cast<const T*>(L.u), L.pitch_u,
-                                               static_cast<T*>(L.c), L.pitch, it.a, it.b, sm);
-        __syncthreads();
-      }
-    } else {
-      for (int i = gwave; i < P.count; i += nwaves) {
-        const PItem it = items[P.first + i];
-        const PProblem& p = probs[it.prob];
-        if (!p.active) continue;
-        const PLevel& L = p.lv[it.level];
-        switch (P.kind) {
-          case kItemRes:
-            (void)residual_wave<BC>(L.n, p.u64, p.pitch64, p.f64, p.pitch64,
-                                    static_cast<float*>(L.f), L.pitch_f, it.a, it.b, kResSegRows,
-                                    (double)(L.n - 1) * (double)(L.n - 1), lane);
-            break;
-          case kItemUpd:
-            upd_rows<BC>(p, it.a, lane);
-            break;
-          case kItemDown: {
-            const PLevel& C = p.lv[it.level + 1];
-            const double hd = 1.0 / (double)(L.n - 1);
-            const T* uin = (it.level == 0 && !p.zero_guess) ? static_cast<const T*>(L.u) : nullptr;
-            down_wave<T, BC>(L.n, uin, L.pitch_u, static_cast<T*>(L.b), L.pitch,
-                             static_cast<const T*>(L.f), L.pitch_f, static_cast<T*>(C.f), C.pitch_f,
-                             it.a, it.b, L.hs_down, T(hd * hd),
-                             T((double)(L.n - 1) * (double)(L.n - 1)), lane);
-            break;
-          }
-          case kItemUp: {
-            const PLevel& C = p.lv[it.level + 1];
-            const double hd = 1.0 / (double)(L.n - 1);
-            // Mixed path, level 0: the finished rows go straight into the
-            // FP64 iterate (the refinement update), as in the graph path.
-            if constexpr (sizeof(T) == sizeof(float)) {
-              if (it.level == 0 && p.zero_guess) {
-                up_wave<T, BC, true>(L.n, static_cast<const T*>(L.b), L.pitch, nullptr, 0,
-                                     static_cast<const T*>(L.f), L.pitch_f,
-                                     static_cast<const T*>(C.c), C.pitch, it.a, it.b, L.hs_up,
-                                     T(hd * hd), lane, p.u64, p.pitch64);
-                break;
-              }
-            }
-            up_wave<T, BC>(L.n, static_cast<const T*>(L.b), L.pitch, static_cast<T*>(L.u),
-                           L.pitch_u, static_cast<const T*>(L.f), L.pitch_f,
-                           static_cast<const T*>(C.c), C.pitch, it.a, it.b, L.hs_up,
-                           T(hd * hd), lane);
-            break;
-          }
-          default:
-            break;
-        }
-      }
+    switch (P.kind) {
+      case kItemTail: run_phase<T, BC, kItemTail>(probs, P, items, inv, sm); break;
+      case kItemPre: run_phase<T, BC, kItemPre>(probs, P, items, inv, sm); break;
+      case kItemRes: run_phase<T, BC, kItemRes>(probs, P, items, inv, sm); break;
+      case kItemUpd: run_phase<T, BC, kItemUpd>(probs, P, items, inv, sm); break;
+      case kItemDown: run_phase<T, BC, kItemDown>(probs, P, items, inv, sm); break;
+      case kItemUp: run_phase<T, BC, kItemUp>(probs, P, items, inv, sm); break;
+      default: break;
     }
     if (ph + 1 < nphases && !grid_barrier(bar, &gen_local)) return;
   }
+}
+
+// One phase per launch (the kernel boundary orders the phases): the kernel
+// holds only its kind's code, so its registers, and its LDS (none for
+// wavefront items), are those of that kind alone.
+template <typename T, int BC, int KIND>
+__global__ void __launch_bounds__(kPersistThreads)
+    k_phase(const PProblem* __restrict__ probs, const PPhase* __restrict__ phases, int ph,
+            const PItem* __restrict__ items, const double* __restrict__ inv) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const PPhase P = phases[ph];
+  run_phase<T, BC, KIND>(probs, P, items, inv, reinterpret_cast<T*>(smem_raw));
 }
 
 __global__ void k_resnorm_batched(int bc, const PProblem* __restrict__ probs, double* partials,
@@ -250,8 +286,26 @@ hipError_t persistent_init(size_t lds64, size_t lds32) {
   e = hipFuncSetAttribute((const void*)k_persistent<float, kDirichlet>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds32);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_persistent<float, kPeriodic>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds32);
+  e = hipFuncSetAttribute((const void*)k_persistent<float, kPeriodic>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds32);
+  if (e != hipSuccess) return e;
+  const void* fns64[] = {(const void*)k_phase<double, kDirichlet, kItemTail>,
+                         (const void*)k_phase<double, kPeriodic, kItemTail>,
+                         (const void*)k_phase<double, kDirichlet, kItemPre>,
+                         (const void*)k_phase<double, kPeriodic, kItemPre>};
+  const void* fns32[] = {(const void*)k_phase<float, kDirichlet, kItemTail>,
+                         (const void*)k_phase<float, kPeriodic, kItemTail>,
+                         (const void*)k_phase<float, kDirichlet, kItemPre>,
+                         (const void*)k_phase<float, kPeriodic, kItemPre>};
+  for (const void* fn : fns64) {
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds64);
+    if (e != hipSuccess) return e;
+  }
+  for (const void* fn : fns32) {
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds32);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename T>
@@ -282,6 +336,32 @@ hipError_t launch_persistent(hipStream_t s, int bc, const PProblem* probs, const
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_phase(hipStream_t s, int bc, int kind, const PProblem* probs,
+                        const PPhase* phases, int ph, const PItem* items, const double* inv,
+                        int blocks, size_t lds) {
+#define MG_PHASE(B, K)                                                                          \
+  hipLaunchKernelGGL((k_phase<T, B, K>), dim3(blocks), dim3(kPersistThreads), lds, s, probs,     \
+                     phases, ph, items, inv)
+#define MG_PHASE_BC(K)          \
+  if (bc == kDirichlet)         \
+    MG_PHASE(kDirichlet, K);    \
+  else                          \
+    MG_PHASE(kPeriodic, K)
+  switch (kind) {
+    case kItemTail: MG_PHASE_BC(kItemTail); break;
+    case kItemPre: MG_PHASE_BC(kItemPre); break;
+    case kItemRes: MG_PHASE_BC(kItemRes); break;
+    case kItemUpd: MG_PHASE_BC(kItemUpd); break;
+    case kItemDown: MG_PHASE_BC(kItemDown); break;
+    case kItemUp: MG_PHASE_BC(kItemUp); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef MG_PHASE_BC
+#undef MG_PHASE
+  return hipGetLastError();
+}
+
 hipError_t launch_resnorm_batched(hipStream_t s, int bc, const PProblem* probs, int nprob,
                                   double* partials, int slots, double* sums) {
   hipLaunchKernelGGL(k_resnorm_batched, dim3(slots, nprob), dim3(256), 0, s, bc, probs, partials,
@@ -301,6 +381,10 @@ template hipError_t launch_persistent<double>(hipStream_t, int, const PProblem*,
                                               size_t);
 template hipError_t launch_persistent<float>(hipStream_t, int, const PProblem*, const PPhase*, int,
                                              const PItem*, PBarrier*, const double*, int, size_t);
+template hipError_t launch_phase<double>(hipStream_t, int, int, const PProblem*, const PPhase*,
+                                         int, const PItem*, const double*, int, size_t);
+template hipError_t launch_phase<float>(hipStream_t, int, int, const PProblem*, const PPhase*,
+                                        int, const PItem*, const double*, int, size_t);
 template hipError_t persistent_blocks<double>(int, size_t, int*);
 template hipError_t persistent_blocks<float>(int, size_t, int*);
 

@@ -194,6 +194,11 @@ struct Persist {
   int blocks = 0;
   size_t lds = 0;
   hipGraphExec_t graph = nullptr;
+  // One launch per phase instead of one launch with device-wide barriers
+  // (schedule 3): per phase, its kind, grid and dynamic LDS.
+  bool phased = false;
+  std::vector<PPhase> h_phases;
+  size_t lds_tail = 0, lds_pre = 0;
   double* d_partials = nullptr;
   double* d_sums = nullptr;
   int slots = 32;
@@ -716,6 +721,7 @@ int32_t build_persistent(mg_ctx_s* ctx) {
   const int B = (int)ctx->probs.size();
   P.bc = ctx->probs[0].bc;
   P.h_probs.assign(B, PProblem{});
+  P.lds_pre = P.lds_tail = 0;
   int K = 0;
   size_t lds = 0;
   for (int b = 0; b < B; ++b) {
@@ -743,10 +749,10 @@ int32_t build_persistent(mg_ctx_s* ctx) {
       const int extent = p.bc == kPeriodic ? L.n - 1 : L.n;
       L.nb_down = (extent + stream_down_owned() - 1) / stream_down_owned();
       L.nb_up = (extent + stream_up_owned() - 1) / stream_up_owned();
-      if (l > 0 && l < p.tail) lds = std::max(lds, dev::PreTile<T>::kLds);
+      if (l > 0 && l < p.tail) P.lds_pre = std::max(P.lds_pre, dev::PreTile<T>::kLds);
     }
     K = std::max(K, p.tail);
-    lds = std::max(lds, dev::tail_bytes(p.side[p.tail], sizeof(T)));
+    P.lds_tail = std::max(P.lds_tail, dev::tail_bytes(p.side[p.tail], sizeof(T)));
   }
   std::vector<PPhase> phases;
   std::vector<PItem> items;
@@ -761,10 +767,13 @@ int32_t build_persistent(mg_ctx_s* ctx) {
     for (int sg = 0; sg < ns; ++sg)
       for (int bd = 0; bd < nb; ++bd) items.push_back({b, l, bd, sg});
   };
+  // Mixed path: the FP64 residual of problems whose level 0 is the tail
+  // (the level-0 down pass makes it for the others).
   if (mixed) {
     const size_t first = items.size();
     const int ow = stream_res_owned();
     for (int b = 0; b < B; ++b) {
+      if (ctx->probs[b].tail > 0) continue;
       const int n = ctx->probs[b].n;
       for (int sg = 0; sg < (n + kResSegRows - 1) / kResSegRows; ++sg)
         for (int bd = 0; bd < (n + ow - 1) / ow; ++bd) items.push_back({b, 0, bd, sg});
@@ -817,10 +826,11 @@ int32_t build_persistent(mg_ctx_s* ctx) {
   // Algorithmic bytes of the step, per pass (m = unknowns per side):
   // residual 20 m^2 (u, f FP64 read, r FP32 written); down pass
   // (2 or 3) m^2 + mc^2 words (f read, pre-smoothed u written, u read
-  // unless the guess is zero, fc written); tail (2 or 3) nt^2 words;
-  // prefilter 2 nc^2 words; up pass 3 m^2 + nc^2 words, where the mixed
-  // level-0 pass adds into the FP64 iterate (16 m^2 instead of 4 m^2 for
-  // u); update 20 m^2.
+  // unless the guess is zero, fc written), the mixed level-0 pass 20 m^2 +
+  // 4 mc^2 (u, f FP64 read, r written, no pre-smoothed u); tail (2 or 3)
+  // nt^2 words; prefilter 2 nc^2 words; up pass 3 m^2 + nc^2 words, the
+  // mixed level-0 pass 20 m^2 + 4 nc^2 (r read, the FP64 iterate read and
+  // written); update 20 m^2.
   {
     const double sz = sizeof(T);
     double by = 0.0;
@@ -830,13 +840,17 @@ int32_t build_persistent(mg_ctx_s* ctx) {
         const double m = unknowns_side(p.side[l], p.bc);
         return m * m;
       };
-      if (mixed) by += 20.0 * unk(0);
+      if (mixed && p.tail == 0) by += 20.0 * unk(0);
       for (int l = 0; l < p.tail; ++l) {
-        const bool uin = l == 0 && !mixed;
-        by += ((uin ? 3.0 : 2.0) * unk(l) + unk(l + 1)) * sz;
         const double nc2 = (double)p.side[l + 1] * p.side[l + 1];
         if (l + 1 < p.tail) by += 2.0 * nc2 * sz;
-        by += (3.0 * unk(l) + nc2) * sz + ((l == 0 && mixed) ? 12.0 * unk(0) : 0.0);
+        if (l == 0 && mixed) {
+          by += 20.0 * unk(0) + 4.0 * unk(1) + 20.0 * unk(0) + 4.0 * nc2;
+          continue;
+        }
+        const bool uin = l == 0 && !mixed;
+        by += ((uin ? 3.0 : 2.0) * unk(l) + unk(l + 1)) * sz;
+        by += (3.0 * unk(l) + nc2) * sz;
       }
       const double nt2 = (double)p.side[p.tail] * p.side[p.tail];
       by += ((p.tail == 0 && !mixed) ? 3.0 : 2.0) * nt2 * sz;
@@ -844,7 +858,9 @@ int32_t build_persistent(mg_ctx_s* ctx) {
     }
     P.bytes = by;
   }
+  lds = std::max(P.lds_pre, P.lds_tail);
   P.lds = lds;
+  P.h_phases = phases;
   MG_HIP(persistent_init(std::max(lds, (size_t)65536), std::max(lds, (size_t)65536)));
   MG_HIP(persistent_blocks<T>(P.bc, lds, &P.blocks));
   if (P.blocks <= 0) return fail(MG_ERR_UNSUPPORTED, "persistent kernel does not fit on a CU");
@@ -898,15 +914,34 @@ int32_t persistent_bind(mg_ctx_s* ctx, double* const* u, const double* const* f,
 
 int32_t persistent_launch(mg_ctx_s* ctx) {
   Persist& P = ctx->ps;
+  const bool mixed = ctx->opt.precision == MG_MIXED;
   auto launch = [&](hipStream_t s) {
-    return ctx->opt.precision == MG_MIXED
-               ? launch_persistent<float>(s, P.bc, P.d_probs, P.d_phases, P.nphases, P.d_items,
-                                          P.d_bar, ctx->inv[P.bc], P.blocks, P.lds)
-               : launch_persistent<double>(s, P.bc, P.d_probs, P.d_phases, P.nphases, P.d_items,
-                                           P.d_bar, ctx->inv[P.bc], P.blocks, P.lds);
+    if (!P.phased)
+      return mixed ? launch_persistent<float>(s, P.bc, P.d_probs, P.d_phases, P.nphases,
+                                              P.d_items, P.d_bar, ctx->inv[P.bc], P.blocks, P.lds)
+                   : launch_persistent<double>(s, P.bc, P.d_probs, P.d_phases, P.nphases,
+                                               P.d_items, P.d_bar, ctx->inv[P.bc], P.blocks,
+                                               P.lds);
+    // One launch per phase: workgroup items one workgroup each, wavefront
+    // items kPersistThreads / 64 per workgroup.
+    for (int ph = 0; ph < P.nphases; ++ph) {
+      const PPhase& q = P.h_phases[ph];
+      const bool wg = q.kind == kItemTail || q.kind == kItemPre;
+      const int per = kPersistThreads / 64;
+      const int blocks = wg ? q.count : (q.count + per - 1) / per;
+      const size_t lds = q.kind == kItemTail ? P.lds_tail : (q.kind == kItemPre ? P.lds_pre : 0);
+      const hipError_t e =
+          mixed ? launch_phase<float>(s, P.bc, q.kind, P.d_probs, P.d_phases, ph, P.d_items,
+                                      ctx->inv[P.bc], blocks, lds)
+                : launch_phase<double>(s, P.bc, q.kind, P.d_probs, P.d_phases, ph, P.d_items,
+                                       ctx->inv[P.bc], blocks, lds);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   };
   if (!ctx->opt.use_graph || ctx->timing) {
-    MG_TRY(timed(ctx, ctx->stream, MG_K_PERSISTENT, 0, P.bytes, [&] { return launch(ctx->stream); }));
+    MG_TRY(timed(ctx, ctx->stream, P.phased ? MG_K_PHASED : MG_K_PERSISTENT, 0, P.bytes,
+                 [&] { return launch(ctx->stream); }));
     return MG_OK;
   }
   if (!P.graph) {
@@ -1339,8 +1374,9 @@ int32_t autotune(mg_ctx_s* ctx) {
   return st;
 }
 
-// Batch schedule: per-problem graphs against the persistent launch, each
-// timed over a few steps on library-owned arrays of the callers' shapes.
+// Batch schedule: per-problem graphs against the persistent launch and
+// against one launch per phase, each timed over a few steps on
+// library-owned arrays of the callers' shapes.
 int32_t tune_schedule(mg_ctx_s* ctx) {
   const int B = (int)ctx->probs.size();
   std::string why;
@@ -1365,7 +1401,10 @@ int32_t tune_schedule(mg_ctx_s* ctx) {
   }
   if (choice == 1) return MG_OK;
   MG_TRY(mixed ? build_persistent<float>(ctx) : build_persistent<double>(ctx));
-  if (choice == 2) return MG_OK;
+  if (choice == 2 || choice == 3) {
+    ctx->ps.phased = choice == 3;
+    return MG_OK;
+  }
 
   // Stand-in arrays (zeros: the work per step does not depend on values).
   std::vector<size_t> off(B + 1, 0);
@@ -1383,7 +1422,7 @@ int32_t tune_schedule(mg_ctx_s* ctx) {
     fs[b] = buf + off[B] + off[b];
   }
   int32_t st = MG_OK;
-  float t_graph = 0.f, t_pers = 0.f;
+  float t_graph = 0.f, t_pers = 0.f, t_phased = 0.f;
   auto per_problem = [&]() -> hipError_t {
     for (int b = 0; b < B; ++b)
       if (run_step(ctx, ctx->probs[b], us[b], fs[b]) != MG_OK) return hipErrorUnknown;
@@ -1403,6 +1442,15 @@ int32_t tune_schedule(mg_ctx_s* ctx) {
     std::vector<double> rel(B);
     st = persistent_relres(ctx, rel.data());  // also reports a timed-out barrier
   }
+  if (st == MG_OK) {
+    if (ctx->ps.graph) (void)hipGraphExecDestroy(ctx->ps.graph);
+    ctx->ps.graph = nullptr;
+    ctx->ps.phased = true;
+    st = time_launches(ctx, 2, persistent, &t_phased);
+    if (ctx->ps.graph) (void)hipGraphExecDestroy(ctx->ps.graph);
+    ctx->ps.graph = nullptr;
+    ctx->ps.phased = false;
+  }
   for (auto& p : ctx->probs)
     for (auto& g : p.graph)
       if (g) {
@@ -1413,6 +1461,8 @@ int32_t tune_schedule(mg_ctx_s* ctx) {
   (void)hipFree(buf);
   if (st != MG_OK) return st;
   choice = t_pers < t_graph ? 2 : 1;
+  if (t_phased < (choice == 2 ? t_pers : t_graph)) choice = 3;
+  ctx->ps.phased = choice == 3;
   if (choice == 1) {
     if (ctx->ps.graph) (void)hipGraphExecDestroy(ctx->ps.graph);
     ctx->ps.graph = nullptr;
@@ -1459,7 +1509,7 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
   if (opt->check_every < 0) return fail(MG_ERR_INVALID_ARG, "check_every must be >= 0");
   if (opt->kernel_path < 0 || opt->kernel_path > 2)
     return fail(MG_ERR_INVALID_ARG, "kernel_path must be 0, 1 or 2");
-  if (opt->schedule < 0 || opt->schedule > 2)
+  if (opt->schedule < 0 || opt->schedule > 3)
     return fail(MG_ERR_INVALID_ARG, "schedule must be 0, 1 or 2");
   for (int b = 0; b < batch; ++b) {
     const mg_grid& g = grids[b];
@@ -1622,12 +1672,13 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
     if (st == MG_OK) st = tune_schedule(ctx);
     if (st != MG_OK) return bail(st);
   }
-  if (opt->schedule == 2) {
+  if (opt->schedule == 2 || opt->schedule == 3) {
     std::string why;
     if (!persistent_eligible(ctx, &why)) return bail(fail(MG_ERR_UNSUPPORTED, why));
     const int32_t st = opt->precision == MG_MIXED ? build_persistent<float>(ctx)
                                                   : build_persistent<double>(ctx);
     if (st != MG_OK) return bail(st);
+    ctx->ps.phased = opt->schedule == 3;
   }
   *out = ctx;
   return MG_OK;
@@ -1677,7 +1728,10 @@ int32_t vcycle_impl(mg_ctx ctx, double* const* u, const double* const* f, int32_
     for (int c = 0; c < ncycles; ++c) MG_TRY(persistent_launch(ctx));
     if (ctx->ps.bc == kPeriodic && ncycles > 0)
       MG_HIP(launch_seam_batched(ctx->stream, ctx->ps.d_probs, B));
-    if (!relres_out) return ncycles > 0 ? persistent_check(ctx) : MG_OK;
+    // The persistent launch's barrier may have timed out: read its error
+    // word (synchronises).  The phased schedule has no barrier and returns
+    // after queueing.
+    if (!relres_out) return (ncycles > 0 && !ctx->ps.phased) ? persistent_check(ctx) : MG_OK;
     MG_TRY(persistent_relres(ctx, relres_out));
     for (int b = 0; b < B; ++b)
       if (!std::isfinite(relres_out[b])) return fail(MG_ERR_NONFINITE, "non-finite residual");
@@ -2208,6 +2262,7 @@ const char* mg_kernel_name(int32_t kind) {
     case MG_K_PERSISTENT: return "persistent";
     case MG_K_CNN: return "cnn_conv";
     case MG_K_CNN_AUX: return "cnn_aux";
+    case MG_K_PHASED: return "phased";
     default: return "?";
   }
 }
@@ -2215,7 +2270,8 @@ const char* mg_kernel_name(int32_t kind) {
 int32_t mg_persistent_mark_timeout(mg_ctx ctx) {
   g_last_error.clear();
   if (!ctx) return fail(MG_ERR_INVALID_ARG, "ctx is NULL");
-  if (!ctx->ps.on) return fail(MG_ERR_UNSUPPORTED, "the context does not use the persistent schedule");
+  if (!ctx->ps.on || ctx->ps.phased)
+    return fail(MG_ERR_UNSUPPORTED, "the context does not use the persistent schedule");
   MG_GUARD(MG_HIP(hipSetDevice(ctx->device));
            const unsigned one = 1u;
            MG_HIP(hipMemcpyAsync(&ctx->ps.d_bar->error, &one, sizeof one, hipMemcpyHostToDevice,

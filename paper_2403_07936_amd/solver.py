@@ -24,7 +24,8 @@ class Solver:
                  cnn_min_relres: float = 1e-7, n_gan: float = 0.0, s_thres: float = 0.0):
         """grids: sequence of (n, bc) with bc 0/1 or "dirichlet"/"periodic".
         pitch: optional sequence of row pitches (elements) of the level-0 arrays.
-        schedule: 0 autotuned, 1 per-problem graphs, 2 one persistent launch per step.
+        schedule: 0 autotuned, 1 per-problem graphs, 2 one persistent launch per step,
+            3 one launch per phase of the step for the whole batch.
         tune_cache_path: optional text file the autotuner reads and appends to.
         cnn_weights: optional flat float32 array of SR-CNN weights (MG_SRCNN_WEIGHT_COUNT
         values, see include/mg.h); selects the network prolongation on the

@@ -290,16 +290,18 @@ def batch256():
     return workloads.workload("batch256", 0)
 
 
-def test_batch256_persistent_step_parity(B, dev):
-    """One persistent launch steps all 256 problems of the batched workload
-    (sides 129..1025, mixed precision); each problem's new iterate is
-    checked element-wise against the oracle's refinement step from the same
-    nonzero state."""
+@pytest.mark.parametrize("schedule", [2, 3])
+def test_batch256_persistent_step_parity(B, dev, schedule):
+    """One persistent launch (schedule 2) or one launch per phase (3) steps
+    all 256 problems of the batched workload (sides 129..1025, mixed
+    precision); each problem's new iterate is checked element-wise against
+    the oracle's refinement step from the same nonzero state."""
     probs = batch256()
-    say(f"batch256: {len(probs)} problems, {sum((n - 1) ** 2 for n, _, _ in probs)} unknowns")
+    say(f"batch256 schedule {schedule}: {len(probs)} problems, "
+        f"{sum((n - 1) ** 2 for n, _, _ in probs)} unknowns")
     o = B.mg_options_default()
     o.precision = B.MG_MIXED
-    o.schedule = 2
+    o.schedule = schedule
     ctx = B.mg_setup([(n, bc, 0) for n, bc, _ in probs], o,
                      torch.cuda.current_stream().cuda_stream)
     try:
@@ -319,6 +321,21 @@ def test_batch256_persistent_step_parity(B, dev):
 
 
 # ------------------------------------------------ barrier timeout report --
+
+def test_phased_schedule_has_no_barrier_to_mark(B, dev):
+    """The phased schedule (3) orders its phases by kernel boundaries; the
+    diagnostic that marks the device barrier refuses it."""
+    o = B.mg_options_default()
+    o.precision = B.MG_MIXED
+    o.schedule = 3
+    ctx = B.mg_setup([(n, P, 0) for n in (129, 257)], o, torch.cuda.current_stream().cuda_stream)
+    try:
+        with pytest.raises(B.MGError) as ei:
+            B.mg_persistent_mark_timeout(ctx)
+        assert ei.value.status == B.MG_ERR_UNSUPPORTED
+    finally:
+        B.mg_destroy(ctx)
+
 
 @pytest.mark.parametrize("call", ["vcycle", "solve"])
 def test_persistent_barrier_timeout_is_reported(B, dev, call):

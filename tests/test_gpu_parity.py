@@ -226,7 +226,12 @@ def test_fp64_cycle_parity_per_cycle(B, dev, bc, n, kernel_path, use_graph):
 @pytest.mark.parametrize("bc,n", [(D, 65), (P, 65), (D, 257), (P, 257), (P, 513)])
 @pytest.mark.parametrize("kernel_path", [0, 1, 2])
 def test_mixed_step_parity(B, dev, bc, n, kernel_path):
-    """One refinement step against the oracle's FP32 emulation."""
+    """One refinement step against the oracle's FP32 emulation.  The GPU's
+    FP32 inner cycle rounds in its own order, so the bar comes from the
+    oracle's own spread: D = the larger of the distances of its FP32 step
+    from the step with an FP64 inner cycle and from its FP32 step on the
+    transposed problem (transposed back), relative to the update e; the GPU
+    step must lie within 3 D (L2), and within 1e-6 |e| where D is smaller."""
     say(f"mixed step bc={bc} n={n} path={kernel_path}")
     f = make_rhs(n, bc, 1)
     ctx = ctx_for(B, n, bc, 1, 1, kernel_path)
@@ -238,9 +243,13 @@ def test_mixed_step_parity(B, dev, bc, n, kernel_path):
             B.mg_vcycle(ctx, [ut.data_ptr()], [ft.data_ptr()], 1)
             ref = oracle.refine_step(u, f, bc)
             e = ref - u
+            e64 = oracle.vcycle(np.zeros_like(f), oracle.residual(u, f, bc), bc)
+            tr = np.ascontiguousarray(oracle.refine_step(
+                np.ascontiguousarray(u.T), np.ascontiguousarray(f.T), bc).T)
+            d = max(np.linalg.norm(ref - (u + e64)), np.linalg.norm(ref - tr)) / np.linalg.norm(e)
             err = np.linalg.norm(host(ut) - ref) / np.linalg.norm(e)
-            say(f"  step {c + 1}: {err:.2e}")
-            assert err <= 1e-5
+            say(f"  step {c + 1}: {err:.2e} (oracle spread D {d:.2e})")
+            assert err <= max(1e-6, 3.0 * d)
             u = ref
     finally:
         B.mg_destroy(ctx)
@@ -462,15 +471,17 @@ def batch_ctx(B, specs, precision, schedule):
     return B.mg_setup([(n, bc, 0) for n, bc in specs], o, torch.cuda.current_stream().cuda_stream)
 
 
+@pytest.mark.parametrize("schedule", [2, 3])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("bc,sizes", [(P, [33, 129, 65, 257, 513, 9]), (D, [257, 65, 1025, 129])])
-def test_persistent_batch_step_parity(B, dev, precision, bc, sizes):
-    """One persistent launch steps every problem of an uneven batch; each
-    problem's step matches the oracle's."""
-    say(f"persistent batch precision={precision} bc={bc} sizes={sizes}")
+def test_persistent_batch_step_parity(B, dev, schedule, precision, bc, sizes):
+    """One persistent launch (schedule 2), or one launch per phase (3),
+    steps every problem of an uneven batch; each problem's step matches the
+    oracle's."""
+    say(f"batch schedule={schedule} precision={precision} bc={bc} sizes={sizes}")
     specs = [(n, bc) for n in sizes]
     fs = [make_rhs(n, bc, 20 + k) for k, n in enumerate(sizes)]
-    ctx = batch_ctx(B, specs, precision, 2)
+    ctx = batch_ctx(B, specs, precision, schedule)
     try:
         fts = [gpu(f, dev) for f in fs]
         us = [np.zeros_like(f) for f in fs]
@@ -494,16 +505,17 @@ def test_persistent_batch_step_parity(B, dev, precision, bc, sizes):
         B.mg_destroy(ctx)
 
 
+@pytest.mark.parametrize("schedule", [2, 3])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_persistent_batch_solve(B, dev, precision):
-    """Batched solve with the persistent schedule: every problem reaches
-    1e-10 in the oracle's number of cycles (+-1), problems stopping
+def test_persistent_batch_solve(B, dev, schedule, precision):
+    """Batched solve with the persistent (or phased) schedule: every problem
+    reaches 1e-10 in the oracle's number of cycles (+-1), problems stopping
     independently, and matches the oracle's solution."""
     sizes = [129, 1025, 257, 129, 513, 257, 1025, 513]
-    say(f"persistent batch solve precision={precision}")
+    say(f"batch solve schedule={schedule} precision={precision}")
     specs = [(n, P) for n in sizes]
     fs = [workloads.rhs_divu_periodic(n, 1000 + k) for k, n in enumerate(sizes)]
-    ctx = batch_ctx(B, specs, precision, 2)
+    ctx = batch_ctx(B, specs, precision, schedule)
     try:
         fts = [gpu(f, dev) for f in fs]
         uts = [torch.zeros_like(t) for t in fts]
@@ -529,16 +541,21 @@ def test_persistent_matches_per_problem_schedule(B, dev):
     specs = [(n, P) for n in sizes]
     fs = [workloads.rhs_divu_periodic(n, 7 + k) for k, n in enumerate(sizes)]
     outs = []
-    for schedule in (1, 2):
+    for schedule in (1, 2, 3):
         ctx = batch_ctx(B, specs, 1, schedule)
         fts = [gpu(f, dev) for f in fs]
         uts = [torch.zeros_like(t) for t in fts]
         rel = B.mg_vcycle(ctx, [t.data_ptr() for t in uts], [t.data_ptr() for t in fts], 3, True)
         outs.append(([host(t) for t in uts], rel))
         B.mg_destroy(ctx)
-    for a, b in zip(outs[0][0], outs[1][0]):
-        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(a)
-    np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=1e-6)
+    for other in outs[1:]:
+        for a, b in zip(outs[0][0], other[0]):
+            assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(a)
+        np.testing.assert_allclose(outs[0][1], other[1], rtol=1e-6)
+    # The persistent and phased schedules run the same device functions on
+    # the same items: bitwise equal.
+    for a, b in zip(outs[1][0], outs[2][0]):
+        assert np.array_equal(a, b)
 
 
 def test_persistent_rejects_mixed_boundary_conditions(B, dev):
