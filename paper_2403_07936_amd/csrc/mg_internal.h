@@ -267,6 +267,10 @@ template <typename T>
 hipError_t launch_phase(hipStream_t s, int bc, int kind, const PProblem* probs,
                         const PPhase* phases, int ph, const PItem* items, const double* inv,
                         int blocks, size_t lds);
+// Wavefronts of the phase kernel of `kind` (kItemDown or kItemUp) that the
+// current device holds at once.
+template <typename T>
+hipError_t phase_wave_slots(int bc, int kind, long* slots);
 // Largest number of co-resident workgroups of the persistent kernel.
 template <typename T>
 hipError_t persistent_blocks(int bc, size_t lds, int* blocks);

@@ -381,6 +381,29 @@ template hipError_t launch_persistent<double>(hipStream_t, int, const PProblem*,
                                               size_t);
 template hipError_t launch_persistent<float>(hipStream_t, int, const PProblem*, const PPhase*, int,
                                              const PItem*, PBarrier*, const double*, int, size_t);
+template <typename T>
+hipError_t phase_wave_slots(int bc, int kind, long* slots) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const bool d = bc == kDirichlet;
+  const void* fn = nullptr;
+  if (kind == kItemDown)
+    fn = d ? (const void*)k_phase<T, kDirichlet, kItemDown> : (const void*)k_phase<T, kPeriodic, kItemDown>;
+  else if (kind == kItemUp)
+    fn = d ? (const void*)k_phase<T, kDirichlet, kItemUp> : (const void*)k_phase<T, kPeriodic, kItemUp>;
+  else
+    return hipErrorInvalidValue;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kPersistThreads, 0);
+  if (e != hipSuccess) return e;
+  *slots = (long)per * kWavesPerBlock * cus;
+  return hipSuccess;
+}
+template hipError_t phase_wave_slots<double>(int, int, long*);
+template hipError_t phase_wave_slots<float>(int, int, long*);
+
 template hipError_t launch_phase<double>(hipStream_t, int, int, const PProblem*, const PPhase*,
                                          int, const PItem*, const double*, int, size_t);
 template hipError_t launch_phase<float>(hipStream_t, int, int, const PProblem*, const PPhase*,

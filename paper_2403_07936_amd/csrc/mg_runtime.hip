@@ -754,6 +754,38 @@ int32_t build_persistent(mg_ctx_s* ctx) {
     K = std::max(K, p.tail);
     P.lds_tail = std::max(P.lds_tail, dev::tail_bytes(p.side[p.tail], sizeof(T)));
   }
+  // Segment rows of the streaming phases: every problem's level in a phase
+  // gets the smallest even height at which the phase's items over the whole
+  // batch fit the kernel's resident wavefronts (a problem alone would cut
+  // its levels much finer, each segment re-reading its halo rows).
+  {
+    long slots_down = 0, slots_up = 0;
+    MG_HIP(phase_wave_slots<T>(P.bc, kItemDown, &slots_down));
+    MG_HIP(phase_wave_slots<T>(P.bc, kItemUp, &slots_up));
+    for (int k = 0; k < K; ++k)
+      for (int down = 0; down < 2; ++down) {
+        const long slots = down ? slots_down : slots_up;
+        auto items_at = [&](int hs) {
+          long tot = 0;
+          for (int b = 0; b < B; ++b) {
+            const int l = ctx->probs[b].tail - 1 - k;
+            if (l < 0) continue;
+            const PLevel& L = P.h_probs[b].lv[l];
+            const int extent = P.bc == kPeriodic ? L.n - 1 : L.n;
+            tot += (long)(down ? L.nb_down : L.nb_up) * ((extent + hs - 1) / hs);
+          }
+          return tot;
+        };
+        int hs = 8;
+        while (hs < 4096 && items_at(hs) > slots) hs += 2;
+        for (int b = 0; b < B; ++b) {
+          const int l = ctx->probs[b].tail - 1 - k;
+          if (l < 0) continue;
+          PLevel& L = P.h_probs[b].lv[l];
+          (down ? L.hs_down : L.hs_up) = hs;
+        }
+      }
+  }
   std::vector<PPhase> phases;
   std::vector<PItem> items;
   auto close_phase = [&](int kind, size_t first) {
