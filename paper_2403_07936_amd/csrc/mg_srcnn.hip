@@ -311,6 +311,174 @@ __global__ void __launch_bounds__(kConvThreads)
   }
 }
 
+// ---------------------------------------------------------------- 64-channel conv, tall tiles
+// The same convolution (MODE as k_cnn_conv) on tiles of 16 x 32 pixels by
+// eight wavefronts: wavefront w computes output rows 4 (w >> 1) .. + 3 for
+// the 32 output channels of half w & 1 (four 32 x 32 accumulator tiles).
+// The K loop runs over (column tap dx, 16-channel chunk kc): the six input
+// rows that four output rows see are read once and serve all three row taps
+// dy, so a step of 12 products reads 3 weight and 6 pixel fragments from
+// LDS (0.75 per product, against 1 in k_cnn_conv, whose products wait on
+// LDS), the next step's reads issued before the current step's products.
+// LDS: the weight set and one input tile (16 + 2) x (32 + 2) pixels; the
+// next tile is fetched into registers during the products and stored after
+// them.
+constexpr int kTH4 = 16;
+constexpr int kConv4Threads = 512;
+constexpr int kTPix4 = (kTH4 + 2) * kHW;
+constexpr int kTileChunks4 = kTPix4 * 8;
+constexpr int kTPerThread4 = (kTileChunks4 + kConv4Threads - 1) / kConv4Threads;  // 10
+constexpr int kWPerThread4 = kWChunks / kConv4Threads;                            // 9
+static_assert(kWChunks % kConv4Threads == 0, "weight chunks split evenly");
+
+template <int MODE>
+__global__ void __launch_bounds__(kConv4Threads)
+    k_cnn_conv4(int N, const unsigned short* __restrict__ in, const unsigned short* __restrict__ w,
+                unsigned short* out, const unsigned short* skip) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  uint4* wl = reinterpret_cast<uint4*>(lds);             // kWChunks
+  uint4* ib = reinterpret_cast<uint4*>(lds) + kWChunks;  // kTileChunks4
+  const int tid = threadIdx.x;
+  const int tiles_x = N / kTW, tiles = tiles_x * (N / kTH4);
+  const uint4* in4 = reinterpret_cast<const uint4*>(in);
+  int tile = blockIdx.x;
+  if (tile >= tiles) return;  // uniform per workgroup
+  // Chunk q of a tile's input (q < kTileChunks4): 16-byte chunk q / kTPix4
+  // of tile pixel q % kTPix4, with periodic wrap.
+  auto chunk_of = [&](int t, int q) {
+    const int row0 = (t / tiles_x) * kTH4, col0 = (t % tiles_x) * kTW;
+    const int c = q / kTPix4, p = q % kTPix4;
+    int gy = row0 - 1 + p / kHW, gx = col0 - 1 + p % kHW;
+    gy = gy < 0 ? gy + N : (gy >= N ? gy - N : gy);
+    gx = gx < 0 ? gx + N : (gx >= N ? gx - N : gx);
+    return in4[((size_t)gy * N + gx) * 8 + c];
+  };
+  {
+    const uint4* wg = reinterpret_cast<const uint4*>(w) + (size_t)(MODE == 2 ? blockIdx.y : 0) * kWChunks;
+    uint4 r[kWPerThread4];
+#pragma unroll
+    for (int k = 0; k < kWPerThread4; ++k) {
+      const int q = k * kConv4Threads + tid;
+      r[k] = wg[(q % kWRows) * 8 + q / kWRows];
+    }
+#pragma unroll
+    for (int k = 0; k < kWPerThread4; ++k) wl[k * kConv4Threads + tid] = r[k];
+    uint4 t[kTPerThread4];
+#pragma unroll
+    for (int k = 0; k < kTPerThread4; ++k) t[k] = chunk_of(tile, min(k * kConv4Threads + tid, kTileChunks4 - 1));
+#pragma unroll
+    for (int k = 0; k < kTPerThread4; ++k)
+      if (k * kConv4Threads + tid < kTileChunks4) ib[k * kConv4Threads + tid] = t[k];
+  }
+  __syncthreads();
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int rg = wave >> 1, hf = wave & 1;
+  const int m = lane & 31, kh = lane >> 5;
+  const uint4* wb = wl + kh * kWRows + 32 * hf + m;           // chunk kh, weight row 32 hf + m
+  const uint4* ibase = ib + kh * kTPix4 + 4 * rg * kHW + m;   // chunk kh, pixel (4 rg, m)
+  for (; tile < tiles; tile += gridDim.x) {
+    const int next = tile + gridDim.x;
+    // The next tile's input, in registers until this tile's products are
+    // done (the last pass re-reads this tile; nothing is stored then).
+    uint4 pre[kTPerThread4];
+#pragma unroll
+    for (int k = 0; k < kTPerThread4; ++k)
+      pre[k] = chunk_of(next < tiles ? next : tile, min(k * kConv4Threads + tid, kTileChunks4 - 1));
+    const int row0 = (tile / tiles_x) * kTH4, col0 = (tile % tiles_x) * kTW;
+
+    f32x16 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
+    // Step st = (dx, kc): fragments A[dy] (weights of tap (dy, dx), output
+    // channel 32 hf + m) and B[r] (input row 4 rg + r, column m + dx), all
+    // of input-channel chunk 2 kc + kh.
+    auto fetch = [&](int st, bf16x8 (&fa)[3], bf16x8 (&fb)[6]) {
+      const int dx = st >> 2, kc = st & 3;
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+        fa[dy] = __builtin_bit_cast(bf16x8, wb[2 * kc * kWRows + (dy * 3 + dx) * kC]);
+#pragma unroll
+      for (int r = 0; r < 6; ++r)
+        fb[r] = __builtin_bit_cast(bf16x8, ibase[2 * kc * kTPix4 + r * kHW + dx]);
+    };
+    // The skip values (MODE 1), read before the products so that their
+    // latency hides behind them (out may alias skip: each value is read
+    // here and written only by this lane's epilogue).
+    uint2 skv[4][4];
+    if (MODE == 1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const size_t ob = ((size_t)(row0 + 4 * rg + i) * N + (col0 + m)) * kC;
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          skv[i][g] = *reinterpret_cast<const uint2*>(skip + ob + 32 * hf + 8 * g + 4 * kh);
+      }
+    }
+    bf16x8 fa[2][3], fb[2][6];
+    fetch(0, fa[0], fb[0]);
+#pragma unroll
+    for (int st = 0; st < 12; ++st) {
+      if (st + 1 < 12) fetch(st + 1, fa[(st + 1) & 1], fb[(st + 1) & 1]);
+      // The next step's reads go out before any of this step's products, a
+      // whole step ahead of their use; without the barrier the compiler
+      // reuses this step's operand registers for them and issues each read
+      // just before it is needed.
+      __builtin_amdgcn_sched_barrier(0);
+      const bf16x8(&a)[3] = fa[st & 1];
+      const bf16x8(&b)[6] = fb[st & 1];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[dy], b[i + dy], acc[i], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // Lane holds pixel column m and output channels 32 hf + 8 g + 4 kh +
+    // (0..3) of output rows 4 rg + i.
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int y = row0 + 4 * rg + i, x = col0 + m;
+      size_t base;
+      if (MODE == 2) {
+        const int a = blockIdx.y >> 1, b = blockIdx.y & 1;
+        base = ((size_t)(2 * y + a) * (2 * N) + (2 * x + b)) * kC;
+      } else {
+        base = ((size_t)y * N + x) * kC;
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int ch = 32 * hf + 8 * g + 4 * kh;
+        float v[4];
+        for (int r = 0; r < 4; ++r) v[r] = acc[i][4 * g + r];
+        if (MODE == 1) {
+          const uint2 sk = skv[i][g];
+          v[0] += from_bf16(sk.x & 0xffff);
+          v[1] += from_bf16(sk.x >> 16);
+          v[2] += from_bf16(sk.y & 0xffff);
+          v[3] += from_bf16(sk.y >> 16);
+        } else {
+          for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
+        }
+        uint2 pk;
+        pk.x = to_bf16(v[0]) | ((unsigned)to_bf16(v[1]) << 16);
+        pk.y = to_bf16(v[2]) | ((unsigned)to_bf16(v[3]) << 16);
+        *reinterpret_cast<uint2*>(out + base + ch) = pk;
+      }
+    }
+    if (next < tiles) {
+      __syncthreads();  // every wavefront is done with this tile
+#pragma unroll
+      for (int k = 0; k < kTPerThread4; ++k)
+        if (k * kConv4Threads + tid < kTileChunks4) ib[k * kConv4Threads + tid] = pre[k];
+      __syncthreads();
+    }
+  }
+}
+
 // ---------------------------------------------------------------- final conv
 // 64 -> 1 at fine resolution M = 2N, times s, added to uin (nullable) and
 // written to uout (the fine grid, M + 1 nodes per side; the seam row and
@@ -385,6 +553,7 @@ int g_cus = 256;  // compute units of the device (set by cnn_init)
 }  // namespace
 
 size_t cnn_conv_lds() { return (size_t)(kWChunks + 2 * kTileChunks) * 16; }
+size_t cnn_conv4_lds() { return (size_t)(kWChunks + kTileChunks4) * 16; }
 
 hipError_t cnn_init() {
   int dev = 0;
@@ -399,6 +568,12 @@ hipError_t cnn_init() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_cnn_conv<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)cnn_conv_lds());
+  const void* tall[] = {(const void*)k_cnn_conv4<0>, (const void*)k_cnn_conv4<1>,
+                        (const void*)k_cnn_conv4<2>};
+  for (const void* fn : tall)
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)cnn_conv4_lds());
   return e;
 }
 
@@ -418,8 +593,23 @@ hipError_t launch_cnn_head(hipStream_t s, int N, const T* e, int pe, float* part
 hipError_t launch_cnn_conv(hipStream_t s, int mode, int N, const unsigned short* in,
                            const unsigned short* w, unsigned short* out, const unsigned short* skip) {
   // One workgroup per compute unit (its LDS holds a whole weight set), each
-  // taking at least two tiles where there are enough.
+  // taking at least two tiles where there are enough.  Tall tiles (16 rows)
+  // where they still give every compute unit a tile; else 8-row tiles.
   const int sets = mode == 2 ? 4 : 1;
+  const int tall = (N / kTW) * (N / kTH4);
+  if (tall * sets >= g_cus) {
+    int g = std::max(1, g_cus / sets);
+    g = std::min(g, tall);
+    const dim3 grid((unsigned)g, (unsigned)sets);
+    const size_t lds = cnn_conv4_lds();
+    if (mode == 0)
+      hipLaunchKernelGGL(k_cnn_conv4<0>, grid, dim3(kConv4Threads), lds, s, N, in, w, out, skip);
+    else if (mode == 1)
+      hipLaunchKernelGGL(k_cnn_conv4<1>, grid, dim3(kConv4Threads), lds, s, N, in, w, out, skip);
+    else
+      hipLaunchKernelGGL(k_cnn_conv4<2>, grid, dim3(kConv4Threads), lds, s, N, in, w, out, skip);
+    return hipGetLastError();
+  }
   const int tiles = (N / kTW) * (N / kTH);
   int g = std::max(1, g_cus / sets);
   g = std::min(g, std::max(1, (tiles + 1) / 2));
