@@ -1,7 +1,7 @@
 // Persistent cycle kernel: one launch runs a whole step (for the mixed path:
 // FP64 residual, the FP32 V-cycle, FP64 update) for every problem of a batch.
 //
-// The host flattens the step into phases (mg_runtime.hip): a phase is a list
+// The host flattens the step into phases (mg_batch.hip): a phase is a list
 // of items of one kind, and every item of a phase is independent of the
 // others.  Phases are aligned from the coarsest level, so the tails of all
 // problems fall in one phase whatever their sizes.  Workgroups take items
