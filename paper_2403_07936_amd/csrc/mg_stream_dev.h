@@ -261,7 +261,7 @@ __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2],
 // stored to rout (pitch pro; f is not used), where the up pass reads them.  The same
 // arithmetic as residual_wave, so r32 is bitwise what that writes on the
 // nodes the up pass reads.
-template <typename T, int BC, int UIN, bool RES, int IN, bool SB = true>
+template <typename T, int BC, int UIN, bool RES, int IN, bool SB = true, bool REV = false>
 __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
@@ -270,9 +270,17 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
                                           const double* __restrict__ f64, int pf64,
                                           double inv_h2d, T* __restrict__ rout, int pro) {
   static_assert(!RES || (UIN == 0 && sizeof(T) == sizeof(float)), "RES: FP32 cycle from u = 0");
+  static_assert(!REV || IN >= 1, "a reversed segment lies inside the grid");
   const int xw = band * kDownOwned - kDownHalo;
   const int x0 = xw + 2 * lane;
-  const int ys = seg * hs;
+  // REV: the segment's rows [seg hs, seg hs + hs) are walked upwards, as
+  // rows v of a mirrored grid, row v = C - (grid row) with C = 2 seg hs + hs
+  // even (so row parities, and with them the colours and the even rows the
+  // restriction reads, are the same in both).  The mirrored segment then
+  // starts at the odd row seg hs + 1.
+  const int ys = REV ? seg * hs + 1 : seg * hs;
+  const int C = 2 * seg * hs + hs;
+  auto ra = [&](int v) { return REV ? C - v : v; };  // grid row of pipeline row v
   const Cols<BC> col = make_cols<BC, IN>(x0, n);
   const int N = n - 1, nc = (n - 1) / 2 + 1;
   const bool lane_owns = lane >= kDownHalo / 2 && lane < 64 - kDownHalo / 2;
@@ -293,8 +301,11 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
 #pragma unroll
   for (int k = 0; k < 4; ++k) R[k][0] = R[k][1] = T(0);
 
-  const int t0 = ys - 6;  // even (hs is even)
-  const int steps = hs + 11;
+  const int t0 = ys - 6;  // even (hs is even); odd when REV
+  constexpr int P = REV ? 1 : 0;  // parity of t - k
+  // The restriction of even row i runs at step i + 6; mirrored, the last
+  // even row the segment owns is ys + hs - 1, one step later than forward.
+  const int steps = hs + 11 + P;
   const bool read_u = UIN == 1 || (UIN == -1 && uin != nullptr);
   // RES: u64 row t0 - 1 + q in RU[q & 7], f64 row t0 + q in RF[q & 3],
   // loaded kAheadR + 1 and kAheadR rows before their residual row.
@@ -306,18 +317,18 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
 #pragma unroll
     for (int q = 0; q < kAheadR + 2; ++q) {
       const int r = t0 - 1 + q;
-      load_row<double, BC, IN>(RU[q], u64, p64, r < tl + 1 ? r : tl + 1, n, col);
+      load_row<double, BC, IN>(RU[q], u64, p64, ra(r < tl + 1 ? r : tl + 1), n, col);
     }
 #pragma unroll
     for (int q = 0; q < kAheadR; ++q) {
       const int r = t0 + q;
-      load_row<double, BC, IN>(RF[q], f64, pf64, r < tl ? r : tl, n, col);
+      load_row<double, BC, IN>(RF[q], f64, pf64, ra(r < tl ? r : tl), n, col);
     }
   } else {
 #pragma unroll
     for (int k = 0; k < kAheadDown; ++k) {
-      if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC, IN>(U[k], uin, pui, t0 + k, n, col);
-      load_row<T, BC, IN>(F[k], f, pf, t0 + k, n, col);
+      if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC, IN>(U[k], uin, pui, ra(t0 + k), n, col);
+      load_row<T, BC, IN>(F[k], f, pf, ra(t0 + k), n, col);
     }
   }
   for (int sb = 0; sb < steps; sb += 16) {
@@ -333,8 +344,8 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
         // t - 1 .. t + 1 and f64 row t.
         const int tu = t + kAheadR + 1 < tl + 1 ? t + kAheadR + 1 : tl + 1;
         const int tf = t + kAheadR < tl ? t + kAheadR : tl;
-        load_row<double, BC, IN>(RU[(k + kAheadR + 2) & 7], u64, p64, tu, n, col);
-        load_row<double, BC, IN>(RF[(k + kAheadR) & 3], f64, pf64, tf, n, col);
+        load_row<double, BC, IN>(RU[(k + kAheadR + 2) & 7], u64, p64, ra(tu), n, col);
+        load_row<double, BC, IN>(RF[(k + kAheadR) & 3], f64, pf64, ra(tf), n, col);
         const double(&um)[2] = RU[k & 7];
         const double(&u0)[2] = RU[(k + 1) & 7];
         const double(&up)[2] = RU[(k + 2) & 7];
@@ -353,42 +364,44 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
         F[k & RM][0] = (T)r0;
         F[k & RM][1] = (T)r1;
         if (t >= ys && t < ys + hs && (IN || t < row_end))
-          store_pair<T>(rout + (size_t)t * pro + x0, rw0, rw1, (T)r0, (T)r1);
+          store_pair<T>(rout + (size_t)ra(t) * pro + x0, rw0, rw1, (T)r0, (T)r1);
         U[k & RM][0] = U[k & RM][1] = T(0);  // row t starts from 0
       } else {
         const int ta = t + kAheadDown < t0 + steps - 1 ? t + kAheadDown : t0 + steps - 1;
         T(&nu)[2] = U[(k + kAheadDown) & RM];
-        if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC, IN>(nu, uin, pui, ta, n, col);
+        if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC, IN>(nu, uin, pui, ra(ta), n, col);
         else nu[0] = nu[1] = T(0);
-        load_row<T, BC, IN>(F[(k + kAheadDown) & RM], f, pf, ta, n, col);
+        load_row<T, BC, IN>(F[(k + kAheadDown) & RM], f, pf, ra(ta), n, col);
       }
       // red (sweep 1) on t-1, black on t-2, red (sweep 2) on t-3, black on
-      // t-4; t has the parity of k (t0 and sb are even).
+      // t-4; t has the parity of k + P (t0 - P and sb are even).
       sweep_row<T, BC, IN>(U[(k + 14) & RM], U[(k + 15) & RM], U[k & RM], F[(k + 15) & RM], t - 1,
-                       (k + 1) & 1, n, col, h2);
+                       (k + 1 + P) & 1, n, col, h2);
       sweep_row<T, BC, IN>(U[(k + 13) & RM], U[(k + 14) & RM], U[(k + 15) & RM], F[(k + 14) & RM],
-                       t - 2, (k + 1) & 1, n, col, h2);
+                       t - 2, (k + 1 + P) & 1, n, col, h2);
       sweep_row<T, BC, IN>(U[(k + 12) & RM], U[(k + 13) & RM], U[(k + 14) & RM], F[(k + 13) & RM],
-                       t - 3, (k + 1) & 1, n, col, h2);
+                       t - 3, (k + 1 + P) & 1, n, col, h2);
       sweep_row<T, BC, IN>(U[(k + 11) & RM], U[(k + 12) & RM], U[(k + 13) & RM], F[(k + 12) & RM],
-                       t - 4, (k + 1) & 1, n, col, h2);
+                       t - 4, (k + 1 + P) & 1, n, col, h2);
       const int tu = t - 4;
       if (SB && tu >= ys && tu < ys + hs && (IN || tu < row_end)) {
-        T* p = uout + (size_t)tu * puo;
+        T* p = uout + (size_t)ra(tu) * puo;
         store_pair<T>(p + x0, wr0, wr1, U[(k + 12) & RM][0], U[(k + 12) & RM][1]);
       }
       residual_row<T, BC, IN>(U[(k + 10) & RM], U[(k + 11) & RM], U[(k + 12) & RM], F[(k + 11) & RM],
                           R[(k + 3) & 3], t - 5, n, col, inv_h2);
       const int i = t - 6;
       if ((i & 1) == 0 && i >= ys && i < ys + hs) {
-        const int I = i >> 1;
+        const int I = ra(i) >> 1;
         const bool rowc = IN || (BC == kPeriodic ? I < nc - 1 : (I >= 1 && I <= nc - 2));
         const T(&rm)[2] = R[(k + 1) & 3];
         const T(&r0)[2] = R[(k + 2) & 3];
         const T(&rp)[2] = R[(k + 3) & 3];
         const T am = from_left(rm[1]), a0 = from_left(r0[1]), ap = from_left(rp[1]);
+        // Sums symmetric in rm and rp (pairs added first), so that a segment
+        // walked upwards rounds as one walked downwards.
         const T edges = ((rm[0] + rp[0]) + a0) + r0[1];
-        const T corners = ((am + rm[1]) + ap) + rp[1];
+        const T corners = (am + rm[1]) + (ap + rp[1]);
         const T v = ((T(4) * r0[0] + T(2) * edges) + corners) * T(0.0625);
         if (rowc && wrc) fc[(size_t)I * pfc + J] = v;
       }
@@ -416,7 +429,18 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
   // The residual-making form stays at IN = 1 across columns: its IN = 2 code
   // (fewer instructions, loads kept in flight differently) measured 78 -> 87
   // us at 4097^2.
-  if (!RES && in && band_inside<BC>(band * kDownOwned - kDownHalo, n))
+  // Odd segments inside the grid walk their rows upwards (REV), so that
+  // neighbouring segments read the rows around their shared edge at the
+  // same time (both at the start, or both at the end of their walk) and one
+  // of the two reads finds them in cache.  Reversed, a segment touches rows
+  // seg hs - 7 .. seg hs + hs + 6.
+  const int lo_r = seg * hs - 7, hi_r = seg * hs + hs + 6;
+  const bool in_r = BC == kPeriodic ? (lo_r >= 0 && hi_r <= n - 2) : (lo_r >= 1 && hi_r <= n - 2);
+  if (RES && (seg & 1) && in_r)
+    down_wave_rows<T, BC, UIN, RES, 1, SB, true>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg,
+                                                 hs, h2, inv_h2, lane, u64, p64, f64, pf64,
+                                                 inv_h2d, rout, pro);
+  else if (!RES && in && band_inside<BC>(band * kDownOwned - kDownHalo, n))
     down_wave_rows<T, BC, UIN, RES, 2, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
                                            h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
                                            pro);
