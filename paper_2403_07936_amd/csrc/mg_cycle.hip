@@ -440,22 +440,37 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
   // null space of A).
   {
     std::vector<int> per;
-    for (int b = 0; b < B; ++b) {
-      Problem& p = ctx->probs[b];
-      if (p.bc != kPeriodic) continue;
-      int nb = 0;
-      MG_HIP(launch_rhs_moments(ctx->stream, p.bc, p.n, f[b], p.pitch0, p.partials, &nb));
-      MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 2, p.sums));
-      per.push_back(b);
+    std::vector<double> mom;
+    if (ctx->ps.on) {
+      // The batch schedules: one launch for every problem's sums.
+      MG_TRY(persistent_bind(ctx, u, f, {}));
+      if (ctx->ps.bc == kPeriodic) {
+        for (int b = 0; b < B; ++b) per.push_back(b);
+        mom.resize(2 * B);
+        MG_HIP(launch_moments_batched(ctx->stream, ctx->ps.d_probs, B, ctx->ps.d_partials,
+                                      ctx->ps.slots, ctx->ps.d_sums));
+        MG_HIP(hipMemcpyAsync(mom.data(), ctx->ps.d_sums, sizeof(double) * 2 * B,
+                              hipMemcpyDeviceToHost, ctx->stream));
+      }
+    } else {
+      for (int b = 0; b < B; ++b) {
+        Problem& p = ctx->probs[b];
+        if (p.bc != kPeriodic) continue;
+        int nb = 0;
+        MG_HIP(launch_rhs_moments(ctx->stream, p.bc, p.n, f[b], p.pitch0, p.partials, &nb));
+        MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 2, p.sums));
+        per.push_back(b);
+      }
+      for (size_t k = 0; k < per.size(); ++k)
+        MG_HIP(hipMemcpyAsync(ctx->host + 2 * k, ctx->probs[per[k]].sums, 2 * sizeof(double),
+                              hipMemcpyDeviceToHost, ctx->stream));
     }
-    for (size_t k = 0; k < per.size(); ++k)
-      MG_HIP(hipMemcpyAsync(ctx->host + 2 * k, ctx->probs[per[k]].sums, 2 * sizeof(double),
-                            hipMemcpyDeviceToHost, ctx->stream));
     MG_HIP(hipStreamSynchronize(ctx->stream));
     for (size_t k = 0; k < per.size(); ++k) {
       const Problem& p = ctx->probs[per[k]];
       const double M = (double)(p.n - 1) * (double)(p.n - 1);
-      const double sum = ctx->host[2 * k], sq = ctx->host[2 * k + 1];
+      const double* m2 = mom.empty() ? ctx->host + 2 * k : mom.data() + 2 * k;
+      const double sum = m2[0], sq = m2[1];
       if (!std::isfinite(sum) || !std::isfinite(sq))
         return fail(MG_ERR_NONFINITE, "non-finite right-hand side");
       if (std::fabs(sum) > 1e-10 * std::sqrt(M) * std::sqrt(sq))

@@ -280,6 +280,9 @@ hipError_t persistent_init(size_t lds64, size_t lds32);
 hipError_t launch_resnorm_batched(hipStream_t s, int bc, const PProblem* probs, int nprob,
                                   double* partials, int slots, double* sums);
 hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob);
+// Per-problem sums of f and f^2 over the unknowns (sums[2 b], sums[2 b + 1]).
+hipError_t launch_moments_batched(hipStream_t s, const PProblem* probs, int nprob,
+                                  double* partials, int slots, double* sums);
 // Mixed path, level 0, from e = 0: the streaming down pass whose
 // right-hand side r32 = fl32(f64 - A u64) it computes itself (and stores on
 // the rows and columns it owns, for the up pass): no separate residual pass.

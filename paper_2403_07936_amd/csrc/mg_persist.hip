@@ -201,7 +201,11 @@ __global__ void __launch_bounds__(kPersistThreads)
 
 __global__ void k_resnorm_batched(int bc, const PProblem* __restrict__ probs, double* partials,
                                   int slots) {
-  // Workgroup (256 threads) = (problem, slot); rows slot, slot + slots, ...
+  // Workgroup (256 threads) = (problem, slot): the unknowns of a run of
+  // consecutive rows; a thread walks its columns j, j + 256, ... down the
+  // run with the rows above and below its node in registers, so each row of
+  // u is read once per column (plus its two neighbours in the row, which
+  // the neighbouring lanes' reads bring into L1).
   __shared__ double sr[256], sf[256];
   const int pi = blockIdx.y, slot = blockIdx.x, t = threadIdx.x;
   const PProblem& p = probs[pi];
@@ -211,23 +215,28 @@ __global__ void k_resnorm_batched(int bc, const PProblem* __restrict__ probs, do
     const double* u = p.u64;
     const double* f = p.f64;
     const double inv_h2 = (double)(n - 1) * (double)(n - 1);
-    const int lo = bc == kDirichlet ? 1 : 0, N = n - 1;
-    for (int i = lo + slot; i <= n - 2; i += slots)
-      for (int j = lo + t; j <= n - 2; j += 256) {
-        int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
-        if (bc == kPeriodic) {
-          im = i == 0 ? N - 1 : im;
-          ip = i == N - 1 ? 0 : ip;
-          jm = j == 0 ? N - 1 : jm;
-          jp = j == N - 1 ? 0 : jp;
-        }
-        const double s = ((u[(size_t)im * pu + j] + u[(size_t)ip * pu + j]) + u[(size_t)i * pu + jm]) +
-                         u[(size_t)i * pu + jp];
+    const int lo = bc == kDirichlet ? 1 : 0, hi = n - 2, N = n - 1;
+    const int rows = hi - lo + 1, run = (rows + slots - 1) / slots;
+    const int r0 = lo + slot * run, r1 = min(r0 + run, hi + 1);
+    auto row_of = [&](int i) { return bc == kPeriodic ? (i < 0 ? i + N : (i >= N ? i - N : i)) : i; };
+    for (int j = lo + t; j <= hi; j += 256) {
+      const int jm = bc == kPeriodic && j == 0 ? N - 1 : j - 1;
+      const int jp = bc == kPeriodic && j == N - 1 ? 0 : j + 1;
+      if (r0 >= r1) break;
+      double um = u[(size_t)row_of(r0 - 1) * pu + j], uc = u[(size_t)r0 * pu + j];
+#pragma unroll 4
+      for (int i = r0; i < r1; ++i) {
+        const double up = u[(size_t)row_of(i + 1) * pu + j];
+        const double* ui = u + (size_t)i * pu;
+        const double s = ((um + up) + ui[jm]) + ui[jp];
         const double fv = f[(size_t)i * pu + j];
-        const double r = fv - (4.0 * u[(size_t)i * pu + j] - s) * inv_h2;
+        const double r = fv - (4.0 * uc - s) * inv_h2;
         rr += r * r;
         ff += fv * fv;
+        um = uc;
+        uc = up;
       }
+    }
   }
   sr[t] = rr;
   sf[t] = ff;
@@ -242,6 +251,41 @@ __global__ void k_resnorm_batched(int bc, const PProblem* __restrict__ probs, do
   if (t == 0) {
     partials[((size_t)pi * slots + slot) * 2] = sr[0];
     partials[((size_t)pi * slots + slot) * 2 + 1] = sf[0];
+  }
+}
+
+// Workgroup (256 threads) = (problem, slot): sums of f and f^2 over the
+// unknowns of rows slot, slot + slots, ... of the problem's right-hand side.
+__global__ void k_moments_batched(const PProblem* __restrict__ probs, double* partials,
+                                  int slots) {
+  __shared__ double sa[256], sb[256];
+  const int pi = blockIdx.y, slot = blockIdx.x, t = threadIdx.x;
+  const PProblem& p = probs[pi];
+  double x = 0.0, x2 = 0.0;
+  {
+    const int n = p.lv[0].n, pf = p.pitch64;
+    const double* f = p.f64;
+    const int lo = p.bc == kDirichlet ? 1 : 0;
+    for (int i = lo + slot; i <= n - 2; i += slots)
+      for (int j = lo + t; j <= n - 2; j += 256) {
+        const double v = f[(size_t)i * pf + j];
+        x += v;
+        x2 += v * v;
+      }
+  }
+  sa[t] = x;
+  sb[t] = x2;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (t < s2) {
+      sa[t] += sa[t + s2];
+      sb[t] += sb[t + s2];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    partials[((size_t)pi * slots + slot) * 2] = sa[0];
+    partials[((size_t)pi * slots + slot) * 2 + 1] = sb[0];
   }
 }
 
@@ -365,6 +409,15 @@ hipError_t launch_phase(hipStream_t s, int bc, int kind, const PProblem* probs,
 hipError_t launch_resnorm_batched(hipStream_t s, int bc, const PProblem* probs, int nprob,
                                   double* partials, int slots, double* sums) {
   hipLaunchKernelGGL(k_resnorm_batched, dim3(slots, nprob), dim3(256), 0, s, bc, probs, partials,
+                     slots);
+  hipLaunchKernelGGL(k_reduce_problem, dim3((nprob + 63) / 64), dim3(64), 0, s, partials, slots,
+                     nprob, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_batched(hipStream_t s, const PProblem* probs, int nprob,
+                                  double* partials, int slots, double* sums) {
+  hipLaunchKernelGGL(k_moments_batched, dim3(slots, nprob), dim3(256), 0, s, probs, partials,
                      slots);
   hipLaunchKernelGGL(k_reduce_problem, dim3((nprob + 63) / 64), dim3(64), 0, s, partials, slots,
                      nprob, sums);
