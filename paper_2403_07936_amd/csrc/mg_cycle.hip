@@ -448,7 +448,7 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
         for (int b = 0; b < B; ++b) per.push_back(b);
         mom.resize(2 * B);
         MG_HIP(launch_moments_batched(ctx->stream, ctx->ps.d_probs, B, ctx->ps.d_partials,
-                                      ctx->ps.slots, ctx->ps.d_sums));
+                                      ctx->ps.slots, ctx->ps.d_sums, false));
         MG_HIP(hipMemcpyAsync(mom.data(), ctx->ps.d_sums, sizeof(double) * 2 * B,
                               hipMemcpyDeviceToHost, ctx->stream));
       }
@@ -644,8 +644,17 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
       next_check[b] = cycles[b] + gap;
     }
   }
-  // Periodic results: zero mean and rewritten seam.
-  for (int b = 0; b < B; ++b) {
+  // Periodic results: zero mean and rewritten seam (the batch schedules: in
+  // three launches for every problem that stepped).
+  if (pers && ctx->ps.bc == kPeriodic) {
+    std::vector<int> stepped(B);
+    for (int b = 0; b < B; ++b) stepped[b] = cycles[b] > 0 ? 1 : 0;
+    MG_TRY(persistent_bind(ctx, u, f, stepped));
+    MG_HIP(launch_moments_batched(ctx->stream, ctx->ps.d_probs, B, ctx->ps.d_partials,
+                                  ctx->ps.slots, ctx->ps.d_sums, true));
+    MG_HIP(launch_remove_mean_batched(ctx->stream, ctx->ps.d_probs, B, ctx->ps.d_sums));
+  }
+  for (int b = 0; b < B && !(pers && ctx->ps.bc == kPeriodic); ++b) {
     Problem& p = ctx->probs[b];
     if (p.bc != kPeriodic || cycles[b] == 0) continue;
     int nb = 0;

@@ -280,9 +280,14 @@ hipError_t persistent_init(size_t lds64, size_t lds32);
 hipError_t launch_resnorm_batched(hipStream_t s, int bc, const PProblem* probs, int nprob,
                                   double* partials, int slots, double* sums);
 hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob);
-// Per-problem sums of f and f^2 over the unknowns (sums[2 b], sums[2 b + 1]).
+// Per-problem sums of f (use_u: of u) and of its square over the unknowns
+// (sums[2 b], sums[2 b + 1]); zeros for inactive problems.
 hipError_t launch_moments_batched(hipStream_t s, const PProblem* probs, int nprob,
-                                  double* partials, int slots, double* sums);
+                                  double* partials, int slots, double* sums, bool use_u);
+// Active periodic problems: u minus its mean over the unknowns (sums[2 b] =
+// the sum of u there), then the seams rewritten.
+hipError_t launch_remove_mean_batched(hipStream_t s, const PProblem* probs, int nprob,
+                                      const double* sums);
 // Mixed path, level 0, from e = 0: the streaming down pass whose
 // right-hand side r32 = fl32(f64 - A u64) it computes itself (and stores on
 // the rows and columns it owns, for the up pass): no separate residual pass.

@@ -254,17 +254,18 @@ __global__ void k_resnorm_batched(int bc, const PProblem* __restrict__ probs, do
   }
 }
 
-// Workgroup (256 threads) = (problem, slot): sums of f and f^2 over the
-// unknowns of rows slot, slot + slots, ... of the problem's right-hand side.
+// Workgroup (256 threads) = (problem, slot): sums of a and a^2 over the
+// unknowns of rows slot, slot + slots, ... of the problem's right-hand side
+// (use_u = 0) or iterate (use_u = 1); zeros for inactive problems.
 __global__ void k_moments_batched(const PProblem* __restrict__ probs, double* partials,
-                                  int slots) {
+                                  int slots, int use_u) {
   __shared__ double sa[256], sb[256];
   const int pi = blockIdx.y, slot = blockIdx.x, t = threadIdx.x;
   const PProblem& p = probs[pi];
   double x = 0.0, x2 = 0.0;
-  {
+  if (p.active) {
     const int n = p.lv[0].n, pf = p.pitch64;
-    const double* f = p.f64;
+    const double* f = use_u ? p.u64 : p.f64;
     const int lo = p.bc == kDirichlet ? 1 : 0;
     for (int i = lo + slot; i <= n - 2; i += slots)
       for (int j = lo + t; j <= n - 2; j += 256) {
@@ -300,6 +301,19 @@ __global__ void k_reduce_problem(const double* __restrict__ partials, int slots,
   }
   sums[2 * pi] = rr;
   sums[2 * pi + 1] = ff;
+}
+
+// Periodic problems that are active: u -= sum(u) / N^2 on the unknowns
+// (sums[2 b] = the sum), rows blockIdx.x, blockIdx.x + gridDim.x, ...
+__global__ void k_remove_mean_batched(const PProblem* __restrict__ probs,
+                                      const double* __restrict__ sums) {
+  const PProblem& p = probs[blockIdx.y];
+  if (p.bc != kPeriodic || !p.active) return;
+  const int n = p.lv[0].n, N = n - 1, pu = p.pitch64;
+  const double mean = sums[2 * blockIdx.y] / ((double)N * (double)N);
+  double* u = p.u64;
+  for (int i = blockIdx.x; i < N; i += gridDim.x)
+    for (int j = threadIdx.x; j < N; j += blockDim.x) u[(size_t)i * pu + j] -= mean;
 }
 
 __global__ void k_seam_batched(const PProblem* __restrict__ probs) {
@@ -416,12 +430,18 @@ hipError_t launch_resnorm_batched(hipStream_t s, int bc, const PProblem* probs, 
 }
 
 hipError_t launch_moments_batched(hipStream_t s, const PProblem* probs, int nprob,
-                                  double* partials, int slots, double* sums) {
+                                  double* partials, int slots, double* sums, bool use_u) {
   hipLaunchKernelGGL(k_moments_batched, dim3(slots, nprob), dim3(256), 0, s, probs, partials,
-                     slots);
+                     slots, (int)use_u);
   hipLaunchKernelGGL(k_reduce_problem, dim3((nprob + 63) / 64), dim3(64), 0, s, partials, slots,
                      nprob, sums);
   return hipGetLastError();
+}
+
+hipError_t launch_remove_mean_batched(hipStream_t s, const PProblem* probs, int nprob,
+                                      const double* sums) {
+  hipLaunchKernelGGL(k_remove_mean_batched, dim3(32, nprob), dim3(256), 0, s, probs, sums);
+  return launch_seam_batched(s, probs, nprob);
 }
 
 hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob) {
