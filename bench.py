@@ -53,7 +53,7 @@ def measured_traffic(kind_name: str, precision: str, bc: int):
         # The mixed level-0 passes: the down pass that makes the FP64
         # residual itself (and stores no pre-smoothed iterate), the up pass
         # that re-makes that iterate and adds into the FP64 one.
-        head = {"down": f"k_down_res_s<{bc}, false>", "up": f"k_up_pre_s<{bc}>"}[kind_name]
+        head = {"down": f"k_down_res_s<{bc}, false, false>", "up": f"k_up_pre_s<{bc}>"}[kind_name]
         ents = [v for k, v in rec["per_launch"].items() if k == head]
     else:
         # Template variants of the kernel (input/accumulation flags); the

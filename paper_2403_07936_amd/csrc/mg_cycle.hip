@@ -106,16 +106,27 @@ int32_t enqueue_cycle(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
   return MG_OK;
 }
 
+// Which part of a mixed refinement step is queued: all of it, only the
+// level-0 down pass that makes the FP64 residual (with its norm), or all but
+// that pass (its outputs are already in place).  The iterate changes only
+// in the level-0 up pass, so the head alone leaves it as it was.
+enum StepPart { kWhole = 0, kHead = 1, kRest = 2 };
+
 // The fused schedule: down passes to the first level of at most 65 x 65,
 // the tail kernel, then prefilter + up passes back to level 0.  Level l's
 // pre-smoothed u goes to h.r[l] (ping-pong against h.u[l] / u0).
+// part (mixed level 0 with the residual made in the down pass and the
+// iterate made again in the up pass): kHead queues that down pass with one
+// partial of ||r||^2 and one of ||f||^2 per wavefront into norm_partials
+// (count per sum to *norm_items); kRest the rest of the cycle.
 template <typename T>
 int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
                             const PrefilterTaps* taps_dev, T* u0, int pu0, const T* f0, int pf0,
                             bool zero_guess, hipStream_t s, bool cnn, double* u64 = nullptr,
                             int p64 = 0, bool* added = nullptr, const double* res_u = nullptr,
                             const double* res_f = nullptr, int res_p = 0, T* r_out = nullptr,
-                            const CallerArgs* ca = nullptr) {
+                            const CallerArgs* ca = nullptr, StepPart part = kWhole,
+                            double* norm_partials = nullptr, int* norm_items = nullptr) {
   const int t = p.tail, bc = p.bc;
   // ca: the caller's FP64 arrays are read from the device table.  They are
   // level 0's u0 and f0 on the FP64 path, u64 / res_u / res_f on the mixed
@@ -134,6 +145,8 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
   // up pass streams into the FP64 iterate: the up pass makes the
   // pre-smoothed iterate again from r32, so the down pass does not store it.
   const bool remake0 = res_u && u64 && t > 0 && !up_tiled(0) && !(cnn && ctx->cnn.levels > 0);
+  if (part != kWhole && !remake0)
+    return fail(MG_ERR_INVALID_ARG, "split step without the residual-making level-0 passes");
   for (int l = 0; l < t; ++l) {
     const int n = p.side[l];
     const double m = unknowns_side(n, bc), mc = unknowns_side(p.side[l + 1], bc);
@@ -143,11 +156,15 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
       if (l == 0 && res_u) {
         // Mixed level 0: the right-hand side is made from the FP64 iterate
         // inside the down pass (and stored for the up pass).
+        if (part == kRest) continue;
         MG_TRY(timed(ctx, s, MG_K_DOWN, 0, (16 + 4 + (remake0 ? 0 : 4)) * m * m + 4 * mc * mc, [&] {
           return launch_down_res_stream(s, bc, n, res_u, res_p, res_f, res_p, r_out, pf0,
                                         remake0 ? nullptr : h.r[0], p.pitch[0], h.f[1],
-                                        p.pitch[1], p.down_hs[0], ca);
+                                        p.pitch[1], p.down_hs[0], ca,
+                                        part == kHead ? norm_partials : nullptr,
+                                        2 * p.nblocks, norm_items);
         }));
+        if (part == kHead) return MG_OK;
         continue;
       }
     }
@@ -220,12 +237,21 @@ bool use_fused(const mg_ctx_s* ctx) {
   return ctx->opt.kernel_path != 1 && ctx->opt.nu_pre == 2 && ctx->opt.nu_post == 2;
 }
 
-// One step of the outer iteration for one problem: an FP64 V-cycle, or one
-// refinement step around inner FP32 cycles.
+// A mixed step of p whose level-0 passes make the residual and the iterate
+// themselves (one inner cycle, both level-0 passes streaming, no network):
+// its convergence check is the step's own first pass (split_head), and a
+// step after a check queues only the rest.
+bool split_step(const mg_ctx_s* ctx, const Problem& p) {
+  return ctx->opt.precision == MG_MIXED && use_fused(ctx) && !cnn_cycles(ctx) &&
+         ctx->opt.inner_cycles == 1 && p.tail > 0 && ctx->opt.kernel_path != 2 &&
+         p.down_var[0] == 0 && p.up_var[0] == 0;
+}
+
 // One step for problem p: an FP64 V-cycle, or one mixed refinement step
 // (FP64 residual, FP32 inner cycles, FP64 update).  have_res: the mixed
 // step's residual of this u is already in the level-0 right-hand side (left
-// there by enqueue_check_mixed), so the step starts with the inner cycles.
+// there by enqueue_check_mixed), so the step starts with the inner cycles;
+// for a split step, the whole level-0 down pass has run (split_head).
 int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f,
                      hipStream_t s, bool cnn, bool have_res = false,
                      const CallerArgs* ca = nullptr) {
@@ -245,8 +271,9 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
     // The first inner cycle's streaming down pass can make the residual
     // itself when level 0 lies above the tail and both level-0 passes stream
     // (the up pass reads only rows and columns that down pass stores).
-    const bool res_in_down = fused && !have_res && p.tail > 0 && ctx->opt.kernel_path != 2 &&
-                             p.down_var[0] == 0 && p.up_var[0] == 0;
+    const bool split = split_step(ctx, p);
+    const bool res_in_down = fused && (!have_res || split) && p.tail > 0 &&
+                             ctx->opt.kernel_path != 2 && p.down_var[0] == 0 && p.up_var[0] == 0;
     if (!have_res && !res_in_down)
       MG_TRY(timed(ctx, s, MG_K_RESIDUAL_MIXED, 0, 20 * nn, [&] {
         return launch_residual_mixed(s, p.bc, p.n, u, p.pitch0, f, p.pitch0, r0, p.pitch[0],
@@ -260,7 +287,7 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
         MG_TRY(enqueue_cycle_fused<float>(ctx, p, p.h32, p.taps32_dev, e0, p.pitch[0], r0,
                                           p.pitch[0], k == 0, s, cnn, k == K - 1 ? u : nullptr,
                                           p.pitch0, &added, rd ? u : nullptr, rd ? f : nullptr,
-                                          p.pitch0, r0, ca));
+                                          p.pitch0, r0, ca, split && have_res ? kRest : kWhole));
       }
     } else {
       MG_TRY(timed(ctx, s, MG_K_ZERO, 0, 4 * nn,
@@ -338,9 +365,20 @@ int32_t enqueue_resnorm(mg_ctx_s* ctx, Problem& p, const double* u, const double
 
 // Mixed path: ||f - A u||^2 into p.sums[0] from the FP64 residual that the
 // next refinement step starts from; its FP32 copy stays in the level-0
-// right-hand side, so that step skips it (run_step with have_res).
+// right-hand side, so that step skips it (run_step with have_res).  A split
+// step's check is that step's level-0 down pass itself, with its norms
+// (||f||^2 into p.sums[1] as well).
 int32_t enqueue_check_mixed(mg_ctx_s* ctx, Problem& p, const double* u, const double* f) {
   int nb = 0;
+  if (split_step(ctx, p)) {
+    MG_TRY(enqueue_cycle_fused<float>(ctx, p, p.h32, p.taps32_dev, p.h32.u[0], p.pitch[0],
+                                      p.h32.f[0], p.pitch[0], true, ctx->stream, false,
+                                      const_cast<double*>(u),  // not written by the head
+                                      p.pitch0, nullptr, u, f, p.pitch0, p.h32.f[0], nullptr,
+                                      kHead, p.partials, &nb));
+    MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 2, p.sums));
+    return MG_OK;
+  }
   const double nn = (double)p.n * p.n;
   MG_TRY(timed(ctx, ctx->stream, MG_K_RESIDUAL_MIXED, 0, 20 * nn, [&] {
     return launch_residual_mixed(ctx->stream, p.bc, p.n, u, p.pitch0, f, p.pitch0, p.h32.f[0],
@@ -494,8 +532,10 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
   } else if (mixed_chk) {
     for (int b = 0; b < B; ++b) {
       // Periodic problems: the right-hand-side check above left ||f||^2 in
-      // p.sums[1] already (the same kernel and reduction).
-      if (ctx->probs[b].bc != kPeriodic) MG_TRY(enqueue_fnorm(ctx, ctx->probs[b], f[b]));
+      // p.sums[1] already (the same kernel and reduction); a split step's
+      // check makes it in its own pass.
+      if (ctx->probs[b].bc != kPeriodic && !split_step(ctx, ctx->probs[b]))
+        MG_TRY(enqueue_fnorm(ctx, ctx->probs[b], f[b]));
       MG_TRY(enqueue_check_mixed(ctx, ctx->probs[b], u[b], f[b]));
       have_res[b] = 1;
     }

@@ -295,9 +295,14 @@ hipError_t launch_remove_mean_batched(hipStream_t s, const PProblem* probs, int 
 hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u64, int p64,
                                   const double* f64, int pf64, float* r32, int pr, float* uout,
                                   int puo, float* fc, int pfc, int hs,
-                                  const CallerArgs* ca = nullptr);
+                                  const CallerArgs* ca = nullptr, double* partials = nullptr,
+                                  int nparts = 0, int* nitems = nullptr);
 // uout == nullptr: the pre-smoothed iterate is not stored; the level's up
 // pass must then be launch_up_pre_stream, which makes it again from r32.
+// partials (with uout == nullptr): also one sum of r^2 per wavefront into
+// partials[0 .. *nitems) and one of f64^2 into partials[*nitems .. 2
+// *nitems), for ||f64 - A u64|| of the iterate the pass starts from and
+// ||f64||; hipErrorInvalidValue when 2 *nitems exceeds nparts.
 // Mixed path, level 0, after launch_down_res_stream without uout: the up
 // pass that re-makes the pre-smoothed iterate from r32 (same values) and
 // adds the result into u64.

@@ -410,6 +410,13 @@ int32_t setup_impl(const mg_grid* grids, int32_t batch, const mg_options* opt, v
       }
     }
     p.nblocks = std::max(blocks_for(p.n, p.bc), (int)((p.n + 63) / 64) * ((p.n + 3) / 4));
+    {
+      // The level-0 down pass's norm partials: one per wavefront at the
+      // shortest segments (2 rows).
+      const int ext = p.bc == kPeriodic ? p.n - 1 : p.n;
+      const int nb = (ext + stream_down_owned() - 1) / stream_down_owned();
+      p.nblocks = std::max(p.nblocks, nb * ((ext + 1) / 2));
+    }
     int32_t st = alloc_level<double>(ctx, 2, p.nblocks, &p.partials);
     if (st == MG_OK) st = alloc_level<double>(ctx, 1, 4, &p.sums);
     if (st == MG_OK && opt->n_gan > 0.0 && opt->s_thres > 0.0)

@@ -23,19 +23,34 @@ __global__ void __launch_bounds__(64 * kWaves)
 // Level-0 down pass of the mixed path with its right-hand side made from
 // the FP64 iterate (down_wave with RES).
 // SB = false: the pre-smoothed iterate is not stored (k_up_pre_s makes it
-// again).
-template <int BC, bool SB>
+// again).  NORM: each wavefront also writes the sums of r^2 and of f^2 over
+// the unknowns it owns to partials[item] and partials[nitems + item] (lanes
+// reduced in a fixed order), so the pass yields ||f - A u|| of the iterate
+// it starts from and ||f||.
+template <int BC, bool SB, bool NORM = false>
 __global__ void __launch_bounds__(64 * kWaves)
     k_down_res_s(int n, const double* __restrict__ u64, int p64, const double* __restrict__ f64,
                  int pf64, float* __restrict__ r32, int pr, float* __restrict__ uout, int puo,
                  float* __restrict__ fc, int pfc, int nbands, int nitems, int hs, float h2,
-                 float inv_h2, double inv_h2d, const CallerArgs* ca) {
+                 float inv_h2, double inv_h2d, const CallerArgs* ca,
+                 double* __restrict__ partials = nullptr) {
   const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
   if (ca) u64 = ca->u, f64 = ca->f;
-  down_wave<float, BC, 0, true, SB>(n, nullptr, 0, uout, puo, nullptr, 0, fc, pfc, item % nbands,
-                                    item / nbands, hs, h2, inv_h2, threadIdx.x & 63, u64, p64,
-                                    f64, pf64, inv_h2d, r32, pr);
+  double2 acc = down_wave<float, BC, 0, true, SB, NORM>(
+      n, nullptr, 0, uout, puo, nullptr, 0, fc, pfc, item % nbands, item / nbands, hs, h2, inv_h2,
+      threadIdx.x & 63, u64, p64, f64, pf64, inv_h2d, r32, pr);
+  if constexpr (NORM) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_down(acc.x, off);
+      acc.y += __shfl_down(acc.y, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      partials[item] = acc.x;
+      partials[nitems + item] = acc.y;
+    }
+  }
 }
 
 // Level-0 up pass of the mixed path after k_down_res_s<BC, false>: the
@@ -186,13 +201,32 @@ hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pu
 
 hipError_t launch_down_res_stream(hipStream_t s, int bc, int n, const double* u64, int p64,
                                   const double* f64, int pf64, float* r32, int pr, float* uout,
-                                  int puo, float* fc, int pfc, int hs, const CallerArgs* ca) {
+                                  int puo, float* fc, int pfc, int hs, const CallerArgs* ca,
+                                  double* partials, int nparts, int* nitems) {
   if ((bc == kPeriodic && n - 1 < 128) || (hs > 0 && (hs & 1))) return hipErrorInvalidValue;
   const int extent = bc == kPeriodic ? n - 1 : n;
   if (hs <= 0) hs = stream_segment_rows(n, bc, kDownOwned);
   const int nb = (extent + kDownOwned - 1) / kDownOwned;
   const int items = nb * ((extent + hs - 1) / hs);
   const int blocks = (items + kWaves - 1) / kWaves;
+  if (nitems) *nitems = items;
+  if (partials) {
+    // The norm form stores no pre-smoothed iterate and writes one partial
+    // per wavefront.
+    if (uout || 2 * items > nparts) return hipErrorInvalidValue;
+    const double hd = 1.0 / (double)(n - 1);
+    const double inv_h2d = (double)(n - 1) * (double)(n - 1);
+    const float h2 = (float)(hd * hd), inv_h2 = (float)inv_h2d;
+    if (bc == kDirichlet)
+      hipLaunchKernelGGL((k_down_res_s<kDirichlet, false, true>), dim3(blocks), dim3(64 * kWaves),
+                         0, s, n, u64, p64, f64, pf64, r32, pr, uout, puo, fc, pfc, nb, items, hs,
+                         h2, inv_h2, inv_h2d, ca, partials);
+    else
+      hipLaunchKernelGGL((k_down_res_s<kPeriodic, false, true>), dim3(blocks), dim3(64 * kWaves),
+                         0, s, n, u64, p64, f64, pf64, r32, pr, uout, puo, fc, pfc, nb, items, hs,
+                         h2, inv_h2, inv_h2d, ca, partials);
+    return hipGetLastError();
+  }
   const double hd = 1.0 / (double)(n - 1);
   const double inv_h2d = (double)(n - 1) * (double)(n - 1);
   const float h2 = (float)(hd * hd), inv_h2 = (float)inv_h2d;

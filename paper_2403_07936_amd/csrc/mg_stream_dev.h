@@ -260,9 +260,13 @@ __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2],
 // pf64), rounded to FP32; the rows and columns the wavefront owns are also
 // stored to rout (pitch pro; f is not used), where the up pass reads them.  The same
 // arithmetic as residual_wave, so r32 is bitwise what that writes on the
-// nodes the up pass reads.
-template <typename T, int BC, int UIN, bool RES, int IN, bool SB = true, bool REV = false>
-__device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin, int pui,
+// nodes the up pass reads.  NORM (RES only): returns the lane's sums of
+// r^2 (x) and f64^2 (y) in FP64 over the unknowns it owns (periodic: the
+// unique nodes), the residual norm of the FP64 iterate the pass starts from
+// and the norm it is measured against; (0, 0) otherwise.
+template <typename T, int BC, int UIN, bool RES, int IN, bool SB = true, bool REV = false,
+          bool NORM = false>
+__device__ __forceinline__ double2 down_wave_rows(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
                                           int hs, T h2, T inv_h2, int lane,
@@ -271,6 +275,7 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
                                           double inv_h2d, T* __restrict__ rout, int pro) {
   static_assert(!RES || (UIN == 0 && sizeof(T) == sizeof(float)), "RES: FP32 cycle from u = 0");
   static_assert(!REV || IN >= 1, "a reversed segment lies inside the grid");
+  static_assert(!NORM || RES, "the norm is of the residual the pass makes");
   const int xw = band * kDownOwned - kDownHalo;
   const int x0 = xw + 2 * lane;
   // REV: the segment's rows [seg hs, seg hs + hs) are walked upwards, as
@@ -313,6 +318,7 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
   double RU[RES ? 8 : 1][2], RF[RES ? 4 : 1][2];
   const int tl = t0 + steps - 1;  // last row a step uses
   const bool rw0 = lane_owns && x0 < n, rw1 = lane_owns && x0 + 1 < n;
+  double acc = 0.0, accf = 0.0;
   if constexpr (RES) {
 #pragma unroll
     for (int q = 0; q < kAheadR + 2; ++q) {
@@ -335,7 +341,13 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int s = sb + k;
-      if (s >= steps) break;
+      // (NORM: the sum of r^2 lives past the loop, and the early exit then
+      // keeps the compiler from unrolling it; skipping the remaining steps
+      // instead does not.)
+      if (s >= steps) {
+        if constexpr (NORM) continue;
+        else break;
+      }
       const int t = t0 + s;
       // Rows kAheadDown ahead; past the last row a step uses, that row again
       // (a cache hit instead of a row of HBM traffic; never used).
@@ -363,8 +375,18 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
         }
         F[k & RM][0] = (T)r0;
         F[k & RM][1] = (T)r1;
-        if (t >= ys && t < ys + hs && (IN || t < row_end))
-          store_pair<T>(rout + (size_t)ra(t) * pro + x0, rw0, rw1, (T)r0, (T)r1);
+        const bool own_row = t >= ys && t < ys + hs && (IN || t < row_end);
+        if (own_row) store_pair<T>(rout + (size_t)ra(t) * pro + x0, rw0, rw1, (T)r0, (T)r1);
+        if constexpr (NORM) {
+          // r is 0 on the Dirichlet boundary rows already; f is not.
+          const bool fr = own_row && (BC == kPeriodic || IN || row_unknown<BC>(t, n));
+          const double q0 = (own_row && wr0) ? r0 : 0.0, q1 = (own_row && wr1) ? r1 : 0.0;
+          const double g0 = (fr && wr0) ? ff[0] : 0.0, g1 = (fr && wr1) ? ff[1] : 0.0;
+          acc += q0 * q0;
+          acc += q1 * q1;
+          accf += g0 * g0;
+          accf += g1 * g1;
+        }
         U[k & RM][0] = U[k & RM][1] = T(0);  // row t starts from 0
       } else {
         const int ta = t + kAheadDown < t0 + steps - 1 ? t + kAheadDown : t0 + steps - 1;
@@ -407,12 +429,14 @@ __device__ __forceinline__ void down_wave_rows(int n, const T* __restrict__ uin,
       }
     }
   }
+  return make_double2(acc, accf);
 }
 
 // SB = false (RES only): the pre-smoothed iterate is not stored (the up pass
-// makes it again from the stored right-hand side, up_pre_wave).
-template <typename T, int BC, int UIN = -1, bool RES = false, bool SB = true>
-__device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int pui,
+// makes it again from the stored right-hand side, up_pre_wave).  NORM: see
+// down_wave_rows (the lane's parts of ||f - A u||^2 and ||f||^2).
+template <typename T, int BC, int UIN = -1, bool RES = false, bool SB = true, bool NORM = false>
+__device__ __forceinline__ double2 down_wave(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
                                           int hs, T h2, T inv_h2, int lane,
@@ -437,21 +461,21 @@ __device__ __forceinline__ void down_wave(int n, const T* __restrict__ uin, int 
   const int lo_r = seg * hs - 7, hi_r = seg * hs + hs + 6;
   const bool in_r = BC == kPeriodic ? (lo_r >= 0 && hi_r <= n - 2) : (lo_r >= 1 && hi_r <= n - 2);
   if (RES && (seg & 1) && in_r)
-    down_wave_rows<T, BC, UIN, RES, 1, SB, true>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg,
-                                                 hs, h2, inv_h2, lane, u64, p64, f64, pf64,
-                                                 inv_h2d, rout, pro);
+    return down_wave_rows<T, BC, UIN, RES, 1, SB, true, NORM>(
+        n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs, h2, inv_h2, lane, u64, p64, f64,
+        pf64, inv_h2d, rout, pro);
   else if (!RES && in && band_inside<BC>(band * kDownOwned - kDownHalo, n))
-    down_wave_rows<T, BC, UIN, RES, 2, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
-                                           h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
-                                           pro);
+    return down_wave_rows<T, BC, UIN, RES, 2, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band,
+                                                  seg, hs, h2, inv_h2, lane, u64, p64, f64, pf64,
+                                                  inv_h2d, rout, pro);
   else if (in)
-    down_wave_rows<T, BC, UIN, RES, 1, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
-                                           h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
-                                           pro);
+    return down_wave_rows<T, BC, UIN, RES, 1, SB, false, NORM>(
+        n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs, h2, inv_h2, lane, u64, p64, f64,
+        pf64, inv_h2d, rout, pro);
   else
-    down_wave_rows<T, BC, UIN, RES, 0, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs,
-                                           h2, inv_h2, lane, u64, p64, f64, pf64, inv_h2d, rout,
-                                           pro);
+    return down_wave_rows<T, BC, UIN, RES, 0, SB, false, NORM>(
+        n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs, h2, inv_h2, lane, u64, p64, f64,
+        pf64, inv_h2d, rout, pro);
 }
 
 // Spline along x at the lane's two columns from coarse row values held one

@@ -310,6 +310,42 @@ def test_mixed_step_residual_in_down_pass_is_bitwise(B, dev, bc, n):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("bc,n", [(D, 257), (P, 257), (D, 1025), (P, 1025)])
+def test_mixed_solve_norm_from_next_down_pass(B, dev, bc, n):
+    """mg_solve on the mixed path takes each norm check from the next step's
+    level-0 down pass (which makes the FP64 residual of the iterate anyway)
+    and queues the rest of that step only while the problem is unconverged.
+    Checked for 1, 2 and 3 steps (check_every 1): the iterate it returns
+    against the same number of mg_vcycle steps, bit for bit (periodic: after
+    the mean mg_solve removes on exit), so the down pass of the final check
+    left the iterate as it was; and the relative residual it returns against
+    the oracle's norm of that iterate before the mean removal (the
+    mg_vcycle result), 1e-12 relative."""
+    from paper_2403_07936_amd.solver import Solver
+    say(f"norm from the next down pass bc={bc} n={n}")
+    f = make_rhs(n, bc, 6)
+    ft = gpu(f, dev)
+    for steps in (1, 2, 3):
+        sa = Solver([(n, bc)], precision="mixed", check_every=1)
+        ua = torch.zeros_like(ft)
+        st, cyc, rel = sa.solve([ua], [ft], rtol=1e-300, max_cycles=steps)
+        sa.close()
+        sb = Solver([(n, bc)], precision="mixed")
+        ub = torch.zeros_like(ft)
+        sb.vcycle([ub], [ft], steps)
+        sb.close()
+        a, b = host(ua), host(ub)
+        ref = oracle.relres(b, f, bc)
+        say(f"  {steps} steps: status {st} cycles {cyc[0]} relres {rel[0]:.6e} oracle {ref:.6e}")
+        assert cyc[0] == steps
+        assert abs(rel[0] - ref) <= 1e-12 * ref
+        if bc == P:
+            a, b = zero_mean(a), zero_mean(b)
+            assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+        else:
+            assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("name", ["dirichlet4097", "periodic1025"])
 def test_full_size_cycle_parity(B, dev, name):
     """The benchmark configurations at full size, in the launch configuration
