@@ -107,6 +107,8 @@ int32_t build_persistent(mg_ctx_s* ctx) {
   }
   std::vector<PPhase> phases;
   std::vector<PItem> items;
+  // Level-0 down items of each problem (mixed path): global index range.
+  std::vector<int> nfirst(B, 0), ncount(B, 0);
   auto close_phase = [&](int kind, size_t first) {
     if (items.size() > first) phases.push_back({kind, (int)first, (int)(items.size() - first), 0});
   };
@@ -135,10 +137,17 @@ int32_t build_persistent(mg_ctx_s* ctx) {
     const size_t first = items.size();
     for (int b = 0; b < B; ++b) {
       const int l = ctx->probs[b].tail - 1 - k;
-      if (l >= 0) band_items(b, l, true);
+      if (l < 0) continue;
+      const int at = (int)items.size();
+      band_items(b, l, true);
+      if (l == 0) {
+        nfirst[b] = at;
+        ncount[b] = (int)items.size() - at;
+      }
     }
     close_phase(kItemDown, first);
   }
+  P.head_end = (int)phases.size();  // the tail phase follows the down phases
   {
     const size_t first = items.size();
     for (int b = 0; b < B; ++b) items.push_back({b, ctx->probs[b].tail, 0, 0});
@@ -226,6 +235,29 @@ int32_t build_persistent(mg_ctx_s* ctx) {
   P.d_bar = reinterpret_cast<PBarrier*>(d);
   MG_TRY(alloc_level<double>(ctx, 2 * B, P.slots, &P.d_partials));
   MG_TRY(alloc_level<double>(ctx, 2, B, &P.d_sums));
+  // Mixed path: the norm partials of the level-0 down items, 1 per item
+  // (every such item writes one, whether or not the steps are split).
+  // Split steps need every problem's level 0 above the tail.
+  P.split = mixed;
+  long nitems0 = 0;
+  for (int b = 0; b < B; ++b) {
+    if (ctx->probs[b].tail == 0) P.split = false;
+    nitems0 += ncount[b];
+  }
+  for (int b = 0; b < B; ++b) P.h_probs[b].npart = nullptr, P.h_probs[b].ncount = 0;
+  if (mixed && nitems0 > 0) {
+    if (nitems0 > (1L << 28)) return fail(MG_ERR_UNSUPPORTED, "batch too large for its norm table");
+    MG_TRY(alloc_level<double>(ctx, 1, (int)nitems0, &P.d_npart));
+    MG_TRY(alloc_level<double>(ctx, 1, B, &P.d_nsums));
+    long off = 0;
+    for (int b = 0; b < B; ++b) {
+      PProblem& q = P.h_probs[b];
+      q.npart = P.d_npart + off;
+      q.nfirst = nfirst[b];
+      q.ncount = ncount[b];
+      off += ncount[b];
+    }
+  }
   MG_HIP(hipMemcpyAsync(P.d_phases, phases.data(), sizeof(PPhase) * phases.size(),
                         hipMemcpyHostToDevice, ctx->stream));
   MG_HIP(hipMemcpyAsync(P.d_items, items.data(), sizeof(PItem) * items.size(),
@@ -263,19 +295,30 @@ int32_t persistent_bind(mg_ctx_s* ctx, double* const* u, const double* const* f,
   return MG_OK;
 }
 
-int32_t persistent_launch(mg_ctx_s* ctx) {
+void persistent_drop_graphs(Persist& P) {
+  for (auto& g : P.graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+int32_t persistent_launch(mg_ctx_s* ctx, StepPart part) {
   Persist& P = ctx->ps;
   const bool mixed = ctx->opt.precision == MG_MIXED;
+  if (part != kWhole && !P.split) return fail(MG_ERR_INVALID_ARG, "batch steps are not split");
+  const int ph0 = part == kRest ? P.head_end : 0;
+  const int ph1 = part == kHead ? P.head_end : P.nphases;
   auto launch = [&](hipStream_t s) {
     if (!P.phased)
-      return mixed ? launch_persistent<float>(s, P.bc, P.d_probs, P.d_phases, P.nphases,
+      return mixed ? launch_persistent<float>(s, P.bc, P.d_probs, P.d_phases, ph0, ph1,
                                               P.d_items, P.d_bar, ctx->inv[P.bc], P.blocks, P.lds)
-                   : launch_persistent<double>(s, P.bc, P.d_probs, P.d_phases, P.nphases,
+                   : launch_persistent<double>(s, P.bc, P.d_probs, P.d_phases, ph0, ph1,
                                                P.d_items, P.d_bar, ctx->inv[P.bc], P.blocks,
                                                P.lds);
     // One launch per phase: workgroup items one workgroup each, wavefront
     // items kPersistThreads / 64 per workgroup.
-    for (int ph = 0; ph < P.nphases; ++ph) {
+    for (int ph = ph0; ph < ph1; ++ph) {
       const PPhase& q = P.h_phases[ph];
       const bool wg = q.kind == kItemTail || q.kind == kItemPre;
       const int per = kPersistThreads / 64;
@@ -291,11 +334,16 @@ int32_t persistent_launch(mg_ctx_s* ctx) {
     return hipSuccess;
   };
   if (!ctx->opt.use_graph || ctx->timing) {
+    if (part != kWhole) {
+      MG_HIP(launch(ctx->stream));
+      return MG_OK;
+    }
     MG_TRY(timed(ctx, ctx->stream, P.phased ? MG_K_PHASED : MG_K_PERSISTENT, 0, P.bytes,
                  [&] { return launch(ctx->stream); }));
     return MG_OK;
   }
-  if (!P.graph) {
+  hipGraphExec_t& ge = P.graph[part];
+  if (!ge) {
     hipGraph_t g = nullptr;
     MG_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
     const hipError_t le = launch(ctx->capture);
@@ -305,14 +353,26 @@ int32_t persistent_launch(mg_ctx_s* ctx) {
       return fail(MG_ERR_HIP, std::string("persistent launch: ") + hipGetErrorString(le));
     }
     if (e != hipSuccess) return fail(MG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-      P.graph = nullptr;
+      ge = nullptr;
       return fail(MG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
   }
-  MG_HIP(hipGraphLaunch(P.graph, ctx->stream));
+  MG_HIP(hipGraphLaunch(ge, ctx->stream));
+  return MG_OK;
+}
+
+int32_t persistent_head(mg_ctx_s* ctx, double* sums) {
+  Persist& P = ctx->ps;
+  const int B = (int)ctx->probs.size();
+  MG_TRY(persistent_launch(ctx, kHead));
+  MG_HIP(launch_reduce_norms(ctx->stream, P.d_probs, B, P.d_nsums));
+  MG_HIP(hipMemcpyAsync(sums, P.d_nsums, sizeof(double) * B, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  if (!P.phased) return persistent_check(ctx);  // synchronises
+  MG_HIP(hipStreamSynchronize(ctx->stream));
   return MG_OK;
 }
 

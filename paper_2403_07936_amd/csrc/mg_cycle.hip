@@ -106,11 +106,10 @@ int32_t enqueue_cycle(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
   return MG_OK;
 }
 
-// Which part of a mixed refinement step is queued: all of it, only the
-// level-0 down pass that makes the FP64 residual (with its norm), or all but
+// StepPart for one problem's mixed refinement step: kHead is the level-0
+// down pass that makes the FP64 residual (with its norms), kRest all but
 // that pass (its outputs are already in place).  The iterate changes only
 // in the level-0 up pass, so the head alone leaves it as it was.
-enum StepPart { kWhole = 0, kHead = 1, kRest = 2 };
 
 // The fused schedule: down passes to the first level of at most 65 x 65,
 // the tail kernel, then prefilter + up passes back to level 0.  Level l's
@@ -474,6 +473,11 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
   MG_HIP(hipSetDevice(ctx->device));
   const int B = (int)ctx->probs.size();
 
+  // Split batches: every check is the head of the next step (hsums: each
+  // problem's sum of r^2; fsq: its sum of f^2, from the moments below).
+  const bool split = ctx->ps.on && ctx->ps.split;
+  std::vector<double> hsums(split ? B : 0), fsq(split ? B : 0);
+  bool have_head = false;
   // Periodic right-hand sides must have zero mean (the constants are the
   // null space of A).
   {
@@ -482,8 +486,9 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
     if (ctx->ps.on) {
       // The batch schedules: one launch for every problem's sums.
       MG_TRY(persistent_bind(ctx, u, f, {}));
-      if (ctx->ps.bc == kPeriodic) {
-        for (int b = 0; b < B; ++b) per.push_back(b);
+      if (ctx->ps.bc == kPeriodic || split) {
+        if (ctx->ps.bc == kPeriodic)
+          for (int b = 0; b < B; ++b) per.push_back(b);
         mom.resize(2 * B);
         MG_HIP(launch_moments_batched(ctx->stream, ctx->ps.d_probs, B, ctx->ps.d_partials,
                                       ctx->ps.slots, ctx->ps.d_sums, false));
@@ -504,6 +509,7 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
                               hipMemcpyDeviceToHost, ctx->stream));
     }
     MG_HIP(hipStreamSynchronize(ctx->stream));
+    for (int b = 0; b < (split ? B : 0); ++b) fsq[b] = mom[2 * b + 1];
     for (size_t k = 0; k < per.size(); ++k) {
       const Problem& p = ctx->probs[per[k]];
       const double M = (double)(p.n - 1) * (double)(p.n - 1);
@@ -526,7 +532,15 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
   const bool mixed_chk = !pers && ctx->opt.precision == MG_MIXED;
   std::vector<char> have_res(B, 0);
   for (int b = 0; b < B; ++b) all[b] = b;
-  if (pers) {
+  if (split) {
+    MG_TRY(persistent_bind(ctx, u, f, {}));
+    MG_TRY(persistent_head(ctx, hsums.data()));
+    have_head = true;
+    for (int b = 0; b < B; ++b) {
+      const double rr = hsums[b], ff = fsq[b];
+      rel[b] = ff > 0.0 ? std::sqrt(rr) / std::sqrt(ff) : std::sqrt(rr);
+    }
+  } else if (pers) {
     MG_TRY(persistent_bind(ctx, u, f, {}));
     MG_TRY(persistent_relres(ctx, rel.data()));
   } else if (mixed_chk) {
@@ -600,8 +614,9 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
           }
         if (any) {
           MG_TRY(persistent_bind(ctx, u, f, on));
-          MG_TRY(persistent_launch(ctx));
+          MG_TRY(persistent_launch(ctx, have_head ? kRest : kWhole));
         }
+        have_head = false;
         continue;
       }
       for (int b : act)
@@ -620,7 +635,19 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
     for (int b : act)
       if (cycles[b] >= next_check[b] || cycles[b] >= max_cycles) chk.push_back(b);
     std::vector<double> r(chk.size());
-    if (pers) {
+    if (split) {
+      // The head of the next step for every problem still running.
+      std::vector<int> run(B, 0);
+      for (int b = 0; b < B; ++b) run[b] = state[b] == 1 ? 1 : 0;
+      MG_TRY(persistent_bind(ctx, u, f, run));
+      MG_TRY(persistent_head(ctx, hsums.data()));
+      have_head = true;
+      for (size_t k = 0; k < chk.size(); ++k) {
+        const int b = chk[k];
+        const double rr = hsums[b], ff = fsq[b];
+        r[k] = ff > 0.0 ? std::sqrt(rr) / std::sqrt(ff) : std::sqrt(rr);
+      }
+    } else if (pers) {
       std::vector<double> rall(B);
       MG_TRY(persistent_relres(ctx, rall.data()));
       for (size_t k = 0; k < chk.size(); ++k) r[k] = rall[chk[k]];

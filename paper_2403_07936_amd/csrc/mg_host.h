@@ -83,7 +83,17 @@ struct Persist {
   PBarrier* d_bar = nullptr;
   int blocks = 0;
   size_t lds = 0;
-  hipGraphExec_t graph = nullptr;
+  // Captured launches of the whole step, of its head and of its rest
+  // (StepPart).
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  // Mixed path with level 0 above the tail for every problem: the level-0
+  // down items write each problem's norm partials (d_npart), so a
+  // convergence check is the head of the next step, phases [0, head_end)
+  // (every down phase), and the rest follows only for unconverged problems.
+  bool split = false;
+  int head_end = 0;
+  double* d_npart = nullptr;
+  double* d_nsums = nullptr;  // per problem: the sum of r^2
   // One launch per phase instead of one launch with device-wide barriers
   // (schedule 3): per phase, its kind, grid and dynamic LDS.
   bool phased = false;
@@ -233,7 +243,15 @@ template <typename T>
 int32_t build_persistent(mg_ctx_s* ctx);
 int32_t persistent_bind(mg_ctx_s* ctx, double* const* u, const double* const* f,
                         const std::vector<int>& active);
-int32_t persistent_launch(mg_ctx_s* ctx);
+// Which part of a step a launch queues: all of it, its head (the phases
+// up to the tail: for a split step, the level-0 down passes that make the
+// FP64 residual and its norms, the iterate untouched) or the rest.
+enum StepPart { kWhole = 0, kHead = 1, kRest = 2 };
+int32_t persistent_launch(mg_ctx_s* ctx, StepPart part = kWhole);
+// Split batches: the head of a step for the bound active problems, and
+// each problem's sum of r^2 (B doubles) read back (synchronises).
+int32_t persistent_head(mg_ctx_s* ctx, double* sums);
+void persistent_drop_graphs(Persist& P);
 int32_t persistent_check(mg_ctx_s* ctx);
 int32_t persistent_relres(mg_ctx_s* ctx, double* rel);
 

@@ -231,6 +231,11 @@ struct PProblem {
   double* u64;          // caller's FP64 u (mixed: refined in place)
   const double* f64;    // caller's FP64 f
   int pitch64, zero_guess;  // zero_guess: level-0 down pass starts from u = 0
+  // Mixed path, level 0 above the tail: the level-0 down items (global item
+  // indices nfirst .. nfirst + ncount) each write the sum of r^2 over the
+  // unknowns they own to npart[item - nfirst].
+  double* npart;
+  int nfirst, ncount;
   PLevel lv[kMaxLevels];
 };
 
@@ -255,11 +260,16 @@ struct PBarrier {
   unsigned count, gen, error, pad;
 };
 
-// One launch of the whole phase list.  T = cycle precision.
+// One launch of phases [ph_begin, ph_end) of the list.  T = cycle
+// precision.
 template <typename T>
 hipError_t launch_persistent(hipStream_t s, int bc, const PProblem* probs, const PPhase* phases,
-                             int nphases, const PItem* items, PBarrier* bar, const double* inv,
-                             int blocks, size_t lds);
+                             int ph_begin, int ph_end, const PItem* items, PBarrier* bar,
+                             const double* inv, int blocks, size_t lds);
+// Per problem, the sum of the partials its level-0 down items wrote
+// (PProblem::npart, the sum of r^2) into sums[b], in a fixed order; 0 for a
+// problem without such items.
+hipError_t launch_reduce_norms(hipStream_t s, const PProblem* probs, int nprob, double* sums);
 // Phase `ph` of the table alone, by a kernel that holds only the code of
 // its kind (`kind` must be phases[ph].kind); blocks of kPersistThreads
 // threads, `lds` bytes of dynamic LDS (tail and prefilter phases).

@@ -121,13 +121,19 @@ __device__ __forceinline__ void run_phase(const PProblem* __restrict__ probs, co
         // right-hand side from the FP64 iterate itself and stores it for the
         // up pass, and stores no pre-smoothed iterate (the up pass makes it
         // again), as in the per-problem schedule.
+        // Its sum of r^2 (the convergence check of the iterate the step
+        // starts from) goes to the problem's partials, lanes reduced in a
+        // fixed order.
         if constexpr (sizeof(T) == sizeof(float)) {
           if (it.level == 0 && p.zero_guess) {
             const double inv_h2d = (double)(L.n - 1) * (double)(L.n - 1);
-            down_wave<float, BC, 0, true, false>(
+            double2 q = down_wave<float, BC, 0, true, false, 1>(
                 L.n, nullptr, 0, nullptr, 0, nullptr, 0, static_cast<float*>(C.f), C.pitch_f,
                 it.a, it.b, L.hs_down, float(hd * hd), float(inv_h2d), lane, p.u64, p.pitch64,
                 p.f64, p.pitch64, inv_h2d, static_cast<float*>(L.f), L.pitch_f);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) q.x += __shfl_down(q.x, off);
+            if (lane == 0 && p.npart) p.npart[P.first + i - p.nfirst] = q.x;
             continue;
           }
         }
@@ -163,7 +169,7 @@ __device__ __forceinline__ void run_phase(const PProblem* __restrict__ probs, co
 template <typename T, int BC>
 __global__ void __launch_bounds__(kPersistThreads)
     k_persistent(const PProblem* __restrict__ probs, const PPhase* __restrict__ phases,
-                 int nphases, const PItem* __restrict__ items, PBarrier* bar,
+                 int ph_begin, int ph_end, const PItem* __restrict__ items, PBarrier* bar,
                  const double* __restrict__ inv) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
@@ -172,7 +178,7 @@ __global__ void __launch_bounds__(kPersistThreads)
     gen_local = __hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   if (__hip_atomic_load(&bar->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  for (int ph = 0; ph < nphases; ++ph) {
+  for (int ph = ph_begin; ph < ph_end; ++ph) {
     const PPhase P = phases[ph];
     switch (P.kind) {
       case kItemTail: run_phase<T, BC, kItemTail>(probs, P, items, inv, sm); break;
@@ -183,7 +189,7 @@ __global__ void __launch_bounds__(kPersistThreads)
       case kItemUp: run_phase<T, BC, kItemUp>(probs, P, items, inv, sm); break;
       default: break;
     }
-    if (ph + 1 < nphases && !grid_barrier(bar, &gen_local)) return;
+    if (ph + 1 < ph_end && !grid_barrier(bar, &gen_local)) return;
   }
 }
 
@@ -252,6 +258,19 @@ __global__ void k_resnorm_batched(int bc, const PProblem* __restrict__ probs, do
     partials[((size_t)pi * slots + slot) * 2] = sr[0];
     partials[((size_t)pi * slots + slot) * 2 + 1] = sf[0];
   }
+}
+
+// One wavefront per problem: the sums its level-0 down items wrote, each
+// lane over items lane, lane + 64, ..., then across the lanes.
+__global__ void k_reduce_norms(const PProblem* __restrict__ probs, int nprob, double* sums) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  if (b >= nprob) return;
+  const PProblem& p = probs[b];
+  double a = 0.0;
+  for (int j = lane; j < p.ncount; j += 64) a += p.npart[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off);
+  if (lane == 0) sums[b] = a;
 }
 
 // Workgroup (256 threads) = (problem, slot): sums of a and a^2 over the
@@ -383,14 +402,19 @@ hipError_t persistent_blocks(int bc, size_t lds, int* blocks) {
 
 template <typename T>
 hipError_t launch_persistent(hipStream_t s, int bc, const PProblem* probs, const PPhase* phases,
-                             int nphases, const PItem* items, PBarrier* bar, const double* inv,
-                             int blocks, size_t lds) {
+                             int ph_begin, int ph_end, const PItem* items, PBarrier* bar,
+                             const double* inv, int blocks, size_t lds) {
   if (bc == kDirichlet)
     hipLaunchKernelGGL((k_persistent<T, kDirichlet>), dim3(blocks), dim3(kPersistThreads), lds, s,
-                       probs, phases, nphases, items, bar, inv);
+                       probs, phases, ph_begin, ph_end, items, bar, inv);
   else
     hipLaunchKernelGGL((k_persistent<T, kPeriodic>), dim3(blocks), dim3(kPersistThreads), lds, s,
-                       probs, phases, nphases, items, bar, inv);
+                       probs, phases, ph_begin, ph_end, items, bar, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_norms(hipStream_t s, const PProblem* probs, int nprob, double* sums) {
+  hipLaunchKernelGGL(k_reduce_norms, dim3(nprob), dim3(64), 0, s, probs, nprob, sums);
   return hipGetLastError();
 }
 
@@ -450,10 +474,11 @@ hipError_t launch_seam_batched(hipStream_t s, const PProblem* probs, int nprob) 
 }
 
 template hipError_t launch_persistent<double>(hipStream_t, int, const PProblem*, const PPhase*,
-                                              int, const PItem*, PBarrier*, const double*, int,
-                                              size_t);
+                                              int, int, const PItem*, PBarrier*, const double*,
+                                              int, size_t);
 template hipError_t launch_persistent<float>(hipStream_t, int, const PProblem*, const PPhase*, int,
-                                             const PItem*, PBarrier*, const double*, int, size_t);
+                                             int, const PItem*, PBarrier*, const double*, int,
+                                             size_t);
 template <typename T>
 hipError_t phase_wave_slots(int bc, int kind, long* slots) {
   int dev = 0, cus = 0, per = 0;

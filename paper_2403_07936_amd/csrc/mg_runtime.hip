@@ -239,7 +239,7 @@ int32_t destroy_ctx(mg_ctx_s* ctx) {
   for (auto& p : ctx->probs)
     for (auto g : p.graph)
       if (g) (void)hipGraphExecDestroy(g);
-  if (ctx->ps.graph) (void)hipGraphExecDestroy(ctx->ps.graph);
+  persistent_drop_graphs(ctx->ps);
   for (void* q : ctx->owned) (void)hipFree(q);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->host) (void)hipHostFree(ctx->host);

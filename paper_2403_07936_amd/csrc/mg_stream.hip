@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(64 * kWaves)
   const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
   if (item >= nitems) return;
   if (ca) u64 = ca->u, f64 = ca->f;
-  double2 acc = down_wave<float, BC, 0, true, SB, NORM>(
+  double2 acc = down_wave<float, BC, 0, true, SB, NORM ? 2 : 0>(
       n, nullptr, 0, uout, puo, nullptr, 0, fc, pfc, item % nbands, item / nbands, hs, h2, inv_h2,
       threadIdx.x & 63, u64, p64, f64, pf64, inv_h2d, r32, pr);
   if constexpr (NORM) {

@@ -260,12 +260,12 @@ __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2],
 // pf64), rounded to FP32; the rows and columns the wavefront owns are also
 // stored to rout (pitch pro; f is not used), where the up pass reads them.  The same
 // arithmetic as residual_wave, so r32 is bitwise what that writes on the
-// nodes the up pass reads.  NORM (RES only): returns the lane's sums of
-// r^2 (x) and f64^2 (y) in FP64 over the unknowns it owns (periodic: the
-// unique nodes), the residual norm of the FP64 iterate the pass starts from
-// and the norm it is measured against; (0, 0) otherwise.
+// nodes the up pass reads.  NORM (RES only): returns the lane's sum of r^2
+// (x) and, with NORM = 2, of f64^2 (y) in FP64 over the unknowns it owns
+// (periodic: the unique nodes), the residual norm of the FP64 iterate the
+// pass starts from and the norm it is measured against; zeros otherwise.
 template <typename T, int BC, int UIN, bool RES, int IN, bool SB = true, bool REV = false,
-          bool NORM = false>
+          int NORM = 0>
 __device__ __forceinline__ double2 down_wave_rows(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,
@@ -384,8 +384,10 @@ __device__ __forceinline__ double2 down_wave_rows(int n, const T* __restrict__ u
           const double g0 = (fr && wr0) ? ff[0] : 0.0, g1 = (fr && wr1) ? ff[1] : 0.0;
           acc += q0 * q0;
           acc += q1 * q1;
-          accf += g0 * g0;
-          accf += g1 * g1;
+          if constexpr (NORM >= 2) {
+            accf += g0 * g0;
+            accf += g1 * g1;
+          }
         }
         U[k & RM][0] = U[k & RM][1] = T(0);  // row t starts from 0
       } else {
@@ -435,7 +437,7 @@ __device__ __forceinline__ double2 down_wave_rows(int n, const T* __restrict__ u
 // SB = false (RES only): the pre-smoothed iterate is not stored (the up pass
 // makes it again from the stored right-hand side, up_pre_wave).  NORM: see
 // down_wave_rows (the lane's parts of ||f - A u||^2 and ||f||^2).
-template <typename T, int BC, int UIN = -1, bool RES = false, bool SB = true, bool NORM = false>
+template <typename T, int BC, int UIN = -1, bool RES = false, bool SB = true, int NORM = 0>
 __device__ __forceinline__ double2 down_wave(int n, const T* __restrict__ uin, int pui,
                                           T* __restrict__ uout, int puo, const T* __restrict__ f,
                                           int pf, T* __restrict__ fc, int pfc, int band, int seg,

@@ -372,12 +372,10 @@ int32_t tune_schedule(mg_ctx_s* ctx) {
     st = persistent_relres(ctx, rel.data());  // also reports a timed-out barrier
   }
   if (st == MG_OK) {
-    if (ctx->ps.graph) (void)hipGraphExecDestroy(ctx->ps.graph);
-    ctx->ps.graph = nullptr;
+    persistent_drop_graphs(ctx->ps);
     ctx->ps.phased = true;
     st = time_launches(ctx, 2, persistent, &t_phased);
-    if (ctx->ps.graph) (void)hipGraphExecDestroy(ctx->ps.graph);
-    ctx->ps.graph = nullptr;
+    persistent_drop_graphs(ctx->ps);
     ctx->ps.phased = false;
   }
   for (auto& p : ctx->probs)
@@ -393,8 +391,7 @@ int32_t tune_schedule(mg_ctx_s* ctx) {
   if (t_phased < (choice == 2 ? t_pers : t_graph)) choice = 3;
   ctx->ps.phased = choice == 3;
   if (choice == 1) {
-    if (ctx->ps.graph) (void)hipGraphExecDestroy(ctx->ps.graph);
-    ctx->ps.graph = nullptr;
+    persistent_drop_graphs(ctx->ps);
     ctx->ps.on = false;
   }
   std::lock_guard<std::mutex> lk(tune_mutex());

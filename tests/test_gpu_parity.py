@@ -500,10 +500,11 @@ def test_unreachable_tolerance_reports_stagnation(B, dev):
 
 # ------------------------------------------------------- persistent schedule --
 
-def batch_ctx(B, specs, precision, schedule):
+def batch_ctx(B, specs, precision, schedule, check_every=0):
     o = B.mg_options_default()
     o.precision = precision
     o.schedule = schedule
+    o.check_every = check_every
     return B.mg_setup([(n, bc, 0) for n, bc in specs], o, torch.cuda.current_stream().cuda_stream)
 
 
@@ -570,6 +571,51 @@ def test_persistent_batch_solve(B, dev, schedule, precision):
             assert np.linalg.norm(got - uo) <= 1e-9 * np.linalg.norm(uo)
     finally:
         B.mg_destroy(ctx)
+
+
+@pytest.mark.parametrize("schedule", [2, 3])
+@pytest.mark.parametrize("bc,sizes", [(P, [257, 129, 513]), (D, [129, 257, 513]),
+                                      (P, [65, 257])])
+def test_batch_solve_norm_from_next_down_pass(B, dev, schedule, bc, sizes):
+    """Mixed batched mg_solve: when every problem's level 0 lies above the
+    tail (sizes from 129 on), each check is the next step's down phases,
+    whose level-0 items also write their sums of r^2, and the rest of that
+    step runs only for the problems still unconverged; otherwise (a 65 x 65
+    problem, its level 0 in the tail) the batched residual norm runs.  For 1,
+    2 and 3 steps (check_every 1): each problem's iterate against the same
+    number of mg_vcycle steps of the same batch, bit for bit (periodic: after
+    the mean mg_solve removes), and its relative residual against the
+    oracle's norm of the mg_vcycle iterate (1e-12 relative)."""
+    say(f"batch norm from the next down pass schedule={schedule} bc={bc} sizes={sizes}")
+    specs = [(n, bc) for n in sizes]
+    fs = [make_rhs(n, bc, 40 + k) for k, n in enumerate(sizes)]
+    fts = [gpu(f, dev) for f in fs]
+    for steps in (1, 2, 3):
+        ctx = batch_ctx(B, specs, 1, schedule, check_every=1)
+        uas = [torch.zeros_like(t) for t in fts]
+        try:
+            st, cyc, rel = B.mg_solve(ctx, [t.data_ptr() for t in uas],
+                                      [t.data_ptr() for t in fts], 1e-300, steps)
+        finally:
+            B.mg_destroy(ctx)
+        assert st == B.MG_ERR_NOT_CONVERGED
+        ctx = batch_ctx(B, specs, 1, schedule)
+        ubs = [torch.zeros_like(t) for t in fts]
+        try:
+            B.mg_vcycle(ctx, [t.data_ptr() for t in ubs], [t.data_ptr() for t in fts], steps)
+        finally:
+            B.mg_destroy(ctx)
+        for k, n in enumerate(sizes):
+            a, b = host(uas[k]), host(ubs[k])
+            ref = oracle.relres(b, fs[k], bc)
+            say(f"  {steps} steps n={n}: cycles {cyc[k]} relres {rel[k]:.6e} oracle {ref:.6e}")
+            assert cyc[k] == steps
+            assert abs(rel[k] - ref) <= 1e-12 * ref
+            if bc == P:
+                a, b = zero_mean(a), zero_mean(b)
+                assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+            else:
+                assert np.array_equal(a, b)
 
 
 def test_persistent_matches_per_problem_schedule(B, dev):
