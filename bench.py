@@ -76,7 +76,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extra", action="store_true",
-                    help="default workload only: skip the periodic1025 and batch256 sub-objects")
+                    help="default workload only: skip the periodic1025, batch256 and "
+                         "periodic1025_srcnn sub-objects")
     ap.add_argument("--weights", default=None,
                     help="periodic1025_srcnn: SR-CNN weight blob (.npy) instead of the committed "
                          "supervised one")
@@ -90,28 +91,20 @@ BF16_PEAK_TFLOPS = 2500.0
 WEIGHTS = os.path.join(ROOT, "paper_2403_07936_amd", "weights", "srcnn_divu_periodic.npy")
 
 
-def bench_srcnn(args) -> int:
-    """1025 x 1025 periodic div-u source, V(2,2) cycles whose two finest
-    prolongations use the SR-CNN (bf16 matrix cores), FP64 cycle.  A step is
-    one such cycle.  Also reported: time to 1e-8 with the network-then-spline
-    schedule, with the hybrid schedule at N_GAN = 1 (network and spline
-    cycles alternating), and the spline cycle for comparison."""
-    import numpy as np
+def measure_srcnn(args, dev, W, steps, warmup):
+    """SR-CNN cycles on the 1025 x 1025 periodic source (FP64 cycle, the
+    network on the two finest prolongations) next to the spline cycle and the
+    hybrid schedule at N_GAN = 1: seconds per cycle and the best of three
+    solves to 1e-8 each; then the level-0 kernels of the network cycle timed
+    by HIP events.  Returns ((n, bc, f), per-mode results, roofline,
+    per-kernel times); the solvers are closed."""
     import torch
 
     import workloads
     from paper_2403_07936_amd import binding as B
     from paper_2403_07936_amd.solver import Solver
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        return 1
-    dev = torch.device("cuda:0")
-    B.lib()
     n, bc, f = workloads.workload("periodic1025", args.seed)
-    unknowns = workloads.grid_unknowns(n, bc)
-    wpath = args.weights or WEIGHTS
-    W = np.load(wpath)
     ft = torch.from_numpy(f).to(dev)
     ut = torch.zeros_like(ft)
     res = {}
@@ -121,12 +114,12 @@ def bench_srcnn(args) -> int:
             kw.update(n_gan=1.0)
         s = Solver([(n, bc)], precision="fp64", use_graph=True, **kw)
         ut.zero_()
-        s.vcycle([ut], [ft], args.warmup)
+        s.vcycle([ut], [ft], warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s.vcycle([ut], [ft], args.steps)
+        s.vcycle([ut], [ft], steps)
         torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / args.steps
+        sec = (time.perf_counter() - t0) / steps
         best = None
         for _ in range(3):
             ut.zero_()
@@ -145,7 +138,7 @@ def bench_srcnn(args) -> int:
     B.mg_timing_enable(hs.ctx, True)
     ut.zero_()
     torch.cuda.synchronize()
-    for _ in range(args.steps):
+    for _ in range(steps):
         hs.vcycle([ut], [ft], 1)
     torch.cuda.synchronize()
     kern = {}
@@ -162,6 +155,45 @@ def bench_srcnn(args) -> int:
                 "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
                 "avg_launch_us": round(ms / cnt * 1e3, 2), "flops_per_launch": flops / cnt}
     per_kernel = {k: {"launches": c, "avg_us": round(m / c * 1e3, 2)} for k, (c, m, b) in kern.items()}
+    for v in res.values():
+        v["solver"].close()
+        del v["solver"]
+    return (n, bc, f), res, roofline, per_kernel
+
+
+def srcnn_summary(res, unknowns):
+    """Compact record of measure_srcnn's modes."""
+    out = {}
+    for mode, r in res.items():
+        out[mode] = {"ms_per_cycle": round(r["sec"] * 1e3, 4),
+                     "grid_points_per_s": round(unknowns / r["sec"], 1),
+                     "time_to_1e-8_s": round(r["ttt"][0], 6), "cycles_to_1e-8": r["ttt"][2],
+                     "final_relres": r["ttt"][3], "status": r["ttt"][1]}
+    out["hybrid"]["prolongations"] = res["hybrid"]["ops"]
+    return out
+
+
+def bench_srcnn(args) -> int:
+    """1025 x 1025 periodic div-u source, V(2,2) cycles whose two finest
+    prolongations use the SR-CNN (bf16 matrix cores), FP64 cycle.  A step is
+    one such cycle.  Also reported: time to 1e-8 with the network-then-spline
+    schedule, with the hybrid schedule at N_GAN = 1 (network and spline
+    cycles alternating), and the spline cycle for comparison."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2403_07936_amd import binding as B
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    B.lib()
+    wpath = args.weights or WEIGHTS
+    W = np.load(wpath)
+    (n, bc, f), res, roofline, per_kernel = measure_srcnn(args, dev, W, args.steps, args.warmup)
+    unknowns = workloads.grid_unknowns(n, bc)
     cpu = None
     if not args.no_cpu:
         from oracle import srcnn
@@ -201,8 +233,6 @@ def bench_srcnn(args) -> int:
                            "prolongations": res["hybrid"]["ops"]},
         "roofline": roofline, "kernels": per_kernel, "cpu_baseline": cpu,
     }
-    for v in res.values():
-        v["solver"].close()
     print(json.dumps(out), flush=True)
     return 0
 
@@ -845,6 +875,16 @@ def main() -> int:
         log(f"generating batch256 seed {args.seed}")
         probs = workloads.workload("batch256", args.seed)
         subs["batch256"] = bench_batch(args, B, dev, probs, full=False)
+        # The learned prolongation on the periodic 1025^2 source: network
+        # cycles (bf16 matrix cores) against the spline and the hybrid
+        # schedule, and the level-0 convolutions against the bf16 peak.
+        import numpy as np
+        W = np.load(args.weights or WEIGHTS)
+        (n5, bc5, _), r5, roof5, _ = measure_srcnn(args, dev, W, args.steps, args.warmup)
+        u5 = workloads.grid_unknowns(n5, bc5)
+        subs["periodic1025_srcnn"] = {"unknowns": u5, "cnn_levels": 2,
+                                      "weights": os.path.relpath(args.weights or WEIGHTS, ROOT),
+                                      "paths": srcnn_summary(r5, u5), "roofline": roof5}
         out["other_workloads"] = subs
     print(json.dumps(out), flush=True)
     return 0
