@@ -75,10 +75,14 @@ __device__ __forceinline__ void run_phase(const PProblem* __restrict__ probs, co
                                           const PItem* __restrict__ items,
                                           const double* __restrict__ inv, T* sm) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int gwave = wave_uniform(blockIdx.x * kWavesPerBlock + wave);
+  // Consecutive items (neighbouring bands, then segments, of one level) go
+  // to workgroups of one XCD, so the rows and columns they share come from
+  // that XCD's L2 (xcd_tile permutes the workgroups).
+  const int wg = xcd_tile(blockIdx.x, gridDim.x);
+  const int gwave = wave_uniform(wg * kWavesPerBlock + wave);
   const int nwaves = gridDim.x * kWavesPerBlock;
   if constexpr (KIND == kItemTail) {
-    for (int i = blockIdx.x; i < P.count; i += gridDim.x) {
+    for (int i = wg; i < P.count; i += gridDim.x) {
       const PItem it = items[P.first + i];
       const PProblem& p = probs[it.prob];
       if (!p.active) continue;
@@ -93,7 +97,7 @@ __device__ __forceinline__ void run_phase(const PProblem* __restrict__ probs, co
       __syncthreads();
     }
   } else if constexpr (KIND == kItemPre) {
-    for (int i = blockIdx.x; i < P.count; i += gridDim.x) {
+    for (int i = wg; i < P.count; i += gridDim.x) {
       const PItem it = items[P.first + i];
       const PProblem& p = probs[it.prob];
       if (!p.active) continue;

@@ -144,13 +144,30 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
     // Fixed heights, plus for each pass the height at which all its items
     // are resident at once (at 4097^2 the mixed up pass runs 85 us at 64
     // rows, 70 us at 38, and 97 us at 32, where the items no longer fit).
+    // Short segments re-read more halo rows.  Timed alone, a pass finds those
+    // rows in the 256 MB last-level cache; inside a cycle over a level larger
+    // than that cache they come from HBM (4097^2 mixed down pass: 16-row
+    // segments time faster here but run 9 % slower in the cycle), so such
+    // levels do not try them, and there the resident heights are timed
+    // first, so that a fixed height must beat them by the margin below
+    // (periodic 4097^2 mixed up pass: 64 rows timed within it alone, but ran
+    // 86.7 us in the cycle against 70.3 us at 38).
+    const double level_bytes = (double)n * n * (add ? 24.0 : 3.0 * sizeof(T));
+    const bool big = level_bytes > 256e6;
     std::vector<int> hs_cands = {0, 4, 8, 16, 32, 64, 96, 128};
     {
       const int fd = stream_fit_rows<T>(add ? kFitDownRes : (uin ? kFitDownIn : kFitDown), p.bc, n);
       const int fu = stream_fit_rows<T>(add ? kFitUpPre : kFitUp, p.bc, n);
-      for (int hs : {fd, fu})
-        if (hs > 0 && std::find(hs_cands.begin(), hs_cands.end(), hs) == hs_cands.end())
+      for (int hs : {fu, fd}) {
+        if (hs <= 0) continue;
+        auto at = std::find(hs_cands.begin(), hs_cands.end(), hs);
+        if (big) {
+          if (at != hs_cands.end()) hs_cands.erase(at);
+          hs_cands.insert(hs_cands.begin(), hs);
+        } else if (at == hs_cands.end()) {
           hs_cands.push_back(hs);
+        }
+      }
     }
     if (add && !u64) {
       if (hipMalloc(&u64, sizeof(double) * (size_t)n * p.pitch[0]) != hipSuccess) {
@@ -178,13 +195,6 @@ int32_t tune_levels(mg_ctx_s* ctx, Problem& p, const std::string& arch, T* scrat
                                        h.c[l + 1], pc);
       }, &mp));
     }
-    // Short segments re-read more halo rows.  Timed alone, a pass finds those
-    // rows in the 256 MB last-level cache; inside a cycle over a level larger
-    // than that cache they come from HBM (4097^2 mixed down pass: 16-row
-    // segments time faster here but run 9 % slower in the cycle), so such
-    // levels do not try them.
-    const double level_bytes = (double)n * n * (add ? 24.0 : 3.0 * sizeof(T));
-    const bool big = level_bytes > 256e6;
     for (int var = 0; var < 3; ++var)
       for (int hs : hs_cands) {
         if (var >= 1 && hs != 0) continue;
