@@ -310,8 +310,9 @@ def test_mixed_step_residual_in_down_pass_is_bitwise(B, dev, bc, n):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("use_graph", [1, 0])
 @pytest.mark.parametrize("bc,n", [(D, 257), (P, 257), (D, 1025), (P, 1025)])
-def test_mixed_solve_norm_from_next_down_pass(B, dev, bc, n):
+def test_mixed_solve_norm_from_next_down_pass(B, dev, bc, n, use_graph):
     """mg_solve on the mixed path takes each norm check from the next step's
     level-0 down pass (which makes the FP64 residual of the iterate anyway)
     and queues the rest of that step only while the problem is unconverged.
@@ -320,17 +321,18 @@ def test_mixed_solve_norm_from_next_down_pass(B, dev, bc, n):
     the mean mg_solve removes on exit), so the down pass of the final check
     left the iterate as it was; and the relative residual it returns against
     the oracle's norm of that iterate before the mean removal (the
-    mg_vcycle result), 1e-12 relative."""
+    mg_vcycle result), 1e-12 relative.  With and without captured graphs
+    (the head and the rest of a step queued eagerly)."""
     from paper_2403_07936_amd.solver import Solver
-    say(f"norm from the next down pass bc={bc} n={n}")
+    say(f"norm from the next down pass bc={bc} n={n} use_graph={use_graph}")
     f = make_rhs(n, bc, 6)
     ft = gpu(f, dev)
     for steps in (1, 2, 3):
-        sa = Solver([(n, bc)], precision="mixed", check_every=1)
+        sa = Solver([(n, bc)], precision="mixed", check_every=1, use_graph=bool(use_graph))
         ua = torch.zeros_like(ft)
         st, cyc, rel = sa.solve([ua], [ft], rtol=1e-300, max_cycles=steps)
         sa.close()
-        sb = Solver([(n, bc)], precision="mixed")
+        sb = Solver([(n, bc)], precision="mixed", use_graph=bool(use_graph))
         ub = torch.zeros_like(ft)
         sb.vcycle([ub], [ft], steps)
         sb.close()
@@ -500,11 +502,12 @@ def test_unreachable_tolerance_reports_stagnation(B, dev):
 
 # ------------------------------------------------------- persistent schedule --
 
-def batch_ctx(B, specs, precision, schedule, check_every=0):
+def batch_ctx(B, specs, precision, schedule, check_every=0, use_graph=1):
     o = B.mg_options_default()
     o.precision = precision
     o.schedule = schedule
     o.check_every = check_every
+    o.use_graph = use_graph
     return B.mg_setup([(n, bc, 0) for n, bc in specs], o, torch.cuda.current_stream().cuda_stream)
 
 
@@ -573,10 +576,11 @@ def test_persistent_batch_solve(B, dev, schedule, precision):
         B.mg_destroy(ctx)
 
 
+@pytest.mark.parametrize("use_graph", [1, 0])
 @pytest.mark.parametrize("schedule", [2, 3])
 @pytest.mark.parametrize("bc,sizes", [(P, [257, 129, 513]), (D, [129, 257, 513]),
                                       (P, [65, 257])])
-def test_batch_solve_norm_from_next_down_pass(B, dev, schedule, bc, sizes):
+def test_batch_solve_norm_from_next_down_pass(B, dev, schedule, bc, sizes, use_graph):
     """Mixed batched mg_solve: when every problem's level 0 lies above the
     tail (sizes from 129 on), each check is the next step's down phases,
     whose level-0 items also write their sums of r^2, and the rest of that
@@ -585,13 +589,15 @@ def test_batch_solve_norm_from_next_down_pass(B, dev, schedule, bc, sizes):
     2 and 3 steps (check_every 1): each problem's iterate against the same
     number of mg_vcycle steps of the same batch, bit for bit (periodic: after
     the mean mg_solve removes), and its relative residual against the
-    oracle's norm of the mg_vcycle iterate (1e-12 relative)."""
-    say(f"batch norm from the next down pass schedule={schedule} bc={bc} sizes={sizes}")
+    oracle's norm of the mg_vcycle iterate (1e-12 relative).  With and without
+    captured launches."""
+    say(f"batch norm from the next down pass schedule={schedule} bc={bc} sizes={sizes} "
+        f"use_graph={use_graph}")
     specs = [(n, bc) for n in sizes]
     fs = [make_rhs(n, bc, 40 + k) for k, n in enumerate(sizes)]
     fts = [gpu(f, dev) for f in fs]
     for steps in (1, 2, 3):
-        ctx = batch_ctx(B, specs, 1, schedule, check_every=1)
+        ctx = batch_ctx(B, specs, 1, schedule, check_every=1, use_graph=use_graph)
         uas = [torch.zeros_like(t) for t in fts]
         try:
             st, cyc, rel = B.mg_solve(ctx, [t.data_ptr() for t in uas],
@@ -599,7 +605,7 @@ def test_batch_solve_norm_from_next_down_pass(B, dev, schedule, bc, sizes):
         finally:
             B.mg_destroy(ctx)
         assert st == B.MG_ERR_NOT_CONVERGED
-        ctx = batch_ctx(B, specs, 1, schedule)
+        ctx = batch_ctx(B, specs, 1, schedule, use_graph=use_graph)
         ubs = [torch.zeros_like(t) for t in fts]
         try:
             B.mg_vcycle(ctx, [t.data_ptr() for t in ubs], [t.data_ptr() for t in fts], steps)
