@@ -325,10 +325,9 @@ int32_t persistent_launch(mg_ctx_s* ctx, StepPart part) {
       const int blocks = wg ? q.count : (q.count + per - 1) / per;
       const size_t lds = q.kind == kItemTail ? P.lds_tail : (q.kind == kItemPre ? P.lds_pre : 0);
       const hipError_t e =
-          mixed ? launch_phase<float>(s, P.bc, q.kind, P.d_probs, P.d_phases, ph, P.d_items,
-                                      ctx->inv[P.bc], blocks, lds)
-                : launch_phase<double>(s, P.bc, q.kind, P.d_probs, P.d_phases, ph, P.d_items,
-                                       ctx->inv[P.bc], blocks, lds);
+          mixed ? launch_phase<float>(s, P.bc, q, P.d_probs, P.d_items, ctx->inv[P.bc], blocks, lds)
+                : launch_phase<double>(s, P.bc, q, P.d_probs, P.d_items, ctx->inv[P.bc], blocks,
+                                       lds);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;

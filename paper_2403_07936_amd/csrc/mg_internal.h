@@ -270,13 +270,12 @@ hipError_t launch_persistent(hipStream_t s, int bc, const PProblem* probs, const
 // (PProblem::npart, the sum of r^2) into sums[b], in a fixed order; 0 for a
 // problem without such items.
 hipError_t launch_reduce_norms(hipStream_t s, const PProblem* probs, int nprob, double* sums);
-// Phase `ph` of the table alone, by a kernel that holds only the code of
-// its kind (`kind` must be phases[ph].kind); blocks of kPersistThreads
-// threads, `lds` bytes of dynamic LDS (tail and prefilter phases).
+// One phase of the table alone (its record passed by value), by a kernel
+// that holds only the code of its kind; blocks of kPersistThreads threads,
+// `lds` bytes of dynamic LDS (tail and prefilter phases).
 template <typename T>
-hipError_t launch_phase(hipStream_t s, int bc, int kind, const PProblem* probs,
-                        const PPhase* phases, int ph, const PItem* items, const double* inv,
-                        int blocks, size_t lds);
+hipError_t launch_phase(hipStream_t s, int bc, const PPhase& phase, const PProblem* probs,
+                        const PItem* items, const double* inv, int blocks, size_t lds);
 // Wavefronts of the phase kernel of `kind` (kItemDown or kItemUp) that the
 // current device holds at once.
 template <typename T>

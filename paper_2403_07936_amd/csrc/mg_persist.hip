@@ -202,10 +202,11 @@ __global__ void __launch_bounds__(kPersistThreads)
 // wavefront items), are those of that kind alone.
 template <typename T, int BC, int KIND>
 __global__ void __launch_bounds__(kPersistThreads)
-    k_phase(const PProblem* __restrict__ probs, const PPhase* __restrict__ phases, int ph,
-            const PItem* __restrict__ items, const double* __restrict__ inv) {
+    k_phase(const PProblem* __restrict__ probs, PPhase P, const PItem* __restrict__ items,
+            const double* __restrict__ inv) {
+  // The phase record comes as an argument: a wavefront's first loads are
+  // then its item and its problem's fields, one dependent load fewer.
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const PPhase P = phases[ph];
   run_phase<T, BC, KIND>(probs, P, items, inv, reinterpret_cast<T*>(smem_raw));
 }
 
@@ -423,12 +424,12 @@ hipError_t launch_reduce_norms(hipStream_t s, const PProblem* probs, int nprob, 
 }
 
 template <typename T>
-hipError_t launch_phase(hipStream_t s, int bc, int kind, const PProblem* probs,
-                        const PPhase* phases, int ph, const PItem* items, const double* inv,
-                        int blocks, size_t lds) {
+hipError_t launch_phase(hipStream_t s, int bc, const PPhase& phase, const PProblem* probs,
+                        const PItem* items, const double* inv, int blocks, size_t lds) {
+  const int kind = phase.kind;
 #define MG_PHASE(B, K)                                                                          \
   hipLaunchKernelGGL((k_phase<T, B, K>), dim3(blocks), dim3(kPersistThreads), lds, s, probs,     \
-                     phases, ph, items, inv)
+                     phase, items, inv)
 #define MG_PHASE_BC(K)          \
   if (bc == kDirichlet)         \
     MG_PHASE(kDirichlet, K);    \
@@ -506,10 +507,10 @@ hipError_t phase_wave_slots(int bc, int kind, long* slots) {
 template hipError_t phase_wave_slots<double>(int, int, long*);
 template hipError_t phase_wave_slots<float>(int, int, long*);
 
-template hipError_t launch_phase<double>(hipStream_t, int, int, const PProblem*, const PPhase*,
-                                         int, const PItem*, const double*, int, size_t);
-template hipError_t launch_phase<float>(hipStream_t, int, int, const PProblem*, const PPhase*,
-                                        int, const PItem*, const double*, int, size_t);
+template hipError_t launch_phase<double>(hipStream_t, int, const PPhase&, const PProblem*,
+                                         const PItem*, const double*, int, size_t);
+template hipError_t launch_phase<float>(hipStream_t, int, const PPhase&, const PProblem*,
+                                        const PItem*, const double*, int, size_t);
 template hipError_t persistent_blocks<double>(int, size_t, int*);
 template hipError_t persistent_blocks<float>(int, size_t, int*);
 
