@@ -348,6 +348,39 @@ def test_mixed_solve_norm_from_next_down_pass(B, dev, bc, n, use_graph):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("bc,n", [(D, 513), (P, 513)])
+def test_mixed_solve_of_a_converged_iterate_changes_nothing(B, dev, bc, n):
+    """A mixed mg_solve started from an iterate that already meets the
+    tolerance stops at its initial check, which is the next step's level-0
+    down pass: zero cycles, status 0, and the iterate bit for bit as it was;
+    single problem and a batch of the same problem twice (schedule 3)."""
+    from paper_2403_07936_amd.solver import Solver
+    say(f"solve of a converged iterate bc={bc} n={n}")
+    f = make_rhs(n, bc, 8)
+    ft = gpu(f, dev)
+    s = Solver([(n, bc)], precision="mixed")
+    u = torch.zeros_like(ft)
+    st, cyc, rel = s.solve([u], [ft], rtol=1e-10, max_cycles=30)
+    assert st == 0 and cyc[0] > 0
+    before = host(u)
+    st, cyc, rel2 = s.solve([u], [ft], rtol=1e-10, max_cycles=30)
+    s.close()
+    say(f"  again: status {st} cycles {cyc[0]} relres {rel2[0]:.3e}")
+    assert st == 0 and cyc[0] == 0 and rel2[0] <= 1e-10
+    assert np.array_equal(host(u), before)
+    ctx = batch_ctx(B, [(n, bc), (n, bc)], 1, 3)
+    try:
+        us = [gpu(before, dev), gpu(before, dev)]
+        st, cyc, rel3 = B.mg_solve(ctx, [t.data_ptr() for t in us], [ft.data_ptr()] * 2,
+                                   1e-10, 30)
+    finally:
+        B.mg_destroy(ctx)
+    say(f"  batch: status {st} cycles {cyc} relres {rel3}")
+    assert st == 0 and cyc == [0, 0]
+    for t in us:
+        assert np.array_equal(host(t), before)
+
+
 @pytest.mark.parametrize("name", ["dirichlet4097", "periodic1025"])
 def test_full_size_cycle_parity(B, dev, name):
     """The benchmark configurations at full size, in the launch configuration
