@@ -176,11 +176,12 @@ MG_API int32_t mg_vcycle(mg_ctx ctx, double* const* u, const double* const* f, i
 /* Iterate cycles from the given u until ||f - A u|| / ||f|| <= rtol
  * (the paper iterates to a tolerance, Section 4.2).  Norms are checked every
  * check_every cycles (auto: after the first cycle, then at predicted
- * crossings).  Synchronises at every check.  On the mixed path with one
- * inner cycle and the streaming level-0 passes, a check is the next step's
- * level-0 down pass (it makes the FP64 residual of the iterate, which it
- * leaves unchanged), and the rest of that step runs only if the problem
- * goes on.  On exit periodic u has zero mean and a rewritten seam; its
+ * crossings).  Synchronises at every check.  When the level-0 down pass
+ * streams (and, mixed, with one inner cycle and a streaming level-0 up
+ * pass; no network), a check of a single-problem context is the next step's
+ * level-0 down pass, which measures the residual of the iterate it reads
+ * and leaves it unchanged, and the rest of that step runs only if the
+ * problem goes on (mixed batches likewise, with every down phase).  On exit periodic u has zero mean and a rewritten seam; its
  * relative residual is the one measured before that mean was removed (the
  * same up to rounding: constants are the null space of A).  cycles_out / relres_out (host arrays [batch],
  * may be NULL) receive per-problem cycle counts and final relative residuals.

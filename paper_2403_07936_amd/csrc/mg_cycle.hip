@@ -144,8 +144,12 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
   // up pass streams into the FP64 iterate: the up pass makes the
   // pre-smoothed iterate again from r32, so the down pass does not store it.
   const bool remake0 = res_u && u64 && t > 0 && !up_tiled(0) && !(cnn && ctx->cnn.levels > 0);
-  if (part != kWhole && !remake0)
-    return fail(MG_ERR_INVALID_ARG, "split step without the residual-making level-0 passes");
+  // FP64 cycle from the caller's iterate whose level-0 down pass streams:
+  // its head is that pass with the residual norm of the iterate it reads.
+  const bool head64 = f64 && !zero_guess && t > 0 && ctx->opt.kernel_path != 2 &&
+                      p.down_var[0] == 0 && !(cnn && ctx->cnn.levels > 0);
+  if (part != kWhole && !remake0 && !head64)
+    return fail(MG_ERR_INVALID_ARG, "split step without a streaming level-0 down pass");
   for (int l = 0; l < t; ++l) {
     const int n = p.side[l];
     const double m = unknowns_side(n, bc), mc = unknowns_side(p.side[l + 1], bc);
@@ -167,13 +171,18 @@ int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>&
         continue;
       }
     }
+    if (l == 0 && head64 && part == kRest) continue;
     MG_TRY(timed(ctx, s, MG_K_DOWN, l, bytes, [&] {
       if (ctx->opt.kernel_path == 2 || p.down_var[l] == 1)
         return launch_down<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l), h.f[l + 1],
                               p.pitch[l + 1], ca_at(l));
+      const bool norm = l == 0 && head64 && part == kHead;
       return launch_down_stream<T>(s, bc, n, uin, pu0, h.r[l], p.pitch[l], F(l), PF(l),
-                                   h.f[l + 1], p.pitch[l + 1], p.down_hs[l], ca_at(l));
+                                   h.f[l + 1], p.pitch[l + 1], p.down_hs[l], ca_at(l),
+                                   norm ? norm_partials : nullptr, 2 * p.nblocks,
+                                   norm ? norm_items : nullptr);
     }));
+    if (l == 0 && head64 && part == kHead) return MG_OK;
   }
   {
     const int nt = p.side[t];
@@ -236,14 +245,18 @@ bool use_fused(const mg_ctx_s* ctx) {
   return ctx->opt.kernel_path != 1 && ctx->opt.nu_pre == 2 && ctx->opt.nu_post == 2;
 }
 
-// A mixed step of p whose level-0 passes make the residual and the iterate
-// themselves (one inner cycle, both level-0 passes streaming, no network):
-// its convergence check is the step's own first pass (split_head), and a
-// step after a check queues only the rest.
+// A step of p whose convergence check is the step's own first pass (the
+// level-0 down pass, which reads the iterate and leaves it unchanged, with
+// the residual norm of that iterate), so that a step after a check queues
+// only the rest: a mixed step whose level-0 passes make the residual and
+// the iterate themselves (one inner cycle, both level-0 passes streaming),
+// or an FP64 cycle whose level-0 down pass streams; no network.
 bool split_step(const mg_ctx_s* ctx, const Problem& p) {
-  return ctx->opt.precision == MG_MIXED && use_fused(ctx) && !cnn_cycles(ctx) &&
-         ctx->opt.inner_cycles == 1 && p.tail > 0 && ctx->opt.kernel_path != 2 &&
-         p.down_var[0] == 0 && p.up_var[0] == 0;
+  if (!use_fused(ctx) || cnn_cycles(ctx) || p.tail == 0 || ctx->opt.kernel_path == 2 ||
+      p.down_var[0] != 0)
+    return false;
+  if (ctx->opt.precision == MG_FP64) return true;
+  return ctx->opt.inner_cycles == 1 && p.up_var[0] == 0;
 }
 
 // One step for problem p: an FP64 V-cycle, or one mixed refinement step
@@ -260,7 +273,8 @@ int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f
     if (fused)
       MG_TRY(enqueue_cycle_fused<double>(ctx, p, p.h64, p.taps64_dev, u, p.pitch0, f, p.pitch0,
                                          false, s, cnn, nullptr, 0, nullptr, nullptr, nullptr, 0,
-                                         nullptr, ca));
+                                         nullptr, ca,
+                                         have_res && split_step(ctx, p) ? kRest : kWhole));
     else
       MG_TRY(enqueue_cycle<double>(ctx, p, p.h64, p.taps64, u, p.pitch0, f, p.pitch0, s, cnn));
   } else {
@@ -383,6 +397,18 @@ int32_t enqueue_check_mixed(mg_ctx_s* ctx, Problem& p, const double* u, const do
     return launch_residual_mixed(ctx->stream, p.bc, p.n, u, p.pitch0, f, p.pitch0, p.h32.f[0],
                                  p.pitch[0], p.partials, &nb);
   }));
+  MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 1, p.sums));
+  return MG_OK;
+}
+
+// FP64 path, split steps: ||f - A u||^2 into p.sums[0] from the next
+// cycle's level-0 down pass (the head of that cycle, which leaves u as it
+// was); ||f||^2 is in p.sums[1] already.
+int32_t enqueue_check_head64(mg_ctx_s* ctx, Problem& p, double* u, const double* f) {
+  int nb = 0;
+  MG_TRY(enqueue_cycle_fused<double>(ctx, p, p.h64, p.taps64_dev, u, p.pitch0, f, p.pitch0, false,
+                                     ctx->stream, false, nullptr, 0, nullptr, nullptr, nullptr, 0,
+                                     nullptr, nullptr, kHead, p.partials, &nb));
   MG_HIP(launch_reduce(ctx->stream, p.partials, nb, nb, 1, p.sums));
   return MG_OK;
 }
@@ -555,7 +581,18 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
     }
     MG_TRY(read_relres(ctx, all, rel.data()));
   } else {
-    for (int b = 0; b < B; ++b) MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
+    for (int b = 0; b < B; ++b) {
+      Problem& p = ctx->probs[b];
+      if (split_step(ctx, p)) {
+        // ||f||^2 once (periodic: the mean check above left it), then the
+        // head of the first cycle.
+        if (p.bc != kPeriodic) MG_TRY(enqueue_fnorm(ctx, p, f[b]));
+        MG_TRY(enqueue_check_head64(ctx, p, u[b], f[b]));
+        have_res[b] = 1;
+      } else {
+        MG_TRY(enqueue_resnorm(ctx, p, u[b], f[b]));
+      }
+    }
     MG_TRY(read_relres(ctx, all, rel.data()));
   }
   for (int b = 0; b < B; ++b) {
@@ -658,7 +695,15 @@ int32_t solve_impl(mg_ctx ctx, double* const* u, const double* const* f, double 
       }
       MG_TRY(read_relres(ctx, chk, r.data(), track ? dif.data() : nullptr));
     } else {
-      for (int b : chk) MG_TRY(enqueue_resnorm(ctx, ctx->probs[b], u[b], f[b]));
+      for (int b : chk) {
+        Problem& p = ctx->probs[b];
+        if (split_step(ctx, p)) {
+          MG_TRY(enqueue_check_head64(ctx, p, u[b], f[b]));
+          have_res[b] = 1;
+        } else {
+          MG_TRY(enqueue_resnorm(ctx, p, u[b], f[b]));
+        }
+      }
       MG_TRY(read_relres(ctx, chk, r.data(), track ? dif.data() : nullptr));
     }
     for (size_t k = 0; k < chk.size(); ++k) {

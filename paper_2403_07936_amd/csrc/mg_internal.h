@@ -161,7 +161,11 @@ hipError_t launch_up(hipStream_t s, int bc, int n, const T* uin, int pui, T* uou
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
                               int puo, const T* f, int pf, T* fc, int pfc, int hs,
-                              const CallerArgs* ca = nullptr);
+                              const CallerArgs* ca = nullptr, double* partials = nullptr,
+                              int nparts = 0, int* nitems = nullptr);
+// partials (FP64, uin given): also one sum of r^2 per wavefront into
+// partials[0 .. *nitems) for ||f - A uin||, the residual of the iterate the
+// pass starts from; hipErrorInvalidValue when *nitems exceeds nparts.
 // u64 (nullable): instead of writing uout, add the result to this FP64
 // array (pitch p64) over the unknowns (the mixed path's refinement update);
 // ca: u64 = ca->u (FP32 with u64), or uout = ca->u and f = ca->f (FP64).

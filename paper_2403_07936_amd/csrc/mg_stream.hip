@@ -20,6 +20,27 @@ __global__ void __launch_bounds__(64 * kWaves)
                         h2, inv_h2, threadIdx.x & 63);
 }
 
+// The FP64 down pass from the caller's iterate that also writes each
+// wavefront's sum of r^2 of that iterate, over the unknowns it owns, to
+// partials[item] (lanes reduced in a fixed order).  Held to three
+// wavefronts per SIMD, as the plain pass runs.
+template <int BC>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3, 3)))
+    k_down_norm_s(int n, const double* __restrict__ uin, int pui, double* __restrict__ uout,
+                  int puo, const double* __restrict__ f, int pf, double* __restrict__ fc, int pfc,
+                  int nbands, int nitems, int hs, double h2, double inv_h2, const CallerArgs* ca,
+                  double* __restrict__ partials) {
+  const int item = wave_uniform(xcd_tile(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6));
+  if (item >= nitems) return;
+  if (ca) uin = ca->u, f = ca->f;
+  double2 acc = down_wave<double, BC, 1, false, true, 1>(
+      n, uin, pui, uout, puo, f, pf, fc, pfc, item % nbands, item / nbands, hs, h2, inv_h2,
+      threadIdx.x & 63);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc.x += __shfl_down(acc.x, off);
+  if ((threadIdx.x & 63) == 0) partials[item] = acc.x;
+}
+
 // Level-0 down pass of the mixed path with its right-hand side made from
 // the FP64 iterate (down_wave with RES).
 // SB = false: the pre-smoothed iterate is not stored (k_up_pre_s makes it
@@ -172,7 +193,7 @@ int stream_res_owned() { return kResOwned; }
 template <typename T>
 hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pui, T* uout,
                               int puo, const T* f, int pf, T* fc, int pfc, int hs,
-                              const CallerArgs* ca) {
+                              const CallerArgs* ca, double* partials, int nparts, int* nitems) {
   // A periodic band wraps at most once only from n - 1 >= 128 on (levels
   // this small are in the tail); hs must be even (row parity of a segment).
   if ((bc == kPeriodic && n - 1 < 128) || (hs > 0 && (hs & 1))) return hipErrorInvalidValue;
@@ -184,6 +205,25 @@ hipError_t launch_down_stream(hipStream_t s, int bc, int n, const T* uin, int pu
   const int blocks = (items + kWaves - 1) / kWaves;
   const double hd = 1.0 / (double)(n - 1);
   const T h2 = T(hd * hd), inv_h2 = T((double)(n - 1) * (double)(n - 1));
+  if (nitems) *nitems = items;
+  if (partials) {
+    // The norm form: FP64, from the caller's iterate, one partial per
+    // wavefront.
+    if constexpr (sizeof(T) == sizeof(double)) {
+      if (!uin || items > nparts) return hipErrorInvalidValue;
+      if (bc == kDirichlet)
+        hipLaunchKernelGGL((k_down_norm_s<kDirichlet>), dim3(blocks), dim3(64 * kWaves), 0, s, n,
+                           uin, pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2, ca,
+                           partials);
+      else
+        hipLaunchKernelGGL((k_down_norm_s<kPeriodic>), dim3(blocks), dim3(64 * kWaves), 0, s, n,
+                           uin, pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2, ca,
+                           partials);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (bc == kDirichlet && uin)
     hipLaunchKernelGGL((k_down_s<T, kDirichlet, 1>), dim3(blocks), dim3(64 * kWaves), 0, s, n, uin,
                        pui, uout, puo, f, pf, fc, pfc, nb, items, hs, h2, inv_h2, ca);
@@ -292,7 +332,8 @@ hipError_t launch_up_stream(hipStream_t s, int bc, int n, const T* uin, int pui,
 
 #define MG_STREAM_INSTANTIATE(T)                                                                \
   template hipError_t launch_down_stream<T>(hipStream_t, int, int, const T*, int, T*, int,      \
-                                            const T*, int, T*, int, int, const CallerArgs*);     \
+                                            const T*, int, T*, int, int, const CallerArgs*,      \
+                                            double*, int, int*);                                 \
   template hipError_t launch_up_stream<T>(hipStream_t, int, int, const T*, int, T*, int,        \
                                           const T*, int, const T*, int, int, double*, int,      \
                                           const CallerArgs*);

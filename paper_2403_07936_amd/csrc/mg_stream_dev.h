@@ -260,10 +260,13 @@ __device__ __forceinline__ void residual_row(const T (&um)[2], const T (&u0)[2],
 // pf64), rounded to FP32; the rows and columns the wavefront owns are also
 // stored to rout (pitch pro; f is not used), where the up pass reads them.  The same
 // arithmetic as residual_wave, so r32 is bitwise what that writes on the
-// nodes the up pass reads.  NORM (RES only): returns the lane's sum of r^2
-// (x) and, with NORM = 2, of f64^2 (y) in FP64 over the unknowns it owns
-// (periodic: the unique nodes), the residual norm of the FP64 iterate the
-// pass starts from and the norm it is measured against; zeros otherwise.
+// nodes the up pass reads.  NORM (RES, or UIN = 1): returns the lane's sum
+// of r^2 (x) and, with NORM = 2, of f^2 (y) in FP64 over the unknowns it owns
+// (periodic: the unique nodes), the residual norm of the iterate the pass
+// starts from and the norm it is measured against; zeros otherwise.  With
+// UIN = 1 the residual of row t is formed at step t, before that step's
+// sweeps, from rows t - 1 .. t + 1 as they were read (the sweeps reach row
+// t - 1 only at that step).
 template <typename T, int BC, int UIN, bool RES, int IN, bool SB = true, bool REV = false,
           int NORM = 0>
 __device__ __forceinline__ double2 down_wave_rows(int n, const T* __restrict__ uin, int pui,
@@ -275,7 +278,7 @@ __device__ __forceinline__ double2 down_wave_rows(int n, const T* __restrict__ u
                                           double inv_h2d, T* __restrict__ rout, int pro) {
   static_assert(!RES || (UIN == 0 && sizeof(T) == sizeof(float)), "RES: FP32 cycle from u = 0");
   static_assert(!REV || IN >= 1, "a reversed segment lies inside the grid");
-  static_assert(!NORM || RES, "the norm is of the residual the pass makes");
+  static_assert(!NORM || RES || UIN == 1, "the norm is of the iterate the pass reads");
   const int xw = band * kDownOwned - kDownHalo;
   const int x0 = xw + 2 * lane;
   // REV: the segment's rows [seg hs, seg hs + hs) are walked upwards, as
@@ -391,6 +394,24 @@ __device__ __forceinline__ double2 down_wave_rows(int n, const T* __restrict__ u
         }
         U[k & RM][0] = U[k & RM][1] = T(0);  // row t starts from 0
       } else {
+        if constexpr (NORM) {
+          static_assert(kAheadDown >= 2, "row t + 1 is in the ring at step t");
+          T rr[2];
+          residual_row<T, BC, IN>(U[(k + 15) & RM], U[k & RM], U[(k + 1) & RM], F[k & RM], rr, t,
+                                  n, col, inv_h2);
+          const bool own_row = t >= ys && t < ys + hs && (IN || t < row_end);
+          const bool fr = own_row && (BC == kPeriodic || IN || row_unknown<BC>(t, n));
+          const double q0 = (own_row && wr0) ? (double)rr[0] : 0.0;
+          const double q1 = (own_row && wr1) ? (double)rr[1] : 0.0;
+          const double g0 = (fr && wr0) ? (double)F[k & RM][0] : 0.0;
+          const double g1 = (fr && wr1) ? (double)F[k & RM][1] : 0.0;
+          acc += q0 * q0;
+          acc += q1 * q1;
+          if constexpr (NORM >= 2) {
+            accf += g0 * g0;
+            accf += g1 * g1;
+          }
+        }
         const int ta = t + kAheadDown < t0 + steps - 1 ? t + kAheadDown : t0 + steps - 1;
         T(&nu)[2] = U[(k + kAheadDown) & RM];
         if (UIN == 1 || (UIN == -1 && read_u)) load_row<T, BC, IN>(nu, uin, pui, ra(ta), n, col);
@@ -467,9 +488,9 @@ __device__ __forceinline__ double2 down_wave(int n, const T* __restrict__ uin, i
         n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs, h2, inv_h2, lane, u64, p64, f64,
         pf64, inv_h2d, rout, pro);
   else if (!RES && in && band_inside<BC>(band * kDownOwned - kDownHalo, n))
-    return down_wave_rows<T, BC, UIN, RES, 2, SB>(n, uin, pui, uout, puo, f, pf, fc, pfc, band,
-                                                  seg, hs, h2, inv_h2, lane, u64, p64, f64, pf64,
-                                                  inv_h2d, rout, pro);
+    return down_wave_rows<T, BC, UIN, RES, 2, SB, false, NORM>(
+        n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs, h2, inv_h2, lane, u64, p64, f64,
+        pf64, inv_h2d, rout, pro);
   else if (in)
     return down_wave_rows<T, BC, UIN, RES, 1, SB, false, NORM>(
         n, uin, pui, uout, puo, f, pf, fc, pfc, band, seg, hs, h2, inv_h2, lane, u64, p64, f64,

@@ -310,12 +310,14 @@ def test_mixed_step_residual_in_down_pass_is_bitwise(B, dev, bc, n):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
 @pytest.mark.parametrize("use_graph", [1, 0])
 @pytest.mark.parametrize("bc,n", [(D, 257), (P, 257), (D, 1025), (P, 1025)])
-def test_mixed_solve_norm_from_next_down_pass(B, dev, bc, n, use_graph):
-    """mg_solve on the mixed path takes each norm check from the next step's
-    level-0 down pass (which makes the FP64 residual of the iterate anyway)
-    and queues the rest of that step only while the problem is unconverged.
+def test_solve_norm_from_next_down_pass(B, dev, bc, n, use_graph, precision):
+    """mg_solve takes each norm check from the next step's level-0 down pass
+    (mixed: the pass makes the FP64 residual of the iterate anyway; FP64: the
+    pass forms the residual of the rows it reads before smoothing them) and
+    queues the rest of that step only while the problem is unconverged.
     Checked for 1, 2 and 3 steps (check_every 1): the iterate it returns
     against the same number of mg_vcycle steps, bit for bit (periodic: after
     the mean mg_solve removes on exit), so the down pass of the final check
@@ -324,15 +326,15 @@ def test_mixed_solve_norm_from_next_down_pass(B, dev, bc, n, use_graph):
     mg_vcycle result), 1e-12 relative.  With and without captured graphs
     (the head and the rest of a step queued eagerly)."""
     from paper_2403_07936_amd.solver import Solver
-    say(f"norm from the next down pass bc={bc} n={n} use_graph={use_graph}")
+    say(f"norm from the next down pass {precision} bc={bc} n={n} use_graph={use_graph}")
     f = make_rhs(n, bc, 6)
     ft = gpu(f, dev)
     for steps in (1, 2, 3):
-        sa = Solver([(n, bc)], precision="mixed", check_every=1, use_graph=bool(use_graph))
+        sa = Solver([(n, bc)], precision=precision, check_every=1, use_graph=bool(use_graph))
         ua = torch.zeros_like(ft)
         st, cyc, rel = sa.solve([ua], [ft], rtol=1e-300, max_cycles=steps)
         sa.close()
-        sb = Solver([(n, bc)], precision="mixed", use_graph=bool(use_graph))
+        sb = Solver([(n, bc)], precision=precision, use_graph=bool(use_graph))
         ub = torch.zeros_like(ft)
         sb.vcycle([ub], [ft], steps)
         sb.close()
@@ -349,25 +351,27 @@ def test_mixed_solve_norm_from_next_down_pass(B, dev, bc, n, use_graph):
 
 
 @pytest.mark.parametrize("bc,n", [(D, 513), (P, 513)])
-def test_mixed_solve_of_a_converged_iterate_changes_nothing(B, dev, bc, n):
-    """A mixed mg_solve started from an iterate that already meets the
-    tolerance stops at its initial check, which is the next step's level-0
-    down pass: zero cycles, status 0, and the iterate bit for bit as it was;
-    single problem and a batch of the same problem twice (schedule 3)."""
+def test_solve_of_a_converged_iterate_changes_nothing(B, dev, bc, n):
+    """An mg_solve started from an iterate that already meets the tolerance
+    stops at its initial check, which is the next step's level-0 down pass:
+    zero cycles, status 0, and the iterate bit for bit as it was; FP64 and
+    mixed single problems, and a mixed batch of the same problem twice
+    (schedule 3)."""
     from paper_2403_07936_amd.solver import Solver
     say(f"solve of a converged iterate bc={bc} n={n}")
     f = make_rhs(n, bc, 8)
     ft = gpu(f, dev)
-    s = Solver([(n, bc)], precision="mixed")
-    u = torch.zeros_like(ft)
-    st, cyc, rel = s.solve([u], [ft], rtol=1e-10, max_cycles=30)
-    assert st == 0 and cyc[0] > 0
-    before = host(u)
-    st, cyc, rel2 = s.solve([u], [ft], rtol=1e-10, max_cycles=30)
-    s.close()
-    say(f"  again: status {st} cycles {cyc[0]} relres {rel2[0]:.3e}")
-    assert st == 0 and cyc[0] == 0 and rel2[0] <= 1e-10
-    assert np.array_equal(host(u), before)
+    for precision in ("fp64", "mixed"):
+        s = Solver([(n, bc)], precision=precision)
+        u = torch.zeros_like(ft)
+        st, cyc, rel = s.solve([u], [ft], rtol=1e-10, max_cycles=30)
+        assert st == 0 and cyc[0] > 0
+        before = host(u)
+        st, cyc, rel2 = s.solve([u], [ft], rtol=1e-10, max_cycles=30)
+        s.close()
+        say(f"  {precision} again: status {st} cycles {cyc[0]} relres {rel2[0]:.3e}")
+        assert st == 0 and cyc[0] == 0 and rel2[0] <= 1e-10
+        assert np.array_equal(host(u), before)
     ctx = batch_ctx(B, [(n, bc), (n, bc)], 1, 3)
     try:
         us = [gpu(before, dev), gpu(before, dev)]
