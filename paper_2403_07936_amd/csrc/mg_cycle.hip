@@ -106,18 +106,21 @@ int32_t enqueue_cycle(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
   return MG_OK;
 }
 
-// StepPart for one problem's mixed refinement step: kHead is the level-0
-// down pass that makes the FP64 residual (with its norms), kRest all but
-// that pass (its outputs are already in place).  The iterate changes only
-// in the level-0 up pass, so the head alone leaves it as it was.
+// StepPart (mg_host.h) for one problem's step: kHead is the level-0 down
+// pass in the form that also sums r^2 of the iterate it starts from (the
+// mixed pass that makes the FP64 residual; the FP64 pass that reads u), kRest
+// all but that pass (its outputs are already in place).  The iterate
+// changes only in the level-0 up pass, so the head alone leaves it as it
+// was.
 
 // The fused schedule: down passes to the first level of at most 65 x 65,
 // the tail kernel, then prefilter + up passes back to level 0.  Level l's
 // pre-smoothed u goes to h.r[l] (ping-pong against h.u[l] / u0).
 // part (mixed level 0 with the residual made in the down pass and the
-// iterate made again in the up pass): kHead queues that down pass with one
-// partial of ||r||^2 and one of ||f||^2 per wavefront into norm_partials
-// (count per sum to *norm_items); kRest the rest of the cycle.
+// iterate made again in the up pass, or an FP64 cycle from the caller's
+// iterate with a streaming level-0 down pass): kHead queues that down pass
+// with per-wavefront partials into norm_partials (mixed: ||r||^2 and ||f||^2;
+// FP64: ||r||^2; count per sum to *norm_items); kRest the rest of the cycle.
 template <typename T>
 int32_t enqueue_cycle_fused(mg_ctx_s* ctx, const Problem& p, const Hierarchy<T>& h,
                             const PrefilterTaps* taps_dev, T* u0, int pu0, const T* f0, int pf0,
@@ -263,7 +266,8 @@ bool split_step(const mg_ctx_s* ctx, const Problem& p) {
 // (FP64 residual, FP32 inner cycles, FP64 update).  have_res: the mixed
 // step's residual of this u is already in the level-0 right-hand side (left
 // there by enqueue_check_mixed), so the step starts with the inner cycles;
-// for a split step, the whole level-0 down pass has run (split_head).
+// for a split step (mixed or FP64), the whole level-0 down pass has run as
+// the check (enqueue_check_mixed, enqueue_check_head64).
 int32_t enqueue_step(mg_ctx_s* ctx, const Problem& p, double* u, const double* f,
                      hipStream_t s, bool cnn, bool have_res = false,
                      const CallerArgs* ca = nullptr) {
