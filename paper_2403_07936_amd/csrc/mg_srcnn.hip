@@ -164,9 +164,11 @@ __device__ __forceinline__ TileRegs tile_fetch(const uint4* __restrict__ in, int
   const int row0 = (tile / tiles_x) * kTH, col0 = (tile % tiles_x) * kTW;
 #pragma unroll
   for (int k = 0; k < kTPerThread; ++k) {
-    // Threads past the tile's last slot re-read that slot's chunk (not stored).
+    // Chunk q is 16-byte chunk q % 8 of tile pixel q / 8 (a pixel's 128
+    // bytes by eight consecutive lanes); threads past the tile's last chunk
+    // re-read that chunk (not stored).
     const int q = min(k * kConvThreads + tid, kTileChunks - 1);
-    const int c = q / kTPix, p = q % kTPix;
+    const int c = q & 7, p = q >> 3;
     int gy = row0 - 1 + p / kHW, gx = col0 - 1 + p % kHW;
     gy = gy < 0 ? gy + N : (gy >= N ? gy - N : gy);
     gx = gx < 0 ? gx + N : (gx >= N ? gx - N : gx);
@@ -175,11 +177,17 @@ __device__ __forceinline__ TileRegs tile_fetch(const uint4* __restrict__ in, int
   return r;
 }
 
+// Chunk q of tile_fetch to its chunk-major LDS slot.  The eight lanes of a
+// pixel write slots kTPix = 340 apart (64 mod 256 bytes): with the pixel
+// offsets each 16-byte bank group serves four lanes of a wavefront, no
+// conflict.
+__device__ __forceinline__ int tile_slot(int q) { return (q & 7) * kTPix + (q >> 3); }
+
 __device__ __forceinline__ void tile_store(uint4* buf, int tid, const TileRegs& r) {
 #pragma unroll
-  for (int k = 0; k < kTPerThread - 1; ++k) buf[k * kConvThreads + tid] = r.v[k];
+  for (int k = 0; k < kTPerThread - 1; ++k) buf[tile_slot(k * kConvThreads + tid)] = r.v[k];
   const int q = (kTPerThread - 1) * kConvThreads + tid;
-  if (q < kTileChunks) buf[q] = r.v[kTPerThread - 1];
+  if (q < kTileChunks) buf[tile_slot(q)] = r.v[kTPerThread - 1];
 }
 
 template <int MODE>
@@ -322,7 +330,13 @@ __global__ void __launch_bounds__(kConvThreads)
 // LDS), the next step's reads issued before the current step's products.
 // LDS: the weight set and one input tile (16 + 2) x (32 + 2) pixels; the
 // next tile is fetched into registers during the products and stored after
-// them.
+// them.  Both sides of HBM are read and written a whole 16-byte chunk per
+// lane, consecutive lanes on consecutive chunks: a tile is fetched eight
+// lanes to a pixel (all of its 128 bytes), and the results go through the
+// input tile's LDS (free once the products are done) so that they leave as
+// whole pixels too.  Reading a chunk per lane across pixels (lanes 128
+// bytes apart) or storing from the accumulator layout (8 bytes per lane)
+// touches a line per lane and ran the kernel at 0.75x the speed.
 constexpr int kTH4 = 16;
 constexpr int kConv4Threads = 512;
 constexpr int kTPix4 = (kTH4 + 2) * kHW;
@@ -330,6 +344,8 @@ constexpr int kTileChunks4 = kTPix4 * 8;
 constexpr int kTPerThread4 = (kTileChunks4 + kConv4Threads - 1) / kConv4Threads;  // 10
 constexpr int kWPerThread4 = kWChunks / kConv4Threads;                            // 9
 static_assert(kWChunks % kConv4Threads == 0, "weight chunks split evenly");
+static_assert(kTH4 * kTW * 8 % kConv4Threads == 0, "result chunks split evenly");
+static_assert(kTH4 * kTW * 8 <= kTileChunks4, "the results fit in the input tile's LDS");
 
 template <int MODE>
 __global__ void __launch_bounds__(kConv4Threads)
@@ -343,11 +359,15 @@ __global__ void __launch_bounds__(kConv4Threads)
   const uint4* in4 = reinterpret_cast<const uint4*>(in);
   int tile = blockIdx.x;
   if (tile >= tiles) return;  // uniform per workgroup
-  // Chunk q of a tile's input (q < kTileChunks4): 16-byte chunk q / kTPix4
-  // of tile pixel q % kTPix4, with periodic wrap.
+  // Chunk q of a tile's input (q < kTileChunks4): 16-byte chunk q % 8 of
+  // tile pixel q / 8, with periodic wrap; it goes to LDS slot lds_slot(q) of
+  // the chunk-major layout.  (The eight lanes of a pixel write slots
+  // kTPix4 = 612 apart, 64 mod 256 bytes: with the pixel offsets each
+  // 16-byte bank group serves four lanes of a wavefront, no conflict.)
+  auto lds_slot = [](int q) { return (q & 7) * kTPix4 + (q >> 3); };
   auto chunk_of = [&](int t, int q) {
     const int row0 = (t / tiles_x) * kTH4, col0 = (t % tiles_x) * kTW;
-    const int c = q / kTPix4, p = q % kTPix4;
+    const int c = q & 7, p = q >> 3;
     int gy = row0 - 1 + p / kHW, gx = col0 - 1 + p % kHW;
     gy = gy < 0 ? gy + N : (gy >= N ? gy - N : gy);
     gx = gx < 0 ? gx + N : (gx >= N ? gx - N : gx);
@@ -368,7 +388,7 @@ __global__ void __launch_bounds__(kConv4Threads)
     for (int k = 0; k < kTPerThread4; ++k) t[k] = chunk_of(tile, min(k * kConv4Threads + tid, kTileChunks4 - 1));
 #pragma unroll
     for (int k = 0; k < kTPerThread4; ++k)
-      if (k * kConv4Threads + tid < kTileChunks4) ib[k * kConv4Threads + tid] = t[k];
+      if (k * kConv4Threads + tid < kTileChunks4) ib[lds_slot(k * kConv4Threads + tid)] = t[k];
   }
   __syncthreads();
 
@@ -406,7 +426,7 @@ __global__ void __launch_bounds__(kConv4Threads)
     };
     // The skip values (MODE 1), read before the products so that their
     // latency hides behind them (out may alias skip: each value is read
-    // here and written only by this lane's epilogue).
+    // here, before the barrier after which this workgroup writes it).
     uint2 skv[4][4];
     if (MODE == 1) {
 #pragma unroll
@@ -438,20 +458,14 @@ __global__ void __launch_bounds__(kConv4Threads)
     }
 
     // Lane holds pixel column m and output channels 32 hf + 8 g + 4 kh +
-    // (0..3) of output rows 4 rg + i.
+    // (0..3) of output rows 4 rg + i.  The bf16 results go to LDS as pixel
+    // records (pixel p = 32 row + column, 16-byte chunk 4 hf + g, half kh;
+    // chunks placed by swz), then out a chunk per lane.
+    __syncthreads();  // every wavefront is done reading this tile's input
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int y = row0 + 4 * rg + i, x = col0 + m;
-      size_t base;
-      if (MODE == 2) {
-        const int a = blockIdx.y >> 1, b = blockIdx.y & 1;
-        base = ((size_t)(2 * y + a) * (2 * N) + (2 * x + b)) * kC;
-      } else {
-        base = ((size_t)y * N + x) * kC;
-      }
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int ch = 32 * hf + 8 * g + 4 * kh;
         float v[4];
         for (int r = 0; r < 4; ++r) v[r] = acc[i][4 * g + r];
         if (MODE == 1) {
@@ -466,14 +480,29 @@ __global__ void __launch_bounds__(kConv4Threads)
         uint2 pk;
         pk.x = to_bf16(v[0]) | ((unsigned)to_bf16(v[1]) << 16);
         pk.y = to_bf16(v[2]) | ((unsigned)to_bf16(v[3]) << 16);
-        *reinterpret_cast<uint2*>(out + base + ch) = pk;
+        reinterpret_cast<uint2*>(ib + swz(32 * (4 * rg + i) + m, 4 * hf + g))[kh] = pk;
       }
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTH4 * kTW * 8 / kConv4Threads; ++k) {
+      const int q = k * kConv4Threads + tid;
+      const int p = q >> 3, c = q & 7;
+      const int y = row0 + (p >> 5), x = col0 + (p & 31);
+      size_t base;
+      if (MODE == 2) {
+        const int a = blockIdx.y >> 1, b = blockIdx.y & 1;
+        base = ((size_t)(2 * y + a) * (2 * N) + (2 * x + b)) * kC;
+      } else {
+        base = ((size_t)y * N + x) * kC;
+      }
+      *reinterpret_cast<uint4*>(out + base + 8 * c) = ib[swz(p, c)];
+    }
     if (next < tiles) {
-      __syncthreads();  // every wavefront is done with this tile
+      __syncthreads();  // every wavefront is done with the results
 #pragma unroll
       for (int k = 0; k < kTPerThread4; ++k)
-        if (k * kConv4Threads + tid < kTileChunks4) ib[k * kConv4Threads + tid] = pre[k];
+        if (k * kConv4Threads + tid < kTileChunks4) ib[lds_slot(k * kConv4Threads + tid)] = pre[k];
       __syncthreads();
     }
   }
