@@ -147,19 +147,31 @@ __global__ void __launch_bounds__(256)
 // channels 8c .. 8c+7) of a weight row (tap * 64 + out channel) or of a
 // tile pixel.  A fragment read by 32 lanes then covers 32 consecutive
 // slots (no bank conflicts), and every read of a step is one per-lane base
-// address plus a compile-time offset.
+// address plus a compile-time offset.  The weight chunks of one c lie
+// kWStride = kWRows + 2 slots apart: a weight set is fetched a row's eight
+// chunks by eight consecutive lanes (whole 128-byte rows from HBM), and
+// with a stride of 32 mod 256 bytes the sixteen 16-byte bank groups each
+// serve four lanes of a wavefront's store (at kWRows, 0 mod 256, eight
+// lanes would share one).
 constexpr int kWRows = 9 * kC;                  // weight rows (tap, out channel)
+constexpr int kWStride = kWRows + 2;            // LDS slots between weight chunks c and c + 1
+constexpr int kWSlots = 8 * kWStride;           // LDS slots of a weight set
 constexpr int kTPix = (kTH + 2) * kHW;          // tile pixels with halo
 constexpr int kWPerThread = kWChunks / kConvThreads;                           // 18
+static_assert(kWChunks % kConvThreads == 0, "weight chunks split evenly");
+static_assert((kWSlots + 2 * kTileChunks) * 16 <= 160 * 1024, "weights and two tiles fit the LDS");
+static_assert(kTH * kTW * 8 % kConvThreads == 0, "result chunks split evenly");
+static_assert(kTH * kTW * 8 <= kTileChunks, "the results fit in a tile buffer");
 constexpr int kTPerThread = (kTileChunks + kConvThreads - 1) / kConvThreads;  // 11
 
-struct TileRegs {
-  uint4 v[kTPerThread];
-};
+// The chunks are held as a native vector type: copies of the uint4 struct
+// became memory copies through a stack array once the results were staged
+// in LDS (192 bytes of scratch per lane).
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ TileRegs tile_fetch(const uint4* __restrict__ in, int N, int tile,
-                                               int tid) {
-  TileRegs r;
+__device__ __forceinline__ void tile_fetch(u32x4 (&r)[kTPerThread], const uint4* __restrict__ in4,
+                                           int N, int tile, int tid) {
+  const u32x4* in = reinterpret_cast<const u32x4*>(in4);
   const int tiles_x = N / kTW;
   const int row0 = (tile / tiles_x) * kTH, col0 = (tile % tiles_x) * kTW;
 #pragma unroll
@@ -172,9 +184,8 @@ __device__ __forceinline__ TileRegs tile_fetch(const uint4* __restrict__ in, int
     int gy = row0 - 1 + p / kHW, gx = col0 - 1 + p % kHW;
     gy = gy < 0 ? gy + N : (gy >= N ? gy - N : gy);
     gx = gx < 0 ? gx + N : (gx >= N ? gx - N : gx);
-    r.v[k] = in[((size_t)gy * N + gx) * 8 + c];
+    r[k] = in[((size_t)gy * N + gx) * 8 + c];
   }
-  return r;
 }
 
 // Chunk q of tile_fetch to its chunk-major LDS slot.  The eight lanes of a
@@ -183,11 +194,12 @@ __device__ __forceinline__ TileRegs tile_fetch(const uint4* __restrict__ in, int
 // conflict.
 __device__ __forceinline__ int tile_slot(int q) { return (q & 7) * kTPix + (q >> 3); }
 
-__device__ __forceinline__ void tile_store(uint4* buf, int tid, const TileRegs& r) {
+__device__ __forceinline__ void tile_store(uint4* buf4, int tid, const u32x4 (&r)[kTPerThread]) {
+  u32x4* buf = reinterpret_cast<u32x4*>(buf4);
 #pragma unroll
-  for (int k = 0; k < kTPerThread - 1; ++k) buf[tile_slot(k * kConvThreads + tid)] = r.v[k];
+  for (int k = 0; k < kTPerThread - 1; ++k) buf[tile_slot(k * kConvThreads + tid)] = r[k];
   const int q = (kTPerThread - 1) * kConvThreads + tid;
-  if (q < kTileChunks) buf[tile_slot(q)] = r.v[kTPerThread - 1];
+  if (q < kTileChunks) buf[tile_slot(q)] = r[kTPerThread - 1];
 }
 
 template <int MODE>
@@ -195,8 +207,8 @@ __global__ void __launch_bounds__(kConvThreads)
     k_cnn_conv(int N, const unsigned short* __restrict__ in, const unsigned short* __restrict__ w,
                unsigned short* out, const unsigned short* skip) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  uint4* wl = reinterpret_cast<uint4*>(lds);                         // kWChunks
-  uint4* ib = reinterpret_cast<uint4*>(lds) + kWChunks;              // 2 x kTileChunks
+  uint4* wl = reinterpret_cast<uint4*>(lds);                         // kWSlots
+  uint4* ib = reinterpret_cast<uint4*>(lds) + kWSlots;               // 2 x kTileChunks
   const int tid = threadIdx.x;
   const int tiles_x = N / kTW, tiles = tiles_x * (N / kTH);
   const uint4* in4 = reinterpret_cast<const uint4*>(in);
@@ -208,12 +220,19 @@ __global__ void __launch_bounds__(kConvThreads)
 #pragma unroll
     for (int k = 0; k < kWPerThread; ++k) {
       const int q = k * kConvThreads + tid;
-      r[k] = wg[(q % kWRows) * 8 + q / kWRows];
+      r[k] = wg[q];  // chunk q & 7 of weight row q >> 3
     }
 #pragma unroll
-    for (int k = 0; k < kWPerThread; ++k) wl[k * kConvThreads + tid] = r[k];
+    for (int k = 0; k < kWPerThread; ++k) {
+      const int q = k * kConvThreads + tid;
+      wl[(q & 7) * kWStride + (q >> 3)] = r[k];
+    }
   }
-  tile_store(ib, tid, tile_fetch(in4, N, tile, tid));
+  {
+    u32x4 first[kTPerThread];
+    tile_fetch(first, in4, N, tile, tid);
+    tile_store(ib, tid, first);
+  }
   __syncthreads();
 
   const int lane = tid & 63, wave = tid >> 6;
@@ -221,38 +240,33 @@ __global__ void __launch_bounds__(kConvThreads)
   int cur = 0;
   for (; tile < tiles; tile += gridDim.x) {
     const int next = tile + gridDim.x;
-    const TileRegs pre = tile_fetch(in4, N, next < tiles ? next : tile, tid);  // last pass: a re-read
+    u32x4 pre[kTPerThread];
+    tile_fetch(pre, in4, N, next < tiles ? next : tile, tid);  // last pass: a re-read
     const uint4* il = ib + cur * kTileChunks;
-    // Output addresses of this lane (pixel column m of rows 2 wave + i), and
-    // for MODE 1 the skip values there, loaded before the product loop so
-    // that their latency hides behind it (out may alias skip: each value is
-    // read here and written only by this lane's epilogue).
+    // The skip values (MODE 1) at this lane's outputs (pixel column m of
+    // rows 2 wave + i), loaded before the product loop so that their
+    // latency hides behind it (out may alias skip: each value is read here,
+    // before the barriers after which this workgroup writes it).
     const int row0 = (tile / tiles_x) * kTH, col0 = (tile % tiles_x) * kTW;
-    size_t obase[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int y = row0 + 2 * wave + i, x = col0 + m;
-      if (MODE == 2) {
-        const int a = blockIdx.y >> 1, b = blockIdx.y & 1;
-        obase[i] = ((size_t)(2 * y + a) * (2 * N) + (2 * x + b)) * kC;
-      } else {
-        obase[i] = ((size_t)y * N + x) * kC;
-      }
-    }
     uint2 skv[2][2][4];
     if (MODE == 1) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) {
+        const size_t ob = ((size_t)(row0 + 2 * wave + i) * N + (col0 + m)) * kC;
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
           for (int g = 0; g < 4; ++g)
-            skv[i][j][g] = *reinterpret_cast<const uint2*>(skip + obase[i] + 32 * j + 8 * g + 4 * kh);
+            skv[i][j][g] = *reinterpret_cast<const uint2*>(skip + ob + 32 * j + 8 * g + 4 * kh);
+      }
     }
 
     f32x16 acc[2][2];
+#pragma unroll
     for (int j = 0; j < 2; ++j)
+#pragma unroll
       for (int i = 0; i < 2; ++i)
+#pragma unroll
         for (int v = 0; v < 16; ++v) acc[j][i][v] = 0.f;
     // K loop of 36 steps (9 taps x 4 chunks of 16 input channels), fully
     // unrolled, with the four operand fragments of step s + kAheadK read
@@ -260,13 +274,13 @@ __global__ void __launch_bounds__(kConvThreads)
     // this load is several steps of products; at most 15 LDS reads may be
     // outstanding, so 3 steps of 4: measured 5 % faster than 2, and 4
     // steps, which make the compiler wait on the counter, slower).
-    const uint4* wb = wl + kh * kWRows + m;                 // chunk kh, row m
+    const uint4* wb = wl + kh * kWStride + m;               // chunk kh, row m
     const uint4* ibase = il + kh * kTPix + 2 * wave * kHW + m;  // chunk kh, pixel (2 wave, m)
     auto fetch = [&](int st, bf16x8 (&fr)[4]) {
       const int tap = st >> 2, kc = st & 3;
       const int poff = 2 * kc * kTPix + (tap / 3) * kHW + tap % 3;
-      fr[0] = __builtin_bit_cast(bf16x8, wb[2 * kc * kWRows + tap * kC]);
-      fr[1] = __builtin_bit_cast(bf16x8, wb[2 * kc * kWRows + tap * kC + 32]);
+      fr[0] = __builtin_bit_cast(bf16x8, wb[2 * kc * kWStride + tap * kC]);
+      fr[1] = __builtin_bit_cast(bf16x8, wb[2 * kc * kWStride + tap * kC + 32]);
       fr[2] = __builtin_bit_cast(bf16x8, ibase[poff]);
       fr[3] = __builtin_bit_cast(bf16x8, ibase[poff + kHW]);
     };
@@ -287,16 +301,24 @@ __global__ void __launch_bounds__(kConvThreads)
       __builtin_amdgcn_sched_barrier(0);
     }
 
-    // Lane holds pixel column m and output channels 32j + 8g + 4kh + (0..3).
+    // Lane holds pixel column m and output channels 32j + 8g + 4kh + (0..3)
+    // of output rows 2 wave + i.  The bf16 results go to this tile's LDS
+    // buffer (read by every wavefront's products until the barrier) as
+    // pixel records (pixel p = 32 row + column, 16-byte chunk 4j + g, half
+    // kh; chunks placed by swz), then out a whole chunk per lane.  The next
+    // tile goes to the other buffer first (free since the last pass's final
+    // barrier), so that its registers are not held through the results.
+    __syncthreads();
+    if (next < tiles) tile_store(ib + (cur ^ 1) * kTileChunks, tid, pre);
+    uint4* rl = ib + cur * kTileChunks;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const size_t base = obase[i];
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-          const int ch = 32 * j + 8 * g + 4 * kh;
           float v[4];
+#pragma unroll
           for (int r = 0; r < 4; ++r) v[r] = acc[j][i][4 * g + r];
           if (MODE == 1) {
             const uint2 sk = skv[i][j][g];
@@ -305,15 +327,30 @@ __global__ void __launch_bounds__(kConvThreads)
             v[2] += from_bf16(sk.y & 0xffff);
             v[3] += from_bf16(sk.y >> 16);
           } else {
+#pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.f);
           }
           uint2 pk;
           pk.x = to_bf16(v[0]) | ((unsigned)to_bf16(v[1]) << 16);
           pk.y = to_bf16(v[2]) | ((unsigned)to_bf16(v[3]) << 16);
-          *reinterpret_cast<uint2*>(out + base + ch) = pk;
+          reinterpret_cast<uint2*>(rl + swz(32 * (2 * wave + i) + m, 4 * j + g))[kh] = pk;
         }
     }
-    if (next < tiles) tile_store(ib + (cur ^ 1) * kTileChunks, tid, pre);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTH * kTW * 8 / kConvThreads; ++k) {
+      const int q = k * kConvThreads + tid;
+      const int p = q >> 3, c = q & 7;
+      const int y = row0 + (p >> 5), x = col0 + (p & 31);
+      size_t base;
+      if (MODE == 2) {
+        const int a = blockIdx.y >> 1, b = blockIdx.y & 1;
+        base = ((size_t)(2 * y + a) * (2 * N) + (2 * x + b)) * kC;
+      } else {
+        base = ((size_t)y * N + x) * kC;
+      }
+      *reinterpret_cast<uint4*>(out + base + 8 * c) = rl[swz(p, c)];
+    }
     __syncthreads();
     cur ^= 1;
   }
@@ -344,6 +381,7 @@ constexpr int kTileChunks4 = kTPix4 * 8;
 constexpr int kTPerThread4 = (kTileChunks4 + kConv4Threads - 1) / kConv4Threads;  // 10
 constexpr int kWPerThread4 = kWChunks / kConv4Threads;                            // 9
 static_assert(kWChunks % kConv4Threads == 0, "weight chunks split evenly");
+static_assert((kWSlots + kTileChunks4) * 16 <= 160 * 1024, "weights and tile fit the LDS");
 static_assert(kTH4 * kTW * 8 % kConv4Threads == 0, "result chunks split evenly");
 static_assert(kTH4 * kTW * 8 <= kTileChunks4, "the results fit in the input tile's LDS");
 
@@ -352,8 +390,8 @@ __global__ void __launch_bounds__(kConv4Threads)
     k_cnn_conv4(int N, const unsigned short* __restrict__ in, const unsigned short* __restrict__ w,
                 unsigned short* out, const unsigned short* skip) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  uint4* wl = reinterpret_cast<uint4*>(lds);             // kWChunks
-  uint4* ib = reinterpret_cast<uint4*>(lds) + kWChunks;  // kTileChunks4
+  uint4* wl = reinterpret_cast<uint4*>(lds);             // kWSlots
+  uint4* ib = reinterpret_cast<uint4*>(lds) + kWSlots;   // kTileChunks4
   const int tid = threadIdx.x;
   const int tiles_x = N / kTW, tiles = tiles_x * (N / kTH4);
   const uint4* in4 = reinterpret_cast<const uint4*>(in);
@@ -379,10 +417,13 @@ __global__ void __launch_bounds__(kConv4Threads)
 #pragma unroll
     for (int k = 0; k < kWPerThread4; ++k) {
       const int q = k * kConv4Threads + tid;
-      r[k] = wg[(q % kWRows) * 8 + q / kWRows];
+      r[k] = wg[q];  // chunk q & 7 of weight row q >> 3
     }
 #pragma unroll
-    for (int k = 0; k < kWPerThread4; ++k) wl[k * kConv4Threads + tid] = r[k];
+    for (int k = 0; k < kWPerThread4; ++k) {
+      const int q = k * kConv4Threads + tid;
+      wl[(q & 7) * kWStride + (q >> 3)] = r[k];
+    }
     uint4 t[kTPerThread4];
 #pragma unroll
     for (int k = 0; k < kTPerThread4; ++k) t[k] = chunk_of(tile, min(k * kConv4Threads + tid, kTileChunks4 - 1));
@@ -395,7 +436,7 @@ __global__ void __launch_bounds__(kConv4Threads)
   const int lane = tid & 63, wave = tid >> 6;
   const int rg = wave >> 1, hf = wave & 1;
   const int m = lane & 31, kh = lane >> 5;
-  const uint4* wb = wl + kh * kWRows + 32 * hf + m;           // chunk kh, weight row 32 hf + m
+  const uint4* wb = wl + kh * kWStride + 32 * hf + m;         // chunk kh, weight row 32 hf + m
   const uint4* ibase = ib + kh * kTPix4 + 4 * rg * kHW + m;   // chunk kh, pixel (4 rg, m)
   for (; tile < tiles; tile += gridDim.x) {
     const int next = tile + gridDim.x;
@@ -419,7 +460,7 @@ __global__ void __launch_bounds__(kConv4Threads)
       const int dx = st >> 2, kc = st & 3;
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy)
-        fa[dy] = __builtin_bit_cast(bf16x8, wb[2 * kc * kWRows + (dy * 3 + dx) * kC]);
+        fa[dy] = __builtin_bit_cast(bf16x8, wb[2 * kc * kWStride + (dy * 3 + dx) * kC]);
 #pragma unroll
       for (int r = 0; r < 6; ++r)
         fb[r] = __builtin_bit_cast(bf16x8, ibase[2 * kc * kTPix4 + r * kHW + dx]);
@@ -581,8 +622,8 @@ int g_cus = 256;  // compute units of the device (set by cnn_init)
 
 }  // namespace
 
-size_t cnn_conv_lds() { return (size_t)(kWChunks + 2 * kTileChunks) * 16; }
-size_t cnn_conv4_lds() { return (size_t)(kWChunks + kTileChunks4) * 16; }
+size_t cnn_conv_lds() { return (size_t)(kWSlots + 2 * kTileChunks) * 16; }
+size_t cnn_conv4_lds() { return (size_t)(kWSlots + kTileChunks4) * 16; }
 
 hipError_t cnn_init() {
   int dev = 0;
@@ -621,9 +662,13 @@ hipError_t launch_cnn_head(hipStream_t s, int N, const T* e, int pe, float* part
 
 hipError_t launch_cnn_conv(hipStream_t s, int mode, int N, const unsigned short* in,
                            const unsigned short* w, unsigned short* out, const unsigned short* skip) {
-  // One workgroup per compute unit (its LDS holds a whole weight set), each
-  // taking at least two tiles where there are enough.  Tall tiles (16 rows)
-  // where they still give every compute unit a tile; else 8-row tiles.
+  // At most one workgroup per compute unit (its LDS holds a whole weight
+  // set).  Tall tiles (16 rows) where they still give every compute unit a
+  // tile; else 8-row tiles, one per workgroup up to a workgroup per compute
+  // unit (a 256^2 layer: 12.9 us on 256 workgroups against 15.8 us on 128
+  // taking two tiles each, measured with 8-byte result stores: the weight
+  // set's load is then shared by fewer products but spread over twice the
+  // compute units).
   const int sets = mode == 2 ? 4 : 1;
   const int tall = (N / kTW) * (N / kTH4);
   if (tall * sets >= g_cus) {
@@ -641,7 +686,7 @@ hipError_t launch_cnn_conv(hipStream_t s, int mode, int N, const unsigned short*
   }
   const int tiles = (N / kTW) * (N / kTH);
   int g = std::max(1, g_cus / sets);
-  g = std::min(g, std::max(1, (tiles + 1) / 2));
+  g = std::min(g, tiles);
   const dim3 grid((unsigned)g, (unsigned)sets);
   const size_t lds = cnn_conv_lds();
   if (mode == 0)
