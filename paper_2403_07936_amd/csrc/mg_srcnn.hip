@@ -86,16 +86,23 @@ __global__ void __launch_bounds__(256) k_cnn_scale(const float* __restrict__ par
 }
 
 // ---------------------------------------------------------------- stem
-// Thread = pixel: its 9 scaled, bf16-rounded inputs, then all 64 output
-// channels (the weight addresses are uniform, so they come through the
-// scalar cache).  stem_w: [64][9] floats.
+// Eight lanes per pixel, lane g of them computing output channels 8g..8g+7
+// (16 bytes) from the pixel's 9 scaled, bf16-rounded inputs, so that the
+// eight store the pixel's 128 bytes together (one pixel per thread, each
+// writing its eight chunks, touched a cache line per lane: 25.9 us at
+// 512^2).  stem_w: [64][9] floats, staged in LDS.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_cnn_stem(int N, const T* __restrict__ e, int pe, const float* __restrict__ scale,
                const float* __restrict__ stem_w, unsigned short* __restrict__ h) {
+  __shared__ float sw[kC * 9];
+  for (int k = threadIdx.x; k < kC * 9; k += 256) sw[k] = stem_w[k];
+  __syncthreads();
   const float s = scale[0];
-  const long pix = (long)blockIdx.x * 256 + threadIdx.x;
-  if (pix >= (long)N * N) return;
+  const long q = (long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (long)N * N * 8) return;
+  const long pix = q >> 3;
+  const int g = (int)(q & 7);
   const int y = (int)(pix / N), x = (int)(pix % N);
   float xv[9];
 #pragma unroll
@@ -108,25 +115,21 @@ __global__ void __launch_bounds__(256)
       const float v = (float)e[(long)yy * pe + xx];
       xv[dy * 3 + dx] = s > 0.f ? from_bf16(to_bf16(v / s)) : 0.f;
     }
-  uint4* dst = reinterpret_cast<uint4*>(h + pix * kC);
+  unsigned short o[8];
 #pragma unroll
-  for (int g = 0; g < 8; ++g) {
-    unsigned short o[8];
+  for (int c = 0; c < 8; ++c) {
+    const float* w = sw + (g * 8 + c) * 9;
+    float acc = 0.f;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const float* w = stem_w + (g * 8 + c) * 9;
-      float acc = 0.f;
-#pragma unroll
-      for (int t = 0; t < 9; ++t) acc += w[t] * xv[t];
-      o[c] = to_bf16(fmaxf(acc, 0.f));
-    }
-    uint4 pk;
-    pk.x = o[0] | ((unsigned)o[1] << 16);
-    pk.y = o[2] | ((unsigned)o[3] << 16);
-    pk.z = o[4] | ((unsigned)o[5] << 16);
-    pk.w = o[6] | ((unsigned)o[7] << 16);
-    dst[g] = pk;
+    for (int t = 0; t < 9; ++t) acc += w[t] * xv[t];
+    o[c] = to_bf16(fmaxf(acc, 0.f));
   }
+  uint4 pk;
+  pk.x = o[0] | ((unsigned)o[1] << 16);
+  pk.y = o[2] | ((unsigned)o[3] << 16);
+  pk.z = o[4] | ((unsigned)o[5] << 16);
+  pk.w = o[6] | ((unsigned)o[7] << 16);
+  reinterpret_cast<uint4*>(h)[q] = pk;  // chunk g of pixel pix
 }
 
 // ---------------------------------------------------------------- 64-channel conv
@@ -654,7 +657,7 @@ hipError_t launch_cnn_head(hipStream_t s, int N, const T* e, int pe, float* part
                            const float* stem_w, unsigned short* h, float* scale) {
   hipLaunchKernelGGL(k_cnn_absmax<T>, dim3(kPartials), dim3(256), 0, s, N, e, pe, partials);
   hipLaunchKernelGGL(k_cnn_scale, dim3(1), dim3(256), 0, s, partials, scale);
-  const long threads = (long)N * N;
+  const long threads = (long)N * N * 8;
   hipLaunchKernelGGL(k_cnn_stem<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, N, e,
                      pe, scale, stem_w, h);
   return hipGetLastError();
