@@ -96,15 +96,16 @@ __global__ void __launch_bounds__(256)
     k_cnn_stem(int N, const T* __restrict__ e, int pe, const float* __restrict__ scale,
                const float* __restrict__ stem_w, unsigned short* __restrict__ h) {
   __shared__ float sw[kC * 9];
-  for (int k = threadIdx.x; k < kC * 9; k += 256) sw[k] = stem_w[k];
-  __syncthreads();
-  const float s = scale[0];
-  const long q = (long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= (long)N * N * 8) return;
+  const long nq = (long)N * N * 8;
+  const long q0 = (long)blockIdx.x * 256 + threadIdx.x;
+  const bool live = q0 < nq;
+  const long q = live ? q0 : nq - 1;  // past the end: a re-read, not stored
   const long pix = q >> 3;
   const int g = (int)(q & 7);
   const int y = (int)(pix / N), x = (int)(pix % N);
-  float xv[9];
+  // The inputs' reads go out before the weights' barrier, so that the two
+  // latencies overlap.
+  T ev[9];
 #pragma unroll
   for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
@@ -112,9 +113,18 @@ __global__ void __launch_bounds__(256)
       int yy = y + dy - 1, xx = x + dx - 1;
       yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
       xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
-      const float v = (float)e[(long)yy * pe + xx];
-      xv[dy * 3 + dx] = s > 0.f ? from_bf16(to_bf16(v / s)) : 0.f;
+      ev[dy * 3 + dx] = e[(long)yy * pe + xx];
     }
+  for (int k = threadIdx.x; k < kC * 9; k += 256) sw[k] = stem_w[k];
+  __syncthreads();
+  if (!live) return;
+  const float s = scale[0];
+  float xv[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const float v = (float)ev[t];
+    xv[t] = s > 0.f ? from_bf16(to_bf16(v / s)) : 0.f;
+  }
   unsigned short o[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -566,9 +576,11 @@ __global__ void __launch_bounds__(256)
   __shared__ __attribute__((aligned(16))) unsigned wf[9 * kC / 2];    // bf16 pairs [tap][ch/2]
   const int tiles_x = M / kFT;
   const int y0 = (blockIdx.x / tiles_x) * kFT, x0 = (blockIdx.x % tiles_x) * kFT;
-  // The weights are bf16 values (rounded at setup), so packing is exact.
-  for (int q = threadIdx.x; q < 9 * kC / 2; q += 256)
-    wf[q] = to_bf16(fin_w[2 * q]) | ((unsigned)to_bf16(fin_w[2 * q + 1]) << 16);
+  const int ty = threadIdx.x / kFT, tx = threadIdx.x % kFT;
+  const int y = y0 + ty, x = x0 + tx;
+  // The tile's reads, the weights' and this node's uin value go out
+  // together (no latency waits on another before the products).
+  const T base = uin ? uin[(size_t)y * pui + x] : T(0);
   {
     constexpr int kChunks = kFHW * kFHW * 8, kPer = (kChunks + 255) / 256;
     uint4 r[kPer];
@@ -581,6 +593,9 @@ __global__ void __launch_bounds__(256)
       gx = gx < 0 ? gx + M : (gx >= M ? gx - M : gx);
       r[k] = reinterpret_cast<const uint4*>(z)[((size_t)gy * M + gx) * 8 + c];
     }
+    // The weights are bf16 values (rounded at setup), so packing is exact.
+    for (int q = threadIdx.x; q < 9 * kC / 2; q += 256)
+      wf[q] = to_bf16(fin_w[2 * q]) | ((unsigned)to_bf16(fin_w[2 * q + 1]) << 16);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int q = threadIdx.x + k * 256;
@@ -588,7 +603,6 @@ __global__ void __launch_bounds__(256)
     }
   }
   __syncthreads();
-  const int ty = threadIdx.x / kFT, tx = threadIdx.x % kFT;
   // Products of two bf16 values are exact in FP32; v_dot2 adds a pair of
   // them to the FP32 accumulator.
   float acc = 0.f;
@@ -610,12 +624,11 @@ __global__ void __launch_bounds__(256)
     }
   }
   const T d = (T)(scale[0] * acc);
-  const int y = y0 + ty, x = x0 + tx;
   auto put = [&](int yy, int xx) {
-    const T base = uin ? uin[(size_t)yy * pui + xx] : T(0);
-    uout[(size_t)yy * puo + xx] = base + d;
+    const T b = uin ? uin[(size_t)yy * pui + xx] : T(0);
+    uout[(size_t)yy * puo + xx] = b + d;
   };
-  put(y, x);
+  uout[(size_t)y * puo + x] = base + d;
   if (y == 0) put(M, x);
   if (x == 0) put(y, M);
   if (x == 0 && y == 0) put(M, M);
