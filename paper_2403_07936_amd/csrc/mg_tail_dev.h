@@ -34,15 +34,19 @@ struct PreCfg {
 template <typename T>
 struct PreTile {
   static constexpr int K = PreCfg<T>::K;
-  static constexpr int S = sizeof(T) == 8 ? 8 : 16;
-  static constexpr int TW = 64;
-  static constexpr int TH = 4 * S;       // one column chunk per thread
+  // FP64: 48 columns so that the 28-node halo still fits two columns per
+  // lane and the LDS (148 KB); 64 x 32 tiles with 8-node chunks loaded
+  // 5.2x their coefficients against 4.1x here and ran 1.3x longer.
+  static constexpr int S = 16;
+  static constexpr int TW = sizeof(T) == 8 ? 48 : 64;
+  static constexpr int TH = 4 * S;       // four column chunks per column
   static constexpr int HI = TH + 2 * K;  // rows of the halo'd tile
   static constexpr int WI = TW + 2 * K;  // columns of the halo'd tile
   static constexpr int PI = WI | 1;      // LDS pitches: odd, so that lanes on
   static constexpr int PM = TW + 1;      // consecutive rows hit distinct banks
   static constexpr size_t kLds = (size_t)(HI * PI + HI * PM) * sizeof(T);
   static_assert(WI <= 128, "a lane loads at most two columns of the halo'd tile");
+  static_assert(TW % S == 0 && TH % S == 0, "whole chunks along both axes");
 };
 
 // S coefficients y from S + 2K consecutive nodes x[0], x[sx], ... of an
@@ -140,7 +144,7 @@ __device__ __forceinline__ void pre_tile_block(int nc, const T* __restrict__ in,
   // Columns along y (lanes on consecutive columns) and the store.
   const int M = BC == kPeriodic ? nc - 1 : nc;
   if (t < C::TW * (C::TH / C::S)) {
-    const int x = lane, q = wave * C::S, gx = x0 + x;
+    const int x = t % C::TW, q = (t / C::TW) * C::S, gx = x0 + x;
     T y[C::S];
     chunk_iir<T, C::S, C::K>(sm + q * C::PM + x, C::PM, y);
     if (gx < M) {
